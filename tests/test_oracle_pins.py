@@ -1,0 +1,443 @@
+"""Pins of the CPU oracle against facts the mathematics fixes (no GPU).
+
+Each test checks the oracle against something other than itself: closed-form
+quadrature integrals, Kronecker/partition-of-unity properties of the basis,
+exact geometric identities, polynomial reproduction (q = -grad u and R = 0 for
+u in Q_p), discrete conservation, symmetry of the Poisson operator, the closed
+form five-point-style stencil at p = 0, manufactured-solution convergence rates
+(the pattern of the Poisson convergence table of Section 4.1: u at order p+1,
+q at order p), Jacobian-vector products against differences, flux consistency,
+and the BDF2 recurrence.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import oracle as O
+from paper_2205_07824_amd import inputs as I
+from tests.util import penalty, poisson_setup, rel
+
+
+# ---------------------------------------------------------------- P1 quadrature
+@pytest.mark.parametrize("m", range(1, 9))
+def test_gauss_legendre_exactness(m):
+    x, w = O.gauss_legendre(m)
+    for k in range(2 * m):
+        exact = 2.0 / (k + 1) if k % 2 == 0 else 0.0
+        assert abs(np.sum(w * x ** k) - exact) < 1e-14
+    # first non-integrated degree is not exact
+    k = 2 * m
+    assert abs(np.sum(w * x ** k) - 2.0 / (k + 1)) > 1e-6
+
+
+def test_gauss_legendre_closed_forms():
+    x, w = O.gauss_legendre(2)
+    assert np.allclose(x, [-1 / math.sqrt(3), 1 / math.sqrt(3)], atol=1e-15, rtol=0)
+    assert np.allclose(w, [1, 1], atol=1e-15, rtol=0)
+    x, w = O.gauss_legendre(3)
+    assert np.allclose(x, [-math.sqrt(0.6), 0, math.sqrt(0.6)], atol=1e-15, rtol=0)
+    assert np.allclose(w, [5 / 9, 8 / 9, 5 / 9], atol=1e-15, rtol=0)
+
+
+# ---------------------------------------------------------------- P2 basis
+@pytest.mark.parametrize("p", range(0, 7))
+def test_lagrange_basis(p):
+    xn, _ = O.gauss_legendre(p + 1)
+    for i in range(p + 1):
+        for j in range(p + 1):
+            assert abs(O.lagrange(xn, i, xn[j]) - (1.0 if i == j else 0.0)) < 1e-14
+    rng = np.random.default_rng(3)
+    for x in rng.uniform(-1, 1, 5):
+        assert abs(sum(O.lagrange(xn, i, x) for i in range(p + 1)) - 1.0) < 1e-13
+        assert abs(sum(O.lagrange(xn, i, x, True) for i in range(p + 1))) < 1e-12
+        for k in range(1, p + 1):  # d/dx x^k = k x^{k-1} reproduced exactly
+            d = sum(xn[i] ** k * O.lagrange(xn, i, x, True) for i in range(p + 1))
+            assert abs(d - k * x ** (k - 1)) < 1e-12
+
+
+# ---------------------------------------------------------------- P3 geometry
+@pytest.mark.parametrize("nd,perturb", [(2, 0.0), (2, 0.05), (3, 0.0), (3, 0.05)])
+def test_geometry_volume_and_closed_surface(nd, perturb):
+    box = I.box_mesh(nd, 4, perturb=perturb, seed=1)
+    m = O.Mesh(box, 2)
+    vol, ns = m.geometry_checks()
+    assert abs(vol.sum() - 1.0) < 1e-14
+    assert np.abs(ns).max() < 1e-14
+    assert (vol > 0).all()
+
+
+def test_geometry_periodic_tgv_box():
+    box = I.box_mesh(3, 4, lo=(0, 0, 0), hi=(2 * np.pi,) * 3, periodic=(True,) * 3)
+    m = O.Mesh(box, 1)
+    vol, _ = m.geometry_checks()
+    assert abs(vol.sum() - (2 * np.pi) ** 3) < 1e-12
+    nb = m.neighbours()
+    assert (nb >= 0).all()  # fully periodic: no boundary faces
+    assert m.nbf == 0
+
+
+# ---------------------------------------------------------------- P4 free stream
+@pytest.mark.parametrize("nd", [2, 3])
+def test_free_stream_poisson_constant(nd):
+    p = 3 if nd == 2 else 2
+    box = I.box_mesh(nd, 3, perturb=0.05, seed=2)
+    m = O.Mesh(box, p)
+    c = 1.7
+    md = O.Model(O.MODEL_POISSON, 1, [1.0, penalty(p, 1 / 3), 0.0], src=np.zeros((m.E, 1, m.nqv)),
+                 bdata=np.full((m.nbf, 1, m.nqf), c), bc_kind=[0])
+    R, q = m.residual(md, np.full(m.size(1), c), want_q=True)
+    assert np.abs(R).max() < 1e-12
+    assert np.abs(q).max() < 1e-12
+
+
+@pytest.mark.parametrize("nd", [2, 3])
+def test_free_stream_euler_perturbed_periodic(nd):
+    p = 2
+    box = I.box_mesh(nd, 3, periodic=(True,) * nd, perturb=0.05, seed=4)
+    m = O.Mesh(box, p)
+    ncu = nd + 2
+    md = O.Model(O.MODEL_EULER, ncu, [1.4])
+    state = np.array([1.2, 0.3, -0.2, 0.1][:nd + 1] + [2.5])
+    u = np.broadcast_to(state[None, :, None], (m.E, ncu, m.nn)).reshape(-1).copy()
+    R = m.residual(md, u)
+    assert np.abs(R).max() < 1e-12
+
+
+# ---------------------------------------------------------------- P5 patch test
+@pytest.mark.parametrize("nd,p", [(2, 1), (2, 2), (2, 3), (3, 1), (3, 2)])
+def test_polynomial_reproduction(nd, p):
+    # u of total degree <= p (invariant under affine maps, so it lies in the
+    # mapped Q_p space): q_h = -grad u exactly and R(u) = 0 with s = -lap u and
+    # exact Dirichlet data.
+    rng = np.random.default_rng(5)
+    degs = []
+    while len(degs) < 4:
+        e = tuple(int(t) for t in rng.integers(0, p + 1, size=nd))
+        if sum(e) <= p:
+            degs.append(e)
+    coeffs = rng.normal(size=4)
+    mms = lambda x: I.mms_poly(x, coeffs, degs)
+    # affine, non-uniform elements: shear the unit box linearly
+    box = I.box_mesh(nd, 3)
+    A = np.eye(nd) + 0.2 * np.triu(np.ones((nd, nd)), 1)
+    box.vert = box.vert @ A.T
+    m = O.Mesh(box, p)
+    xn, xq, xb, _ = m.points()
+    u_ex, g_ex, f = mms(xq)
+    ub, _, _ = mms(xb)
+    md = O.Model(O.MODEL_POISSON, 1, [1.0, 5.0, 0.0], src=f.reshape(m.E, 1, m.nqv),
+                 bdata=ub.reshape(m.nbf, 1, m.nqf), bc_kind=[0])
+    un, gn, _ = mms(xn)
+    R, q = m.residual(md, un.reshape(-1), want_q=True)
+    q = q.reshape(m.E, 1, nd, m.nn)
+    assert np.abs(q[:, 0] + gn.transpose(0, 2, 1)).max() < 1e-11 * (1 + np.abs(gn).max())
+    assert np.abs(R).max() < 1e-11 * (1 + np.abs(f).max())
+
+
+# ---------------------------------------------------------------- P6 conservation
+def test_conservation_euler_periodic():
+    nd = 2
+    box = I.box_mesh(nd, 4, periodic=(True, True), perturb=0.05, seed=6)
+    m = O.Mesh(box, 3)
+    md = O.Model(O.MODEL_EULER, 4, [1.4])
+    rng = np.random.default_rng(1)
+    u = np.zeros((m.E, 4, m.nn))
+    u[:, 0] = 1 + 0.2 * rng.uniform(-1, 1, (m.E, m.nn))
+    u[:, 1:3] = 0.3 * rng.uniform(-1, 1, (m.E, 2, m.nn))
+    u[:, 3] = 3 + 0.2 * rng.uniform(-1, 1, (m.E, m.nn))
+    R = m.residual(md, u.reshape(-1)).reshape(m.E, 4, m.nn)
+    v = rng.uniform(-1, 1, u.shape)
+    Jv = m.jvp(md, u.reshape(-1), v.reshape(-1)).reshape(m.E, 4, m.nn)
+    for c in range(4):
+        assert abs(R[:, c].sum()) < 1e-12 * np.abs(R[:, c]).sum()
+        assert abs(Jv[:, c].sum()) < 1e-12 * np.abs(Jv[:, c]).sum()
+
+
+def test_conservation_convdiff_periodic():
+    nd = 2
+    box = I.box_mesh(nd, 4, periodic=(True, True))
+    m = O.Mesh(box, 2)
+    xn, _, _, _ = m.points()
+    grf = I.GRF.sample(0, ell=0.3)
+    b = I.DivFreeVelocity.sample(0)
+    aux = np.concatenate([np.exp(grf.log_kappa(xn))[:, None, :], b(xn).transpose(0, 2, 1)], axis=1)
+    md = O.Model(O.MODEL_CONVDIFF, 1, [1.0, penalty(2, 0.25)], aux=aux)
+    u = np.random.default_rng(2).uniform(-1, 1, m.size(1))
+    R = m.residual(md, u)
+    assert abs(R.sum()) < 1e-12 * np.abs(R).sum()
+
+
+# ---------------------------------------------------------------- P7 symmetry / SPD
+@pytest.mark.parametrize("nd", [2, 3])
+def test_poisson_symmetric_positive(nd):
+    box, m, md = poisson_setup(nd, 3, 2, I.mms_sin2d if nd == 2 else I.mms_sin3d, perturb=0.05)
+    md = md.replace(src=None, bdata=None)  # homogeneous: R is linear
+    rng = np.random.default_rng(7)
+    N = m.size(1)
+    v, w = rng.uniform(-1, 1, N), rng.uniform(-1, 1, N)
+    Av = m.jvp(md, np.zeros(N), v)
+    Aw = m.jvp(md, np.zeros(N), w)
+    assert abs(w @ Av - v @ Aw) < 1e-12 * abs(w @ Av)
+    assert v @ Av > 0
+
+
+# ---------------------------------------------------------------- P8 p = 0 stencil
+def test_p0_closed_form_stencil():
+    n = 6
+    h = 1.0 / n
+    tau = 3.0
+    box = I.box_mesh(2, n, periodic=(True, True))
+    m = O.Mesh(box, 0, 1)
+    md = O.Model(O.MODEL_POISSON, 1, [1.0, tau, 0.0])
+    u = np.random.default_rng(8).uniform(-1, 1, (n, n))  # [j][i], x fastest
+    R = m.residual(md, u.reshape(-1)).reshape(n, n)
+    r = lambda a, s, ax: np.roll(a, -s, axis=ax)
+    wide = (r(u, 2, 1) - 2 * u + r(u, -2, 1)) + (r(u, 2, 0) - 2 * u + r(u, -2, 0))
+    std = 4 * u - r(u, 1, 1) - r(u, -1, 1) - r(u, 1, 0) - r(u, -1, 0)
+    expect = -0.25 * wide + tau * h * std
+    assert np.abs(R - expect).max() < 1e-14
+
+
+# ---------------------------------------------------------------- P9 MMS rates
+def _mms_errors(nd, n, p, mms, perturb=0.0):
+    box, m, md = poisson_setup(nd, n, p, mms, perturb=perturb)
+    N = m.size(1)
+    J = m.jacobian(md, np.zeros(N))
+    u = spla.spsolve(J.tocsc(), -m.residual(md, np.zeros(N)))
+    _, q = m.residual(md, u, want_q=True)
+    xe = m.error_points(p + 3)
+    ue, ge, _ = mms(xe)
+    return m.l2_error(p + 3, 1, 0, u, q, ue, -ge)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_mms_rates_2d(p):
+    errs = [_mms_errors(2, n, p, I.mms_sin2d) for n in (4, 8, 16)]
+    ru = math.log2(errs[1][0] / errs[2][0])
+    rq = math.log2(errs[1][1] / errs[2][1])
+    assert abs(ru - (p + 1)) < 0.2, (p, ru)
+    assert abs(rq - p) < 0.2, (p, rq)
+
+
+@pytest.mark.parametrize("p", [1])
+def test_mms_rates_3d_perturbed(p):
+    # the 3D manufactured solution of the perturbed-hex workload
+    errs = [_mms_errors(3, n, p, I.mms_expsin3d, perturb=0.05) for n in (2, 4, 8)]
+    ru = math.log2(errs[1][0] / errs[2][0])
+    rq = math.log2(errs[1][1] / errs[2][1])
+    assert ru > p + 1 - 0.3, (p, ru)
+    assert rq > p - 0.3, (p, rq)
+
+
+# ---------------------------------------------------------------- P10 JVP
+def test_jvp_linear_equals_difference():
+    box, m, md = poisson_setup(3, 2, 2, I.mms_expsin3d, perturb=0.05)
+    rng = np.random.default_rng(9)
+    N = m.size(1)
+    u, v = rng.uniform(-1, 1, N), rng.uniform(-1, 1, N)
+    Jv = m.jvp(md, u, v)
+    d = m.residual(md, v) - m.residual(md, np.zeros(N))
+    assert rel(Jv, d) < 1e-13
+
+
+@pytest.mark.parametrize("kind", [O.MODEL_EULER, O.MODEL_NS])
+def test_jvp_nonlinear_vs_central_difference(kind):
+    nd = 2
+    box = I.box_mesh(nd, 3, periodic=(True, True), perturb=0.04, seed=3)
+    m = O.Mesh(box, 2)
+    mu = [1.4] if kind == O.MODEL_EULER else [1.4, 100.0, 0.72, penalty(2, 1 / 3)]
+    md = O.Model(kind, 4, mu, a0=2.0, r=np.random.default_rng(3).uniform(-1, 1, m.size(4)))
+    rng = np.random.default_rng(10)
+    u = np.zeros((m.E, 4, m.nn))
+    u[:, 0] = 1 + 0.1 * rng.uniform(-1, 1, (m.E, m.nn))
+    u[:, 1:3] = 0.3 * rng.uniform(-1, 1, (m.E, 2, m.nn))
+    u[:, 3] = 3 + 0.1 * rng.uniform(-1, 1, (m.E, m.nn))
+    u = u.reshape(-1)
+    v = rng.uniform(-1, 1, u.shape)
+    Jv = m.jvp(md, u, v)
+    eps = 1e-6 * (1 + np.linalg.norm(u)) / np.linalg.norm(v)
+    fd = (m.residual(md, u + eps * v) - m.residual(md, u - eps * v)) / (2 * eps)
+    assert rel(Jv, fd) < 1e-7
+
+
+# ---------------------------------------------------------------- P11 fluxes
+@pytest.mark.parametrize("kind", [O.MODEL_EULER, O.MODEL_NS])
+def test_numerical_flux_consistency_and_antisymmetry(kind):
+    nd = 3
+    mu = [1.4] if kind == O.MODEL_EULER else [1.4, 50.0, 0.71, 2.0]
+    md = O.Model(kind, 5, mu)
+    rng = np.random.default_rng(11)
+    for _ in range(5):
+        uL = np.array([1.1, 0.2, -0.3, 0.1, 2.7]) + 0.05 * rng.normal(size=5)
+        uR = np.array([0.9, -0.1, 0.2, 0.3, 2.4]) + 0.05 * rng.normal(size=5)
+        qL, qR = rng.normal(size=15), rng.normal(size=15)
+        n = rng.normal(size=3)
+        n /= np.linalg.norm(n)
+        a = np.zeros(4)
+        f = O.point_flux(md, nd, uL, qL, a)
+        Fc = O.point_numflux(md, nd, uL, qL, a, uL, qL, a, n)
+        assert np.abs(Fc - f @ n).max() < 1e-14 * (1 + np.abs(f).max())
+        F1 = O.point_numflux(md, nd, uL, qL, a, uR, qR, a, n)
+        F2 = O.point_numflux(md, nd, uR, qR, a, uL, qL, a, -n)
+        assert np.abs(F1 + F2).max() < 1e-14 * (1 + np.abs(F1).max())
+
+
+def test_euler_flux_closed_form():
+    md = O.Model(O.MODEL_EULER, 4, [1.4])
+    rho, vx, vy, p = 1.3, 0.4, -0.7, 2.1
+    E = p / 0.4 + 0.5 * rho * (vx * vx + vy * vy)
+    f = O.point_flux(md, 2, [rho, rho * vx, rho * vy, E], np.zeros(8), np.zeros(4))
+    expect = np.array([[rho * vx, rho * vy], [rho * vx * vx + p, rho * vx * vy],
+                       [rho * vx * vy, rho * vy * vy + p], [(E + p) * vx, (E + p) * vy]])
+    assert np.abs(f - expect).max() < 1e-14
+
+
+def test_ns_viscous_flux_couette():
+    # simple shear u = (a y, 0), constant rho, p: viscous x-momentum flux in y is mu * a
+    md = O.Model(O.MODEL_NS, 4, [1.4, 10.0, 0.72, 1.0])
+    rho, a, y, p = 1.0, 0.3, 0.5, 1.0
+    vx = a * y
+    E = p / 0.4 + 0.5 * rho * vx * vx
+    # gradients of conservative variables; q = -grad u
+    grad = np.zeros((4, 2))
+    grad[1, 1] = rho * a              # d(rho u)/dy
+    grad[3, 1] = rho * vx * a         # d(rho E)/dy (p constant)
+    q = (-grad).reshape(-1)
+    f = O.point_flux(md, 2, [rho, rho * vx, 0.0, E], q, np.zeros(4))
+    fi = O.point_flux(O.Model(O.MODEL_EULER, 4, [1.4]), 2, [rho, rho * vx, 0.0, E], q, np.zeros(4))
+    visc = fi - f
+    mu = 0.1
+    assert abs(visc[1, 1] - mu * a) < 1e-14
+    assert abs(visc[1, 0]) < 1e-14
+    assert abs(visc[3, 1] - vx * mu * a) < 1e-14  # work of the shear stress; e is uniform
+
+
+# ---------------------------------------------------------------- P12 blocks / GMRES
+def test_blocks_equal_diagonal_of_assembled_jacobian():
+    box, m, md = poisson_setup(2, 3, 2, I.mms_sin2d, perturb=0.05)
+    N = m.size(1)
+    J = m.jacobian(md, np.zeros(N)).toarray()
+    B = m.blocks(md, np.zeros(N))
+    nb = m.nn
+    for K in range(m.E):
+        assert np.abs(B[K] - J[K * nb:(K + 1) * nb, K * nb:(K + 1) * nb]).max() < 1e-13
+
+
+def test_jacobian_columns_match_jvp():
+    box = I.box_mesh(2, 3, periodic=(True, True), perturb=0.03, seed=2)
+    m = O.Mesh(box, 1)
+    md = O.Model(O.MODEL_NS, 4, [1.4, 20.0, 0.72, 2.0])
+    rng = np.random.default_rng(12)
+    u = np.zeros((m.E, 4, m.nn))
+    u[:, 0] = 1 + 0.1 * rng.uniform(-1, 1, (m.E, m.nn))
+    u[:, 1:3] = 0.2 * rng.uniform(-1, 1, (m.E, 2, m.nn))
+    u[:, 3] = 3 + 0.1 * rng.uniform(-1, 1, (m.E, m.nn))
+    u = u.reshape(-1)
+    J = m.jacobian(md, u)
+    v = rng.uniform(-1, 1, u.shape)
+    assert rel(J @ v, m.jvp(md, u, v)) < 1e-13
+
+
+def test_fgmres_block_jacobi_matches_direct_solve():
+    box, m, md = poisson_setup(2, 8, 2, I.mms_sin2d, nq=5)
+    N = m.size(1)
+    J = m.jacobian(md, np.zeros(N))
+    b = -m.residual(md, np.zeros(N))
+    x_direct = spla.spsolve(J.tocsc(), b)
+    lu = O.BlockLU(m.blocks(md, np.zeros(N)))
+    A = lambda z: m.jvp(md, np.zeros(N), z)
+    hist = []
+    x, info = O.fgmres(A, b, M=lu.solve, restart=30, rtol=1e-12, history=hist)
+    assert info["converged"]
+    assert rel(x, x_direct) < 1e-10
+    # the Givens estimate tracks the true residual at the end of a cycle
+    assert abs(hist[-1] - info["res_true"]) <= 1e-3 * info["res0"] * 1e-10 + 1e-9 * info["res_true"] + 1e-18
+
+
+# ---------------------------------------------------------------- P13 BDF2
+def test_bdf2_recurrence_reaction():
+    lam, dt = 0.7, 0.3
+    box = I.box_mesh(2, 3, periodic=(True, True))
+    m = O.Mesh(box, 1)
+    N = m.size(1)
+    u_prev = np.full(N, 1.0)
+    # BDF1 first step
+    md = O.Model(O.MODEL_POISSON, 1, [1.0, 4.0, lam], a0=1 / dt, r=u_prev / dt)
+    u1 = spla.spsolve(m.jacobian(md, np.zeros(N)).tocsc(), -m.residual(md, np.zeros(N)))
+    assert np.allclose(u1, 1.0 / (1 + lam * dt), atol=1e-14, rtol=0)
+    un, unm1 = u1, u_prev
+    s_n, s_nm1 = 1.0 / (1 + lam * dt), 1.0
+    for _ in range(3):
+        md = md.replace(a0=1.5 / dt, r=(4 * un - unm1) / (2 * dt))
+        unew = spla.spsolve(m.jacobian(md, np.zeros(N)).tocsc(), -m.residual(md, np.zeros(N)))
+        s_new = (4 * s_n - s_nm1) / (3 + 2 * dt * lam)
+        assert np.abs(unew - s_new).max() < 1e-13
+        unm1, un = un, unew
+        s_nm1, s_n = s_n, s_new
+
+
+# ---------------------------------------------------------------- P14 Newton
+def test_newton_quadratic_on_euler_implicit_step():
+    box = I.box_mesh(2, 4, lo=(0, 0), hi=(20, 20), periodic=(True, True))
+    m = O.Mesh(box, 2)
+    xn, _, _, _ = m.points()
+    cents = I.vortex_centres(1, 20.0, 5.0, 0)
+    un = I.isentropic_vortices(xn, cents).transpose(0, 2, 1).reshape(-1).copy()
+    dt = 0.5
+    md = O.Model(O.MODEL_EULER, 4, [1.4], a0=1 / dt, r=un / dt)
+    G = lambda u: m.residual(md, u)
+    solve = lambda u, rhs: spla.spsolve(m.jacobian(md, u).tocsc(), rhs)
+    hist = []
+    u, info = O.newton(G, solve, un, rtol=1e-13, maxit=8, history=hist)
+    assert info["res"] <= 1e-12 * info["res0"] or info["res"] < 1e-13
+    # quadratic: ||G_{k+1}|| / ||G_k||^2 bounded while above rounding
+    r = [h for h in hist if h > 1e-11]
+    for a, b in zip(r[:-1], r[1:]):
+        assert b <= 50.0 * a * a + 1e-12
+
+
+# ---------------------------------------------------------------- P15 MLP gradient
+def test_mlp_backward_vs_central_difference():
+    rng = np.random.default_rng(13)
+    dims = [(6, 5), (6,), (4, 6), (4,), (3, 4), (3,)]
+    params = [rng.normal(size=s) * 0.5 for s in dims]
+    X, Y = rng.normal(size=(7, 5)), rng.normal(size=(7, 3))
+    loss, grads = O.mlp_loss_and_grad(params, X, Y)
+    for pi in range(len(params)):
+        flat = params[pi].reshape(-1)
+        for idx in range(min(flat.size, 6)):
+            h = 1e-6
+            old = flat[idx]
+            flat[idx] = old + h
+            lp, _ = O.mlp_loss_and_grad(params, X, Y)
+            flat[idx] = old - h
+            lm, _ = O.mlp_loss_and_grad(params, X, Y)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - grads[pi].reshape(-1)[idx]) < 1e-7 * (1 + abs(fd))
+
+
+# ---------------------------------------------------------------- P17 / P18 inputs
+def test_grf_statistics_and_divergence_free_velocity():
+    grf = I.GRF.sample(4, ell=0.1)
+    x = np.random.default_rng(5).uniform(0, 1, (20000, 2))
+    lk = grf.log_kappa(x)
+    assert abs(lk.var() - 1.0) < 0.1
+    b = I.DivFreeVelocity.sample(4)
+    h = 1e-6
+    pts = np.random.default_rng(6).uniform(0, 1, (50, 2))
+    div = ((b(pts + [h, 0])[:, 0] - b(pts - [h, 0])[:, 0]) + (b(pts + [0, h])[:, 1] - b(pts - [0, h])[:, 1])) / (2 * h)
+    assert np.abs(div).max() < 1e-5 * b.A
+
+
+def test_taylor_green_closed_forms():
+    n = 48
+    g = (np.arange(n) + 0.5) * 2 * np.pi / n
+    X = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1)
+    U = I.taylor_green(X)
+    rho = U[..., 0]
+    vel = U[..., 1:4] / rho[..., None]
+    ek = np.mean(0.5 * rho * (vel ** 2).sum(-1))
+    assert abs(ek - 0.125) < 2e-3
