@@ -1,0 +1,199 @@
+"""Benchmark: LDG Jacobian-vector product throughput and Newton-GMRES time-to-1e-8.
+
+Workload: 3D Poisson/heat, LDG p=3 on a 32^3 hex mesh of the unit cube with
+interior vertices perturbed by +-5% of h (seed 0), manufactured solution
+exp(x+y+z) sin(pi x y z), Dirichlet data; N = 32^3 * 64 = 2,097,152 DOF.
+
+Timed steps: K applications of the FP64 Jacobian-vector product J v (the
+gradient kernel + the residual/tangent kernel), inputs resident in HBM.
+value = N * K / (timed seconds) in GDOF/s.  After the timed region the same
+run reports: the JVP in FP32, the residual, per-kernel HIP-event timings,
+Newton-GMRES time-to-1e-8 for the plain FP64 block-Jacobi form and the mixed
+forms, and the oracle on a bounded sample of elements on the host (1 core).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_workload(ldg, I, n=32, p=3):
+    import torch
+    box = I.box_mesh(3, n, perturb=0.05, seed=0)
+    m = ldg.Mesh(box, p)
+    xn, xq, xb, _ = m.points()
+    _, _, f = I.mms_expsin3d(xq)
+    ub, _, _ = I.mms_expsin3d(xb)
+    tau = (p + 1) ** 2 * n
+    md = ldg.Model(m, ldg.MODEL_POISSON, 1, [1.0, tau, 0.0], src=f.reshape(m.E, 1, m.nqv),
+                   bdata=ub.reshape(m.nbf, 1, m.nqf), bc_kind=(0,))
+    return box, m, md
+
+
+def event_time(fn, reps):
+    import torch
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=32)
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-jvp-only", action="store_true",
+                    help="only the timed JVP steps (for counter collection)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2205_07824_amd import inputs as I
+    from paper_2205_07824_amd import ldg
+
+    assert torch.cuda.is_available()
+    box, m, md = build_workload(ldg, I, n=args.n)
+    N = md.N
+    log(f"workload: E={m.E} nn={m.nn} N={N} colours={m.ncolors}")
+    v = torch.as_tensor(np.random.default_rng(2).uniform(-1, 1, N), device="cuda")
+    u = torch.as_tensor(np.random.default_rng(1).uniform(-1, 1, N), device="cuda")
+    Jv = md.empty()
+
+    for _ in range(args.warmup):
+        md.jvp(None, v, out=Jv)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e_jvp = event_time(lambda: md.jvp(None, v, out=Jv), args.steps)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    value = N * args.steps / T / 1e9
+    log(f"FP64 JVP: {e_jvp * 1e6:.1f} us/launch (events), wall {T / args.steps * 1e6:.1f} us/step")
+
+    # roofline of the JVP (gradient + tangent kernels): algorithmic bytes = read v,
+    # write Jv (8 B/DOF each) + element geometry (8 vertices x 3 coords x 8 B)
+    alg_bytes = 16.0 * N + 192.0 * m.E
+    achieved = alg_bytes / e_jvp / 1e9
+    out = {
+        "metric": "LDG JVP GDOF/s + Newton-GMRES time-to-1e-8, plain FP64 vs mixed/learned",
+        "value": round(value, 4),
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(T / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"3D Poisson LDG p=3, {args.n}^3 hexes, interior vertices perturbed +-5% h, "
+                               f"exp(x+y+z)sin(pi xyz) manufactured solution",
+                   "dof": N, "elements": m.E, "p": 3, "quadrature": "collocated Gauss-Legendre 4^3"},
+        "roofline": {"bound": "hbm", "kernel": "ldg_jvp (k_grad + k_resid, FP64)", "achieved": round(achieved, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "alg_bytes_per_launch": alg_bytes,
+                     "launch_us": round(e_jvp * 1e6, 3)},
+    }
+    if args.profile_jvp_only:
+        print(json.dumps(out))
+        return
+
+    # other precisions / operator evaluations (events, outside the timed steps)
+    extra = {}
+    e32 = event_time(lambda: md.jvp(None, v, out=Jv, prec=ldg.FP32), 50)
+    extra["jvp_fp32_gdofs"] = round(N / e32 / 1e9, 3)
+    try:
+        eb = event_time(lambda: md.jvp(None, v, out=Jv, prec=ldg.BF16_MFMA), 50)
+        extra["jvp_bf16_mfma_gdofs"] = round(N / eb / 1e9, 3)
+    except ldg.LDGError as ex:
+        extra["jvp_bf16_mfma_gdofs"] = None
+        log("bf16 mfma jvp:", ex)
+    G = md.empty()
+    er = event_time(lambda: md.residual(u, out=G), 50)
+    extra["residual_fp64_gdofs"] = round(N / er / 1e9, 3)
+    extra["jvp_fp64_us"] = round(e_jvp * 1e6, 2)
+    extra["jvp_fp32_us"] = round(e32 * 1e6, 2)
+    log("extra:", extra)
+
+    # Newton-GMRES to ||G|| <= 1e-8 ||G(u0)||, u0 = 0, GMRES(30) + block Jacobi
+    if not args.no_solve:
+        forms = {}
+        for name, jp, bp, eta in (("fp64_jvp+fp64_bj", ldg.FP64, ldg.FP64, 1e-9),
+                                  ("fp64_jvp+fp32_bj", ldg.FP64, ldg.FP32, 1e-9),
+                                  ("fp32_jvp+fp32_bj", ldg.FP32, ldg.FP32, 1e-4)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pc = ldg.BlockJacobi(md, prec=bp)
+            torch.cuda.synchronize()
+            t_bj = time.perf_counter() - t0
+            x = torch.zeros(N, dtype=torch.float64, device="cuda")
+            x, st, status = ldg.newton(md, x, rtol=1e-8, eta=eta, maxit=8, pc=pc, restart=30, lin_maxit=4000,
+                                       jvp_prec=jp, check=False)
+            torch.cuda.synchronize()
+            t_all = time.perf_counter() - t0
+            forms[name] = {"time_to_1e-8_s": round(t_all, 4), "bj_build_s": round(t_bj, 4),
+                           "converged": status == ldg.LDG_OK, "newton_iters": st["iters"],
+                           "gmres_iters": st["gmres_iters"],
+                           "res_ratio": st["res_final"] / max(st["res0"], 1e-300)}
+            log(name, forms[name])
+            del pc
+        out["newton_gmres"] = forms
+
+    # oracle on a bounded sample of elements, host, one core
+    if not args.no_cpu:
+        try:
+            import oracle as O
+            om = O.Mesh(box, 3)
+            xn, xq, xb, _ = om.points()
+            _, _, f = I.mms_expsin3d(xq)
+            ub, _, _ = I.mms_expsin3d(xb)
+            omd = O.Model(O.MODEL_POISSON, 1, [1.0, 16.0 * args.n, 0.0], src=f.reshape(om.E, 1, om.nqv),
+                          bdata=ub.reshape(om.nbf, 1, om.nqf), bc_kind=[0])
+            vv = v.cpu().numpy()
+            uu = np.zeros(N)
+            sel = np.arange(0, om.E, max(1, om.E // 4096), dtype=np.int64)[:4096]
+            t0 = time.process_time()
+            _, Jv_s = om.sample(omd, uu, vv, sel)
+            tc = time.process_time() - t0
+            # spot parity of the timed GPU kernels on the sample
+            Jg = md.jvp(None, v).cpu().numpy().reshape(om.E, -1)[sel]
+            err = float(np.linalg.norm(Jg - Jv_s) / np.linalg.norm(Jv_s))
+            dofs = len(sel) * om.nn
+            out["cpu_baseline"] = {"value": round(dofs / tc / 1e9, 6), "unit": "GDOF/s", "cores": 1,
+                                   "kind": "oracle",
+                                   "sample": f"FP64 oracle JVP on {len(sel)} of {om.E} elements (each with its q "
+                                             f"neighbourhood), {tc:.1f} s process time",
+                                   "gpu_vs_oracle_rel_err_on_sample": err}
+            log("cpu baseline", out["cpu_baseline"])
+        except Exception as ex:  # the oracle is optional on the measuring box
+            log("cpu baseline skipped:", ex)
+            out["cpu_baseline"] = None
+    out["extra"] = extra
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,247 @@
+/* ldg.h -- C ABI of the MI355X (gfx950) matrix-free LDG residual / Jacobian-vector
+ * product library and its Newton-GMRES solvers.
+ *
+ * The operator is the local discontinuous Galerkin discretization of the
+ * parametrized first-order system of Section 2.1 (Eq. 1a: q + grad u = 0;
+ * Eq. 1b: m du/dt + div f(u,q) = s with m = 1), discretized as Section 2.2
+ * states (LDG in space with user numerical traces/fluxes; implicit time
+ * stepping), and solved by the matrix-free Newton-GMRES method of Section 3.3
+ * (Jacobian-vector products by automatic differentiation or finite differences,
+ * tensor-product sum factorization for the residual).
+ *
+ * Conventions shared by every call:
+ *  - Meshes are quadrilaterals (nd = 2) or hexahedra (nd = 3) with multilinear
+ *    maps; corners are numbered lexicographically (bit k of the corner index set
+ *    <=> upper side in reference direction k).  Two elements that share a face
+ *    must see it as opposite sides of the same reference direction with the same
+ *    tangential orientation (structured-like topology); other meshes are rejected
+ *    with LDG_EUNSUPPORTED.
+ *  - The basis is the Lagrange basis on the (p+1)^nd tensor Gauss-Legendre nodes;
+ *    volume and face integrals use nq1d Gauss-Legendre points per direction.
+ *    nq1d = p+1 (collocated) is the general path; nq1d > p+1 is accepted only for
+ *    the Poisson model with constant kappa on affine meshes, where the collocated
+ *    rule integrates every solution-dependent term exactly and the data terms
+ *    (source, boundary data) are integrated with the nq1d rule.
+ *  - Degrees of freedom are element-major, then variable, then node with the
+ *    first reference direction fastest: u[E][ncu][(p+1)^nd].  q = -grad u (Eq. 1a)
+ *    is stored as q[E][ncu][nd][(p+1)^nd].
+ *  - Boundary faces are numbered element-major, local-face-minor; local faces
+ *    are (-xi, +xi, -eta, +eta, -zeta, +zeta).  Face points are the tensor
+ *    Gauss-Legendre points of the two tangential directions, lower direction
+ *    fastest.
+ *  - Vector arguments are HIP device pointers owned by the caller, unless marked
+ *    HOST.  Work is enqueued on the caller's stream (NULL = default stream); the
+ *    operator calls never synchronize; the solvers synchronize on scalars to test
+ *    convergence.  Handles are created/destroyed by the library and are not
+ *    thread-safe.
+ *  - Every call returns an ldg_status; on error, ldg_last_error() returns a
+ *    thread-local message and outputs are unspecified, except that the solvers
+ *    leave their last iterate in x / u and fill their stats.
+ */
+#ifndef LDG_H
+#define LDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LDG_OK = 0,
+  LDG_EINVAL = 1,        /* bad argument (null pointer, size, inconsistent model) */
+  LDG_EUNSUPPORTED = 2,  /* valid but not implemented combination                 */
+  LDG_EDEVICE = 3,       /* HIP runtime error                                     */
+  LDG_ENOMEM = 4,        /* device allocation failed                              */
+  LDG_ENOCONV = 5,       /* solver stopped without reaching its tolerance         */
+  LDG_EBREAKDOWN = 6     /* non-finite value met inside a solver                  */
+} ldg_status;
+
+/* Precision of the Jacobian-vector product / operator evaluation.  Inputs and
+ * outputs stay FP64; the mode sets the arithmetic and the storage of the
+ * intermediates (q, face values). */
+typedef enum {
+  LDG_FP64 = 0,
+  LDG_FP32 = 1,
+  LDG_BF16_MFMA = 2,   /* derivative/test contractions on MFMA, bf16 operands, fp32 accumulation */
+  LDG_FP16_MFMA = 3,   /* same with fp16 operands                                              */
+  LDG_JVP_FD = 4       /* finite-difference JVP: (R(u + eps v) - R(u)) / eps in FP64             */
+} ldg_precision;
+
+/* Built-in PDE models (Section 2.1 classes): diffusion (Poisson/heat,
+ * convection-diffusion, compressible Navier-Stokes) and convection (Euler).
+ *   POISSON  f = kappa0 * kappa(x) q, s = src - lambda u;  mu = [kappa0, tau, lambda];
+ *            aux = [kappa(x)] (optional, naux = 0 means kappa(x) = 1)
+ *   CONVDIFF f = kappa0 kappa(x) q + b(x) u, s = src;     mu = [kappa0, tau]; aux = [kappa, b_1..b_nd]
+ *   EULER    inviscid flux of (rho, rho v, rho E);         mu = [gamma]
+ *   NS       inviscid - viscous flux (Stokes hypothesis, heat flux mu*gamma/Pr grad e),
+ *            mu = [gamma, Re, Pr, tau]
+ * Interior numerical flux: 1/2 (f- + f+).n + sigma (u- - u+) with
+ *   sigma = tau kappa0 {kappa} (Poisson), + 1/2 max|b.n| (convection-diffusion),
+ *   sigma = 1/2 max(|v.n| + c) (Euler), + tau / Re (NS);
+ * numerical trace uhat = (u- + u+)/2.  tau is the interior-penalty parameter
+ * chosen by the caller (the tests use (p+1)^2 / h). */
+typedef enum { LDG_MODEL_POISSON = 0, LDG_MODEL_CONVDIFF = 1, LDG_MODEL_EULER = 2, LDG_MODEL_NS = 3 } ldg_model_kind;
+
+/* Boundary condition per boundary tag.
+ *   DIRICHLET: uhat = g, u+ = g, q+ = q- in the interior flux formula
+ *   NEUMANN:   uhat = u-, Fhat = h (normal flux data)
+ *   EXTRAP:    uhat = u-, Fhat = f(u-, q-).n
+ * Periodicity is a property of the mesh (matched faces), not a tag. */
+typedef enum { LDG_BC_DIRICHLET = 0, LDG_BC_NEUMANN = 1, LDG_BC_EXTRAP = 2 } ldg_bc_kind;
+
+typedef struct ldg_mesh_s* ldg_mesh;
+typedef struct ldg_model_s* ldg_model;
+typedef struct ldg_precond_s* ldg_precond;
+typedef struct ldg_mlp_s* ldg_mlp;
+
+/* Text of the last non-OK status on this thread (empty if none). */
+const char* ldg_last_error(void);
+
+/* ---------------------------------------------------------------- mesh ---- */
+/* Mesh set-up (runs once, on the host, then uploads): connectivity, periodic
+ * matching, boundary-face list and tags, distance-2 element colouring (used to
+ * probe Jacobian diagonal blocks), multilinear geometry.  Section 3.2 (mesh
+ * module for simple geometries).
+ *   nd in {2,3}; p in [1,5]; nq1d >= p+1
+ *   vert      HOST [nvert][nd]
+ *   elem_vert HOST [nelem][2^nd], lexicographic corners
+ *   period    HOST [nd], >0 marks a periodic direction of that length (vertices
+ *             on the two periodic ends must be the same vertex ids), 0 = none
+ *   face_tag  HOST [nelem][2nd] tag of each boundary face (ignored for
+ *             interior faces), or NULL = tag 0 everywhere
+ * Errors: LDG_EINVAL (sizes, degenerate element, face shared by >2 elements),
+ * LDG_EUNSUPPORTED (inconsistent face orientation, nq1d > p+1 on a non-affine
+ * mesh is only rejected later at model creation). */
+ldg_status ldg_mesh_create(int nd, int p, int nq1d, int64_t nvert, const double* vert, int64_t nelem,
+                           const int64_t* elem_vert, const double* period, const int32_t* face_tag,
+                           ldg_mesh* out);
+
+/* info HOST [8] = {nelem, nodes per element, volume quadrature points per
+ * element, points per face, boundary faces, colours, affine (0/1), nd}. */
+ldg_status ldg_mesh_info(ldg_mesh mesh, int64_t* info);
+
+/* HOST outputs (any may be NULL): node coordinates [E][nn][nd], volume
+ * quadrature points [E][nqv][nd], boundary-face quadrature points
+ * [nbf][nqf][nd], boundary faces as (element, local face) [nbf][2]. */
+ldg_status ldg_mesh_points(ldg_mesh mesh, double* xnode, double* xquad, double* xbface, int64_t* bface);
+ldg_status ldg_mesh_destroy(ldg_mesh mesh);
+
+/* ---------------------------------------------------------------- model --- */
+typedef struct {
+  int kind;                 /* ldg_model_kind                                    */
+  int ncu;                  /* 1 (Poisson, conv.-diff.) or nd+2 (Euler, NS)      */
+  int nmu;                  /* <= 8                                              */
+  const double* mu;         /* HOST [nmu] parameters (see ldg_model_kind)        */
+  int naux;                 /* nodal coefficient fields                          */
+  const double* aux;        /* DEVICE [E][naux][nn] or NULL                      */
+  const double* src;        /* DEVICE [E][ncu][nqv] source at quadrature points  */
+  const double* bdata;      /* DEVICE [nbf][ncu][nqf] boundary data or NULL      */
+  int nbc;                  /* <= 8 tags                                         */
+  const int32_t* bc_kind;   /* HOST [nbc] ldg_bc_kind per tag                    */
+} ldg_model_desc;
+
+/* Binds a model to a mesh.  The aux/src/bdata arrays are read during this call
+ * (data terms of linear models are integrated once here) and, for the nonlinear
+ * models, kept by pointer: they must stay valid while the model is used.
+ * Errors: LDG_EINVAL (ncu, nmu, tags), LDG_EUNSUPPORTED (see nq1d above; no
+ * compiled kernel for this (nd, p, model)). */
+ldg_status ldg_model_create(ldg_mesh mesh, const ldg_model_desc* desc, void* stream, ldg_model* out);
+ldg_status ldg_model_destroy(ldg_model model);
+
+/* Implicit time wrapper (the configurations use BDF1/BDF2; DIRK stages have the
+ * same form): G(u) = a0 M u - M (c1 r1 + c2 r2) + R(u).  r1, r2 are DEVICE
+ * [E][ncu][nn] or NULL.  A NULL ldg_time* means steady: G = R. */
+typedef struct {
+  double a0;
+  const double* r1;
+  double c1;
+  const double* r2;
+  double c2;
+} ldg_time;
+
+/* ------------------------------------------------------------- operator --- */
+/* G(u) (Eq. 1a-1b discretized, with the time wrapper) and optionally
+ * q_out = q(u).  prec: LDG_FP64 or LDG_FP32 (others -> LDG_EINVAL). */
+ldg_status ldg_residual(ldg_model model, const ldg_time* t, const double* u, double* G, double* q_out,
+                        ldg_precision prec, void* stream);
+
+/* Jv = dG/du(u) v, exact forward-mode tangent (Section 3.3: JVP by automatic
+ * differentiation) in the requested precision, or a one-sided finite
+ * difference with prec = LDG_JVP_FD.  For the linear models u is not read
+ * (may be NULL).  u, v, Jv: DEVICE [E][ncu][nn]; Jv must not alias u or v. */
+ldg_status ldg_jvp(ldg_model model, const ldg_time* t, const double* u, const double* v, double* Jv,
+                   ldg_precision prec, void* stream);
+
+/* ------------------------------------------------------- preconditioners --- */
+/* Exact diagonal blocks dG_K/du_K of the Jacobian at u_lin, by probing with the
+ * distance-2 element colouring (one JVP per colour and local unknown), written
+ * to blocks: DEVICE [E][nb][nb] row-major, nb = ncu*nn (per_variable = 0) or
+ * [E][ncu][nn][nn] (per_variable = 1: the variable-diagonal sub-blocks). */
+ldg_status ldg_jacobian_blocks(ldg_model model, const ldg_time* t, const double* u_lin, int per_variable,
+                               double* blocks, void* stream);
+
+/* Block-Jacobi preconditioner: the blocks above, inverted by Gauss-Jordan
+ * elimination with partial pivoting, stored in FP64 or FP32 (factor_prec).
+ * Apply: z_K = B_K^{-1} r_K. */
+ldg_status ldg_precond_block_jacobi(ldg_model model, const ldg_time* t, const double* u_lin, int per_variable,
+                                    ldg_precision factor_prec, void* stream, ldg_precond* out);
+ldg_status ldg_precond_apply(ldg_precond pc, const double* r, double* z, void* stream);
+ldg_status ldg_precond_destroy(ldg_precond pc);
+
+/* ---------------------------------------------------------------- solvers - */
+typedef struct {
+  int restart;            /* Krylov basis size m                                  */
+  int maxit;              /* total iteration cap                                  */
+  int flexible;           /* 1 = FGMRES (store Z), 0 = right-preconditioned GMRES */
+  double rtol, atol;      /* stop when |g_{j+1}| <= max(rtol ||r0||, atol)        */
+  ldg_precision jvp_prec; /* precision of the Jacobian-vector products            */
+  ldg_precond pc;         /* NULL = no preconditioner                             */
+  int inject_fault;       /* test hook: 1 = poison the preconditioner output with NaN */
+} ldg_gmres_opts;
+
+typedef struct {
+  int iters, restarts, fell_back;
+  double res0, res_est, res_true;          /* ||b - J x0||, Givens estimate, true ||b - J x|| */
+  double t_jvp, t_pc, t_orth, t_total;     /* seconds per phase                             */
+} ldg_gmres_stats;
+
+/* Solves J(u_lin) x = b by restarted (F)GMRES with classical Gram-Schmidt and
+ * one re-orthogonalization pass (CGS2) in FP64, Givens rotations in FP64 on the
+ * host.  x holds the initial guess on entry and the solution on exit.
+ * Returns LDG_ENOCONV if maxit is reached, LDG_EBREAKDOWN on a non-finite
+ * value. */
+ldg_status ldg_gmres_solve(ldg_model model, const ldg_time* t, const double* u_lin, const double* b, double* x,
+                           const ldg_gmres_opts* opts, ldg_gmres_stats* stats, void* stream);
+
+typedef struct {
+  int maxit;             /* Newton iteration cap                                       */
+  double rtol, atol;     /* stop when ||G(u_k)|| <= max(rtol ||G(u_0)||, atol)          */
+  double eta;            /* linear solve relative tolerance (forcing term)              */
+  int bj_refresh;        /* rebuild a block-Jacobi preconditioner at every iterate      */
+  int bj_per_variable;   /* for bj_refresh                                              */
+  ldg_precision bj_prec; /* storage precision of the refreshed blocks                   */
+  ldg_gmres_opts lin;    /* inner solver options (rtol is replaced by eta)              */
+} ldg_newton_opts;
+
+typedef struct {
+  int iters, gmres_iters;
+  double res0, res_final, seconds;
+  int lin_status;
+} ldg_newton_stats;
+
+/* Newton's method on G(u) = 0 (Section 3.3), FP64 residual, u updated in place. */
+ldg_status ldg_newton_solve(ldg_model model, const ldg_time* t, double* u, const ldg_newton_opts* opts,
+                            ldg_newton_stats* stats, void* stream);
+
+/* ------------------------------------------------------------- utilities -- */
+/* Device vector helpers used by the Python binding and the solvers:
+ * y = a x + b y, and the squared 2-norm of x written to HOST *out (synchronizes). */
+ldg_status ldg_axpby(int64_t n, double a, const double* x, double b, double* y, void* stream);
+ldg_status ldg_norm2(int64_t n, const double* x, double* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LDG_H */

@@ -60,6 +60,7 @@ def lib():
         L.ldgo_jacobian_coo.restype = C.c_int64
         L.ldgo_jacobian_coo.argtypes = [C.c_void_p, C.c_void_p, dp, C.c_int64, ip64, ip64, dp]
         L.ldgo_jacobian_blocks.argtypes = [C.c_void_p, C.c_void_p, dp, C.c_int64, ip64, C.c_int, dp]
+        L.ldgo_sample_elements.argtypes = [C.c_void_p, C.c_void_p, dp, dp, C.c_int64, ip64, dp, dp]
         L.ldgo_mass_apply.argtypes = [C.c_void_p, C.c_int, dp, dp]
         L.ldgo_lu_factor.argtypes = [C.c_int, dp, C.POINTER(C.c_int)]
         L.ldgo_lu_solve.argtypes = [C.c_int, dp, C.POINTER(C.c_int), dp]
@@ -220,6 +221,19 @@ class Mesh:
                                       _d(out)) != 0:
             raise RuntimeError("oracle blocks: " + _err())
         return out
+
+    def sample(self, model, u, v, elems):
+        """G_K(u) and (J(u) v)_K on the listed elements: [len(elems)][ncu*nn] each."""
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        v = None if v is None else np.ascontiguousarray(v, dtype=np.float64)
+        elems = np.ascontiguousarray(elems, dtype=np.int64)
+        nb = model.ncu * self.nn
+        G = np.zeros((len(elems), nb))
+        Jv = np.zeros((len(elems), nb))
+        if lib().ldgo_sample_elements(self.h, model.desc(), _d(u), _d(v), len(elems), _i64(elems), _d(G),
+                                      _d(Jv)) != 0:
+            raise RuntimeError("oracle sample: " + _err())
+        return G, Jv
 
     def mass_apply(self, ncu, u):
         u = np.ascontiguousarray(u, dtype=np.float64)

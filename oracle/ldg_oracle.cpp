@@ -1032,6 +1032,33 @@ int ldgo_jacobian_blocks(void* h, const ldgo_model_desc* d, const double* u, int
   })
 }
 
+// G_K and (J v)_K for the listed elements only (q computed on each element and
+// its face neighbours): lets large meshes be checked on a sample of elements.
+int ldgo_sample_elements(void* h, const ldgo_model_desc* d, const double* u, const double* v, int64_t nsel,
+                         const int64_t* sel, double* G, double* Jv) {
+  GUARD({
+    OMesh& M = *(OMesh*)h;
+    OModel md = to_model(M, d);
+    const int ncu = md.ncu, nn = M.nn, nd = M.nd, nb = ncu * nn;
+    const size_t N = (size_t)M.E * nb;
+    std::vector<Dual> ud(N);
+    for (size_t i = 0; i < N; ++i) ud[i] = Dual(u[i], v ? v[i] : 0.0);
+    const size_t qsz = (size_t)ncu * nd * nn;
+    std::vector<Dual> q(model_has_q(md) ? (size_t)M.E * qsz : 1);
+    std::vector<Dual> RK(nb);
+    for (int64_t s = 0; s < nsel; ++s) {
+      long K = sel[s];
+      if (model_has_q(md))
+        for (long e : neighbourhood(M, K, 1)) compute_q(M, md, ud.data(), e, &q[(size_t)e * qsz]);
+      element_residual(M, md, ud.data(), q.data(), K, RK.data());
+      for (int i = 0; i < nb; ++i) {
+        if (G) G[(size_t)s * nb + i] = RK[i].v;
+        if (Jv) Jv[(size_t)s * nb + i] = RK[i].d;
+      }
+    }
+  })
+}
+
 // consistent mass matrix applied element by element: Mu = M u
 void ldgo_mass_apply(void* h, int ncu, const double* u, double* Mu) {
   OMesh& M = *(OMesh*)h;

@@ -1,0 +1,565 @@
+// C ABI: mesh set-up, model binding, residual and Jacobian-vector product.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <unordered_map>
+
+#include "ldg_physics.hpp"
+
+namespace ldg {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+// ----------------------------------------------------------------------------
+// Gauss-Legendre nodes/weights (Newton on P_m in long double) and the
+// barycentric form of the Lagrange basis on them.
+// ----------------------------------------------------------------------------
+static void gl_rule(int m, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(m);
+  w.resize(m);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int i = 0; i < m; ++i) {
+    long double z = cosl(pi * (m - i - 0.25L) / (m + 0.5L));  // ascending order
+    long double pp = 0;
+    for (int it = 0; it < 60; ++it) {
+      long double p0 = 1, p1 = 0;
+      for (int k = 0; k < m; ++k) {   // P_{k+1} = ((2k+1) z P_k - k P_{k-1}) / (k+1)
+        long double p2 = p1;
+        p1 = p0;
+        p0 = ((2.0L * k + 1.0L) * z * p1 - k * p2) / (k + 1.0L);
+      }
+      pp = m * (z * p0 - p1) / (z * z - 1.0L);
+      long double dz = p0 / pp;
+      z -= dz;
+      if (fabsl(dz) < 1e-19L) break;
+    }
+    if (m == 1) { z = 0; pp = 1; }
+    x[i] = (double)z;
+    w[i] = (double)(2.0L / ((1.0L - z * z) * pp * pp));
+  }
+}
+
+static void make_basis(int p1, BasisTab& t, BasisTabF& tf) {
+  std::memset(&t, 0, sizeof(t));
+  std::vector<double> x, w;
+  gl_rule(p1, x, w);
+  long double lam[MAXP1];
+  for (int a = 0; a < p1; ++a) {
+    long double s = 1;
+    for (int j = 0; j < p1; ++j)
+      if (j != a) s *= ((long double)x[a] - x[j]);
+    lam[a] = 1.0L / s;
+  }
+  for (int a = 0; a < p1; ++a) {
+    t.x[a] = x[a];
+    t.w[a] = w[a];
+    long double diag = 0;
+    for (int mm = 0; mm < p1; ++mm) {
+      if (mm == a) continue;
+      long double d = (lam[mm] / lam[a]) / ((long double)x[a] - x[mm]);
+      t.D[a][mm] = (double)d;
+      diag -= d;
+    }
+    t.D[a][a] = (double)diag;
+  }
+  for (int s = 0; s < 2; ++s) {
+    long double tt = s ? 1.0L : -1.0L;
+    long double den = 0;
+    for (int j = 0; j < p1; ++j) den += lam[j] / (tt - x[j]);
+    for (int mm = 0; mm < p1; ++mm) t.lf[s][mm] = (double)((lam[mm] / (tt - x[mm])) / den);
+  }
+  for (int a = 0; a < MAXP1; ++a) {
+    tf.x[a] = (float)t.x[a];
+    tf.w[a] = (float)t.w[a];
+    for (int b = 0; b < MAXP1; ++b) tf.D[a][b] = (float)t.D[a][b];
+    tf.lf[0][a] = (float)t.lf[0][a];
+    tf.lf[1][a] = (float)t.lf[1][a];
+  }
+}
+
+static void eval_map(const Mesh& m, int64_t K, const double* xi, double* x, double J[3][3]) {
+  const int nd = m.nd;
+  const double* c = &m.h_coef[(size_t)K * m.nv * nd];
+  for (int i = 0; i < nd; ++i) {
+    x[i] = 0;
+    for (int j = 0; j < nd; ++j) J[i][j] = 0;
+  }
+  for (int mm = 0; mm < m.nv; ++mm) {
+    double t = 1;
+    for (int k = 0; k < nd; ++k)
+      if ((mm >> k) & 1) t *= xi[k];
+    for (int i = 0; i < nd; ++i) x[i] += c[mm * nd + i] * t;
+    for (int j = 0; j < nd; ++j) {
+      if (!((mm >> j) & 1)) continue;
+      double tj = 1;
+      for (int k = 0; k < nd; ++k)
+        if (k != j && ((mm >> k) & 1)) tj *= xi[k];
+      for (int i = 0; i < nd; ++i) J[i][j] += c[mm * nd + i] * tj;
+    }
+  }
+}
+
+struct KeyHash {
+  size_t operator()(const std::vector<int64_t>& k) const {
+    size_t h = 1469598103934665603ull;
+    for (auto v : k) h = (h ^ (size_t)v) * 1099511628211ull;
+    return h;
+  }
+};
+
+}  // namespace ldg
+
+using namespace ldg;
+
+
+#define CHECK_ARG(cond, msg)           \
+  do {                                 \
+    if (!(cond)) {                     \
+      set_error(msg);                  \
+      return LDG_EINVAL;               \
+    }                                  \
+  } while (0)
+
+extern "C" {
+
+const char* ldg_last_error(void) { return g_err.c_str(); }
+
+ldg_status ldg_mesh_create(int nd, int p, int nq1d, int64_t nvert, const double* vert, int64_t nelem,
+                           const int64_t* elem_vert, const double* period, const int32_t* face_tag, ldg_mesh* out) {
+  LDG_ENTER();
+  CHECK_ARG(out && vert && elem_vert, "null argument");
+  CHECK_ARG(nd == 2 || nd == 3, "nd must be 2 or 3");
+  CHECK_ARG(p >= 1 && p + 1 <= MAXP1, "p must be in [1, 5]");
+  CHECK_ARG(nq1d >= p + 1 && nq1d <= 16, "nq1d must be in [p+1, 16]");
+  CHECK_ARG(nvert > 0 && nelem > 0 && nelem < (1ll << 31), "bad sizes");
+  auto* m = new ldg_mesh_s();
+  m->nd = nd; m->p = p; m->p1 = p + 1; m->nq1 = nq1d;
+  m->nv = 1 << nd; m->nf = 2 * nd;
+  m->nn = ipow(p + 1, nd); m->nfp = ipow(p + 1, nd - 1);
+  m->nqv = ipow(nq1d, nd); m->nqf = ipow(nq1d, nd - 1);
+  m->E = nelem;
+  make_basis(p + 1, m->tab, m->tabf);
+  gl_rule(nq1d, m->xq1, m->wq1);
+
+  // element coordinates (periodic images unwrapped against the low corner) and
+  // their multilinear monomial coefficients
+  const int nv = m->nv;
+  std::vector<double> X((size_t)nv * nd);
+  m->h_coef.assign((size_t)nelem * nv * nd, 0.0);
+  double scale = 0;
+  for (int64_t i = 0; i < nvert * nd; ++i) scale = std::max(scale, std::fabs(vert[i]));
+  scale = std::max(scale, 1.0);
+  bool affine = true;
+  for (int64_t K = 0; K < nelem; ++K) {
+    for (int v = 0; v < nv; ++v) {
+      int64_t vid = elem_vert[K * nv + v];
+      if (vid < 0 || vid >= nvert) { delete m; set_error("vertex index out of range"); return LDG_EINVAL; }
+      for (int k = 0; k < nd; ++k) {
+        double c = vert[vid * nd + k];
+        const double c0 = vert[elem_vert[K * nv] * nd + k];
+        const double L = period ? period[k] : 0.0;
+        if (L > 0) {
+          while (c - c0 > 0.5 * L) c -= L;
+          while (c0 - c >= 0.5 * L) c += L;
+        }
+        X[v * nd + k] = c;
+      }
+    }
+    double* C = &m->h_coef[(size_t)K * nv * nd];
+    for (int mm = 0; mm < nv; ++mm)
+      for (int i = 0; i < nd; ++i) {
+        double s = 0;
+        for (int v = 0; v < nv; ++v) {
+          double sg = 1;
+          for (int k = 0; k < nd; ++k)
+            if ((mm >> k) & 1) sg *= ((v >> k) & 1) ? 1.0 : -1.0;
+          s += sg * X[v * nd + i];
+        }
+        C[mm * nd + i] = s / nv;
+      }
+    for (int mm = 0; mm < nv; ++mm)
+      if (__builtin_popcount(mm) >= 2)
+        for (int i = 0; i < nd; ++i)
+          if (std::fabs(C[mm * nd + i]) > 1e-13 * scale) affine = false;
+    // positivity of det J at the corners and the centre
+    for (int v = 0; v <= nv; ++v) {
+      double xi[3] = {0, 0, 0}, x[3], J[3][3];
+      if (v < nv)
+        for (int k = 0; k < nd; ++k) xi[k] = ((v >> k) & 1) ? 1.0 : -1.0;
+      eval_map(*m, K, xi, x, J);
+      double det = nd == 2 ? J[0][0] * J[1][1] - J[0][1] * J[1][0]
+                           : J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                                 J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                                 J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+      if (!(det > 0)) { delete m; set_error("element with non-positive Jacobian"); return LDG_EINVAL; }
+    }
+  }
+  m->affine = affine;
+
+  // faces keyed by sorted corner ids
+  const int nf = m->nf;
+  m->h_nbr.assign((size_t)nelem * nf, INT32_MIN);
+  std::unordered_map<std::vector<int64_t>, std::pair<int64_t, int>, KeyHash> open;
+  open.reserve((size_t)nelem * nf);
+  for (int64_t K = 0; K < nelem; ++K)
+    for (int F = 0; F < nf; ++F) {
+      const int dir = F >> 1, side = F & 1;
+      std::vector<int64_t> corners;
+      for (int v = 0; v < nv; ++v)
+        if (((v >> dir) & 1) == side) corners.push_back(elem_vert[K * nv + v]);
+      std::vector<int64_t> key = corners;
+      std::sort(key.begin(), key.end());
+      auto it = open.find(key);
+      if (it == open.end()) {
+        open.emplace(key, std::make_pair(K, F));
+        continue;
+      }
+      const int64_t K2 = it->second.first;
+      const int F2 = it->second.second;
+      if (K2 < 0) { delete m; set_error("face shared by more than two elements"); return LDG_EINVAL; }
+      if (K2 == K) { delete m; set_error("element adjacent to itself (periodic direction with fewer than 3 elements)"); return LDG_EINVAL; }
+      // required: opposite side of the same reference direction, same tangential orientation
+      std::vector<int64_t> c2;
+      for (int v = 0; v < nv; ++v)
+        if (((v >> (F2 >> 1)) & 1) == (F2 & 1)) c2.push_back(elem_vert[K2 * nv + v]);
+      if ((F2 >> 1) != dir || (F2 & 1) == side || c2 != corners) {
+        delete m;
+        set_error("inconsistent face orientation between neighbouring elements");
+        return LDG_EUNSUPPORTED;
+      }
+      m->h_nbr[(size_t)K * nf + F] = (int32_t)K2;
+      m->h_nbr[(size_t)K2 * nf + F2] = (int32_t)K;
+      it->second.first = -1;
+    }
+  // boundary faces, element-major then local face
+  m->nbf = 0;
+  for (int64_t K = 0; K < nelem; ++K)
+    for (int F = 0; F < nf; ++F)
+      if (m->h_nbr[(size_t)K * nf + F] == INT32_MIN) {
+        m->h_nbr[(size_t)K * nf + F] = -(int32_t)(1 + m->nbf);
+        m->h_bface.push_back(K);
+        m->h_bface.push_back(F);
+        int32_t tg = face_tag ? face_tag[K * nf + F] : 0;
+        m->h_btag.push_back(tg < 0 ? 0 : tg);
+        ++m->nbf;
+      }
+
+  // greedy distance-2 colouring of the element face graph
+  m->h_color.assign(nelem, -1);
+  m->ncolors = 0;
+  std::vector<int64_t> ball;
+  std::vector<char> used;
+  for (int64_t K = 0; K < nelem; ++K) {
+    ball.clear();
+    for (int F = 0; F < nf; ++F) {
+      int32_t n1 = m->h_nbr[(size_t)K * nf + F];
+      if (n1 < 0) continue;
+      ball.push_back(n1);
+      for (int F2 = 0; F2 < nf; ++F2) {
+        int32_t n2 = m->h_nbr[(size_t)n1 * nf + F2];
+        if (n2 >= 0) ball.push_back(n2);
+      }
+    }
+    used.assign(m->ncolors + 1, 0);
+    for (int64_t e : ball)
+      if (e != K && m->h_color[e] >= 0) used[m->h_color[e]] = 1;
+    int c = 0;
+    while (used[c]) ++c;
+    m->h_color[K] = c;
+    m->ncolors = std::max(m->ncolors, c + 1);
+  }
+  m->color_elems.assign(m->ncolors, {});
+  for (int64_t K = 0; K < nelem; ++K) m->color_elems[m->h_color[K]].push_back((int32_t)K);
+  std::vector<int32_t> clist;
+  m->color_off.assign(m->ncolors + 1, 0);
+  for (int c = 0; c < m->ncolors; ++c) {
+    m->color_off[c] = (int64_t)clist.size();
+    clist.insert(clist.end(), m->color_elems[c].begin(), m->color_elems[c].end());
+  }
+  m->color_off[m->ncolors] = (int64_t)clist.size();
+
+  // upload
+  hipError_t e = hipSuccess;
+  e = hipMalloc((void**)&m->d_coef, m->h_coef.size() * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpy(m->d_coef, m->h_coef.data(), m->h_coef.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->d_nbr, m->h_nbr.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMemcpy(m->d_nbr, m->h_nbr.data(), m->h_nbr.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->d_btag, std::max<size_t>(1, m->h_btag.size()) * sizeof(int32_t));
+  if (e == hipSuccess && !m->h_btag.empty())
+    e = hipMemcpy(m->d_btag, m->h_btag.data(), m->h_btag.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->d_color_list, clist.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMemcpy(m->d_color_list, clist.data(), clist.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    set_error(std::string("mesh upload: ") + hipGetErrorString(e));
+    hipFree(m->d_coef); hipFree(m->d_nbr); hipFree(m->d_btag); hipFree(m->d_color_list);
+    delete m;
+    return e == hipErrorOutOfMemory ? LDG_ENOMEM : LDG_EDEVICE;
+  }
+  *out = m;
+  return LDG_OK;
+}
+
+ldg_status ldg_mesh_info(ldg_mesh m, int64_t* info) {
+  LDG_ENTER();
+  CHECK_ARG(m && info, "null argument");
+  info[0] = m->E; info[1] = m->nn; info[2] = m->nqv; info[3] = m->nqf; info[4] = m->nbf;
+  info[5] = m->ncolors; info[6] = m->affine ? 1 : 0; info[7] = m->nd;
+  return LDG_OK;
+}
+
+ldg_status ldg_mesh_points(ldg_mesh m, double* xnode, double* xquad, double* xbface, int64_t* bface) {
+  LDG_ENTER();
+  CHECK_ARG(m, "null mesh");
+  const int nd = m->nd;
+  double x[3], J[3][3], xi[3];
+  for (int64_t K = 0; K < m->E; ++K) {
+    if (xnode)
+      for (int i = 0; i < m->nn; ++i) {
+        int t = i;
+        for (int k = 0; k < nd; ++k) { xi[k] = m->tab.x[t % m->p1]; t /= m->p1; }
+        eval_map(*m, K, xi, x, J);
+        for (int k = 0; k < nd; ++k) xnode[((size_t)K * m->nn + i) * nd + k] = x[k];
+      }
+    if (xquad)
+      for (int i = 0; i < m->nqv; ++i) {
+        int t = i;
+        for (int k = 0; k < nd; ++k) { xi[k] = m->xq1[t % m->nq1]; t /= m->nq1; }
+        eval_map(*m, K, xi, x, J);
+        for (int k = 0; k < nd; ++k) xquad[((size_t)K * m->nqv + i) * nd + k] = x[k];
+      }
+  }
+  for (int64_t b = 0; b < m->nbf; ++b) {
+    const int64_t K = m->h_bface[2 * b];
+    const int F = (int)m->h_bface[2 * b + 1];
+    if (bface) { bface[2 * b] = K; bface[2 * b + 1] = F; }
+    if (!xbface) continue;
+    const int dir = F >> 1, side = F & 1;
+    for (int f = 0; f < m->nqf; ++f) {
+      int t = f;
+      for (int k = 0; k < nd; ++k) {
+        if (k == dir) { xi[k] = side ? 1.0 : -1.0; continue; }
+        xi[k] = m->xq1[t % m->nq1];
+        t /= m->nq1;
+      }
+      eval_map(*m, K, xi, x, J);
+      for (int k = 0; k < nd; ++k) xbface[((size_t)b * m->nqf + f) * nd + k] = x[k];
+    }
+  }
+  return LDG_OK;
+}
+
+ldg_status ldg_mesh_destroy(ldg_mesh m) {
+  LDG_ENTER();
+  if (!m) return LDG_OK;
+  hipFree(m->d_coef); hipFree(m->d_nbr); hipFree(m->d_btag); hipFree(m->d_color_list);
+  delete m;
+  return LDG_OK;
+}
+
+ldg_status ldg_model_create(ldg_mesh m, const ldg_model_desc* d, void* stream, ldg_model* out) {
+  LDG_ENTER();
+  CHECK_ARG(m && d && out, "null argument");
+  CHECK_ARG(d->kind >= 0 && d->kind <= 3, "unknown model kind");
+  const int want_ncu = d->kind <= 1 ? 1 : m->nd + 2;
+  CHECK_ARG(d->ncu == want_ncu, "ncu inconsistent with the model");
+  CHECK_ARG(d->nmu >= 0 && d->nmu <= MAXMU && (d->nmu == 0 || d->mu), "bad mu");
+  CHECK_ARG(d->nbc >= 1 && d->nbc <= MAXTAG && d->bc_kind, "need 1..8 boundary kinds");
+  CHECK_ARG(d->naux >= 0 && (d->naux == 0 || d->aux), "bad aux");
+  if (d->kind == LDG_MODEL_CONVDIFF) CHECK_ARG(d->naux == 1 + m->nd, "convection-diffusion needs aux = [kappa, b]");
+  if (d->kind == LDG_MODEL_POISSON) CHECK_ARG(d->naux <= 1, "Poisson takes at most one aux field");
+  if (d->kind >= 2) CHECK_ARG(d->naux == 0, "Euler / NS take no aux fields");
+  for (int i = 0; i < d->nbc; ++i) CHECK_ARG(d->bc_kind[i] >= 0 && d->bc_kind[i] <= 2, "bad bc kind");
+  if (m->nq1 != m->p1) {
+    if (!(d->kind == LDG_MODEL_POISSON && d->naux == 0 && m->affine)) {
+      set_error("nq1d > p+1 is supported only for Poisson with constant kappa on affine meshes");
+      return LDG_EUNSUPPORTED;
+    }
+  }
+  hipStream_t s = (hipStream_t)stream;
+  auto* md = new ldg_model_s();
+  md->mesh = m;
+  md->kind = d->kind; md->ncu = d->ncu; md->nmu = d->nmu; md->naux = d->naux;
+  for (int i = 0; i < MAXMU; ++i) md->mu[i] = i < d->nmu ? d->mu[i] : 0.0;
+  // defaults for missing parameters
+  if (d->kind <= 1) {
+    if (d->nmu < 1) md->mu[0] = 1.0;
+    if (d->nmu < 2) md->mu[1] = 1.0;
+  } else {
+    if (d->nmu < 1) md->mu[0] = 1.4;
+    if (d->kind == 3) {
+      if (d->nmu < 2) md->mu[1] = 1.0;
+      if (d->nmu < 3) md->mu[2] = 0.72;
+      if (d->nmu < 4) md->mu[3] = 1.0;
+    }
+  }
+  md->nbc = d->nbc;
+  for (int i = 0; i < MAXTAG; ++i) md->bc_kind[i] = i < d->nbc ? d->bc_kind[i] : d->bc_kind[d->nbc - 1];
+  md->aux = d->aux; md->src = d->src; md->bdata = d->bdata;
+  md->linear = d->kind <= 1;
+  const size_t N = md->N();
+  const size_t NQ = N * m->nd;
+  hipError_t e = hipSuccess;
+  e = hipMalloc((void**)&md->d_q, NQ * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&md->d_q32, NQ * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc((void**)&md->d_qres, NQ * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&md->d_dq, NQ * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&md->d_tmp, N * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&md->d_tmp2, N * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&md->d_red, 4096 * sizeof(double));
+  if (e == hipSuccess && md->linear) {
+    e = hipMalloc((void**)&md->d_qg, NQ * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&md->d_dterm, N * sizeof(double));
+  }
+  if (e != hipSuccess) {
+    set_error(std::string("model allocation: ") + hipGetErrorString(e));
+    ldg_model_destroy(md);
+    return LDG_ENOMEM;
+  }
+  if (md->linear) {
+    ldg_status st = op_data_terms(*md, s);
+    if (st != LDG_OK) { ldg_model_destroy(md); return st; }
+  } else {
+    md->d_srcn = const_cast<double*>(d->src);   // collocated: quadrature points are the nodes
+  }
+  *out = md;
+  return LDG_OK;
+}
+
+ldg_status ldg_model_destroy(ldg_model md) {
+  LDG_ENTER();
+  if (!md) return LDG_OK;
+  hipFree(md->d_q); hipFree(md->d_q32); hipFree(md->d_qres); hipFree(md->d_dq); hipFree(md->d_tmp); hipFree(md->d_tmp2); hipFree(md->d_red);
+  hipFree(md->d_qg); hipFree(md->d_dterm);
+  delete md;
+  return LDG_OK;
+}
+
+}  // extern "C"
+
+namespace ldg {
+
+TimeDev make_time(const ldg_time* t, bool with_rhs) {
+  TimeDev d{0.0, 0.0, 0.0, nullptr, nullptr};
+  if (!t) return d;
+  d.a0 = t->a0;
+  if (with_rhs) {
+    d.r1 = t->r1; d.c1 = t->c1;
+    d.r2 = t->r2; d.c2 = t->c2;
+  }
+  return d;
+}
+
+__global__ void k_f32_to_f64(int64_t n, const float* __restrict__ a, double* __restrict__ b) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (double)a[i];
+}
+
+ldg_status residual_impl(Model& md, const ldg_time* t, const double* u, double* G, double* q_out, bool fp32,
+                         hipStream_t s) {
+  void* qbuf = (!fp32 && q_out) ? (void*)q_out : (void*)md.d_qres;
+  ldg_status st = op_grad(md, u, qbuf, fp32, true, s);
+  if (st != LDG_OK) return st;
+  st = op_resid(md, make_time(t, true), u, qbuf, G, fp32, true, s);
+  if (st != LDG_OK) return st;
+  if (q_out && qbuf != q_out && md.kind != LDG_MODEL_EULER) {
+    const int64_t n = (int64_t)md.N() * md.mesh->nd;
+    hipLaunchKernelGGL(k_f32_to_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, (const float*)qbuf, q_out);
+    LDG_TRY(hipGetLastError());
+  }
+  return LDG_OK;
+}
+
+// J(u) v; for nonlinear models q(u) must already be in md.d_q (prepared = true)
+// or is computed here.
+ldg_status jvp_impl(Model& md, const ldg_time* t, const double* u, const double* v, double* Jv, ldg_precision prec,
+                    bool prepared, hipStream_t s) {
+  if (prec == LDG_JVP_FD) {
+    // one-sided difference, eps = sqrt(macheps) (1 + ||u||) / ||v|| (Knoll & Keyes 2004)
+    const int64_t n = (int64_t)md.N();
+    double nu = 0.0, nv = 0.0;
+    ldg_status st;
+    if (u) { st = vec_norm2(n, u, md.d_red, &nu, s); if (st != LDG_OK) return st; }
+    st = vec_norm2(n, v, md.d_red, &nv, s);
+    if (st != LDG_OK) return st;
+    if (nv == 0.0) return vec_fill(n, 0.0, Jv, s);
+    const double eps = 1.4901161193847656e-08 * (1.0 + std::sqrt(nu)) / std::sqrt(nv);
+    if (u) LDG_TRY(hipMemcpyAsync(md.d_tmp, u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    else if ((st = vec_fill(n, 0.0, md.d_tmp, s)) != LDG_OK) return st;
+    if ((st = residual_impl(md, t, md.d_tmp, Jv, nullptr, false, s)) != LDG_OK) return st;
+    if ((st = vec_axpby(n, eps, v, 1.0, md.d_tmp, s)) != LDG_OK) return st;
+    if ((st = residual_impl(md, t, md.d_tmp, md.d_tmp2, nullptr, false, s)) != LDG_OK) return st;
+    return vec_axpby(n, 1.0 / eps, md.d_tmp2, -1.0 / eps, Jv, s);
+  }
+  if (prec == LDG_BF16_MFMA || prec == LDG_FP16_MFMA) {
+    if (!md.linear) {
+      set_error("MFMA JVP is implemented for the linear models");
+      return LDG_EUNSUPPORTED;
+    }
+    return op_mfma_jvp(md, make_time(t, false), v, Jv, prec == LDG_FP16_MFMA, s);
+  }
+  if (prec != LDG_FP64 && prec != LDG_FP32) {
+    set_error("unknown precision");
+    return LDG_EINVAL;
+  }
+  const bool fp32 = prec == LDG_FP32;
+  const TimeDev td = make_time(t, false);
+  if (md.linear) {
+    ldg_status st = op_grad(md, v, md.d_dq, fp32, false, s);
+    if (st != LDG_OK) return st;
+    return op_resid(md, td, v, md.d_dq, Jv, fp32, false, s);
+  }
+  if (!u) {
+    set_error("nonlinear model needs u");
+    return LDG_EINVAL;
+  }
+  ldg_status st;
+  void* qc = fp32 ? (void*)md.d_q32 : (void*)md.d_q;
+  if (!prepared && md.kind != LDG_MODEL_EULER) {
+    st = op_grad(md, u, qc, fp32, true, s);
+    if (st != LDG_OK) return st;
+  }
+  if (md.kind != LDG_MODEL_EULER) {
+    st = op_grad(md, v, md.d_dq, fp32, false, s);
+    if (st != LDG_OK) return st;
+  }
+  return op_jvp_nonlinear(md, td, u, qc, v, md.d_dq, Jv, fp32, s);
+}
+
+}  // namespace ldg
+
+extern "C" {
+
+ldg_status ldg_residual(ldg_model md, const ldg_time* t, const double* u, double* G, double* q_out, ldg_precision prec,
+                        void* stream) {
+  LDG_ENTER();
+  CHECK_ARG(md && u && G, "null argument");
+  CHECK_ARG(prec == LDG_FP64 || prec == LDG_FP32, "residual precision must be FP64 or FP32");
+  return residual_impl(*md, t, u, G, q_out, prec == LDG_FP32, (hipStream_t)stream);
+}
+
+ldg_status ldg_jvp(ldg_model md, const ldg_time* t, const double* u, const double* v, double* Jv, ldg_precision prec,
+                   void* stream) {
+  LDG_ENTER();
+  CHECK_ARG(md && v && Jv, "null argument");
+  CHECK_ARG(Jv != v && Jv != u, "Jv must not alias u or v");
+  return jvp_impl(*md, t, u, v, Jv, prec, false, (hipStream_t)stream);
+}
+
+ldg_status ldg_axpby(int64_t n, double a, const double* x, double b, double* y, void* stream) {
+  LDG_ENTER();
+  CHECK_ARG(n >= 0 && x && y, "bad arguments");
+  return vec_axpby(n, a, x, b, y, (hipStream_t)stream);
+}
+
+ldg_status ldg_norm2(int64_t n, const double* x, double* out, void* stream) {
+  LDG_ENTER();
+  CHECK_ARG(n >= 0 && x && out, "bad arguments");
+  double* part = nullptr;
+  LDG_TRY(hipMalloc((void**)&part, 4096 * sizeof(double)));   // reduction partials + result slot
+  ldg_status st = vec_norm2(n, x, part, out, (hipStream_t)stream);
+  hipFree(part);
+  return st;
+}
+
+}  // extern "C"

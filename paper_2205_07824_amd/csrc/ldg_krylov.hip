@@ -1,0 +1,512 @@
+// FP64 Krylov machinery for the matrix-free Newton-GMRES solver (Section 3.3):
+// vector kernels, the block-wise multi-dot / update pair of classical
+// Gram-Schmidt with one re-orthogonalization pass (CGS2), Givens rotations on
+// the device, restarted flexible GMRES, and Newton's method.
+#include <chrono>
+#include <cstring>
+#include <cmath>
+
+#include "ldg_internal.hpp"
+
+namespace ldg {
+
+constexpr int RED_BLOCKS = 1024;   // partial-sum slots per reduction
+constexpr int VB = 256;            // threads per block of the vector kernels
+
+// ---------------------------------------------------------------- vectors ---
+__global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i] + (b == 0.0 ? 0.0 : b * y[i]);
+}
+__global__ void k_zero_int(int* p) { if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0; }
+ldg_status zero_int(int* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, p);
+  LDG_TRY(hipGetLastError());
+  return LDG_OK;
+}
+__global__ void k_fill(int64_t n, double a, double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) y[i] = a;
+}
+__global__ void k_scale_dev(int64_t n, const double* __restrict__ sc, const double* __restrict__ x,
+                            double* __restrict__ y) {
+  const double a = *sc;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i];
+}
+
+__device__ inline double block_sum(double v, double* sh) {
+  // wave64 shuffle reduction, then across waves through LDS
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) t += sh[w];
+  __syncthreads();
+  return t;
+}
+
+__global__ void k_dot_partial(int64_t n, const double* __restrict__ x, const double* __restrict__ y,
+                              double* __restrict__ part) {
+  __shared__ double sh[16];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s += x[i] * y[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void k_sum_partials(int nparts, const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double sh[16];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += part[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) *out = s;
+}
+
+static int grid_for(int64_t n) {
+  int64_t g = (n + VB - 1) / VB;
+  if (g > RED_BLOCKS) g = RED_BLOCKS;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+ldg_status vec_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s) {
+  if (n == 0) return LDG_OK;
+  hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(VB), 0, s, n, a, x, b, y);
+  LDG_TRY(hipGetLastError());
+  return LDG_OK;
+}
+ldg_status vec_fill(int64_t n, double a, double* y, hipStream_t s) {
+  if (n == 0) return LDG_OK;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(VB), 0, s, n, a, y);
+  LDG_TRY(hipGetLastError());
+  return LDG_OK;
+}
+ldg_status vec_scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t s) {
+  return vec_axpby(n, a, x, 0.0, y, s);
+}
+// sum(x^2) to the host; part needs >= RED_BLOCKS + 1 doubles
+ldg_status vec_norm2(int64_t n, const double* x, double* part, double* host_out, hipStream_t s) {
+  const int g = grid_for(n);
+  hipLaunchKernelGGL(k_dot_partial, dim3(g), dim3(VB), 0, s, n, x, x, part);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(VB), 0, s, g, part, part + RED_BLOCKS);
+  LDG_TRY(hipGetLastError());
+  LDG_TRY(hipMemcpyAsync(host_out, part + RED_BLOCKS, sizeof(double), hipMemcpyDeviceToHost, s));
+  LDG_TRY(hipStreamSynchronize(s));
+  return LDG_OK;
+}
+
+// ------------------------------------------------------- Gram-Schmidt pair ---
+// h_i = V_i . w for i = 0..j (one pass over w, j+1 basis vectors), block partials
+// part[i * nblk + b].
+constexpr int MAXM = 128;
+__global__ void __launch_bounds__(VB) k_multidot(int64_t n, int nv, const double* __restrict__ V, int64_t ldv,
+                                                 const double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double sh[16];
+  const int nblk = gridDim.x;
+  // each block owns a contiguous chunk; w is read once into registers per chunk pass
+  const int64_t chunk = ((n + nblk - 1) / nblk + VB - 1) / VB * VB;
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  for (int i0 = 0; i0 < nv; i0 += 4) {
+    double s[4] = {0, 0, 0, 0};
+    const int ni = nv - i0 < 4 ? nv - i0 : 4;
+    for (int64_t t = lo + threadIdx.x; t < hi; t += VB) {
+      const double wt = w[t];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (r < ni) s[r] += V[(int64_t)(i0 + r) * ldv + t] * wt;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (r < ni) {
+        double tot = block_sum(s[r], sh);
+        if (threadIdx.x == 0) part[(int64_t)(i0 + r) * nblk + blockIdx.x] = tot;
+      }
+    }
+  }
+}
+
+// reduce the partials of nv dot products into h[0..nv) (one block per dot)
+__global__ void k_reduce_rows(int nv, int nblk, const double* __restrict__ part, double* __restrict__ h) {
+  __shared__ double sh[16];
+  const int i = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += part[(int64_t)i * nblk + b];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0 && i < nv) h[i] = s;
+}
+
+// w -= sum_i h_i V_i ; optionally the partial sums of ||w||^2 after the update
+__global__ void __launch_bounds__(VB) k_update(int64_t n, int nv, const double* __restrict__ V, int64_t ldv,
+                                               const double* __restrict__ h, double* __restrict__ w,
+                                               double* __restrict__ npart) {
+  __shared__ double sh[16];
+  __shared__ double hs[MAXM + 1];
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) hs[i] = h[i];
+  __syncthreads();
+  double ss = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    double acc = w[t];
+    for (int i = 0; i < nv; ++i) acc -= hs[i] * V[(int64_t)i * ldv + t];
+    w[t] = acc;
+    ss += acc * acc;
+  }
+  if (npart) {
+    ss = block_sum(ss, sh);
+    if (threadIdx.x == 0) npart[blockIdx.x] = ss;
+  }
+}
+
+// x += sum_i y_i Z_i
+__global__ void k_combine(int64_t n, int k, const double* __restrict__ Z, int64_t ldz, const double* __restrict__ y,
+                          double* __restrict__ x) {
+  __shared__ double ys[MAXM];
+  for (int i = threadIdx.x; i < k; i += blockDim.x) ys[i] = y[i];
+  __syncthreads();
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    double acc = x[t];
+    for (int i = 0; i < k; ++i) acc += ys[i] * Z[(int64_t)i * ldz + t];
+    x[t] = acc;
+  }
+}
+
+// Arnoldi bookkeeping on the device, FP64, one block:
+//  column j of H = h1 + h2 (two Gram-Schmidt passes), h_{j+1,j} = ||w||,
+//  apply the previous rotations, build rotation j (hypot), update g,
+//  write 1/h_{j+1,j} for the normalization and |g_{j+1}|, breakdown flag.
+struct ArnoldiState {
+  double H[(MAXM + 1) * MAXM];   // column-major, ld = MAXM + 1
+  double cs[MAXM], sn[MAXM], g[MAXM + 1], y[MAXM];
+  double inv_hnext;
+  double resid;                  // |g_{j+1}|
+  double wnorm0;                 // ||w|| before orthogonalization
+  int breakdown;
+};
+
+__global__ void k_givens(ArnoldiState* st, int j, int nblk, const double* __restrict__ h1, const double* __restrict__ h2,
+                         const double* __restrict__ npart) {
+  __shared__ double sh[16];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += npart[b];
+  s = block_sum(s, sh);
+  if (threadIdx.x != 0) return;
+  const int ld = MAXM + 1;
+  double* col = st->H + (int64_t)j * ld;
+  for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
+  const double hn = sqrt(s);
+  col[j + 1] = hn;
+  st->breakdown = (hn <= 1e-14 * st->wnorm0) ? 1 : 0;
+  st->inv_hnext = hn > 0 ? 1.0 / hn : 0.0;
+  for (int i = 0; i < j; ++i) {
+    const double t = st->cs[i] * col[i] + st->sn[i] * col[i + 1];
+    col[i + 1] = -st->sn[i] * col[i] + st->cs[i] * col[i + 1];
+    col[i] = t;
+  }
+  const double d = hypot(col[j], col[j + 1]);
+  st->cs[j] = d > 0 ? col[j] / d : 1.0;
+  st->sn[j] = d > 0 ? col[j + 1] / d : 0.0;
+  col[j] = d;
+  col[j + 1] = 0.0;
+  st->g[j + 1] = -st->sn[j] * st->g[j];
+  st->g[j] = st->cs[j] * st->g[j];
+  st->resid = fabs(st->g[j + 1]);
+}
+
+// ||w|| before orthogonalization (for the breakdown test)
+__global__ void k_store_norm(ArnoldiState* st, int nblk, const double* __restrict__ npart) {
+  __shared__ double sh[16];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += npart[b];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) st->wnorm0 = sqrt(s);
+}
+
+__global__ void k_arnoldi_start(ArnoldiState* st, int nblk, const double* __restrict__ npart) {
+  __shared__ double sh[16];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += npart[b];
+  s = block_sum(s, sh);
+  if (threadIdx.x != 0) return;
+  const double beta = sqrt(s);
+  for (int i = 0; i <= MAXM; ++i) st->g[i] = 0.0;
+  st->g[0] = beta;
+  st->resid = beta;
+  st->inv_hnext = beta > 0 ? 1.0 / beta : 0.0;
+}
+
+// back substitution H(0:k,0:k) y = g(0:k)
+__global__ void k_backsolve(ArnoldiState* st, int k) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int ld = MAXM + 1;
+  for (int i = k - 1; i >= 0; --i) {
+    double s = st->g[i];
+    for (int c = i + 1; c < k; ++c) s -= st->H[(int64_t)c * ld + i] * st->y[c];
+    st->y[i] = s / st->H[(int64_t)i * ld + i];
+  }
+}
+
+// NaN injection for the failure-handling tests
+__global__ void k_poison(int64_t n, double* z) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && (i % 97) == 0) z[i] = __longlong_as_double(0x7ff8000000000000ll);
+}
+
+}  // namespace ldg
+
+using namespace ldg;
+
+struct ldg_precond_s;
+namespace ldg {
+ldg_status precond_apply_impl(ldg_precond_s* pc, const double* r, double* z, hipStream_t s);
+ldg_status precond_rebuild(ldg_precond_s* pc, const ldg_time* t, const double* u_lin, hipStream_t s);
+}
+
+namespace {
+
+struct Workspace {
+  int64_t n = 0;
+  int m = 0;
+  double* V = nullptr;     // [(m+1)][n]
+  double* Z = nullptr;     // [m][n]
+  double* w = nullptr;
+  double* r = nullptr;
+  double* part = nullptr;  // [(MAXM+1) * RED_BLOCKS]
+  double* npart = nullptr; // [RED_BLOCKS]
+  double* h1 = nullptr;
+  double* h2 = nullptr;
+  ArnoldiState* st = nullptr;
+  double* pinned = nullptr;  // host scalars
+  hipEvent_t ev[8];
+  bool ok = false;
+  void release() {
+    if (!ok) return;
+    hipFree(V); hipFree(Z); hipFree(w); hipFree(r); hipFree(part); hipFree(npart); hipFree(h1); hipFree(h2);
+    hipFree(st); hipHostFree(pinned);
+    for (auto& e : ev) hipEventDestroy(e);
+    ok = false;
+  }
+  ldg_status ensure(int64_t nn, int mm) {
+    if (ok && nn == n && mm <= m) return LDG_OK;
+    release();
+    n = nn; m = mm;
+    LDG_TRY(hipMalloc((void**)&V, sizeof(double) * (m + 1) * n));
+    LDG_TRY(hipMalloc((void**)&Z, sizeof(double) * m * n));
+    LDG_TRY(hipMalloc((void**)&w, sizeof(double) * n));
+    LDG_TRY(hipMalloc((void**)&r, sizeof(double) * n));
+    LDG_TRY(hipMalloc((void**)&part, sizeof(double) * (MAXM + 1) * RED_BLOCKS));
+    LDG_TRY(hipMalloc((void**)&npart, sizeof(double) * RED_BLOCKS));
+    LDG_TRY(hipMalloc((void**)&h1, sizeof(double) * (MAXM + 1)));
+    LDG_TRY(hipMalloc((void**)&h2, sizeof(double) * (MAXM + 1)));
+    LDG_TRY(hipMalloc((void**)&st, sizeof(ArnoldiState)));
+    LDG_TRY(hipHostMalloc((void**)&pinned, sizeof(double) * 8, hipHostMallocDefault));
+    for (auto& e : ev) LDG_TRY(hipEventCreate(&e));
+    ok = true;
+    return LDG_OK;
+  }
+};
+
+// per-thread solver workspace, kept until the process ends
+thread_local Workspace* g_ws_ptr = nullptr;
+
+inline int nblk_for(int64_t n) {
+  int64_t g = (n + VB - 1) / VB;
+  return (int)(g > RED_BLOCKS ? RED_BLOCKS : (g < 1 ? 1 : g));
+}
+
+}  // namespace
+
+namespace ldg {
+
+// w = b - J x  -> ws.r ; returns ||r|| on the host
+static ldg_status true_residual(Model& md, const ldg_time* t, const double* u, const double* b, const double* x,
+                                ldg_precision prec, Workspace& ws, double* out_norm, hipStream_t s) {
+  ldg_status st = jvp_impl(md, t, u, x, ws.r, prec == LDG_JVP_FD ? LDG_JVP_FD : LDG_FP64, true, s);
+  if (st != LDG_OK) return st;
+  st = vec_axpby(ws.n, 1.0, b, -1.0, ws.r, s);
+  if (st != LDG_OK) return st;
+  double nr = 0.0;
+  st = vec_norm2(ws.n, ws.r, ws.part, &nr, s);
+  *out_norm = std::sqrt(nr);
+  return st;
+}
+
+ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const double* b, double* x,
+                      const ldg_gmres_opts& o, ldg_gmres_stats* stats, hipStream_t s) {
+  auto T0 = std::chrono::steady_clock::now();
+  ldg_gmres_stats S{};
+  const int64_t n = (int64_t)md.N();
+  const int m = o.restart;
+  if (m < 1 || m > MAXM) { set_error("restart must be in [1, 128]"); return LDG_EINVAL; }
+  if (!g_ws_ptr) g_ws_ptr = new Workspace();
+  Workspace& ws = *g_ws_ptr;
+  ldg_status st = ws.ensure(n, m);
+  if (st != LDG_OK) return st;
+  const int nb = nblk_for(n);
+  const int gV = nb;
+  // linearization point: q(u_lin) for the nonlinear models, once per solve
+  if (!md.linear && md.kind != LDG_MODEL_EULER) {
+    st = op_grad(md, u_lin, md.d_q, false, true, s);
+    if (st != LDG_OK) return st;
+    if (o.jvp_prec == LDG_FP32) {
+      st = op_grad(md, u_lin, md.d_q32, true, true, s);
+      if (st != LDG_OK) return st;
+    }
+  }
+  const ldg_precision jp = o.jvp_prec;
+  const bool use_pc = o.pc != nullptr;
+  double r0 = 0.0;
+  st = true_residual(md, t, u_lin, b, x, jp, ws, &r0, s);
+  if (st != LDG_OK) return st;
+  S.res0 = r0;
+  const double tol = std::max(o.rtol * r0, o.atol);
+  double beta = r0;
+  int its = 0;
+  ldg_status result = LDG_OK;
+  float ms = 0.0f;
+  while (beta > tol && its < o.maxit) {
+    if (!std::isfinite(beta)) { result = LDG_EBREAKDOWN; break; }
+    // V0 = r / beta
+    hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(VB), 0, s, n, ws.r, ws.r, ws.npart);
+    hipLaunchKernelGGL(k_arnoldi_start, dim3(1), dim3(VB), 0, s, ws.st, nb, ws.npart);
+    hipLaunchKernelGGL(k_scale_dev, dim3(gV), dim3(VB), 0, s, n, &ws.st->inv_hnext, ws.r, ws.V);
+    int k = 0;
+    bool stop = false;
+    for (int j = 0; j < m && its < o.maxit; ++j) {
+      double* vj = ws.V + (int64_t)j * n;
+      double* zj = use_pc ? ws.Z + (int64_t)j * n : vj;
+      hipEventRecord(ws.ev[0], s);
+      if (use_pc) {
+        st = precond_apply_impl(o.pc, vj, zj, s);
+        if (st != LDG_OK) return st;
+        if (o.inject_fault == 1) hipLaunchKernelGGL(k_poison, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, zj);
+      }
+      hipEventRecord(ws.ev[1], s);
+      st = jvp_impl(md, t, u_lin, zj, ws.w, jp, true, s);
+      if (st != LDG_OK) return st;
+      hipEventRecord(ws.ev[2], s);
+      // ||w|| before orthogonalization
+      hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(VB), 0, s, n, ws.w, ws.w, ws.npart);
+      hipLaunchKernelGGL(k_store_norm, dim3(1), dim3(VB), 0, s, ws.st, nb, ws.npart);
+      // CGS2: two passes of (h = V^T w ; w -= V h)
+      hipLaunchKernelGGL(k_multidot, dim3(nb), dim3(VB), 0, s, n, j + 1, ws.V, n, ws.w, ws.part);
+      hipLaunchKernelGGL(k_reduce_rows, dim3(j + 1), dim3(VB), 0, s, j + 1, nb, ws.part, ws.h1);
+      hipLaunchKernelGGL(k_update, dim3(gV), dim3(VB), 0, s, n, j + 1, ws.V, n, ws.h1, ws.w, (double*)nullptr);
+      hipLaunchKernelGGL(k_multidot, dim3(nb), dim3(VB), 0, s, n, j + 1, ws.V, n, ws.w, ws.part);
+      hipLaunchKernelGGL(k_reduce_rows, dim3(j + 1), dim3(VB), 0, s, j + 1, nb, ws.part, ws.h2);
+      hipLaunchKernelGGL(k_update, dim3(gV), dim3(VB), 0, s, n, j + 1, ws.V, n, ws.h2, ws.w, ws.npart);
+      hipLaunchKernelGGL(k_givens, dim3(1), dim3(VB), 0, s, ws.st, j, gV, ws.h1, ws.h2, ws.npart);
+      hipLaunchKernelGGL(k_scale_dev, dim3(gV), dim3(VB), 0, s, n, &ws.st->inv_hnext, ws.w,
+                         ws.V + (int64_t)(j + 1) * n);
+      LDG_TRY(hipGetLastError());
+      hipEventRecord(ws.ev[3], s);
+      LDG_TRY(hipMemcpyAsync(ws.pinned, &ws.st->resid, sizeof(double), hipMemcpyDeviceToHost, s));
+      LDG_TRY(hipMemcpyAsync(ws.pinned + 1, &ws.st->breakdown, sizeof(int), hipMemcpyDeviceToHost, s));
+      LDG_TRY(hipStreamSynchronize(s));
+      if (hipEventElapsedTime(&ms, ws.ev[0], ws.ev[1]) == hipSuccess) S.t_pc += ms * 1e-3;
+      if (hipEventElapsedTime(&ms, ws.ev[1], ws.ev[2]) == hipSuccess) S.t_jvp += ms * 1e-3;
+      if (hipEventElapsedTime(&ms, ws.ev[2], ws.ev[3]) == hipSuccess) S.t_orth += ms * 1e-3;
+      ++its;
+      k = j + 1;
+      const double res = ws.pinned[0];
+      int brk = 0;
+      std::memcpy(&brk, ws.pinned + 1, sizeof(int));
+      S.res_est = res;
+      if (!std::isfinite(res)) { stop = true; result = LDG_EBREAKDOWN; break; }
+      if (res <= tol || brk) { stop = true; break; }
+    }
+    // x += Z y
+    if (k > 0 && result == LDG_OK) {
+      hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, s, ws.st, k);
+      hipLaunchKernelGGL(k_combine, dim3(gV), dim3(VB), 0, s, n, k, use_pc ? ws.Z : ws.V, n, ws.st->y, x);
+      LDG_TRY(hipGetLastError());
+    }
+    ++S.restarts;
+    if (result != LDG_OK) break;
+    st = true_residual(md, t, u_lin, b, x, jp, ws, &beta, s);
+    if (st != LDG_OK) return st;
+    (void)stop;
+  }
+  S.iters = its;
+  S.res_true = beta;
+  if (result == LDG_OK && !(beta <= tol * (1.0 + 1e-6) || beta <= tol)) {
+    // Givens estimate met the tolerance but the true residual did not, or maxit reached
+    result = LDG_ENOCONV;
+  }
+  if (!std::isfinite(beta)) result = LDG_EBREAKDOWN;
+  S.t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - T0).count();
+  if (stats) *stats = S;
+  if (result == LDG_ENOCONV) set_error("GMRES did not reach the tolerance");
+  if (result == LDG_EBREAKDOWN) set_error("non-finite value in GMRES");
+  return result;
+}
+
+}  // namespace ldg
+
+
+extern "C" {
+
+ldg_status ldg_gmres_solve(ldg_model md, const ldg_time* t, const double* u_lin, const double* b, double* x,
+                           const ldg_gmres_opts* opts, ldg_gmres_stats* stats, void* stream) {
+  LDG_ENTER();
+  if (!md || !b || !x || !opts) { set_error("null argument"); return LDG_EINVAL; }
+  if (!md->linear && !u_lin) { set_error("nonlinear model needs u_lin"); return LDG_EINVAL; }
+  return gmres_impl(*md, t, u_lin, b, x, *opts, stats, (hipStream_t)stream);
+}
+
+ldg_status ldg_newton_solve(ldg_model md, const ldg_time* t, double* u, const ldg_newton_opts* opts,
+                            ldg_newton_stats* stats, void* stream) {
+  LDG_ENTER();
+  if (!md || !u || !opts) { set_error("null argument"); return LDG_EINVAL; }
+  hipStream_t s = (hipStream_t)stream;
+  auto T0 = std::chrono::steady_clock::now();
+  ldg_newton_stats S{};
+  const int64_t n = (int64_t)md->N();
+  double *G = nullptr, *du = nullptr;
+  LDG_TRY(hipMalloc((void**)&G, sizeof(double) * n));
+  if (hipMalloc((void**)&du, sizeof(double) * n) != hipSuccess) { hipFree(G); set_error("alloc"); return LDG_ENOMEM; }
+  auto cleanup = [&]() { hipFree(G); hipFree(du); };
+  ldg_status st = residual_impl(*md, t, u, G, nullptr, false, s);
+  double g2 = 0.0;
+  if (st == LDG_OK) st = vec_norm2(n, G, md->d_red, &g2, s);
+  if (st != LDG_OK) { cleanup(); return st; }
+  const double g0 = std::sqrt(g2);
+  double gn = g0;
+  S.res0 = g0;
+  ldg_status result = LDG_OK;
+  ldg_gmres_opts lin = opts->lin;
+  lin.rtol = opts->eta;
+  while (gn > std::max(opts->rtol * g0, opts->atol)) {
+    if (S.iters >= opts->maxit) { result = LDG_ENOCONV; set_error("Newton did not converge"); break; }
+    if (!std::isfinite(gn)) { result = LDG_EBREAKDOWN; set_error("non-finite Newton residual"); break; }
+    if (opts->bj_refresh && lin.pc) {
+      st = precond_rebuild(lin.pc, t, u, s);
+      if (st != LDG_OK) { result = st; break; }
+    }
+    // J du = -G
+    st = vec_axpby(n, -1.0, G, 0.0, G, s);
+    if (st == LDG_OK) st = vec_fill(n, 0.0, du, s);
+    if (st != LDG_OK) { result = st; break; }
+    ldg_gmres_stats gs{};
+    st = gmres_impl(*md, t, u, G, du, lin, &gs, s);
+    S.gmres_iters += gs.iters;
+    S.lin_status = st;
+    if (st != LDG_OK && st != LDG_ENOCONV) { result = st; break; }
+    st = vec_axpby(n, 1.0, du, 1.0, u, s);
+    if (st == LDG_OK) st = residual_impl(*md, t, u, G, nullptr, false, s);
+    if (st == LDG_OK) st = vec_norm2(n, G, md->d_red, &g2, s);
+    if (st != LDG_OK) { result = st; break; }
+    gn = std::sqrt(g2);
+    ++S.iters;
+  }
+  S.res_final = gn;
+  S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - T0).count();
+  if (stats) *stats = S;
+  cleanup();
+  return result;
+}
+
+}  // extern "C"

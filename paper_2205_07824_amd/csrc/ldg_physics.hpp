@@ -1,0 +1,137 @@
+// Pointwise physics of the built-in models: flux f(u, q) [NCU][D], numerical
+// flux across a face, max wave speed.  Written once for plain values and for
+// dual numbers (value, tangent), so that the tangent kernels differentiate
+// exactly the arithmetic of the residual kernels.
+#pragma once
+
+#include "ldg_internal.hpp"
+
+namespace ldg {
+
+enum { K_POISSON = 0, K_CONVDIFF = 1, K_EULER = 2, K_NS = 3 };
+
+template <int KIND, int D>
+struct Phys {
+  static constexpr int NCU = (KIND <= 1) ? 1 : D + 2;
+  static constexpr bool HASQ = (KIND != K_EULER);
+  static constexpr bool LINEAR = (KIND <= 1);
+  static constexpr int NAUX = (KIND == K_CONVDIFF) ? 1 + D : (KIND == K_POISSON ? 1 : 0);
+};
+
+// physical flux; a = aux at the point (R), naux = number of aux fields present
+template <int KIND, int D, class V, class R>
+__device__ inline void phys_flux(const double* mu, int naux, const V* u, const V (*q)[D], const R* a,
+                                 V (*f)[D]) {
+  using T = VT<V>;
+  if constexpr (KIND == K_POISSON) {
+    R kap = R(mu[0]) * (naux >= 1 ? a[0] : R(1));
+#pragma unroll
+    for (int k = 0; k < D; ++k) f[0][k] = kap * q[0][k];
+  } else if constexpr (KIND == K_CONVDIFF) {
+    R kap = R(mu[0]) * a[0];
+#pragma unroll
+    for (int k = 0; k < D; ++k) f[0][k] = kap * q[0][k] + a[1 + k] * u[0];
+  } else {
+    const R gam = R(mu[0]);
+    constexpr int NE = D + 1;
+    V rho = u[0], E = u[NE];
+    V rinv = T::mk(R(1)) / rho;
+    V vel[D];
+    V ke = T::mk(R(0));
+#pragma unroll
+    for (int k = 0; k < D; ++k) { vel[k] = u[1 + k] * rinv; ke += u[1 + k] * vel[k]; }
+    V pr = (gam - R(1)) * (E - R(0.5) * ke);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      f[0][k] = u[1 + k];
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        f[1 + i][k] = u[1 + i] * vel[k];
+        if (i == k) f[1 + i][k] += pr;
+      }
+      f[NE][k] = (E + pr) * vel[k];
+    }
+    if constexpr (KIND == K_NS) {
+      const R vis = R(1) / R(mu[1]);
+      const R kcond = vis * gam / R(mu[2]);
+      V gv[D][D], ge[D];
+      V Em = E * rinv;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        V gr = -q[0][k];                     // grad u = -q
+#pragma unroll
+        for (int i = 0; i < D; ++i) gv[i][k] = (-q[1 + i][k] - vel[i] * gr) * rinv;
+        V gEm = (-q[NE][k] - Em * gr) * rinv;
+        V s = gEm;
+#pragma unroll
+        for (int i = 0; i < D; ++i) s -= vel[i] * gv[i][k];
+        ge[k] = s;
+      }
+      V divv = gv[0][0];
+#pragma unroll
+      for (int i = 1; i < D; ++i) divv += gv[i][i];
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        V work = T::mk(R(0));
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+          V tau = vis * (gv[i][k] + gv[k][i]);
+          if (i == k) tau -= (vis * R(2.0 / 3.0)) * divv;
+          f[1 + i][k] -= tau;
+          work += vel[i] * tau;
+        }
+        f[NE][k] -= work + kcond * ge[k];
+      }
+    }
+  }
+}
+
+template <int D, class V, class R>
+__device__ inline V wave_speed(R gam, const V* u, const R* n) {
+  using T = VT<V>;
+  V rho = u[0], E = u[D + 1];
+  V rinv = T::mk(R(1)) / rho;
+  V vn = T::mk(R(0)), ke = T::mk(R(0));
+#pragma unroll
+  for (int k = 0; k < D; ++k) { vn += (u[1 + k] * rinv) * n[k]; ke += u[1 + k] * u[1 + k] * rinv; }
+  V pr = (gam - R(1)) * (E - R(0.5) * ke);
+  return vabs(vn) + vsqrt(gam * pr * rinv);
+}
+
+// interior numerical flux (also used at Dirichlet faces with u+ = g, q+ = q-, a+ = a-)
+template <int KIND, int D, class V, class R>
+__device__ inline void num_flux(const double* mu, int naux, const V* uL, const V (*qL)[D], const R* aL,
+                                const V* uR, const V (*qR)[D], const R* aR, const R* n, V* Fh) {
+  constexpr int NCU = Phys<KIND, D>::NCU;
+  V fL[NCU][D], fR[NCU][D];
+  phys_flux<KIND, D, V, R>(mu, naux, uL, qL, aL, fL);
+  phys_flux<KIND, D, V, R>(mu, naux, uR, qR, aR, fR);
+#pragma unroll
+  for (int c = 0; c < NCU; ++c) {
+    V s = R(0.5) * (fL[c][0] + fR[c][0]) * n[0];
+#pragma unroll
+    for (int k = 1; k < D; ++k) s += R(0.5) * (fL[c][k] + fR[c][k]) * n[k];
+    Fh[c] = s;
+  }
+  if constexpr (KIND == K_POISSON) {
+    R kL = naux >= 1 ? aL[0] : R(1), kR = naux >= 1 ? aR[0] : R(1);
+    R sig = R(mu[1]) * R(mu[0]) * R(0.5) * (kL + kR);
+    Fh[0] += sig * (uL[0] - uR[0]);
+  } else if constexpr (KIND == K_CONVDIFF) {
+    R sig = R(mu[1]) * R(mu[0]) * R(0.5) * (aL[0] + aR[0]);
+    R bnL = R(0), bnR = R(0);
+#pragma unroll
+    for (int k = 0; k < D; ++k) { bnL += aL[1 + k] * n[k]; bnR += aR[1 + k] * n[k]; }
+    sig += R(0.5) * vmax(vabs(bnL), vabs(bnR));
+    Fh[0] += sig * (uL[0] - uR[0]);
+  } else {
+    const R gam = R(mu[0]);
+    V lam = vmax(wave_speed<D, V, R>(gam, uL, n), wave_speed<D, V, R>(gam, uR, n));
+    V sig = R(0.5) * lam;
+    if constexpr (KIND == K_NS) sig = sig + R(mu[3] / mu[1]);
+#pragma unroll
+    for (int c = 0; c < NCU; ++c) Fh[c] += sig * (uL[c] - uR[c]);
+  }
+}
+
+}  // namespace ldg

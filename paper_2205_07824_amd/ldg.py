@@ -1,0 +1,290 @@
+"""Thin ctypes binding of the gfx950 LDG library (libldg.so).
+
+Argument marshalling only: every step of the residual / Jacobian-vector product
+/ preconditioner / GMRES / Newton path runs in the library's HIP kernels.  Torch
+supplies device memory and the current stream.  The names mirror the C ABI
+declared in include/ldg.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libldg.so")
+
+LDG_OK, LDG_EINVAL, LDG_EUNSUPPORTED, LDG_EDEVICE, LDG_ENOMEM, LDG_ENOCONV, LDG_EBREAKDOWN = range(7)
+FP64, FP32, BF16_MFMA, FP16_MFMA, JVP_FD = range(5)
+MODEL_POISSON, MODEL_CONVDIFF, MODEL_EULER, MODEL_NS = range(4)
+BC_DIRICHLET, BC_NEUMANN, BC_EXTRAP = range(3)
+
+_STATUS = {0: "OK", 1: "EINVAL", 2: "EUNSUPPORTED", 3: "EDEVICE", 4: "ENOMEM", 5: "ENOCONV", 6: "EBREAKDOWN"}
+
+
+class LDGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Time(C.Structure):
+    _fields_ = [("a0", C.c_double), ("r1", C.c_void_p), ("c1", C.c_double), ("r2", C.c_void_p), ("c2", C.c_double)]
+
+
+class _ModelDesc(C.Structure):
+    _fields_ = [("kind", C.c_int), ("ncu", C.c_int), ("nmu", C.c_int), ("mu", C.POINTER(C.c_double)),
+                ("naux", C.c_int), ("aux", C.c_void_p), ("src", C.c_void_p), ("bdata", C.c_void_p),
+                ("nbc", C.c_int), ("bc_kind", C.POINTER(C.c_int32))]
+
+
+class GmresOpts(C.Structure):
+    _fields_ = [("restart", C.c_int), ("maxit", C.c_int), ("flexible", C.c_int), ("rtol", C.c_double),
+                ("atol", C.c_double), ("jvp_prec", C.c_int), ("pc", C.c_void_p), ("inject_fault", C.c_int)]
+
+
+class GmresStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("fell_back", C.c_int), ("res0", C.c_double),
+                ("res_est", C.c_double), ("res_true", C.c_double), ("t_jvp", C.c_double), ("t_pc", C.c_double),
+                ("t_orth", C.c_double), ("t_total", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class NewtonOpts(C.Structure):
+    _fields_ = [("maxit", C.c_int), ("rtol", C.c_double), ("atol", C.c_double), ("eta", C.c_double),
+                ("bj_refresh", C.c_int), ("bj_per_variable", C.c_int), ("bj_prec", C.c_int), ("lin", GmresOpts)]
+
+
+class NewtonStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("gmres_iters", C.c_int), ("res0", C.c_double), ("res_final", C.c_double),
+                ("seconds", C.c_double), ("lin_status", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+EXPORTED = ["ldg_last_error", "ldg_mesh_create", "ldg_mesh_info", "ldg_mesh_points", "ldg_mesh_destroy",
+            "ldg_model_create", "ldg_model_destroy", "ldg_residual", "ldg_jvp", "ldg_jacobian_blocks",
+            "ldg_precond_block_jacobi", "ldg_precond_apply", "ldg_precond_destroy", "ldg_gmres_solve",
+            "ldg_newton_solve", "ldg_axpby", "ldg_norm2"]
+
+
+def lib():
+    """Load libldg.so; fails loudly if the HIP library has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    L = C.CDLL(LIB_PATH)
+    vp, dp, i64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)
+    L.ldg_last_error.restype = C.c_char_p
+    sig = {
+        "ldg_mesh_create": [C.c_int, C.c_int, C.c_int, C.c_int64, dp, C.c_int64, i64p, dp, C.POINTER(C.c_int32),
+                            C.POINTER(vp)],
+        "ldg_mesh_info": [vp, i64p],
+        "ldg_mesh_points": [vp, dp, dp, dp, i64p],
+        "ldg_mesh_destroy": [vp],
+        "ldg_model_create": [vp, C.POINTER(_ModelDesc), vp, C.POINTER(vp)],
+        "ldg_model_destroy": [vp],
+        "ldg_residual": [vp, C.POINTER(_Time), vp, vp, vp, C.c_int, vp],
+        "ldg_jvp": [vp, C.POINTER(_Time), vp, vp, vp, C.c_int, vp],
+        "ldg_jacobian_blocks": [vp, C.POINTER(_Time), vp, C.c_int, vp, vp],
+        "ldg_precond_block_jacobi": [vp, C.POINTER(_Time), vp, C.c_int, C.c_int, vp, C.POINTER(vp)],
+        "ldg_precond_apply": [vp, vp, vp, vp],
+        "ldg_precond_destroy": [vp],
+        "ldg_gmres_solve": [vp, C.POINTER(_Time), vp, vp, vp, C.POINTER(GmresOpts), C.POINTER(GmresStats), vp],
+        "ldg_newton_solve": [vp, C.POINTER(_Time), vp, C.POINTER(NewtonOpts), C.POINTER(NewtonStats), vp],
+        "ldg_axpby": [C.c_int64, C.c_double, vp, C.c_double, vp, vp],
+        "ldg_norm2": [C.c_int64, vp, dp, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(status, what=""):
+    if status != LDG_OK:
+        raise LDGError(status, f"{what}: {lib().ldg_last_error().decode()}")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA/HIP tensors"
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _np(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+# ----------------------------------------------------------------------------
+class Mesh:
+    def __init__(self, box, p, nq=None):
+        self.nd, self.p = box.nd, p
+        self.nq = p + 1 if nq is None else nq
+        v = _np(box.vert, np.float64)
+        ev = _np(box.elem_vert, np.int64)
+        per = _np(box.period, np.float64)
+        ft = _np(box.face_tag, np.int32)
+        h = C.c_void_p()
+        _check(lib().ldg_mesh_create(self.nd, p, self.nq, v.shape[0], v.ctypes.data_as(C.POINTER(C.c_double)),
+                                     ev.shape[0], ev.ctypes.data_as(C.POINTER(C.c_int64)),
+                                     per.ctypes.data_as(C.POINTER(C.c_double)),
+                                     ft.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(h)), "ldg_mesh_create")
+        self.h = h
+        info = np.zeros(8, dtype=np.int64)
+        _check(lib().ldg_mesh_info(h, info.ctypes.data_as(C.POINTER(C.c_int64))), "ldg_mesh_info")
+        self.E, self.nn, self.nqv, self.nqf, self.nbf, self.ncolors, self.affine, _ = (int(x) for x in info)
+
+    def points(self):
+        xn = np.zeros((self.E, self.nn, self.nd))
+        xq = np.zeros((self.E, self.nqv, self.nd))
+        xb = np.zeros((max(self.nbf, 1), self.nqf, self.nd))
+        bf = np.zeros((max(self.nbf, 1), 2), dtype=np.int64)
+        dp = C.POINTER(C.c_double)
+        _check(lib().ldg_mesh_points(self.h, xn.ctypes.data_as(dp), xq.ctypes.data_as(dp), xb.ctypes.data_as(dp),
+                                     bf.ctypes.data_as(C.POINTER(C.c_int64))), "ldg_mesh_points")
+        return xn, xq, xb[:self.nbf], bf[:self.nbf]
+
+    def size(self, ncu):
+        return self.E * ncu * self.nn
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ldg_mesh_destroy(self.h)
+            self.h = None
+
+
+@dataclass
+class Time:
+    """G(u) = a0 M u - M (c1 r1 + c2 r2) + R(u)."""
+    a0: float = 0.0
+    r1: torch.Tensor = None
+    c1: float = 0.0
+    r2: torch.Tensor = None
+    c2: float = 0.0
+
+    def c(self):
+        self._c = _Time(self.a0, None if self.r1 is None else self.r1.data_ptr(), self.c1,
+                        None if self.r2 is None else self.r2.data_ptr(), self.c2)
+        return C.byref(self._c)
+
+
+def _time(t):
+    return None if t is None else t.c()
+
+
+class Model:
+    def __init__(self, mesh, kind, ncu, mu, aux=None, src=None, bdata=None, bc_kind=(0,)):
+        self.mesh, self.kind, self.ncu = mesh, kind, ncu
+        dev = torch.device("cuda")
+        to = lambda a: None if a is None else torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64).to(dev).contiguous()
+        # keep the device copies alive for the lifetime of the model
+        self.aux, self.src, self.bdata = to(aux), to(src), to(bdata)
+        self._mu = _np(mu, np.float64)
+        self._bc = _np(bc_kind, np.int32)
+        naux = 0 if self.aux is None else int(self.aux.shape[1])
+        d = _ModelDesc(kind, ncu, len(self._mu), self._mu.ctypes.data_as(C.POINTER(C.c_double)), naux,
+                       _ptr(self.aux), _ptr(self.src), _ptr(self.bdata), len(self._bc),
+                       self._bc.ctypes.data_as(C.POINTER(C.c_int32)))
+        h = C.c_void_p()
+        _check(lib().ldg_model_create(mesh.h, C.byref(d), _stream(), C.byref(h)), "ldg_model_create")
+        self.h = h
+        self.N = mesh.size(ncu)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ldg_model_destroy(self.h)
+            self.h = None
+
+    def empty(self):
+        return torch.empty(self.N, dtype=torch.float64, device="cuda")
+
+    def residual(self, u, time=None, prec=FP64, q_out=None, out=None):
+        out = self.empty() if out is None else out
+        _check(lib().ldg_residual(self.h, _time(time), _ptr(u), _ptr(out), _ptr(q_out), prec, _stream()),
+               "ldg_residual")
+        return out
+
+    def jvp(self, u, v, time=None, prec=FP64, out=None):
+        out = self.empty() if out is None else out
+        _check(lib().ldg_jvp(self.h, _time(time), _ptr(u), _ptr(v), _ptr(out), prec, _stream()), "ldg_jvp")
+        return out
+
+    def jacobian_blocks(self, u, time=None, per_variable=False):
+        nn = self.mesh.nn
+        if per_variable:
+            out = torch.zeros((self.mesh.E, self.ncu, nn, nn), dtype=torch.float64, device="cuda")
+        else:
+            nb = self.ncu * nn
+            out = torch.zeros((self.mesh.E, nb, nb), dtype=torch.float64, device="cuda")
+        _check(lib().ldg_jacobian_blocks(self.h, _time(time), _ptr(u), int(per_variable), _ptr(out), _stream()),
+               "ldg_jacobian_blocks")
+        return out
+
+
+class BlockJacobi:
+    def __init__(self, model, u_lin=None, time=None, per_variable=False, prec=FP64):
+        self.model = model
+        h = C.c_void_p()
+        _check(lib().ldg_precond_block_jacobi(model.h, _time(time), _ptr(u_lin), int(per_variable), prec, _stream(),
+                                              C.byref(h)), "ldg_precond_block_jacobi")
+        self.h = h
+
+    def apply(self, r, out=None):
+        out = self.model.empty() if out is None else out
+        _check(lib().ldg_precond_apply(self.h, _ptr(r), _ptr(out), _stream()), "ldg_precond_apply")
+        return out
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ldg_precond_destroy(self.h)
+            self.h = None
+
+
+def gmres_opts(restart=30, maxit=1000, rtol=1e-8, atol=0.0, jvp_prec=FP64, pc=None, flexible=True, inject_fault=0):
+    return GmresOpts(restart, maxit, int(flexible), rtol, atol, jvp_prec, None if pc is None else pc.h, inject_fault)
+
+
+def gmres(model, b, x=None, u_lin=None, time=None, check=True, **kw):
+    x = torch.zeros_like(b) if x is None else x
+    o = gmres_opts(**kw)
+    st = GmresStats()
+    status = lib().ldg_gmres_solve(model.h, _time(time), _ptr(u_lin), _ptr(b), _ptr(x), C.byref(o), C.byref(st),
+                                   _stream())
+    if check and status not in (LDG_OK,):
+        _check(status, "ldg_gmres_solve")
+    return x, st.as_dict(), status
+
+
+def newton(model, u, time=None, maxit=20, rtol=1e-8, atol=0.0, eta=1e-3, bj_refresh=False, bj_per_variable=False,
+           bj_prec=FP64, check=True, lin_maxit=1000, **lin):
+    o = NewtonOpts(maxit, rtol, atol, eta, int(bj_refresh), int(bj_per_variable), bj_prec,
+                   gmres_opts(maxit=lin_maxit, **lin))
+    st = NewtonStats()
+    status = lib().ldg_newton_solve(model.h, _time(time), _ptr(u), C.byref(o), C.byref(st), _stream())
+    if check and status != LDG_OK:
+        _check(status, "ldg_newton_solve")
+    return u, st.as_dict(), status
+
+
+def norm(x):
+    out = C.c_double()
+    _check(lib().ldg_norm2(x.numel(), _ptr(x), C.byref(out), _stream()), "ldg_norm2")
+    return float(np.sqrt(out.value))

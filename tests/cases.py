@@ -1,0 +1,161 @@
+"""Problem instances shaped like the five workloads, at sizes the oracle handles.
+
+Each case is built from the seeded input generators; coefficient fields,
+sources and boundary data are sampled at the oracle's own node / quadrature /
+boundary points, and the same arrays are handed to the HIP library.  The HIP
+library's point coordinates are checked against the oracle's separately.
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+import oracle as O
+from paper_2205_07824_amd import inputs as I
+
+
+def penalty(p, h):
+    return (p + 1) ** 2 / h
+
+
+@dataclass
+class Case:
+    name: str
+    box: object
+    p: int
+    nq: int
+    kind: int
+    ncu: int
+    mu: list
+    aux: np.ndarray = None
+    src: np.ndarray = None
+    bdata: np.ndarray = None
+    bc_kind: tuple = (0,)
+    a0: float = 0.0
+    r1: np.ndarray = None
+    c1: float = 0.0
+    r2: np.ndarray = None
+    c2: float = 0.0
+    u: np.ndarray = None
+    v: np.ndarray = None
+    om: object = field(default=None, repr=False)
+
+    def oracle_model(self):
+        r = None
+        if self.r1 is not None or self.r2 is not None:
+            r = np.zeros(self.om.size(self.ncu))
+            if self.r1 is not None:
+                r += self.c1 * self.r1
+            if self.r2 is not None:
+                r += self.c2 * self.r2
+        return O.Model(self.kind, self.ncu, self.mu, aux=self.aux, src=self.src, bdata=self.bdata,
+                       bc_kind=self.bc_kind, a0=self.a0, r=r)
+
+
+def _off_kink(U, ncu, nn, seed, amp=0.02):
+    """Additive random perturbation of every conserved variable, scaled per variable.
+
+    Keeps parity inputs away from the non-smooth points of the Lax-Friedrichs
+    flux (|v.n| = 0, equal wave speeds), where the tangent follows a tie-break
+    convention instead of a derivative; e.g. the Taylor-Green state has w = 0
+    exactly, which puts |v.n| at its kink on every z-face."""
+    Ur = U.reshape(-1, ncu, nn)
+    scale = np.abs(Ur).mean(axis=(0, 2))[None, :, None] + 0.1
+    rng = np.random.default_rng(seed)
+    return (Ur + amp * scale * rng.uniform(-1, 1, Ur.shape)).reshape(-1)
+
+
+def c1_poisson2d(n=8, p=2, seed=1):
+    """2D Poisson p=2 on n x n quads of the unit square, 2p+1 Gauss points, sin-sin solution."""
+    box = I.box_mesh(2, n)
+    om = O.Mesh(box, p, 2 * p + 1)
+    xn, xq, xb, _ = om.points()
+    _, _, f = I.mms_sin2d(xq)
+    ub, _, _ = I.mms_sin2d(xb)
+    rng = np.random.default_rng(seed)
+    N = om.size(1)
+    return Case("c1", box, p, 2 * p + 1, O.MODEL_POISSON, 1, [1.0, penalty(p, 1 / n), 0.0],
+                src=f.reshape(om.E, 1, om.nqv), bdata=ub.reshape(om.nbf, 1, om.nqf), bc_kind=(0,),
+                u=rng.uniform(-1, 1, N), v=np.random.default_rng(seed + 1).uniform(-1, 1, N), om=om)
+
+
+def c2_poisson3d(n=4, p=3, seed=1, a0=0.0):
+    """3D Poisson/heat p=3 on a perturbed n^3 hex mesh of the unit cube, exp-sin solution."""
+    box = I.box_mesh(3, n, perturb=0.05, seed=0)
+    om = O.Mesh(box, p)
+    xn, xq, xb, _ = om.points()
+    _, _, f = I.mms_expsin3d(xq)
+    ub, _, _ = I.mms_expsin3d(xb)
+    rng = np.random.default_rng(seed)
+    N = om.size(1)
+    c = Case("c2", box, p, p + 1, O.MODEL_POISSON, 1, [1.0, penalty(p, 1 / n), 0.0],
+             src=f.reshape(om.E, 1, om.nqv), bdata=ub.reshape(om.nbf, 1, om.nqf), bc_kind=(0,),
+             u=rng.uniform(-1, 1, N), v=np.random.default_rng(seed + 1).uniform(-1, 1, N), om=om)
+    if a0:
+        c.a0, c.r1, c.c1 = a0, np.random.default_rng(seed + 2).uniform(-1, 1, N), a0
+    return c
+
+
+def c3_euler2d(n=6, p=4, seed=1, dt=0.5):
+    """2D Euler p=4 on a periodic n x n mesh of [0,20]^2, superposed isentropic vortices, BDF2 wrapper."""
+    L = 20.0
+    box = I.box_mesh(2, n, lo=(0, 0), hi=(L, L), periodic=(True, True))
+    om = O.Mesh(box, p)
+    xn, _, _, _ = om.points()
+    cents = I.vortex_centres(4, L, 5.0, 0)
+    U = I.isentropic_vortices(xn, cents, L=L).transpose(0, 2, 1).reshape(-1)
+    u = _off_kink(U, 4, om.nn, seed)
+    un = U.copy()
+    unm1 = _off_kink(U, 4, om.nn, seed + 5, 0.01)
+    return Case("c3", box, p, p + 1, O.MODEL_EULER, 4, [1.4], bc_kind=(0,),
+                a0=1.5 / dt, r1=un, c1=2.0 / dt, r2=unm1, c2=-0.5 / dt,
+                u=u, v=np.random.default_rng(seed + 1).uniform(-1, 1, U.shape), om=om)
+
+
+def c4_ns3d(n=3, p=3, seed=1, dt=0.1):
+    """3D Navier-Stokes Taylor-Green vortex p=3 on a periodic n^3 mesh of (0,2pi)^3, BDF2 wrapper."""
+    L = 2 * np.pi
+    box = I.box_mesh(3, n, lo=(0, 0, 0), hi=(L, L, L), periodic=(True,) * 3)
+    om = O.Mesh(box, p)
+    xn, _, _, _ = om.points()
+    U = I.taylor_green(xn, mach=0.1).transpose(0, 2, 1).reshape(-1)
+    u = _off_kink(U, 5, om.nn, seed)
+    unm1 = _off_kink(U, 5, om.nn, seed + 5, 0.01)
+    return Case("c4", box, p, p + 1, O.MODEL_NS, 5, [1.4, 1600.0, 0.71, penalty(p, L / n)], bc_kind=(0,),
+                a0=1.5 / dt, r1=U.copy(), c1=2.0 / dt, r2=unm1, c2=-0.5 / dt,
+                u=u, v=np.random.default_rng(seed + 1).uniform(-1, 1, U.shape), om=om)
+
+
+def c5_convdiff2d(n=6, p=3, seed=1):
+    """2D convection-diffusion p=3, log-normal kappa (ell = 0.1), divergence-free b, f = 1, u = 0 on the boundary."""
+    box = I.box_mesh(2, n)
+    om = O.Mesh(box, p)
+    xn, xq, xb, _ = om.points()
+    grf = I.GRF.sample(seed)
+    bvel = I.DivFreeVelocity.sample(seed)
+    aux = np.concatenate([np.exp(grf.log_kappa(xn))[:, None, :], bvel(xn).transpose(0, 2, 1)], axis=1)
+    rng = np.random.default_rng(seed)
+    N = om.size(1)
+    return Case("c5", box, p, p + 1, O.MODEL_CONVDIFF, 1, [1.0, penalty(p, 1 / n)], aux=aux,
+                src=np.ones((om.E, 1, om.nqv)), bdata=np.zeros((om.nbf, 1, om.nqf)), bc_kind=(0,),
+                u=rng.uniform(-1, 1, N), v=np.random.default_rng(seed + 1).uniform(-1, 1, N), om=om)
+
+
+def poisson_mixed_bc(nd=2, n=4, p=2, seed=3):
+    """Poisson with a kappa field and Dirichlet / Neumann / extrapolation tags on different sides."""
+    box = I.box_mesh(nd, n, perturb=0.04, seed=seed)
+    om = O.Mesh(box, p)
+    xn, xq, xb, bf = om.points()
+    rng = np.random.default_rng(seed)
+    kap = 1.0 + 0.5 * np.sin(3 * xn[..., 0]) * np.cos(2 * xn[..., 1])
+    N = om.size(1)
+    # tags are the box sides 0..2nd-1; kinds: Dirichlet on x-, Neumann on x+, extrapolation elsewhere
+    kinds = [0, 1] + [2] * (2 * nd - 2)
+    return Case(f"mixed{nd}d", box, p, p + 1, O.MODEL_POISSON, 1, [1.3, penalty(p, 1 / n), 0.4],
+                aux=kap[:, None, :], src=rng.uniform(-1, 1, (om.E, 1, om.nqv)),
+                bdata=rng.uniform(-1, 1, (om.nbf, 1, om.nqf)), bc_kind=tuple(kinds),
+                a0=0.7, r1=rng.uniform(-1, 1, N), c1=0.3,
+                u=rng.uniform(-1, 1, N), v=np.random.default_rng(seed + 1).uniform(-1, 1, N), om=om)
+
+
+ALL = {"c1": c1_poisson2d, "c2": c2_poisson3d, "c3": c3_euler2d, "c4": c4_ns3d, "c5": c5_convdiff2d,
+       "mixed2d": lambda: poisson_mixed_bc(2), "mixed3d": lambda: poisson_mixed_bc(3, 3, 2)}

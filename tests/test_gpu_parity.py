@@ -1,0 +1,231 @@
+"""Parity of the HIP library with the CPU oracle (needs an MI355X).
+
+Residual G(u), Jacobian-vector products and q(u) are compared element by
+element on seeded random inputs; tolerances are the relative global 2-norm
+bounds of the method's precision modes: 1e-12 (FP64), 1e-5 (FP32).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from tests import cases as CS
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    from paper_2205_07824_amd import ldg
+    assert torch.cuda.is_available()
+    ldg.lib()
+    return ldg
+
+
+def build_gpu(L, c):
+    import torch
+    m = L.Mesh(c.box, c.p, c.nq)
+    md = L.Model(m, c.kind, c.ncu, c.mu, aux=c.aux, src=c.src, bdata=c.bdata, bc_kind=c.bc_kind)
+    dev = lambda a: None if a is None else torch.as_tensor(a, dtype=torch.float64, device="cuda").contiguous()
+    t = None
+    if c.a0 or c.r1 is not None:
+        t = L.Time(a0=c.a0, r1=dev(c.r1), c1=c.c1, r2=dev(c.r2), c2=c.c2)
+    return m, md, t, dev
+
+
+@pytest.mark.parametrize("name", list(CS.ALL))
+def test_mesh_points_match_oracle(L, name):
+    c = CS.ALL[name]()
+    _say("case", name)
+    m = L.Mesh(c.box, c.p, c.nq)
+    xn, xq, xb, bf = m.points()
+    on, oq, ob, obf = c.om.points()
+    assert m.E == c.om.E and m.nbf == c.om.nbf
+    assert np.abs(xn - on).max() < 1e-13
+    assert np.abs(xq - oq).max() < 1e-13
+    if m.nbf:
+        assert (bf == obf).all()
+        assert np.abs(xb - ob).max() < 1e-13
+
+
+@pytest.mark.parametrize("name", list(CS.ALL))
+def test_residual_fp64(L, name):
+    import torch
+    c = CS.ALL[name]()
+    _say("case", name, "E", c.om.E)
+    m, md, t, dev = build_gpu(L, c)
+    om = c.oracle_model()
+    G_ref, q_ref = c.om.residual(om, c.u, want_q=True)
+    u = dev(c.u)
+    q = torch.zeros(c.om.E * c.ncu * c.box.nd * c.om.nn, dtype=torch.float64, device="cuda")
+    G = md.residual(u, time=t, q_out=q if c.kind != 2 else None)
+    torch.cuda.synchronize()
+    assert rel(G.cpu().numpy(), G_ref) < 1e-12
+    if c.kind != 2:
+        assert rel(q.cpu().numpy(), q_ref) < 1e-12
+
+
+@pytest.mark.parametrize("name", list(CS.ALL))
+def test_jvp_fp64(L, name):
+    c = CS.ALL[name]()
+    _say("case", name)
+    m, md, t, dev = build_gpu(L, c)
+    om = c.oracle_model()
+    Jv_ref = c.om.jvp(om, c.u, c.v)
+    Jv = md.jvp(dev(c.u), dev(c.v), time=t)
+    assert rel(Jv.cpu().numpy(), Jv_ref) < 1e-12
+
+
+@pytest.mark.parametrize("name", list(CS.ALL))
+def test_jvp_and_residual_fp32(L, name):
+    c = CS.ALL[name]()
+    _say("case", name)
+    m, md, t, dev = build_gpu(L, c)
+    om = c.oracle_model()
+    Jv_ref = c.om.jvp(om, c.u, c.v)
+    Jv = md.jvp(dev(c.u), dev(c.v), time=t, prec=L.FP32)
+    e_jv = rel(Jv.cpu().numpy(), Jv_ref)
+    G_ref = c.om.residual(om, c.u)
+    G = md.residual(dev(c.u), time=t, prec=L.FP32)
+    e_g = rel(G.cpu().numpy(), G_ref)
+    _say(name, "fp32 rel err: Jv", e_jv, "G", e_g)
+    assert e_jv < 1e-5
+    assert e_g < 1e-5
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c5"])
+def test_jvp_finite_difference_mode(L, name):
+    c = CS.ALL[name]()
+    _say("case", name)
+    m, md, t, dev = build_gpu(L, c)
+    Jv_ref = c.om.jvp(c.oracle_model(), c.u, c.v)
+    Jv = md.jvp(dev(c.u), dev(c.v), time=t, prec=L.JVP_FD)
+    assert rel(Jv.cpu().numpy(), Jv_ref) < 1e-5
+
+
+def test_residual_deterministic(L):
+    import torch
+    c = CS.c2_poisson3d()
+    _say("case determinism c2")
+    m, md, t, dev = build_gpu(L, c)
+    u = dev(c.u)
+    a = md.residual(u).cpu().numpy()
+    for _ in range(3):
+        b = md.residual(u).cpu().numpy()
+        assert (a == b).all()
+    va = md.jvp(u, dev(c.v)).cpu().numpy()
+    vb = md.jvp(u, dev(c.v)).cpu().numpy()
+    assert (va == vb).all()
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c5", "mixed2d"])
+def test_jacobian_blocks_match_oracle(L, name):
+    c = CS.ALL[name]()
+    _say("case", name)
+    m, md, t, dev = build_gpu(L, c)
+    B = md.jacobian_blocks(dev(c.u), time=t).cpu().numpy()
+    Bref = c.om.blocks(c.oracle_model(), c.u)
+    assert rel(B, Bref) < 1e-12
+
+
+def test_jacobian_blocks_per_variable_ns(L):
+    c = CS.c4_ns3d(n=3, p=2)
+    _say("case c4 p=2 per-variable blocks")
+    m, md, t, dev = build_gpu(L, c)
+    B = md.jacobian_blocks(dev(c.u), time=t, per_variable=True).cpu().numpy()
+    Bref = c.om.blocks(c.oracle_model(), c.u, elems=np.arange(6), per_variable=True)
+    assert rel(B[:6], Bref) < 1e-12
+
+
+def test_block_jacobi_apply_inverts_blocks(L):
+    import torch
+    c = CS.c2_poisson3d()
+    _say("case c2 block-Jacobi apply")
+    m, md, t, dev = build_gpu(L, c)
+    Bref = c.om.blocks(c.oracle_model(), c.u)
+    for prec, tol in ((L.FP64, 1e-12), (L.FP32, 1e-5)):
+        pc = L.BlockJacobi(md, u_lin=None, time=t, prec=prec)
+        r = np.random.default_rng(4).uniform(-1, 1, c.om.size(1))
+        z = pc.apply(dev(r)).cpu().numpy().reshape(c.om.E, -1)
+        back = np.einsum("eij,ej->ei", Bref, z).reshape(-1)
+        assert rel(back, r) < tol * 100
+
+
+def test_gmres_block_jacobi_c1_matches_oracle_solution(L):
+    import scipy.sparse.linalg as spla
+    c = CS.c1_poisson2d()
+    _say("case c1 gmres")
+    m, md, t, dev = build_gpu(L, c)
+    om = c.oracle_model()
+    N = c.om.size(1)
+    J = c.om.jacobian(om, np.zeros(N))
+    b = -c.om.residual(om, np.zeros(N))
+    x_ref = spla.spsolve(J.tocsc(), b)
+    # GPU: the same linear system J x = -G(0)
+    import torch
+    zero = torch.zeros(N, dtype=torch.float64, device="cuda")
+    bg = -md.residual(zero)
+    pc = L.BlockJacobi(md)
+    x, st, status = L.gmres(md, bg, pc=pc, restart=30, rtol=1e-10, maxit=500)
+    _say("gmres stats", st)
+    assert status == L.LDG_OK
+    assert rel(x.cpu().numpy(), x_ref) < 1e-8
+    assert st["res_true"] <= 1e-10 * st["res0"] * 1.01
+
+
+def test_gmres_without_preconditioner_and_cgs2_orthogonality(L):
+    c = CS.c5_convdiff2d()
+    _say("case c5 gmres no pc")
+    m, md, t, dev = build_gpu(L, c)
+    import torch
+    N = c.om.size(1)
+    b = dev(np.random.default_rng(9).uniform(-1, 1, N))
+    x, st, status = L.gmres(md, b, restart=40, rtol=1e-9, maxit=4000)
+    assert status == L.LDG_OK
+    r = b - md.jvp(None, x)
+    assert L.norm(r) <= 1.01e-9 * L.norm(b)
+
+
+def test_newton_euler_bdf2_step_matches_oracle(L):
+    import scipy.sparse.linalg as spla
+    import torch
+    c = CS.c3_euler2d(n=4, p=3)
+    _say("case c3 newton")
+    m, md, t, dev = build_gpu(L, c)
+    om = c.oracle_model()
+    G = lambda u: c.om.residual(om, u)
+    solve = lambda u, rhs: spla.spsolve(c.om.jacobian(om, u).tocsc(), rhs)
+    import oracle as O
+    u_ref, info = O.newton(G, solve, c.r1.copy(), rtol=1e-13, maxit=10)
+    u = dev(c.r1.copy())
+    pc = L.BlockJacobi(md, u_lin=u, time=t)
+    u, st, status = L.newton(md, u, time=t, rtol=1e-12, eta=1e-10, maxit=12, bj_refresh=True, pc=pc, restart=50)
+    _say("newton stats", st)
+    assert status == L.LDG_OK
+    assert rel(u.cpu().numpy(), u_ref) < 1e-8
+
+
+def test_gmres_failure_paths(L):
+    c = CS.c1_poisson2d()
+    _say("case c1 failure paths")
+    m, md, t, dev = build_gpu(L, c)
+    import torch
+    N = c.om.size(1)
+    b = dev(np.random.default_rng(2).uniform(-1, 1, N))
+    # maxit too small -> ENOCONV, last iterate kept
+    x, st, status = L.gmres(md, b, restart=5, rtol=1e-12, maxit=3, check=False)
+    assert status == L.LDG_ENOCONV and st["iters"] == 3
+    # NaN injected into the preconditioner output -> EBREAKDOWN
+    pc = L.BlockJacobi(md)
+    x, st, status = L.gmres(md, b, pc=pc, restart=10, rtol=1e-12, maxit=50, inject_fault=1, check=False)
+    assert status == L.LDG_EBREAKDOWN
