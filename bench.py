@@ -65,6 +65,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-jvp-only", action="store_true",
                     help="only the timed JVP steps (for counter collection)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 512 MiB buffer 10 times (scales the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
@@ -75,6 +77,14 @@ def main():
     from paper_2205_07824_amd import ldg
 
     assert torch.cuda.is_available()
+    if args.copy_calibration:
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        c = torch.empty_like(a)
+        for _ in range(10):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_dispatch": a.numel() * 8, "copy_bytes_written_per_dispatch": a.numel() * 8}))
+        return
     box, m, md = build_workload(ldg, I, n=args.n)
     N = md.N
     log(f"workload: E={m.E} nn={m.nn} N={N} colours={m.ncolors}")
@@ -125,12 +135,15 @@ def main():
     extra = {}
     e32 = event_time(lambda: md.jvp(None, v, out=Jv, prec=ldg.FP32), 50)
     extra["jvp_fp32_gdofs"] = round(N / e32 / 1e9, 3)
-    try:
-        eb = event_time(lambda: md.jvp(None, v, out=Jv, prec=ldg.BF16_MFMA), 50)
-        extra["jvp_bf16_mfma_gdofs"] = round(N / eb / 1e9, 3)
-    except ldg.LDGError as ex:
-        extra["jvp_bf16_mfma_gdofs"] = None
-        log("bf16 mfma jvp:", ex)
+    Jref = md.jvp(None, v).clone()
+    for nm, pr in (("bf16_mfma", ldg.BF16_MFMA), ("fp16_mfma", ldg.FP16_MFMA), ("fp32", ldg.FP32)):
+        try:
+            eb = event_time(lambda: md.jvp(None, v, out=Jv, prec=pr), 50)
+            extra[f"jvp_{nm}_gdofs"] = round(N / eb / 1e9, 3)
+            extra[f"jvp_{nm}_rel_err_vs_fp64"] = float(((Jv - Jref).norm() / Jref.norm()).item())
+        except ldg.LDGError as ex:
+            extra[f"jvp_{nm}_gdofs"] = None
+            log(nm, "jvp:", ex)
     G = md.empty()
     er = event_time(lambda: md.residual(u, out=G), 50)
     extra["residual_fp64_gdofs"] = round(N / er / 1e9, 3)
@@ -157,7 +170,9 @@ def main():
             forms[name] = {"time_to_1e-8_s": round(t_all, 4), "bj_build_s": round(t_bj, 4),
                            "converged": status == ldg.LDG_OK, "newton_iters": st["iters"],
                            "gmres_iters": st["gmres_iters"],
-                           "res_ratio": st["res_final"] / max(st["res0"], 1e-300)}
+                           "res_ratio": st["res_final"] / max(st["res0"], 1e-300),
+                           "t_jvp_s": round(st["t_jvp"], 4), "t_pc_s": round(st["t_pc"], 4),
+                           "t_orth_s": round(st["t_orth"], 4)}
             log(name, forms[name])
             del pc
         out["newton_gmres"] = forms

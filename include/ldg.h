@@ -189,6 +189,41 @@ ldg_status ldg_precond_block_jacobi(ldg_model model, const ldg_time* t, const do
 ldg_status ldg_precond_apply(ldg_precond pc, const double* r, double* z, void* stream);
 ldg_status ldg_precond_destroy(ldg_precond pc);
 
+/* ------------------------------------------------- learned preconditioner - */
+/* Element-patch MLP (3 layers, ReLU): y = W3 relu(W2 relu(W1 x + b1) + b2) + b3,
+ * FP32 master weights, GEMMs on MFMA with bf16 operands and fp32 accumulation
+ * (use_bf16 = 1) or in FP32 (use_bf16 = 0).  The network is the learned right
+ * preconditioner of flexible GMRES (with block-Jacobi as fallback); it is
+ * trained on (residual, correction) pairs the solver generates. */
+ldg_status ldg_mlp_create(int in_dim, int width, int out_dim, int nlayers, int use_bf16, ldg_mlp* out);
+ldg_status ldg_mlp_destroy(ldg_mlp net);
+/* HOST float [nparams], packed W1 b1 W2 b2 W3 b3, W row-major [out][in];
+ * nparams = width*in + width + width*width + width + out*width + out.
+ * set_params also resets the Adam state. */
+ldg_status ldg_mlp_set_params(ldg_mlp net, const float* host_params);
+ldg_status ldg_mlp_get_params(ldg_mlp net, float* host_params, float* host_grads);
+/* Y[B][out] = net(X[B][in]); DEVICE float arrays. */
+ldg_status ldg_mlp_forward(ldg_mlp net, const float* X, int64_t B, float* Y, void* stream);
+/* One step on the mean squared error (1/(B out)) sum (net(X) - Y)^2: forward,
+ * backward into the gradient buffer, then Adam (beta 0.9/0.999, eps 1e-8) with
+ * learning rate lr when lr > 0.  The loss goes to HOST *loss_host (synchronizes). */
+ldg_status ldg_mlp_train_step(ldg_mlp net, const float* X, const float* Y, int64_t B, float lr, float* loss_host,
+                              void* stream);
+/* Patch features of the listed elements (elem_idx DEVICE int32 [B], or NULL =
+ * all elements in order) of a 2D scalar model: the element and its four face
+ * neighbours (-x, +x, -y, +y; zeros outside the domain) give
+ * X[B][20 nn] = [r/s (5 nn) | log kappa (5 nn) | b_x, b_y per patch element (10 nn)],
+ * s = ||r on the patch||_2 + 1e-300 (S[B], DEVICE double, optional), and when
+ * e_target is given Y[B][nn] = e on the element / s. */
+ldg_status ldg_mlp_gather_patches(ldg_model model, const double* r, const double* e_target, const int32_t* elem_idx,
+                                  int64_t B, float* X, float* Y, double* S, void* stream);
+/* Learned right preconditioner z = B^-1 r + s N(patches(r)) (composite = 1, needs
+ * the block-Jacobi fallback_bj) or z = s N(patches(r)) (composite = 0).
+ * Inside ldg_gmres_solve it is replaced by fallback_bj for the rest of the
+ * solve when its output is non-finite or the residual drops by less than 1%
+ * over 10 iterations (stats.fell_back = 1).  The handles must outlive it. */
+ldg_status ldg_precond_mlp(ldg_model model, ldg_mlp net, ldg_precond fallback_bj, int composite, ldg_precond* out);
+
 /* ---------------------------------------------------------------- solvers - */
 typedef struct {
   int restart;            /* Krylov basis size m                                  */
@@ -228,6 +263,7 @@ typedef struct {
   int iters, gmres_iters;
   double res0, res_final, seconds;
   int lin_status;
+  double t_jvp, t_pc, t_orth;   /* seconds per phase, summed over the inner solves */
 } ldg_newton_stats;
 
 /* Newton's method on G(u) = 0 (Section 3.3), FP64 residual, u updated in place. */

@@ -429,6 +429,7 @@ ldg_status ldg_model_create(ldg_mesh m, const ldg_model_desc* d, void* stream, l
 ldg_status ldg_model_destroy(ldg_model md) {
   LDG_ENTER();
   if (!md) return LDG_OK;
+  mfma_release(*md);
   hipFree(md->d_q); hipFree(md->d_q32); hipFree(md->d_qres); hipFree(md->d_dq); hipFree(md->d_tmp); hipFree(md->d_tmp2); hipFree(md->d_red);
   hipFree(md->d_qg); hipFree(md->d_dterm);
   delete md;

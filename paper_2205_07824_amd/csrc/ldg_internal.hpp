@@ -252,6 +252,7 @@ ldg_status op_jvp_nonlinear(const Model& md, const TimeDev& t, const double* u, 
                             const void* dq, double* out, bool fp32, hipStream_t s);
 ldg_status op_data_terms(Model& md, hipStream_t s);
 ldg_status op_mfma_jvp(const Model& md, const TimeDev& t, const double* v, double* out, bool fp16, hipStream_t s);
+void mfma_release(const Model& md);
 
 // shared host helpers (ldg_api.hip)
 TimeDev make_time(const ldg_time* t, bool with_rhs);

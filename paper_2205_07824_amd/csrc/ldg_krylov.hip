@@ -161,6 +161,46 @@ __global__ void __launch_bounds__(VB) k_update(int64_t n, int nv, const double* 
   }
 }
 
+// Fused: w -= sum_i h_i V_i, then the block partials of V_i . w (second CGS pass)
+// in the same sweep over V (the second read of V[i][t] hits L2).
+__global__ void __launch_bounds__(VB) k_update_multidot(int64_t n, int nv, const double* __restrict__ V, int64_t ldv,
+                                                        const double* __restrict__ h, double* __restrict__ w,
+                                                        double* __restrict__ part) {
+  __shared__ double sh[16];
+  __shared__ double hs[MAXM + 1];
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) hs[i] = h[i];
+  __syncthreads();
+  const int nblk = gridDim.x;
+  const int64_t chunk = ((n + nblk - 1) / nblk + VB - 1) / VB * VB;
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < n ? lo + chunk : n;
+  for (int i0 = 0; i0 < nv; i0 += 8) {
+    // (the update is applied in the first group sweep only)
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int ni = nv - i0 < 8 ? nv - i0 : 8;
+    for (int64_t t = lo + threadIdx.x; t < hi; t += VB) {
+      double acc;
+      if (i0 == 0) {
+        acc = w[t];
+        for (int i = 0; i < nv; ++i) acc -= hs[i] * V[(int64_t)i * ldv + t];
+        w[t] = acc;
+      } else {
+        acc = w[t];
+      }
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+        if (r < ni) s[r] += V[(int64_t)(i0 + r) * ldv + t] * acc;
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      if (r < ni) {
+        double tot = block_sum(s[r], sh);
+        if (threadIdx.x == 0) part[(int64_t)(i0 + r) * nblk + blockIdx.x] = tot;
+      }
+    }
+  }
+}
+
 // x += sum_i y_i Z_i
 __global__ void k_combine(int64_t n, int k, const double* __restrict__ Z, int64_t ldz, const double* __restrict__ y,
                           double* __restrict__ x) {
@@ -263,6 +303,9 @@ struct ldg_precond_s;
 namespace ldg {
 ldg_status precond_apply_impl(ldg_precond_s* pc, const double* r, double* z, hipStream_t s);
 ldg_status precond_rebuild(ldg_precond_s* pc, const ldg_time* t, const double* u_lin, hipStream_t s);
+int precond_kind(const ldg_precond_s* pc);
+ldg_precond_s* precond_fallback(ldg_precond_s* pc);
+ldg_status precond_count_nonfinite(ldg_precond_s* pc, const double* z, int64_t n, int* host_cnt, hipStream_t s);
 }
 
 namespace {
@@ -358,6 +401,12 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
   }
   const ldg_precision jp = o.jvp_prec;
   const bool use_pc = o.pc != nullptr;
+  // learned preconditioner: watched for non-finite output and stagnation
+  // (residual reduced by less than 1% over 10 iterations); then block-Jacobi
+  ldg_precond_s* pc_cur = o.pc;
+  const bool watch = use_pc && precond_kind(o.pc) == 1;
+  double watch_ref = -1.0;
+  int watch_it = 0;
   double r0 = 0.0;
   st = true_residual(md, t, u_lin, b, x, jp, ws, &r0, s);
   if (st != LDG_OK) return st;
@@ -380,9 +429,22 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
       double* zj = use_pc ? ws.Z + (int64_t)j * n : vj;
       hipEventRecord(ws.ev[0], s);
       if (use_pc) {
-        st = precond_apply_impl(o.pc, vj, zj, s);
+        st = precond_apply_impl(pc_cur, vj, zj, s);
         if (st != LDG_OK) return st;
         if (o.inject_fault == 1) hipLaunchKernelGGL(k_poison, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, zj);
+        if (watch && pc_cur == o.pc) {
+          int bad = 0;
+          st = precond_count_nonfinite(pc_cur, zj, n, &bad, s);
+          if (st != LDG_OK) return st;
+          if (bad) {
+            ldg_precond_s* fb = precond_fallback(o.pc);
+            if (!fb) { result = LDG_EBREAKDOWN; break; }
+            pc_cur = fb;
+            S.fell_back = 1;
+            st = precond_apply_impl(pc_cur, vj, zj, s);
+            if (st != LDG_OK) return st;
+          }
+        }
       }
       hipEventRecord(ws.ev[1], s);
       st = jvp_impl(md, t, u_lin, zj, ws.w, jp, true, s);
@@ -394,8 +456,7 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
       // CGS2: two passes of (h = V^T w ; w -= V h)
       hipLaunchKernelGGL(k_multidot, dim3(nb), dim3(VB), 0, s, n, j + 1, ws.V, n, ws.w, ws.part);
       hipLaunchKernelGGL(k_reduce_rows, dim3(j + 1), dim3(VB), 0, s, j + 1, nb, ws.part, ws.h1);
-      hipLaunchKernelGGL(k_update, dim3(gV), dim3(VB), 0, s, n, j + 1, ws.V, n, ws.h1, ws.w, (double*)nullptr);
-      hipLaunchKernelGGL(k_multidot, dim3(nb), dim3(VB), 0, s, n, j + 1, ws.V, n, ws.w, ws.part);
+      hipLaunchKernelGGL(k_update_multidot, dim3(nb), dim3(VB), 0, s, n, j + 1, ws.V, n, ws.h1, ws.w, ws.part);
       hipLaunchKernelGGL(k_reduce_rows, dim3(j + 1), dim3(VB), 0, s, j + 1, nb, ws.part, ws.h2);
       hipLaunchKernelGGL(k_update, dim3(gV), dim3(VB), 0, s, n, j + 1, ws.V, n, ws.h2, ws.w, ws.npart);
       hipLaunchKernelGGL(k_givens, dim3(1), dim3(VB), 0, s, ws.st, j, gV, ws.h1, ws.h2, ws.npart);
@@ -416,6 +477,14 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
       std::memcpy(&brk, ws.pinned + 1, sizeof(int));
       S.res_est = res;
       if (!std::isfinite(res)) { stop = true; result = LDG_EBREAKDOWN; break; }
+      if (watch && pc_cur == o.pc) {
+        if (watch_ref < 0) { watch_ref = res; watch_it = 0; }
+        if (++watch_it >= 10) {
+          if (res > 0.99 * watch_ref && precond_fallback(o.pc)) { pc_cur = precond_fallback(o.pc); S.fell_back = 1; }
+          watch_ref = res;
+          watch_it = 0;
+        }
+      }
       if (res <= tol || brk) { stop = true; break; }
     }
     // x += Z y
@@ -493,6 +562,9 @@ ldg_status ldg_newton_solve(ldg_model md, const ldg_time* t, double* u, const ld
     ldg_gmres_stats gs{};
     st = gmres_impl(*md, t, u, G, du, lin, &gs, s);
     S.gmres_iters += gs.iters;
+    S.t_jvp += gs.t_jvp;
+    S.t_pc += gs.t_pc;
+    S.t_orth += gs.t_orth;
     S.lin_status = st;
     if (st != LDG_OK && st != LDG_ENOCONV) { result = st; break; }
     st = vec_axpby(n, 1.0, du, 1.0, u, s);

@@ -13,6 +13,15 @@
 // (read directly from the neighbour's nodal lines), and lifts it into its own
 // nodes.  No element writes another element's output, so there are no atomics,
 // no face colouring passes, and the result is bitwise deterministic.
+//
+// Face work is organised by reference direction (a compile-time constant), so
+// the line strides, the tangential directions and the normal (cross product of
+// the two tangential Jacobian columns) need no per-lane selects.  The 1D tables
+// live in LDS.  Work-groups are mapped to elements so that each of the eight
+// XCDs (which receive work-groups round-robin) walks a contiguous range of
+// elements and finds most neighbours in its own L2.
+#include <type_traits>
+
 #include "ldg_physics.hpp"
 
 namespace ldg {
@@ -30,30 +39,86 @@ constexpr int pick_epb() {
   return e;
 }
 
-// node multi-index of flat node i (first direction fastest)
+template <int P1>
+struct TabLayout {
+  static constexpr int X = 0, W = P1, DM = 2 * P1, LF = 2 * P1 + P1 * P1, SIZE = 4 * P1 + P1 * P1;
+};
+
+// copy the 1D tables into LDS: x, w, D (row-major D[a][m]), lf[0], lf[1]
+template <int P1, class R, class TAB>
+__device__ inline void stage_tables(const TAB& tab, R* st) {
+  using L = TabLayout<P1>;
+  for (int t = threadIdx.x; t < L::SIZE; t += blockDim.x) {
+    R v;
+    if (t < L::W) v = tab.x[t];
+    else if (t < L::DM) v = tab.w[t - L::W];
+    else if (t < L::LF) { const int r = (t - L::DM) / P1, c = (t - L::DM) % P1; v = tab.D[r][c]; }
+    else { const int r = (t - L::LF) / P1, c = (t - L::LF) % P1; v = tab.lf[r][c]; }
+    st[t] = v;
+  }
+}
+
+// work-group -> element block, XCD-aware (work-group b runs on XCD b % 8)
+__device__ inline int64_t xcd_block(int64_t b, int64_t nblk) {
+  const int64_t q = nblk >> 3;
+  if (b < (q << 3)) return (b & 7) * q + (b >> 3);
+  return b;
+}
+
+__host__ __device__ constexpr int stride_c(int P1, int k) { return k == 0 ? 1 : (k == 1 ? P1 : P1 * P1); }
+
+// tangential directions of a face normal to DIR
+template <int D, int DIR> struct Tang {
+  static constexpr int T0 = (DIR == 0) ? 1 : 0;
+  static constexpr int T1 = (D == 3) ? ((DIR == 2) ? 1 : 2) : -1;
+};
+
+// column j of the Jacobian of the multilinear map at xi
+template <int D, int J, class R>
+__device__ inline void jac_col(const double* __restrict__ c, const R* xi, R* col) {
+#pragma unroll
+  for (int i = 0; i < D; ++i) col[i] = R(0);
+#pragma unroll
+  for (int m = 0; m < (1 << D); ++m) {
+    if (!((m >> J) & 1)) continue;
+    R t = R(1);
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+      if (k != J && ((m >> k) & 1)) t *= xi[k];
+#pragma unroll
+    for (int i = 0; i < D; ++i) col[i] += R(c[m * D + i]) * t;
+  }
+}
+
+// scaled outward normal N = ds n at a point of face (DIR, side): (2 side - 1) * row DIR of adj(J)
+template <int D, int DIR, class R>
+__device__ inline void face_normal(const double* __restrict__ c, const R* xi, int side, R* N) {
+  const R s = side ? R(1) : R(-1);
+  if constexpr (D == 2) {
+    constexpr int T = 1 - DIR;
+    R col[2];
+    jac_col<2, T, R>(c, xi, col);
+    if constexpr (DIR == 0) { N[0] = s * col[1]; N[1] = -s * col[0]; }
+    else { N[0] = -s * col[1]; N[1] = s * col[0]; }
+  } else {
+    // row DIR of adj = col(DIR+1) x col(DIR+2) (cyclic)
+    constexpr int A = (DIR + 1) % 3, B = (DIR + 2) % 3;
+    R a[3], b[3];
+    jac_col<3, A, R>(c, xi, a);
+    jac_col<3, B, R>(c, xi, b);
+    N[0] = s * (a[1] * b[2] - a[2] * b[1]);
+    N[1] = s * (a[2] * b[0] - a[0] * b[2]);
+    N[2] = s * (a[0] * b[1] - a[1] * b[0]);
+  }
+}
+
 template <int D, int P1>
 __device__ inline void node_index(int i, int* a) {
 #pragma unroll
   for (int k = 0; k < D; ++k) { a[k] = i % P1; i /= P1; }
 }
 
-// tangential indices of face point f on a face normal to dir; returns the
-// flat node offset of the face point's line (the dir index set to 0)
-template <int D, int P1>
-__device__ inline int face_line(int dir, int f, int* tix) {
-  int off = 0, t = 0, ff = f;
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
-    if (k == dir) continue;
-    tix[t] = ff % P1;
-    ff /= P1;
-    off += tix[t] * ipow(P1, k);
-    ++t;
-  }
-  return off;
-}
-
-// tangential flat index of node a[] with respect to direction dir
+// tangential flat index of node a[] on a face normal to dir (lower tangential direction fastest)
 template <int D, int P1>
 __device__ inline int face_index_of_node(const int* a, int dir) {
   int f = 0, s = 1;
@@ -66,7 +131,24 @@ __device__ inline int face_index_of_node(const int* a, int dir) {
   return f;
 }
 
-__device__ inline int stride_of(int P1, int k) { return k == 0 ? 1 : (k == 1 ? P1 : P1 * P1); }
+template <int KIND, int D, int P1, class R>
+struct GradCfg {
+  static constexpr int NCU = Phys<KIND, D>::NCU, NN = ipow(P1, D), NFP = ipow(P1, D - 1), NF = 2 * D, NV = 1 << D;
+  static constexpr int BYTES = sizeof(R) * (NCU * NN + NF * NCU * D * NFP) + 8 * NV * D;
+  static constexpr int EPB = pick_epb<NN, BYTES>();
+};
+
+template <int KIND, int D, int P1, class R, int MODE>
+struct ResidCfg {
+  using PH = Phys<KIND, D>;
+  using V = typename std::conditional<MODE == 2, Dl<R>, R>::type;
+  static constexpr int NCU = PH::NCU, NN = ipow(P1, D), NFP = ipow(P1, D - 1), NF = 2 * D, NV = 1 << D;
+  static constexpr bool HASQ = PH::HASQ;
+  static constexpr int NQ = HASQ ? NCU * D : 1;
+  static constexpr int BYTES = sizeof(V) * (NCU * NN + (HASQ ? NCU * D * NN : 0)) +
+                               sizeof(R) * (NCU * D * NN + NF * NCU * NFP) + 8 * NV * D;
+  static constexpr int EPB = pick_epb<NN, BYTES>();
+};
 
 // ============================================================================
 // Local gradient: q = M^-1 [ (u, div r) - <uhat n, r> ], evaluated in the
@@ -75,51 +157,66 @@ __device__ inline int stride_of(int P1, int k) { return k == 0 ? 1 : (k == 1 ? P
 // DATA = true: Dirichlet uhat = g from bdata (nonlinear models); false:
 // homogeneous (tangents, and linear models whose data enter through qoff).
 // ============================================================================
-template <int KIND, int D, int P1, class R, bool DATA>
+template <int KIND, int D, int P1, class R, bool DATA, bool EXT = false>
 __global__ void __launch_bounds__(256)
 k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const double* __restrict__ u, R* __restrict__ q,
-       const double* __restrict__ qoff) {
-  using PH = Phys<KIND, D>;
-  constexpr int NCU = PH::NCU, NN = ipow(P1, D), NFP = ipow(P1, D - 1), NF = 2 * D, NV = 1 << D;
-  constexpr int BYTES = sizeof(R) * (NCU * NN + NF * NCU * D * NFP) + 8 * NV * D;
-  constexpr int EPB = pick_epb<NN, BYTES>();
+       const double* __restrict__ qoff, const float* __restrict__ dux = nullptr) {
+  using C = GradCfg<KIND, D, P1, R>;
+  constexpr int NCU = C::NCU, NN = C::NN, NFP = C::NFP, NF = C::NF, NV = C::NV, EPB = C::EPB;
+  using L = TabLayout<P1>;
+  __shared__ R s_tab[L::SIZE];
   __shared__ R s_u[EPB][NCU][NN];
   __shared__ R s_L[EPB][NF][NCU][D][NFP];
   __shared__ double s_c[EPB][NV * D];
 
+  const int64_t eb = xcd_block(blockIdx.x, gridDim.x);
   const int el = threadIdx.x / NN, i = threadIdx.x % NN;
-  const int64_t K = (int64_t)blockIdx.x * EPB + el;
+  const int64_t K = eb * EPB + el;
   const bool active = K < m.E;
+  stage_tables<P1, R>(tab, s_tab);
   if (active) {
 #pragma unroll
     for (int c = 0; c < NCU; ++c) s_u[el][c][i] = R(u[(K * NCU + c) * NN + i]);
     for (int t = i; t < NV * D; t += NN) s_c[el][t] = m.coef[K * NV * D + t];
   }
   __syncthreads();
+  const R* tx = s_tab + L::X;
+  const R* tw = s_tab + L::W;
+  const R* tD = s_tab + L::DM;
+  const R* tl = s_tab + L::LF;
 
-  if (active) {
-    for (int fp = i; fp < NF * NFP; fp += NN) {
-      const int F = fp / NFP, f = fp % NFP, dir = F >> 1, side = F & 1;
-      int tix[2] = {0, 0};
-      const int base = face_line<D, P1>(dir, f, tix);
-      const int sd = stride_of(P1, dir);
+  // ---- faces, one reference direction at a time
+  auto face_dir = [&](auto dirc) {
+    constexpr int DIR = decltype(dirc)::value;
+    constexpr int T0 = Tang<D, DIR>::T0, T1 = Tang<D, DIR>::T1;
+    constexpr int SD = stride_c(P1, DIR);
+    for (int it = threadIdx.x; it < EPB * 2 * NFP; it += blockDim.x) {
+      const int e = it / (2 * NFP), side = (it / NFP) & 1, f = it % NFP;
+      const int64_t Ke = eb * EPB + e;
+      if (Ke >= m.E) continue;
+      const int t0 = f % P1, t1 = (D == 3) ? f / P1 : 0;
+      int base = t0 * stride_c(P1, T0);
+      if constexpr (D == 3) base += t1 * stride_c(P1, T1);
+      const R* l_own = tl + side * P1;
+      const R* l_nbr = tl + (1 - side) * P1;
       R um[NCU], uh[NCU];
 #pragma unroll
       for (int c = 0; c < NCU; ++c) {
-        R s = R(0);
+        R sacc = R(0);
 #pragma unroll
-        for (int mm = 0; mm < P1; ++mm) s += tab.lf[side][mm] * s_u[el][c][base + mm * sd];
-        um[c] = s;
+        for (int mm = 0; mm < P1; ++mm) sacc += l_own[mm] * s_u[e][c][base + mm * SD];
+        um[c] = sacc;
       }
-      const int nb = m.nbr[K * NF + F];
+      const int F = 2 * DIR + side;
+      const int nb = m.nbr[Ke * NF + F];
       if (nb >= 0) {
 #pragma unroll
         for (int c = 0; c < NCU; ++c) {
-          R s = R(0);
           const double* un = u + ((int64_t)nb * NCU + c) * NN + base;
+          R sacc = R(0);
 #pragma unroll
-          for (int mm = 0; mm < P1; ++mm) s += tab.lf[1 - side][mm] * R(un[mm * sd]);
-          uh[c] = R(0.5) * (um[c] + s);
+          for (int mm = 0; mm < P1; ++mm) sacc += l_nbr[mm] * R(un[mm * SD]);
+          uh[c] = R(0.5) * (um[c] + sacc);
         }
       } else {
         const int b = -(nb + 1);
@@ -135,17 +232,20 @@ k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const double* __restric
         }
       }
       R xi[D];
-#pragma unroll
-      for (int k = 0, t = 0; k < D; ++k) xi[k] = (k == dir) ? (side ? R(1) : R(-1)) : tab.x[tix[t++]];
-      R J[D][D], N[D];
-      jacobian_at<D, R>(s_c[el], xi, J);
-      scaled_normal<D, R>(J, dir, side, N);
+      xi[DIR] = side ? R(1) : R(-1);
+      xi[T0] = tx[t0];
+      if constexpr (D == 3) xi[T1] = tx[t1];
+      R N[D];
+      face_normal<D, DIR, R>(s_c[e], xi, side, N);
 #pragma unroll
       for (int c = 0; c < NCU; ++c)
 #pragma unroll
-        for (int k = 0; k < D; ++k) s_L[el][F][c][k][f] = (um[c] - uh[c]) * N[k];
+        for (int k = 0; k < D; ++k) s_L[e][F][c][k][f] = (um[c] - uh[c]) * N[k];
     }
-  }
+  };
+  face_dir(std::integral_constant<int, 0>{});
+  face_dir(std::integral_constant<int, 1>{});
+  if constexpr (D == 3) face_dir(std::integral_constant<int, 2>{});
   __syncthreads();
   if (!active) return;
 
@@ -153,22 +253,34 @@ k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const double* __restric
   node_index<D, P1>(i, a);
   R xi[D];
 #pragma unroll
-  for (int k = 0; k < D; ++k) xi[k] = tab.x[a[k]];
+  for (int k = 0; k < D; ++k) xi[k] = tx[a[k]];
   R J[D][D], adj[D][D];
   jacobian_at<D, R>(s_c[el], xi, J);
   const R det = adjugate<D, R>(J, adj);
   const R idet = R(1) / det;
+  R liftw[NF];      // l_{a_dir}(side) / (w_{a_dir} det)
+  int fidx[D];
+#pragma unroll
+  for (int F = 0; F < NF; ++F) liftw[F] = tl[(F & 1) * P1 + a[F >> 1]] / tw[a[F >> 1]] * idet;
+#pragma unroll
+  for (int dd = 0; dd < D; ++dd) fidx[dd] = face_index_of_node<D, P1>(a, dd);
 #pragma unroll
   for (int c = 0; c < NCU; ++c) {
     R du[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      const int sj = stride_of(P1, j);
-      const int b0 = i - a[j] * sj;
-      R s = R(0);
+      if constexpr (EXT) {
+        // reference gradient computed outside (MFMA GEMM)
+        du[j] = R(dux[((K * NCU + c) * D + j) * NN + i]);
+      } else {
+        const int sj = stride_c(P1, j);
+        const int b0 = i - a[j] * sj;
+        const R* Drow = tD + a[j] * P1;
+        R sacc = R(0);
 #pragma unroll
-      for (int mm = 0; mm < P1; ++mm) s += tab.D[a[j]][mm] * s_u[el][c][b0 + mm * sj];
-      du[j] = s;
+        for (int mm = 0; mm < P1; ++mm) sacc += Drow[mm] * s_u[el][c][b0 + mm * sj];
+        du[j] = sacc;
+      }
     }
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -177,10 +289,7 @@ k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const double* __restric
       for (int j = 0; j < D; ++j) g += adj[j][k] * du[j];
       R qv = -g * idet;
 #pragma unroll
-      for (int F = 0; F < NF; ++F) {
-        const int dir = F >> 1, side = F & 1;
-        qv += tab.lf[side][a[dir]] / (tab.w[a[dir]] * det) * s_L[el][F][c][k][face_index_of_node<D, P1>(a, dir)];
-      }
+      for (int F = 0; F < NF; ++F) qv += liftw[F] * s_L[el][F][c][k][fidx[F >> 1]];
       const int64_t o = ((K * NCU + c) * D + k) * NN + i;
       if (qoff) qv += R(qoff[o]);
       q[o] = qv;
@@ -197,31 +306,30 @@ k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const double* __restric
 //   MODE 2: tangent of the nonlinear residual at (u, q) in direction (v, dq),
 //           dual-number arithmetic; + a0 M v
 // ============================================================================
-template <int KIND, int D, int P1, class R, int MODE>
+template <int KIND, int D, int P1, class R, int MODE, bool EXT = false>
 __global__ void __launch_bounds__(256)
 k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const double* __restrict__ u,
         const R* __restrict__ q, const double* __restrict__ v, const R* __restrict__ dq,
-        const double* __restrict__ dterm, double* __restrict__ out) {
-  using PH = Phys<KIND, D>;
-  using V = typename std::conditional<MODE == 2, Dl<R>, R>::type;
+        const double* __restrict__ dterm, double* __restrict__ out, float* __restrict__ Fout = nullptr) {
+  using C = ResidCfg<KIND, D, P1, R, MODE>;
+  using V = typename C::V;
   using T = VT<V>;
-  constexpr int NCU = PH::NCU, NN = ipow(P1, D), NFP = ipow(P1, D - 1), NF = 2 * D, NV = 1 << D;
-  constexpr bool HASQ = PH::HASQ;
-  constexpr int NQ = HASQ ? NCU * D : 1;
-  constexpr int NA = PH::NAUX > 0 ? PH::NAUX : 1;
-  constexpr int BYTES = sizeof(V) * (NCU * NN + (HASQ ? NCU * D * NN : 0)) +
-                        sizeof(R) * (NCU * D * NN + NF * NCU * NFP) + 8 * NV * D;
-  constexpr int EPB = pick_epb<NN, BYTES>();
+  constexpr int NCU = C::NCU, NN = C::NN, NFP = C::NFP, NF = C::NF, NV = C::NV, EPB = C::EPB, NQ = C::NQ;
+  constexpr bool HASQ = C::HASQ;
+  constexpr int NA = Phys<KIND, D>::NAUX > 0 ? Phys<KIND, D>::NAUX : 1;
+  using L = TabLayout<P1>;
+  __shared__ R s_tab[L::SIZE];
   __shared__ V s_u[EPB][NCU][NN];
   __shared__ V s_q[EPB][NQ][HASQ ? NN : 1];
   __shared__ R s_F[EPB][NCU][D][NN];
   __shared__ R s_Fh[EPB][NF][NCU][NFP];
   __shared__ double s_c[EPB][NV * D];
 
+  const int64_t eb = xcd_block(blockIdx.x, gridDim.x);
   const int el = threadIdx.x / NN, i = threadIdx.x % NN;
-  const int64_t K = (int64_t)blockIdx.x * EPB + el;
+  const int64_t K = eb * EPB + el;
   const bool active = K < m.E;
-
+  stage_tables<P1, R>(tab, s_tab);
   // state loads: MODE 0 reads the input vector from u (the vector the linear
   // operator is applied to); MODE 2 pairs (u, v) and (q, dq).
   if (active) {
@@ -242,133 +350,85 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const doub
     for (int t = i; t < NV * D; t += NN) s_c[el][t] = m.coef[K * NV * D + t];
   }
   __syncthreads();
+  const R* tx = s_tab + L::X;
+  const R* tw = s_tab + L::W;
+  const R* tD = s_tab + L::DM;
+  const R* tl = s_tab + L::LF;
 
-  R r[NCU];
-  int a[D];
-  node_index<D, P1>(i, a);
-  if (active) {
-    // ---- volume: flux at the node, contravariant components to LDS
-    R xi[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) xi[k] = tab.x[a[k]];
-    R J[D][D], adj[D][D];
-    jacobian_at<D, R>(s_c[el], xi, J);
-    const R det = adjugate<D, R>(J, adj);
-    R wi = R(1);
-#pragma unroll
-    for (int k = 0; k < D; ++k) wi *= tab.w[a[k]];
-    const R wdet = wi * det;
-
-    V uu[NCU];
-    V qq[NCU][D];
-#pragma unroll
-    for (int c = 0; c < NCU; ++c) {
-      uu[c] = s_u[el][c][i];
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        if constexpr (HASQ) qq[c][k] = s_q[el][c * D + k][i];
-        else qq[c][k] = T::mk(R(0));
-      }
-    }
-    R aa[NA];
-#pragma unroll
-    for (int t = 0; t < NA; ++t) aa[t] = (t < md.naux) ? R(md.aux[(K * md.naux + t) * NN + i]) : R(0);
-    V f[NCU][D];
-    phys_flux<KIND, D, V, R>(md.mu, md.naux, uu, qq, aa, f);
-#pragma unroll
-    for (int c = 0; c < NCU; ++c) {
-#pragma unroll
-      for (int j = 0; j < D; ++j) {
-        V s = adj[j][0] * f[c][0];
-#pragma unroll
-        for (int k = 1; k < D; ++k) s += adj[j][k] * f[c][k];
-        if constexpr (MODE == 2) s_F[el][c][j][i] = wi * s.d;
-        else s_F[el][c][j][i] = wi * s;
-      }
-      // pointwise terms: time wrapper, source
-      R rc;
-      if constexpr (MODE == 2) {
-        rc = R(tm.a0) * wdet * uu[c].d;
-      } else {
-        const int64_t o = (K * NCU + c) * NN + i;
-        R t = R(tm.a0) * uu[c];
-        if (tm.r1) t -= R(tm.c1) * R(tm.r1[o]);
-        if (tm.r2) t -= R(tm.c2) * R(tm.r2[o]);
-        rc = wdet * t;
-        if constexpr (KIND == K_POISSON) rc += wdet * R(md.mu[2]) * uu[c];
-        if constexpr (MODE == 1) {
-          if (md.src) rc -= wdet * R(md.src[o]);
-        }
-      }
-      r[c] = rc;
-    }
-
-    // ---- faces: numerical flux times w ds, to LDS
-    for (int fp = i; fp < NF * NFP; fp += NN) {
-      const int F = fp / NFP, ff = fp % NFP, dir = F >> 1, side = F & 1;
-      int tix[2] = {0, 0};
-      const int base = face_line<D, P1>(dir, ff, tix);
-      const int sd = stride_of(P1, dir);
+  // ---- faces: numerical flux times w ds, to LDS, one reference direction at a time
+  auto face_dir = [&](auto dirc) {
+    constexpr int DIR = decltype(dirc)::value;
+    constexpr int T0 = Tang<D, DIR>::T0, T1 = Tang<D, DIR>::T1;
+    constexpr int SD = stride_c(P1, DIR);
+    for (int it = threadIdx.x; it < EPB * 2 * NFP; it += blockDim.x) {
+      const int e = it / (2 * NFP), side = (it / NFP) & 1, ff = it % NFP;
+      const int64_t Ke = eb * EPB + e;
+      if (Ke >= m.E) continue;
+      const int t0 = ff % P1, t1 = (D == 3) ? ff / P1 : 0;
+      int base = t0 * stride_c(P1, T0);
+      if constexpr (D == 3) base += t1 * stride_c(P1, T1);
+      const R* l_own = tl + side * P1;
+      const R* l_nbr = tl + (1 - side) * P1;
       V um[NCU], qm[NCU][D];
       R am[NA];
 #pragma unroll
       for (int c = 0; c < NCU; ++c) {
-        V s = T::mk(R(0));
+        V sacc = T::mk(R(0));
 #pragma unroll
-        for (int mm = 0; mm < P1; ++mm) s += tab.lf[side][mm] * s_u[el][c][base + mm * sd];
-        um[c] = s;
+        for (int mm = 0; mm < P1; ++mm) sacc += l_own[mm] * s_u[e][c][base + mm * SD];
+        um[c] = sacc;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
           V t = T::mk(R(0));
           if constexpr (HASQ) {
 #pragma unroll
-            for (int mm = 0; mm < P1; ++mm) t += tab.lf[side][mm] * s_q[el][c * D + k][base + mm * sd];
+            for (int mm = 0; mm < P1; ++mm) t += l_own[mm] * s_q[e][c * D + k][base + mm * SD];
           }
           qm[c][k] = t;
         }
       }
 #pragma unroll
       for (int t = 0; t < NA; ++t) {
-        R s = R(0);
+        R sacc = R(0);
         if (t < md.naux) {
-          const double* ap = md.aux + (K * md.naux + t) * NN + base;
+          const double* ap = md.aux + (Ke * md.naux + t) * NN + base;
 #pragma unroll
-          for (int mm = 0; mm < P1; ++mm) s += tab.lf[side][mm] * R(ap[mm * sd]);
+          for (int mm = 0; mm < P1; ++mm) sacc += l_own[mm] * R(ap[mm * SD]);
         }
-        am[t] = s;
+        am[t] = sacc;
       }
       R xi2[D];
-#pragma unroll
-      for (int k = 0, t = 0; k < D; ++k) xi2[k] = (k == dir) ? (side ? R(1) : R(-1)) : tab.x[tix[t++]];
-      R J2[D][D], N[D], n[D];
-      jacobian_at<D, R>(s_c[el], xi2, J2);
-      scaled_normal<D, R>(J2, dir, side, N);
+      xi2[DIR] = side ? R(1) : R(-1);
+      xi2[T0] = tx[t0];
+      if constexpr (D == 3) xi2[T1] = tx[t1];
+      R N[D], n[D];
+      face_normal<D, DIR, R>(s_c[e], xi2, side, N);
       R ds = R(0);
 #pragma unroll
       for (int k = 0; k < D; ++k) ds += N[k] * N[k];
       ds = vsqrt(ds);
+      const R ids = R(1) / ds;
 #pragma unroll
-      for (int k = 0; k < D; ++k) n[k] = N[k] / ds;
-      R wf = R(1);
-#pragma unroll
-      for (int t = 0; t < D - 1; ++t) wf *= tab.w[tix[t]];
+      for (int k = 0; k < D; ++k) n[k] = N[k] * ids;
+      R wf = tw[t0];
+      if constexpr (D == 3) wf *= tw[t1];
 
+      const int F = 2 * DIR + side;
       V Fh[NCU];
-      const int nb = m.nbr[K * NF + F];
+      const int nb = m.nbr[Ke * NF + F];
       if (nb >= 0) {
         V up[NCU], qp[NCU][D];
         R ap2[NA];
-        const int os = 1 - side;
 #pragma unroll
         for (int c = 0; c < NCU; ++c) {
           const int64_t o = ((int64_t)nb * NCU + c) * NN + base;
-          V s = T::mk(R(0));
+          V sacc = T::mk(R(0));
 #pragma unroll
           for (int mm = 0; mm < P1; ++mm) {
-            if constexpr (MODE == 2) s += tab.lf[os][mm] * T::mk(R(u[o + mm * sd]), R(v[o + mm * sd]));
-            else s += tab.lf[os][mm] * R(u[o + mm * sd]);
+            if constexpr (MODE == 2) sacc += l_nbr[mm] * T::mk(R(u[o + mm * SD]), R(v[o + mm * SD]));
+            else sacc += l_nbr[mm] * R(u[o + mm * SD]);
           }
-          up[c] = s;
+          up[c] = sacc;
 #pragma unroll
           for (int k = 0; k < D; ++k) {
             V t = T::mk(R(0));
@@ -376,8 +436,8 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const doub
               const int64_t oq = (((int64_t)nb * NCU + c) * D + k) * NN + base;
 #pragma unroll
               for (int mm = 0; mm < P1; ++mm) {
-                if constexpr (MODE == 2) t += tab.lf[os][mm] * T::mk(q[oq + mm * sd], dq[oq + mm * sd]);
-                else t += tab.lf[os][mm] * q[oq + mm * sd];
+                if constexpr (MODE == 2) t += l_nbr[mm] * T::mk(q[oq + mm * SD], dq[oq + mm * SD]);
+                else t += l_nbr[mm] * q[oq + mm * SD];
               }
             }
             qp[c][k] = t;
@@ -385,13 +445,13 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const doub
         }
 #pragma unroll
         for (int t = 0; t < NA; ++t) {
-          R s = R(0);
+          R sacc = R(0);
           if (t < md.naux) {
             const double* ap = md.aux + ((int64_t)nb * md.naux + t) * NN + base;
 #pragma unroll
-            for (int mm = 0; mm < P1; ++mm) s += tab.lf[os][mm] * R(ap[mm * sd]);
+            for (int mm = 0; mm < P1; ++mm) sacc += l_nbr[mm] * R(ap[mm * SD]);
           }
-          ap2[t] = s;
+          ap2[t] = sacc;
         }
         num_flux<KIND, D, V, R>(md.mu, md.naux, um, qm, am, up, qp, ap2, n, Fh);
       } else {
@@ -415,18 +475,83 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const doub
           phys_flux<KIND, D, V, R>(md.mu, md.naux, um, qm, am, fl);
 #pragma unroll
           for (int c = 0; c < NCU; ++c) {
-            V s = fl[c][0] * n[0];
+            V sacc = fl[c][0] * n[0];
 #pragma unroll
-            for (int k = 1; k < D; ++k) s += fl[c][k] * n[k];
-            Fh[c] = s;
+            for (int k = 1; k < D; ++k) sacc += fl[c][k] * n[k];
+            Fh[c] = sacc;
           }
         }
       }
+      const R wds = wf * ds;
 #pragma unroll
       for (int c = 0; c < NCU; ++c) {
-        if constexpr (MODE == 2) s_Fh[el][F][c][ff] = wf * ds * Fh[c].d;
-        else s_Fh[el][F][c][ff] = wf * ds * Fh[c];
+        if constexpr (MODE == 2) s_Fh[e][F][c][ff] = wds * Fh[c].d;
+        else s_Fh[e][F][c][ff] = wds * Fh[c];
       }
+    }
+  };
+  face_dir(std::integral_constant<int, 0>{});
+  face_dir(std::integral_constant<int, 1>{});
+  if constexpr (D == 3) face_dir(std::integral_constant<int, 2>{});
+
+  // ---- volume: flux at the node, contravariant components to LDS, pointwise terms
+  R r[NCU];
+  int a[D];
+  node_index<D, P1>(i, a);
+  if (active) {
+    R xi[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) xi[k] = tx[a[k]];
+    R J[D][D], adj[D][D];
+    jacobian_at<D, R>(s_c[el], xi, J);
+    const R det = adjugate<D, R>(J, adj);
+    R wi = R(1);
+#pragma unroll
+    for (int k = 0; k < D; ++k) wi *= tw[a[k]];
+    const R wdet = wi * det;
+
+    V uu[NCU];
+    V qq[NCU][D];
+#pragma unroll
+    for (int c = 0; c < NCU; ++c) {
+      uu[c] = s_u[el][c][i];
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        if constexpr (HASQ) qq[c][k] = s_q[el][c * D + k][i];
+        else qq[c][k] = T::mk(R(0));
+      }
+    }
+    R aa[NA];
+#pragma unroll
+    for (int t = 0; t < NA; ++t) aa[t] = (t < md.naux) ? R(md.aux[(K * md.naux + t) * NN + i]) : R(0);
+    V f[NCU][D];
+    phys_flux<KIND, D, V, R>(md.mu, md.naux, uu, qq, aa, f);
+#pragma unroll
+    for (int c = 0; c < NCU; ++c) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        V sacc = adj[j][0] * f[c][0];
+#pragma unroll
+        for (int k = 1; k < D; ++k) sacc += adj[j][k] * f[c][k];
+        if constexpr (MODE == 2) s_F[el][c][j][i] = wi * sacc.d;
+        else if constexpr (EXT) Fout[((K * NCU + c) * D + j) * NN + i] = float(wi * sacc);   // divergence done outside
+        else s_F[el][c][j][i] = wi * sacc;
+      }
+      R rc;
+      if constexpr (MODE == 2) {
+        rc = R(tm.a0) * wdet * uu[c].d;
+      } else {
+        const int64_t o = (K * NCU + c) * NN + i;
+        R t = R(tm.a0) * uu[c];
+        if (tm.r1) t -= R(tm.c1) * R(tm.r1[o]);
+        if (tm.r2) t -= R(tm.c2) * R(tm.r2[o]);
+        rc = wdet * t;
+        if constexpr (KIND == K_POISSON) rc += wdet * R(md.mu[2]) * uu[c];
+        if constexpr (MODE == 1) {
+          if (md.src) rc -= wdet * R(md.src[o]);
+        }
+      }
+      r[c] = rc;
     }
   }
   __syncthreads();
@@ -437,18 +562,18 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const doub
   for (int c = 0; c < NCU; ++c) {
     R acc = r[c];
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-      const int sj = stride_of(P1, j);
+    for (int j = 0; j < D && !EXT; ++j) {
+      const int sj = stride_c(P1, j);
       const int b0 = i - a[j] * sj;
-      R s = R(0);
+      R sacc = R(0);
 #pragma unroll
-      for (int mm = 0; mm < P1; ++mm) s += tab.D[mm][a[j]] * s_F[el][c][j][b0 + mm * sj];
-      acc -= s;
+      for (int mm = 0; mm < P1; ++mm) sacc += tD[mm * P1 + a[j]] * s_F[el][c][j][b0 + mm * sj];
+      acc -= sacc;
     }
 #pragma unroll
     for (int F = 0; F < NF; ++F) {
       const int dir = F >> 1, side = F & 1;
-      acc += tab.lf[side][a[dir]] * s_Fh[el][F][c][face_index_of_node<D, P1>(a, dir)];
+      acc += tl[side * P1 + a[dir]] * s_Fh[el][F][c][face_index_of_node<D, P1>(a, dir)];
     }
     const int64_t o = (K * NCU + c) * NN + i;
     double res = double(acc);
@@ -588,9 +713,7 @@ static ldg_status launch_grad(const Model& md, const double* u, void* q, bool wi
   // linear models: homogeneous kernel + boundary-data offset; nonlinear: data in the kernel
   const bool in_kernel_data = with_data && !Phys<KIND, D>::LINEAR;
   const double* qoff = (with_data && Phys<KIND, D>::LINEAR) ? md.d_qg : nullptr;
-  constexpr int NN = ipow(P1, D), NCU = Phys<KIND, D>::NCU, NFP = ipow(P1, D - 1), NF = 2 * D, NV = 1 << D;
-  constexpr int BYTES = sizeof(R) * (NCU * NN + NF * NCU * D * NFP) + 8 * NV * D;
-  constexpr int EPB = pick_epb<NN, BYTES>();
+  constexpr int NN = GradCfg<KIND, D, P1, R>::NN, EPB = GradCfg<KIND, D, P1, R>::EPB;
   const Mesh& m = *md.mesh;
   const int nblk = (int)((m.E + EPB - 1) / EPB);
   typename TabOf<R>::T tab;
@@ -608,19 +731,36 @@ static ldg_status launch_grad(const Model& md, const double* u, void* q, bool wi
 template <int KIND, int D, int P1, class R, int MODE>
 static ldg_status launch_resid(const Model& md, const TimeDev& t, const double* u, const void* q, const double* v,
                                const void* dq, const double* dterm, double* out, hipStream_t s) {
-  using PH = Phys<KIND, D>;
-  using V = typename std::conditional<MODE == 2, Dl<R>, R>::type;
-  constexpr int NN = ipow(P1, D), NCU = PH::NCU, NFP = ipow(P1, D - 1), NF = 2 * D, NV = 1 << D;
-  constexpr bool HASQ = PH::HASQ;
-  constexpr int BYTES = sizeof(V) * (NCU * NN + (HASQ ? NCU * D * NN : 0)) +
-                        sizeof(R) * (NCU * D * NN + NF * NCU * NFP) + 8 * NV * D;
-  constexpr int EPB = pick_epb<NN, BYTES>();
+  constexpr int NN = ResidCfg<KIND, D, P1, R, MODE>::NN, EPB = ResidCfg<KIND, D, P1, R, MODE>::EPB;
   const Mesh& m = *md.mesh;
   const int nblk = (int)((m.E + EPB - 1) / EPB);
   typename TabOf<R>::T tab;
   if constexpr (std::is_same<R, double>::value) tab = m.tab; else tab = m.tabf;
   hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), tab, md.dev(), t, u,
                      (const R*)q, v, (const R*)dq, dterm, out);
+  LDG_TRY(hipGetLastError());
+  return LDG_OK;
+}
+
+template <int KIND, int D, int P1>
+static ldg_status launch_grad_ext(const Model& md, const double* u, const float* du, float* q, hipStream_t s) {
+  constexpr int NN = GradCfg<KIND, D, P1, float>::NN, EPB = GradCfg<KIND, D, P1, float>::EPB;
+  const Mesh& m = *md.mesh;
+  const int nblk = (int)((m.E + EPB - 1) / EPB);
+  hipLaunchKernelGGL((k_grad<KIND, D, P1, float, false, true>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), m.tabf,
+                     md.dev(), u, q, (const double*)nullptr, du);
+  LDG_TRY(hipGetLastError());
+  return LDG_OK;
+}
+
+template <int KIND, int D, int P1>
+static ldg_status launch_resid_ext(const Model& md, const TimeDev& t, const double* u, const float* q, float* F,
+                                   double* out, hipStream_t s) {
+  constexpr int NN = ResidCfg<KIND, D, P1, float, 0>::NN, EPB = ResidCfg<KIND, D, P1, float, 0>::EPB;
+  const Mesh& m = *md.mesh;
+  const int nblk = (int)((m.E + EPB - 1) / EPB);
+  hipLaunchKernelGGL((k_resid<KIND, D, P1, float, 0, true>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), m.tabf,
+                     md.dev(), t, u, q, (const double*)nullptr, (const float*)nullptr, (const double*)nullptr, out, F);
   LDG_TRY(hipGetLastError());
   return LDG_OK;
 }
@@ -683,6 +823,30 @@ struct TangentOp {
     }
   }
 };
+
+template <int KI, int DD, int PP>
+struct GradExtOp {
+  static ldg_status run(const Model& md, const double* u, const float* du, float* q, hipStream_t s) {
+    if constexpr (KI <= K_CONVDIFF) return launch_grad_ext<KI, DD, PP>(md, u, du, q, s);
+    else { set_error("external contractions are for the linear models"); return LDG_EUNSUPPORTED; }
+  }
+};
+template <int KI, int DD, int PP>
+struct ResidExtOp {
+  static ldg_status run(const Model& md, const TimeDev& t, const double* u, const float* q, float* F, double* out,
+                        hipStream_t s) {
+    if constexpr (KI <= K_CONVDIFF) return launch_resid_ext<KI, DD, PP>(md, t, u, q, F, out, s);
+    else { set_error("external contractions are for the linear models"); return LDG_EUNSUPPORTED; }
+  }
+};
+
+ldg_status op_grad_ext(const Model& md, const double* u, const float* du, float* q, hipStream_t s) {
+  return dispatch<GradExtOp>(md.kind, md.mesh->nd, md.mesh->p1, md, u, du, q, s);
+}
+ldg_status op_resid_ext(const Model& md, const TimeDev& t, const double* u, const float* q, float* F, double* out,
+                        hipStream_t s) {
+  return dispatch<ResidExtOp>(md.kind, md.mesh->nd, md.mesh->p1, md, t, u, q, F, out, s);
+}
 
 ldg_status op_grad(const Model& md, const double* u, void* q, bool fp32, bool with_data, hipStream_t s) {
   return dispatch<GradOp>(md.kind, md.mesh->nd, md.mesh->p1, md, u, q, fp32, with_data, s);

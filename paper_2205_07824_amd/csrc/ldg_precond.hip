@@ -8,6 +8,8 @@
 #include "ldg_internal.hpp"
 
 struct ldg_precond_s {
+  int kind = 0;           // 0 block-Jacobi, 1 learned (MLP) composite
+  void* mlp_data = nullptr;
   ldg::Model* md;
   int per_variable;
   ldg_precision prec;     // storage precision of the inverse blocks
@@ -193,12 +195,21 @@ static ldg_status invert_blocks(ldg_precond_s* pc, hipStream_t s) {
 }
 
 ldg_status precond_rebuild(ldg_precond_s* pc, const ldg_time* t, const double* u_lin, hipStream_t s) {
+  if (pc->kind == 1) {
+    set_error("the learned preconditioner is rebuilt through its block-Jacobi part");
+    return LDG_EINVAL;
+  }
   ldg_status st = assemble_blocks(*pc->md, t, u_lin, pc->per_variable, pc->scratch, s);
   if (st != LDG_OK) return st;
   return invert_blocks(pc, s);
 }
 
+ldg_status mlp_precond_apply(void* data, const double* r, double* z, hipStream_t s);
+void* mlp_precond_create(Model* md, struct MlpNet* net, ldg_precond_s* bj, int composite);
+void mlp_precond_destroy(void* data);
+
 ldg_status precond_apply_impl(ldg_precond_s* pc, const double* r, double* z, hipStream_t s) {
+  if (pc->kind == 1) return mlp_precond_apply(pc->mlp_data, r, z, s);
   const int nb = pc->nb;
   int bpb = 256 / nb;
   if (bpb < 1) bpb = 1;
@@ -212,6 +223,20 @@ ldg_status precond_apply_impl(ldg_precond_s* pc, const double* r, double* z, hip
                        (const double*)pc->inv, r, z);
   LDG_TRY(hipGetLastError());
   return LDG_OK;
+}
+
+int precond_kind(const ldg_precond_s* pc) { return pc ? pc->kind : -1; }
+
+ldg_status mlp_precond_count_nonfinite(void* data, const double* z, int64_t n, int* host_cnt, hipStream_t s);
+ldg_precond_s* mlp_precond_fallback(void* data);
+
+ldg_precond_s* precond_fallback(ldg_precond_s* pc) {
+  return (pc && pc->kind == 1) ? mlp_precond_fallback(pc->mlp_data) : nullptr;
+}
+
+ldg_status precond_count_nonfinite(ldg_precond_s* pc, const double* z, int64_t n, int* host_cnt, hipStream_t s) {
+  if (!pc || pc->kind != 1) { *host_cnt = 0; return LDG_OK; }
+  return mlp_precond_count_nonfinite(pc->mlp_data, z, n, host_cnt, s);
 }
 
 }  // namespace ldg
@@ -269,9 +294,27 @@ ldg_status ldg_precond_apply(ldg_precond pc, const double* r, double* z, void* s
   return precond_apply_impl(pc, r, z, (hipStream_t)stream);
 }
 
+ldg_status ldg_precond_mlp(ldg_model md, ldg_mlp net, ldg_precond fallback_bj, int composite, ldg_precond* out) {
+  LDG_ENTER();
+  if (!md || !net || !out) { set_error("null argument"); return LDG_EINVAL; }
+  if (md->mesh->nd != 2 || md->ncu != 1) { set_error("element patches are defined for 2D scalar models"); return LDG_EUNSUPPORTED; }
+  if (fallback_bj && fallback_bj->kind != 0) { set_error("fallback must be a block-Jacobi preconditioner"); return LDG_EINVAL; }
+  if (composite && !fallback_bj) { set_error("composite form needs the block-Jacobi part"); return LDG_EINVAL; }
+  auto* pc = new ldg_precond_s();
+  pc->kind = 1;
+  pc->md = md;
+  pc->nb = 0;
+  pc->nblocks = 0;
+  pc->mlp_data = mlp_precond_create(md, (MlpNet*)net, fallback_bj, composite);
+  if (!pc->mlp_data) { delete pc; set_error("allocation failed"); return LDG_ENOMEM; }
+  *out = pc;
+  return LDG_OK;
+}
+
 ldg_status ldg_precond_destroy(ldg_precond pc) {
   LDG_ENTER();
   if (!pc) return LDG_OK;
+  if (pc->kind == 1) { mlp_precond_destroy(pc->mlp_data); delete pc; return LDG_OK; }
   hipFree(pc->scratch); hipFree(pc->inv); hipFree(pc->info);
   delete pc;
   return LDG_OK;

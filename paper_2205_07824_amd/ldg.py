@@ -62,7 +62,8 @@ class NewtonOpts(C.Structure):
 
 class NewtonStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("gmres_iters", C.c_int), ("res0", C.c_double), ("res_final", C.c_double),
-                ("seconds", C.c_double), ("lin_status", C.c_int)]
+                ("seconds", C.c_double), ("lin_status", C.c_int), ("t_jvp", C.c_double), ("t_pc", C.c_double),
+                ("t_orth", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -73,7 +74,9 @@ _lib = None
 EXPORTED = ["ldg_last_error", "ldg_mesh_create", "ldg_mesh_info", "ldg_mesh_points", "ldg_mesh_destroy",
             "ldg_model_create", "ldg_model_destroy", "ldg_residual", "ldg_jvp", "ldg_jacobian_blocks",
             "ldg_precond_block_jacobi", "ldg_precond_apply", "ldg_precond_destroy", "ldg_gmres_solve",
-            "ldg_newton_solve", "ldg_axpby", "ldg_norm2"]
+            "ldg_newton_solve", "ldg_axpby", "ldg_norm2", "ldg_mlp_create", "ldg_mlp_destroy", "ldg_mlp_set_params",
+            "ldg_mlp_get_params", "ldg_mlp_forward", "ldg_mlp_train_step", "ldg_mlp_gather_patches",
+            "ldg_precond_mlp"]
 
 
 def lib():
@@ -104,6 +107,14 @@ def lib():
         "ldg_newton_solve": [vp, C.POINTER(_Time), vp, C.POINTER(NewtonOpts), C.POINTER(NewtonStats), vp],
         "ldg_axpby": [C.c_int64, C.c_double, vp, C.c_double, vp, vp],
         "ldg_norm2": [C.c_int64, vp, dp, vp],
+        "ldg_mlp_create": [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(vp)],
+        "ldg_mlp_destroy": [vp],
+        "ldg_mlp_set_params": [vp, C.POINTER(C.c_float)],
+        "ldg_mlp_get_params": [vp, C.POINTER(C.c_float), C.POINTER(C.c_float)],
+        "ldg_mlp_forward": [vp, vp, C.c_int64, vp, vp],
+        "ldg_mlp_train_step": [vp, vp, vp, C.c_int64, C.c_float, C.POINTER(C.c_float), vp],
+        "ldg_mlp_gather_patches": [vp, vp, vp, vp, C.c_int64, vp, vp, vp, vp],
+        "ldg_precond_mlp": [vp, vp, vp, C.c_int, C.POINTER(vp)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -245,6 +256,85 @@ class BlockJacobi:
         h = C.c_void_p()
         _check(lib().ldg_precond_block_jacobi(model.h, _time(time), _ptr(u_lin), int(per_variable), prec, _stream(),
                                               C.byref(h)), "ldg_precond_block_jacobi")
+        self.h = h
+
+    def apply(self, r, out=None):
+        out = self.model.empty() if out is None else out
+        _check(lib().ldg_precond_apply(self.h, _ptr(r), _ptr(out), _stream()), "ldg_precond_apply")
+        return out
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ldg_precond_destroy(self.h)
+            self.h = None
+
+
+class MLP:
+    """3-layer element-patch network; params packed W1 b1 W2 b2 W3 b3 (row-major W[out][in])."""
+
+    def __init__(self, in_dim, width, out_dim, bf16=True):
+        self.dims = (in_dim, width, out_dim)
+        h = C.c_void_p()
+        _check(lib().ldg_mlp_create(in_dim, width, out_dim, 3, int(bf16), C.byref(h)), "ldg_mlp_create")
+        self.h = h
+        self.shapes = [(width, in_dim), (width,), (width, width), (width,), (out_dim, width), (out_dim,)]
+        self.nparams = int(sum(np.prod(s) for s in self.shapes))
+
+    def set_params(self, params):
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.float32).reshape(-1) for p in params]))
+        assert flat.size == self.nparams
+        _check(lib().ldg_mlp_set_params(self.h, flat.ctypes.data_as(C.POINTER(C.c_float))), "ldg_mlp_set_params")
+
+    def _unpack(self, flat):
+        out, o = [], 0
+        for s in self.shapes:
+            n = int(np.prod(s))
+            out.append(flat[o:o + n].reshape(s).copy())
+            o += n
+        return out
+
+    def get_params(self):
+        p = np.zeros(self.nparams, dtype=np.float32)
+        g = np.zeros(self.nparams, dtype=np.float32)
+        _check(lib().ldg_mlp_get_params(self.h, p.ctypes.data_as(C.POINTER(C.c_float)),
+                                        g.ctypes.data_as(C.POINTER(C.c_float))), "ldg_mlp_get_params")
+        return self._unpack(p), self._unpack(g)
+
+    def forward(self, X, out=None):
+        B = X.shape[0]
+        out = torch.empty((B, self.dims[2]), dtype=torch.float32, device="cuda") if out is None else out
+        _check(lib().ldg_mlp_forward(self.h, _ptr(X), B, _ptr(out), _stream()), "ldg_mlp_forward")
+        return out
+
+    def train_step(self, X, Y, lr):
+        loss = C.c_float()
+        _check(lib().ldg_mlp_train_step(self.h, _ptr(X), _ptr(Y), X.shape[0], float(lr), C.byref(loss), _stream()),
+               "ldg_mlp_train_step")
+        return float(loss.value)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ldg_mlp_destroy(self.h)
+            self.h = None
+
+
+def gather_patches(model, r, e=None, elems=None, want_scale=False):
+    B = model.mesh.E if elems is None else elems.numel()
+    nn = model.mesh.nn
+    X = torch.empty((B, 20 * nn), dtype=torch.float32, device="cuda")
+    Y = torch.empty((B, nn), dtype=torch.float32, device="cuda") if e is not None else None
+    S = torch.empty(B, dtype=torch.float64, device="cuda") if want_scale else None
+    _check(lib().ldg_mlp_gather_patches(model.h, _ptr(r), _ptr(e), _ptr(elems), B, _ptr(X), _ptr(Y), _ptr(S),
+                                        _stream()), "ldg_mlp_gather_patches")
+    return X, Y, S
+
+
+class LearnedPrecond:
+    def __init__(self, model, net, bj, composite=True):
+        self.model, self.net, self.bj = model, net, bj
+        h = C.c_void_p()
+        _check(lib().ldg_precond_mlp(model.h, net.h, None if bj is None else bj.h, int(composite), C.byref(h)),
+               "ldg_precond_mlp")
         self.h = h
 
     def apply(self, r, out=None):

@@ -229,3 +229,22 @@ def test_gmres_failure_paths(L):
     pc = L.BlockJacobi(md)
     x, st, status = L.gmres(md, b, pc=pc, restart=10, rtol=1e-12, maxit=50, inject_fault=1, check=False)
     assert status == L.LDG_EBREAKDOWN
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c5", "mixed2d", "mixed3d"])
+def test_jvp_mfma_modes_error_vs_oracle(L, name):
+    """Volume contractions on MFMA (bf16 / fp16 operands, fp32 accumulation).
+
+    The achieved error against the FP64 oracle is recorded per case; the bounds
+    are a few units of the operand precision (2^-8 for bf16, 2^-11 for fp16)
+    amplified by the operator's cancellation on random input vectors."""
+    c = CS.ALL[name]()
+    _say("case", name)
+    m, md, t, dev = build_gpu(L, c)
+    Jv_ref = c.om.jvp(c.oracle_model(), c.u, c.v)
+    errs = {}
+    for prec, tol in ((L.BF16_MFMA, 0.1), (L.FP16_MFMA, 0.02)):
+        Jv = md.jvp(None, dev(c.v), time=t, prec=prec)
+        errs[prec] = rel(Jv.cpu().numpy(), Jv_ref)
+        assert errs[prec] < tol, (name, prec, errs[prec])
+    _say(name, "mfma rel err bf16", errs[L.BF16_MFMA], "fp16", errs[L.FP16_MFMA])
