@@ -197,41 +197,43 @@ ldg_status ldg_mesh_create(int nd, int p, int nq1d, int64_t nvert, const double*
   }
   m->affine = affine;
 
-  // faces keyed by sorted corner ids
+  // faces keyed by sorted corner ids; every key must occur once (boundary) or twice
   const int nf = m->nf;
   m->h_nbr.assign((size_t)nelem * nf, INT32_MIN);
-  std::unordered_map<std::vector<int64_t>, std::pair<int64_t, int>, KeyHash> open;
-  open.reserve((size_t)nelem * nf);
+  std::unordered_map<std::vector<int64_t>, std::vector<std::pair<int64_t, int>>, KeyHash> faces;
+  faces.reserve((size_t)nelem * nf);
+  auto corners_of = [&](int64_t K, int F) {
+    std::vector<int64_t> c;
+    for (int v = 0; v < nv; ++v)
+      if (((v >> (F >> 1)) & 1) == (F & 1)) c.push_back(elem_vert[K * nv + v]);
+    return c;
+  };
   for (int64_t K = 0; K < nelem; ++K)
     for (int F = 0; F < nf; ++F) {
-      const int dir = F >> 1, side = F & 1;
-      std::vector<int64_t> corners;
-      for (int v = 0; v < nv; ++v)
-        if (((v >> dir) & 1) == side) corners.push_back(elem_vert[K * nv + v]);
-      std::vector<int64_t> key = corners;
+      std::vector<int64_t> key = corners_of(K, F);
       std::sort(key.begin(), key.end());
-      auto it = open.find(key);
-      if (it == open.end()) {
-        open.emplace(key, std::make_pair(K, F));
-        continue;
-      }
-      const int64_t K2 = it->second.first;
-      const int F2 = it->second.second;
-      if (K2 < 0) { delete m; set_error("face shared by more than two elements"); return LDG_EINVAL; }
-      if (K2 == K) { delete m; set_error("element adjacent to itself (periodic direction with fewer than 3 elements)"); return LDG_EINVAL; }
-      // required: opposite side of the same reference direction, same tangential orientation
-      std::vector<int64_t> c2;
-      for (int v = 0; v < nv; ++v)
-        if (((v >> (F2 >> 1)) & 1) == (F2 & 1)) c2.push_back(elem_vert[K2 * nv + v]);
-      if ((F2 >> 1) != dir || (F2 & 1) == side || c2 != corners) {
-        delete m;
-        set_error("inconsistent face orientation between neighbouring elements");
-        return LDG_EUNSUPPORTED;
-      }
-      m->h_nbr[(size_t)K * nf + F] = (int32_t)K2;
-      m->h_nbr[(size_t)K2 * nf + F2] = (int32_t)K;
-      it->second.first = -1;
+      faces[key].emplace_back(K, F);
     }
+  for (auto& kv : faces)
+    if (kv.second.size() > 2) {
+      delete m;
+      set_error("face shared by more than two elements (or a periodic direction with fewer than 3 elements)");
+      return LDG_EINVAL;
+    }
+  for (auto& kv : faces) {
+    if (kv.second.size() != 2) continue;
+    const int64_t K = kv.second[0].first, K2 = kv.second[1].first;
+    const int F = kv.second[0].second, F2 = kv.second[1].second;
+    if (K2 == K) { delete m; set_error("element adjacent to itself"); return LDG_EINVAL; }
+    // required: opposite sides of the same reference direction, same tangential orientation
+    if ((F2 >> 1) != (F >> 1) || (F2 & 1) == (F & 1) || corners_of(K, F) != corners_of(K2, F2)) {
+      delete m;
+      set_error("inconsistent face orientation between neighbouring elements");
+      return LDG_EUNSUPPORTED;
+    }
+    m->h_nbr[(size_t)K * nf + F] = (int32_t)K2;
+    m->h_nbr[(size_t)K2 * nf + F2] = (int32_t)K;
+  }
   // boundary faces, element-major then local face
   m->nbf = 0;
   for (int64_t K = 0; K < nelem; ++K)
