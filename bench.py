@@ -55,6 +55,53 @@ def event_time(fn, reps):
     return e0.elapsed_time(e1) / 1e3 / reps
 
 
+def other_workloads(ldg, I, log):
+    import torch
+    res = {}
+    # 2D Euler, p=4, periodic 256^2 on [0,20]^2, four isentropic vortices, BDF2 wrapper at dt = 0.05
+    box = I.box_mesh(2, 256, lo=(0, 0), hi=(20, 20), periodic=(True, True))
+    m = ldg.Mesh(box, 4)
+    xn, _, _, _ = m.points()
+    U = I.isentropic_vortices(xn, I.vortex_centres(4, 20.0, 5.0, 0)).transpose(0, 2, 1).reshape(-1)
+    md = ldg.Model(m, ldg.MODEL_EULER, 4, [1.4])
+    u = torch.as_tensor(U, device="cuda")
+    v = torch.as_tensor(np.random.default_rng(2).uniform(-1, 1, md.N), device="cuda")
+    t = ldg.Time(a0=1.5 / 0.05)
+    Jv = md.empty()
+    for nm, pr in (("fp64", ldg.FP64), ("fp32", ldg.FP32)):
+        md.jvp(u, v, time=t, out=Jv, prec=pr)
+        e = event_time(lambda: md.jvp(u, v, time=t, out=Jv, prec=pr), 20)
+        res[f"euler2d_p4_256sq_jvp_{nm}_gdofs"] = round(md.N / e / 1e9, 3)
+    res["euler2d_p4_256sq_dof"] = md.N
+    log("euler", res)
+    del md, m, u, v, Jv
+    torch.cuda.empty_cache()
+    # 3D Navier-Stokes Taylor-Green vortex, p=3, periodic 64^3 on (0, 2 pi)^3, Re 1600, Mach 0.1, Pr 0.71
+    L = 2 * np.pi
+    n = 64
+    box = I.box_mesh(3, n, lo=(0, 0, 0), hi=(L, L, L), periodic=(True,) * 3)
+    m = ldg.Mesh(box, 3)
+    xn, _, _, _ = m.points()
+    U = I.taylor_green(xn).transpose(0, 2, 1).reshape(-1)
+    del xn
+    md = ldg.Model(m, ldg.MODEL_NS, 5, [1.4, 1600.0, 0.71, 16.0 * n / L])
+    u = torch.as_tensor(U, device="cuda")
+    del U
+    v = torch.as_tensor(np.random.default_rng(2).uniform(-1, 1, md.N), device="cuda")
+    t = ldg.Time(a0=1.5 / 0.01)
+    Jv = md.empty()
+    for nm, pr in (("fp64", ldg.FP64), ("fp32", ldg.FP32)):
+        md.jvp(u, v, time=t, out=Jv, prec=pr)
+        e = event_time(lambda: md.jvp(u, v, time=t, out=Jv, prec=pr), 5)
+        res[f"ns3d_tgv_p3_64cube_jvp_{nm}_gdofs"] = round(md.N / e / 1e9, 3)
+        res[f"ns3d_tgv_p3_64cube_jvp_{nm}_ms"] = round(e * 1e3, 3)
+    res["ns3d_tgv_p3_64cube_dof"] = md.N
+    log("ns", res)
+    del md, m, u, v, Jv
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +110,8 @@ def main():
     ap.add_argument("--n", type=int, default=32)
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra-workloads", action="store_true",
+                    help="skip the 2D Euler and 3D Navier-Stokes JVP throughput legs")
     ap.add_argument("--profile-jvp-only", action="store_true",
                     help="only the timed JVP steps (for counter collection)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -176,6 +225,10 @@ def main():
             log(name, forms[name])
             del pc
         out["newton_gmres"] = forms
+
+    # JVP throughput on the other workload shapes (FP64 and FP32, HIP events)
+    if not args.no_extra_workloads:
+        out["other_workloads"] = other_workloads(ldg, I, log)
 
     # oracle on a bounded sample of elements, host, one core
     if not args.no_cpu:

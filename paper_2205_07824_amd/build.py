@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libldg.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["ldg_api.hip", "ldg_operator.hip", "ldg_krylov.hip", "ldg_precond.hip", "ldg_mfma.hip", "ldg_mlp.hip"]
+SOURCES = ["ldg_api.hip", "ldg_operator.hip", "ldg_op_poisson.hip", "ldg_op_convdiff.hip", "ldg_op_euler.hip", "ldg_op_ns.hip", "ldg_krylov.hip", "ldg_precond.hip", "ldg_mfma.hip", "ldg_mlp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wno-unused-result", "-Wno-unused-value",

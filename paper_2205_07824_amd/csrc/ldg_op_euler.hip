@@ -1,0 +1,6 @@
+// Operator kernels instantiated for one model kind (euler).
+#include "ldg_operator_kernels.hpp"
+
+namespace ldg {
+LDG_DEFINE_KIND_OPS(2)
+}  // namespace ldg

@@ -1,0 +1,6 @@
+// Operator kernels instantiated for one model kind (ns).
+#include "ldg_operator_kernels.hpp"
+
+namespace ldg {
+LDG_DEFINE_KIND_OPS(3)
+}  // namespace ldg

@@ -1,0 +1,6 @@
+// Operator kernels instantiated for one model kind (poisson).
+#include "ldg_operator_kernels.hpp"
+
+namespace ldg {
+LDG_DEFINE_KIND_OPS(0)
+}  // namespace ldg

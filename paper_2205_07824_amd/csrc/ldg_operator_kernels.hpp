@@ -1,0 +1,796 @@
+// LDG operator kernels for gfx950 (instantiated per model kind in ldg_op_*.hip): the local gradient q (Eq. 1a in weak form),
+// the residual R(u) with the implicit time wrapper, and its exact tangent.
+//
+// Layout: one thread per (element, node); EPB elements per work-group.  The
+// basis is the Lagrange basis on the (p+1)^D Gauss-Legendre nodes and the
+// quadrature is collocated with the nodes, so the element mass matrix is
+// diagonal (w_i |J_i|) and every volume contraction is a sum-factorized
+// application of the 1D derivative matrix along one direction (p+1 products
+// per node and direction), staged through LDS.
+//
+// Faces are handled element-centrically: every element evaluates the numerical
+// flux on each of its 2D faces from its own trace and the neighbour's trace
+// (read directly from the neighbour's nodal lines), and lifts it into its own
+// nodes.  No element writes another element's output, so there are no atomics,
+// no face colouring passes, and the result is bitwise deterministic.
+//
+// Face work is organised by reference direction (a compile-time constant), so
+// the line strides, the tangential directions and the normal (cross product of
+// the two tangential Jacobian columns) need no per-lane selects.  The 1D tables
+// live in LDS.  Work-groups are mapped to elements so that each of the eight
+// XCDs (which receive work-groups round-robin) walks a contiguous range of
+// elements and finds most neighbours in its own L2.
+#include <type_traits>
+
+#pragma once
+
+#include "ldg_physics.hpp"
+
+namespace ldg {
+
+template <class R> struct TabOf;
+template <> struct TabOf<double> { using T = BasisTab; };
+template <> struct TabOf<float> { using T = BasisTabF; };
+
+// Elements per work-group: fill 256 threads, bounded by an LDS budget per group.
+template <int NN, int BYTES_PER_ELEM>
+constexpr int pick_epb() {
+  int e = 256 / NN;
+  if (e < 1) e = 1;
+  while (e > 1 && e * BYTES_PER_ELEM > 40 * 1024) --e;
+  return e;
+}
+
+template <int P1>
+struct TabLayout {
+  static constexpr int X = 0, W = P1, DM = 2 * P1, LF = 2 * P1 + P1 * P1, SIZE = 4 * P1 + P1 * P1;
+};
+
+// copy the 1D tables into LDS: x, w, D (row-major D[a][m]), lf[0], lf[1]
+template <int P1, class R, class TAB>
+__device__ inline void stage_tables(const TAB& tab, R* st) {
+  using L = TabLayout<P1>;
+  for (int t = threadIdx.x; t < L::SIZE; t += blockDim.x) {
+    R v;
+    if (t < L::W) v = tab.x[t];
+    else if (t < L::DM) v = tab.w[t - L::W];
+    else if (t < L::LF) { const int r = (t - L::DM) / P1, c = (t - L::DM) % P1; v = tab.D[r][c]; }
+    else { const int r = (t - L::LF) / P1, c = (t - L::LF) % P1; v = tab.lf[r][c]; }
+    st[t] = v;
+  }
+}
+
+// work-group -> element block, XCD-aware (work-group b runs on XCD b % 8)
+__device__ inline int64_t xcd_block(int64_t b, int64_t nblk) {
+  const int64_t q = nblk >> 3;
+  if (b < (q << 3)) return (b & 7) * q + (b >> 3);
+  return b;
+}
+
+__host__ __device__ constexpr int stride_c(int P1, int k) { return k == 0 ? 1 : (k == 1 ? P1 : P1 * P1); }
+
+// tangential directions of a face normal to DIR
+template <int D, int DIR> struct Tang {
+  static constexpr int T0 = (DIR == 0) ? 1 : 0;
+  static constexpr int T1 = (D == 3) ? ((DIR == 2) ? 1 : 2) : -1;
+};
+
+// column j of the Jacobian of the multilinear map at xi
+template <int D, int J, class R, bool AFF = false>
+__device__ inline void jac_col(const double* __restrict__ c, const R* xi, R* col) {
+  if constexpr (AFF) {
+    // affine element: only the linear monomial of the map contributes
+#pragma unroll
+    for (int i = 0; i < D; ++i) col[i] = R(c[(1 << J) * D + i]);
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i) col[i] = R(0);
+#pragma unroll
+  for (int m = 0; m < (1 << D); ++m) {
+    if (!((m >> J) & 1)) continue;
+    R t = R(1);
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+      if (k != J && ((m >> k) & 1)) t *= xi[k];
+#pragma unroll
+    for (int i = 0; i < D; ++i) col[i] += R(c[m * D + i]) * t;
+  }
+}
+
+// scaled outward normal N = ds n at a point of face (DIR, side): (2 side - 1) * row DIR of adj(J)
+template <int D, int DIR, class R, bool AFF = false>
+__device__ inline void face_normal(const double* __restrict__ c, const R* xi, int side, R* N) {
+  const R s = side ? R(1) : R(-1);
+  if constexpr (D == 2) {
+    constexpr int T = 1 - DIR;
+    R col[2];
+    jac_col<2, T, R, AFF>(c, xi, col);
+    if constexpr (DIR == 0) { N[0] = s * col[1]; N[1] = -s * col[0]; }
+    else { N[0] = -s * col[1]; N[1] = s * col[0]; }
+  } else {
+    // row DIR of adj = col(DIR+1) x col(DIR+2) (cyclic)
+    constexpr int A = (DIR + 1) % 3, B = (DIR + 2) % 3;
+    R a[3], b[3];
+    jac_col<3, A, R, AFF>(c, xi, a);
+    jac_col<3, B, R, AFF>(c, xi, b);
+    N[0] = s * (a[1] * b[2] - a[2] * b[1]);
+    N[1] = s * (a[2] * b[0] - a[0] * b[2]);
+    N[2] = s * (a[0] * b[1] - a[1] * b[0]);
+  }
+}
+
+// full Jacobian J[i][j] = d x_i / d xi_j from its columns
+template <int D, class R, bool AFF>
+__device__ inline void jac_full(const double* __restrict__ c, const R* xi, R J[D][D]) {
+  R col[D];
+  jac_col<D, 0, R, AFF>(c, xi, col);
+#pragma unroll
+  for (int i = 0; i < D; ++i) J[i][0] = col[i];
+  jac_col<D, 1, R, AFF>(c, xi, col);
+#pragma unroll
+  for (int i = 0; i < D; ++i) J[i][1] = col[i];
+  if constexpr (D == 3) {
+    jac_col<D, 2, R, AFF>(c, xi, col);
+#pragma unroll
+    for (int i = 0; i < D; ++i) J[i][2] = col[i];
+  }
+}
+
+template <int D, int P1>
+__device__ inline void node_index(int i, int* a) {
+#pragma unroll
+  for (int k = 0; k < D; ++k) { a[k] = i % P1; i /= P1; }
+}
+
+// tangential flat index of node a[] on a face normal to dir (lower tangential direction fastest)
+template <int D, int P1>
+__device__ inline int face_index_of_node(const int* a, int dir) {
+  int f = 0, s = 1;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    if (k == dir) continue;
+    f += a[k] * s;
+    s *= P1;
+  }
+  return f;
+}
+
+template <int KIND, int D, int P1, class R>
+struct GradCfg {
+  static constexpr int NCU = Phys<KIND, D>::NCU, NN = ipow(P1, D), NFP = ipow(P1, D - 1), NF = 2 * D, NV = 1 << D;
+  static constexpr int BYTES = sizeof(R) * (NCU * NN + NF * NCU * D * NFP) + 8 * NV * D;
+  static constexpr int EPB = pick_epb<NN, BYTES>();
+};
+
+template <int KIND, int D, int P1, class R, int MODE>
+struct ResidCfg {
+  using PH = Phys<KIND, D>;
+  using V = typename std::conditional<MODE == 2, Dl<R>, R>::type;
+  static constexpr int NCU = PH::NCU, NN = ipow(P1, D), NFP = ipow(P1, D - 1), NF = 2 * D, NV = 1 << D;
+  static constexpr bool HASQ = PH::HASQ;
+  static constexpr int NQ = HASQ ? NCU * D : 1;
+  static constexpr int BYTES = sizeof(V) * (NCU * NN + (HASQ ? NCU * D * NN : 0)) +
+                               sizeof(R) * (NCU * D * NN + NF * NCU * NFP) + 8 * NV * D;
+  static constexpr int EPB = pick_epb<NN, BYTES>();
+};
+
+// ============================================================================
+// Local gradient: q = M^-1 [ (u, div r) - <uhat n, r> ], evaluated in the
+// equivalent strong form q = -grad u + M^-1 <(u- - uhat) n, r> (integration by
+// parts is exact under the collocated Gauss rule for multilinear elements).
+// DATA = true: Dirichlet uhat = g from bdata (nonlinear models); false:
+// homogeneous (tangents, and linear models whose data enter through qoff).
+// ============================================================================
+template <int KIND, int D, int P1, class R, bool DATA, bool EXT = false, bool AFF = false>
+__global__ void __launch_bounds__(256)
+k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const double* __restrict__ u, R* __restrict__ q,
+       const double* __restrict__ qoff, const float* __restrict__ dux = nullptr) {
+  using C = GradCfg<KIND, D, P1, R>;
+  constexpr int NCU = C::NCU, NN = C::NN, NFP = C::NFP, NF = C::NF, NV = C::NV, EPB = C::EPB;
+  using L = TabLayout<P1>;
+  __shared__ R s_tab[L::SIZE];
+  __shared__ R s_u[EPB][NCU][NN];
+  __shared__ R s_L[EPB][NF][NCU][D][NFP];
+  __shared__ double s_c[EPB][NV * D];
+
+  const int64_t eb = xcd_block(blockIdx.x, gridDim.x);
+  const int el = threadIdx.x / NN, i = threadIdx.x % NN;
+  const int64_t K = eb * EPB + el;
+  const bool active = K < m.E;
+  stage_tables<P1, R>(tab, s_tab);
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < NCU; ++c) s_u[el][c][i] = R(u[(K * NCU + c) * NN + i]);
+    for (int t = i; t < NV * D; t += NN) s_c[el][t] = m.coef[K * NV * D + t];
+  }
+  __syncthreads();
+  const R* tx = s_tab + L::X;
+  const R* tw = s_tab + L::W;
+  const R* tD = s_tab + L::DM;
+  const R* tl = s_tab + L::LF;
+
+  // ---- faces, one reference direction at a time
+  auto face_dir = [&](auto dirc, const int it) {
+    constexpr int DIR = decltype(dirc)::value;
+    constexpr int T0 = Tang<D, DIR>::T0, T1 = Tang<D, DIR>::T1;
+    constexpr int SD = stride_c(P1, DIR);
+    {
+      const int e = it / (2 * NFP), side = (it / NFP) & 1, f = it % NFP;
+      const int64_t Ke = eb * EPB + e;
+      if (Ke >= m.E) return;
+      const int t0 = f % P1, t1 = (D == 3) ? f / P1 : 0;
+      int base = t0 * stride_c(P1, T0);
+      if constexpr (D == 3) base += t1 * stride_c(P1, T1);
+      const R* l_own = tl + side * P1;
+      const R* l_nbr = tl + (1 - side) * P1;
+      R um[NCU], uh[NCU];
+#pragma unroll
+      for (int c = 0; c < NCU; ++c) {
+        R sacc = R(0);
+#pragma unroll
+        for (int mm = 0; mm < P1; ++mm) sacc += l_own[mm] * s_u[e][c][base + mm * SD];
+        um[c] = sacc;
+      }
+      const int F = 2 * DIR + side;
+      const int nb = m.nbr[Ke * NF + F];
+      if (nb >= 0) {
+#pragma unroll
+        for (int c = 0; c < NCU; ++c) {
+          const double* un = u + ((int64_t)nb * NCU + c) * NN + base;
+          R sacc = R(0);
+#pragma unroll
+          for (int mm = 0; mm < P1; ++mm) sacc += l_nbr[mm] * R(un[mm * SD]);
+          uh[c] = R(0.5) * (um[c] + sacc);
+        }
+      } else {
+        const int b = -(nb + 1);
+        int tag = m.btag[b];
+        tag = tag < 0 ? 0 : (tag >= md.nbc ? md.nbc - 1 : tag);
+        const int kind = md.bc_kind[tag];
+#pragma unroll
+        for (int c = 0; c < NCU; ++c) {
+          if (kind == LDG_BC_DIRICHLET)
+            uh[c] = (DATA && md.bdata) ? R(md.bdata[((int64_t)b * NCU + c) * NFP + f]) : R(0);
+          else
+            uh[c] = um[c];
+        }
+      }
+      R xi[D];
+      xi[DIR] = side ? R(1) : R(-1);
+      xi[T0] = tx[t0];
+      if constexpr (D == 3) xi[T1] = tx[t1];
+      R N[D];
+      face_normal<D, DIR, R, AFF>(s_c[e], xi, side, N);
+#pragma unroll
+      for (int c = 0; c < NCU; ++c)
+#pragma unroll
+        for (int k = 0; k < D; ++k) s_L[e][F][c][k][f] = (um[c] - uh[c]) * N[k];
+    }
+  };
+  // face items flattened over the directions (direction-major), so that the
+  // direction is uniform across a wave whenever EPB * 2 * NFP is a multiple of 64
+  for (int it = threadIdx.x; it < D * EPB * 2 * NFP; it += blockDim.x) {
+    const int dir = it / (EPB * 2 * NFP), loc = it % (EPB * 2 * NFP);
+    if (dir == 0) face_dir(std::integral_constant<int, 0>{}, loc);
+    else if (dir == 1) face_dir(std::integral_constant<int, 1>{}, loc);
+    else if constexpr (D == 3) face_dir(std::integral_constant<int, 2>{}, loc);
+  }
+  __syncthreads();
+  if (!active) return;
+
+  int a[D];
+  node_index<D, P1>(i, a);
+  R xi[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) xi[k] = tx[a[k]];
+  R J[D][D], adj[D][D];
+  jac_full<D, R, AFF>(s_c[el], xi, J);
+  const R det = adjugate<D, R>(J, adj);
+  const R idet = R(1) / det;
+  R liftw[NF];      // l_{a_dir}(side) / (w_{a_dir} det)
+  int fidx[D];
+#pragma unroll
+  for (int F = 0; F < NF; ++F) liftw[F] = tl[(F & 1) * P1 + a[F >> 1]] / tw[a[F >> 1]] * idet;
+#pragma unroll
+  for (int dd = 0; dd < D; ++dd) fidx[dd] = face_index_of_node<D, P1>(a, dd);
+#pragma unroll
+  for (int c = 0; c < NCU; ++c) {
+    R du[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      if constexpr (EXT) {
+        // reference gradient computed outside (MFMA GEMM)
+        du[j] = R(dux[((K * NCU + c) * D + j) * NN + i]);
+      } else {
+        const int sj = stride_c(P1, j);
+        const int b0 = i - a[j] * sj;
+        const R* Drow = tD + a[j] * P1;
+        R sacc = R(0);
+#pragma unroll
+        for (int mm = 0; mm < P1; ++mm) sacc += Drow[mm] * s_u[el][c][b0 + mm * sj];
+        du[j] = sacc;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      R g = R(0);
+#pragma unroll
+      for (int j = 0; j < D; ++j) g += adj[j][k] * du[j];
+      R qv = -g * idet;
+#pragma unroll
+      for (int F = 0; F < NF; ++F) qv += liftw[F] * s_L[el][F][c][k][fidx[F >> 1]];
+      const int64_t o = ((K * NCU + c) * D + k) * NN + i;
+      if (qoff) qv += R(qoff[o]);
+      q[o] = qv;
+    }
+  }
+}
+
+// ============================================================================
+// Residual and tangent.
+//   MODE 0: linear operator applied to the input (linear models' R_hom(u, q) and
+//           their JVP), + a0 M u - M (c1 r1 + c2 r2) + dterm
+//   MODE 1: nonlinear residual with data (source, Dirichlet/Neumann data) and
+//           the time wrapper
+//   MODE 2: tangent of the nonlinear residual at (u, q) in direction (v, dq),
+//           dual-number arithmetic; + a0 M v
+// ============================================================================
+template <int KIND, int D, int P1, class R, int MODE, bool EXT = false, bool AFF = false>
+__global__ void __launch_bounds__(256)
+k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const double* __restrict__ u,
+        const R* __restrict__ q, const double* __restrict__ v, const R* __restrict__ dq,
+        const double* __restrict__ dterm, double* __restrict__ out, float* __restrict__ Fout = nullptr) {
+  using C = ResidCfg<KIND, D, P1, R, MODE>;
+  using V = typename C::V;
+  using T = VT<V>;
+  constexpr int NCU = C::NCU, NN = C::NN, NFP = C::NFP, NF = C::NF, NV = C::NV, EPB = C::EPB, NQ = C::NQ;
+  constexpr bool HASQ = C::HASQ;
+  constexpr int NA = Phys<KIND, D>::NAUX > 0 ? Phys<KIND, D>::NAUX : 1;
+  using L = TabLayout<P1>;
+  __shared__ R s_tab[L::SIZE];
+  __shared__ V s_u[EPB][NCU][NN];
+  __shared__ V s_q[EPB][NQ][HASQ ? NN : 1];
+  __shared__ R s_F[EPB][NCU][D][NN];
+  __shared__ R s_Fh[EPB][NF][NCU][NFP];
+  __shared__ double s_c[EPB][NV * D];
+
+  const int64_t eb = xcd_block(blockIdx.x, gridDim.x);
+  const int el = threadIdx.x / NN, i = threadIdx.x % NN;
+  const int64_t K = eb * EPB + el;
+  const bool active = K < m.E;
+  stage_tables<P1, R>(tab, s_tab);
+  // state loads: MODE 0 reads the input vector from u (the vector the linear
+  // operator is applied to); MODE 2 pairs (u, v) and (q, dq).
+  if (active) {
+#pragma unroll
+    for (int c = 0; c < NCU; ++c) {
+      const int64_t o = (K * NCU + c) * NN + i;
+      if constexpr (MODE == 2) s_u[el][c][i] = T::mk(R(u[o]), R(v[o]));
+      else s_u[el][c][i] = R(u[o]);
+    }
+    if constexpr (HASQ) {
+#pragma unroll
+      for (int c = 0; c < NQ; ++c) {
+        const int64_t o = (K * NQ + c) * NN + i;
+        if constexpr (MODE == 2) s_q[el][c][i] = T::mk(q[o], dq[o]);
+        else s_q[el][c][i] = q[o];
+      }
+    }
+    for (int t = i; t < NV * D; t += NN) s_c[el][t] = m.coef[K * NV * D + t];
+  }
+  __syncthreads();
+  const R* tx = s_tab + L::X;
+  const R* tw = s_tab + L::W;
+  const R* tD = s_tab + L::DM;
+  const R* tl = s_tab + L::LF;
+
+  // ---- faces: numerical flux times w ds, to LDS, one reference direction at a time
+  auto face_dir = [&](auto dirc, const int it) {
+    constexpr int DIR = decltype(dirc)::value;
+    constexpr int T0 = Tang<D, DIR>::T0, T1 = Tang<D, DIR>::T1;
+    constexpr int SD = stride_c(P1, DIR);
+    {
+      const int e = it / (2 * NFP), side = (it / NFP) & 1, ff = it % NFP;
+      const int64_t Ke = eb * EPB + e;
+      if (Ke >= m.E) return;
+      const int t0 = ff % P1, t1 = (D == 3) ? ff / P1 : 0;
+      int base = t0 * stride_c(P1, T0);
+      if constexpr (D == 3) base += t1 * stride_c(P1, T1);
+      const R* l_own = tl + side * P1;
+      const R* l_nbr = tl + (1 - side) * P1;
+      V um[NCU], qm[NCU][D];
+      R am[NA];
+#pragma unroll
+      for (int c = 0; c < NCU; ++c) {
+        V sacc = T::mk(R(0));
+#pragma unroll
+        for (int mm = 0; mm < P1; ++mm) sacc += l_own[mm] * s_u[e][c][base + mm * SD];
+        um[c] = sacc;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          V t = T::mk(R(0));
+          if constexpr (HASQ) {
+#pragma unroll
+            for (int mm = 0; mm < P1; ++mm) t += l_own[mm] * s_q[e][c * D + k][base + mm * SD];
+          }
+          qm[c][k] = t;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < NA; ++t) {
+        R sacc = R(0);
+        if (t < md.naux) {
+          const double* ap = md.aux + (Ke * md.naux + t) * NN + base;
+#pragma unroll
+          for (int mm = 0; mm < P1; ++mm) sacc += l_own[mm] * R(ap[mm * SD]);
+        }
+        am[t] = sacc;
+      }
+      R xi2[D];
+      xi2[DIR] = side ? R(1) : R(-1);
+      xi2[T0] = tx[t0];
+      if constexpr (D == 3) xi2[T1] = tx[t1];
+      R N[D], n[D];
+      face_normal<D, DIR, R, AFF>(s_c[e], xi2, side, N);
+      R ds = R(0);
+#pragma unroll
+      for (int k = 0; k < D; ++k) ds += N[k] * N[k];
+      ds = vsqrt(ds);
+      const R ids = R(1) / ds;
+#pragma unroll
+      for (int k = 0; k < D; ++k) n[k] = N[k] * ids;
+      R wf = tw[t0];
+      if constexpr (D == 3) wf *= tw[t1];
+
+      const int F = 2 * DIR + side;
+      V Fh[NCU];
+      const int nb = m.nbr[Ke * NF + F];
+      if (nb >= 0) {
+        V up[NCU], qp[NCU][D];
+        R ap2[NA];
+#pragma unroll
+        for (int c = 0; c < NCU; ++c) {
+          const int64_t o = ((int64_t)nb * NCU + c) * NN + base;
+          V sacc = T::mk(R(0));
+#pragma unroll
+          for (int mm = 0; mm < P1; ++mm) {
+            if constexpr (MODE == 2) sacc += l_nbr[mm] * T::mk(R(u[o + mm * SD]), R(v[o + mm * SD]));
+            else sacc += l_nbr[mm] * R(u[o + mm * SD]);
+          }
+          up[c] = sacc;
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            V t = T::mk(R(0));
+            if constexpr (HASQ) {
+              const int64_t oq = (((int64_t)nb * NCU + c) * D + k) * NN + base;
+#pragma unroll
+              for (int mm = 0; mm < P1; ++mm) {
+                if constexpr (MODE == 2) t += l_nbr[mm] * T::mk(q[oq + mm * SD], dq[oq + mm * SD]);
+                else t += l_nbr[mm] * q[oq + mm * SD];
+              }
+            }
+            qp[c][k] = t;
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < NA; ++t) {
+          R sacc = R(0);
+          if (t < md.naux) {
+            const double* ap = md.aux + ((int64_t)nb * md.naux + t) * NN + base;
+#pragma unroll
+            for (int mm = 0; mm < P1; ++mm) sacc += l_nbr[mm] * R(ap[mm * SD]);
+          }
+          ap2[t] = sacc;
+        }
+        num_flux<KIND, D, V, R>(md.mu, md.naux, um, qm, am, up, qp, ap2, n, Fh);
+      } else {
+        const int b = -(nb + 1);
+        int tag = m.btag[b];
+        tag = tag < 0 ? 0 : (tag >= md.nbc ? md.nbc - 1 : tag);
+        const int kind = md.bc_kind[tag];
+        if (kind == LDG_BC_DIRICHLET) {
+          // the state outside is the data g (zero tangent); the linear operator (MODE 0) sees g = 0
+          V ub[NCU];
+#pragma unroll
+          for (int c = 0; c < NCU; ++c)
+            ub[c] = (MODE != 0 && md.bdata) ? T::mk(R(md.bdata[((int64_t)b * NCU + c) * NFP + ff])) : T::mk(R(0));
+          num_flux<KIND, D, V, R>(md.mu, md.naux, um, qm, am, ub, qm, am, n, Fh);
+        } else if (kind == LDG_BC_NEUMANN) {
+#pragma unroll
+          for (int c = 0; c < NCU; ++c)
+            Fh[c] = (MODE == 1 && md.bdata) ? T::mk(R(md.bdata[((int64_t)b * NCU + c) * NFP + ff])) : T::mk(R(0));
+        } else {
+          V fl[NCU][D];
+          phys_flux<KIND, D, V, R>(md.mu, md.naux, um, qm, am, fl);
+#pragma unroll
+          for (int c = 0; c < NCU; ++c) {
+            V sacc = fl[c][0] * n[0];
+#pragma unroll
+            for (int k = 1; k < D; ++k) sacc += fl[c][k] * n[k];
+            Fh[c] = sacc;
+          }
+        }
+      }
+      const R wds = wf * ds;
+#pragma unroll
+      for (int c = 0; c < NCU; ++c) {
+        if constexpr (MODE == 2) s_Fh[e][F][c][ff] = wds * Fh[c].d;
+        else s_Fh[e][F][c][ff] = wds * Fh[c];
+      }
+    }
+  };
+  for (int it = threadIdx.x; it < D * EPB * 2 * NFP; it += blockDim.x) {
+    const int dir = it / (EPB * 2 * NFP), loc = it % (EPB * 2 * NFP);
+    if (dir == 0) face_dir(std::integral_constant<int, 0>{}, loc);
+    else if (dir == 1) face_dir(std::integral_constant<int, 1>{}, loc);
+    else if constexpr (D == 3) face_dir(std::integral_constant<int, 2>{}, loc);
+  }
+
+  // ---- volume: flux at the node, contravariant components to LDS, pointwise terms
+  R r[NCU];
+  int a[D];
+  node_index<D, P1>(i, a);
+  if (active) {
+    R xi[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) xi[k] = tx[a[k]];
+    R J[D][D], adj[D][D];
+    jac_full<D, R, AFF>(s_c[el], xi, J);
+    const R det = adjugate<D, R>(J, adj);
+    R wi = R(1);
+#pragma unroll
+    for (int k = 0; k < D; ++k) wi *= tw[a[k]];
+    const R wdet = wi * det;
+
+    V uu[NCU];
+    V qq[NCU][D];
+#pragma unroll
+    for (int c = 0; c < NCU; ++c) {
+      uu[c] = s_u[el][c][i];
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        if constexpr (HASQ) qq[c][k] = s_q[el][c * D + k][i];
+        else qq[c][k] = T::mk(R(0));
+      }
+    }
+    R aa[NA];
+#pragma unroll
+    for (int t = 0; t < NA; ++t) aa[t] = (t < md.naux) ? R(md.aux[(K * md.naux + t) * NN + i]) : R(0);
+    V f[NCU][D];
+    phys_flux<KIND, D, V, R>(md.mu, md.naux, uu, qq, aa, f);
+#pragma unroll
+    for (int c = 0; c < NCU; ++c) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        V sacc = adj[j][0] * f[c][0];
+#pragma unroll
+        for (int k = 1; k < D; ++k) sacc += adj[j][k] * f[c][k];
+        if constexpr (MODE == 2) s_F[el][c][j][i] = wi * sacc.d;
+        else if constexpr (EXT) Fout[((K * NCU + c) * D + j) * NN + i] = float(wi * sacc);   // divergence done outside
+        else s_F[el][c][j][i] = wi * sacc;
+      }
+      R rc;
+      if constexpr (MODE == 2) {
+        rc = R(tm.a0) * wdet * uu[c].d;
+      } else {
+        const int64_t o = (K * NCU + c) * NN + i;
+        R t = R(tm.a0) * uu[c];
+        if (tm.r1) t -= R(tm.c1) * R(tm.r1[o]);
+        if (tm.r2) t -= R(tm.c2) * R(tm.r2[o]);
+        rc = wdet * t;
+        if constexpr (KIND == K_POISSON) rc += wdet * R(md.mu[2]) * uu[c];
+        if constexpr (MODE == 1) {
+          if (md.src) rc -= wdet * R(md.src[o]);
+        }
+      }
+      r[c] = rc;
+    }
+  }
+  __syncthreads();
+  if (!active) return;
+
+  // ---- contraction with the transposed derivative matrix, lifting, store
+#pragma unroll
+  for (int c = 0; c < NCU; ++c) {
+    R acc = r[c];
+#pragma unroll
+    for (int j = 0; j < D && !EXT; ++j) {
+      const int sj = stride_c(P1, j);
+      const int b0 = i - a[j] * sj;
+      R sacc = R(0);
+#pragma unroll
+      for (int mm = 0; mm < P1; ++mm) sacc += tD[mm * P1 + a[j]] * s_F[el][c][j][b0 + mm * sj];
+      acc -= sacc;
+    }
+#pragma unroll
+    for (int F = 0; F < NF; ++F) {
+      const int dir = F >> 1, side = F & 1;
+      acc += tl[side * P1 + a[dir]] * s_Fh[el][F][c][face_index_of_node<D, P1>(a, dir)];
+    }
+    const int64_t o = (K * NCU + c) * NN + i;
+    double res = double(acc);
+    if (dterm) res += dterm[o];
+    out[o] = res;
+  }
+}
+
+// ============================================================================
+// host dispatch
+// ============================================================================
+template <int KIND, int D, int P1, class R>
+static ldg_status launch_grad(const Model& md, const double* u, void* q, bool with_data, hipStream_t s) {
+  // linear models: homogeneous kernel + boundary-data offset; nonlinear: data in the kernel
+  const bool in_kernel_data = with_data && !Phys<KIND, D>::LINEAR;
+  const double* qoff = (with_data && Phys<KIND, D>::LINEAR) ? md.d_qg : nullptr;
+  constexpr int NN = GradCfg<KIND, D, P1, R>::NN, EPB = GradCfg<KIND, D, P1, R>::EPB;
+  const Mesh& m = *md.mesh;
+  const int nblk = (int)((m.E + EPB - 1) / EPB);
+  typename TabOf<R>::T tab;
+  if constexpr (std::is_same<R, double>::value) tab = m.tab; else tab = m.tabf;
+  const float* nodu = nullptr;
+  if (in_kernel_data) {
+    if (m.affine)
+      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, true, false, true>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), tab,
+                         md.dev(), u, (R*)q, qoff, nodu);
+    else
+      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, true, false, false>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), tab,
+                         md.dev(), u, (R*)q, qoff, nodu);
+  } else {
+    if (m.affine)
+      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, false, false, true>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), tab,
+                         md.dev(), u, (R*)q, qoff, nodu);
+    else
+      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, false, false, false>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), tab,
+                         md.dev(), u, (R*)q, qoff, nodu);
+  }
+  LDG_TRY(hipGetLastError());
+  return LDG_OK;
+}
+
+template <int KIND, int D, int P1, class R, int MODE>
+static ldg_status launch_resid(const Model& md, const TimeDev& t, const double* u, const void* q, const double* v,
+                               const void* dq, const double* dterm, double* out, hipStream_t s) {
+  constexpr int NN = ResidCfg<KIND, D, P1, R, MODE>::NN, EPB = ResidCfg<KIND, D, P1, R, MODE>::EPB;
+  const Mesh& m = *md.mesh;
+  const int nblk = (int)((m.E + EPB - 1) / EPB);
+  typename TabOf<R>::T tab;
+  if constexpr (std::is_same<R, double>::value) tab = m.tab; else tab = m.tabf;
+  float* noF = nullptr;
+  if (m.affine)
+    hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, true>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), tab,
+                       md.dev(), t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
+  else
+    hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, false>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), tab,
+                       md.dev(), t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
+  LDG_TRY(hipGetLastError());
+  return LDG_OK;
+}
+
+template <int KIND, int D, int P1>
+static ldg_status launch_grad_ext(const Model& md, const double* u, const float* du, float* q, hipStream_t s) {
+  constexpr int NN = GradCfg<KIND, D, P1, float>::NN, EPB = GradCfg<KIND, D, P1, float>::EPB;
+  const Mesh& m = *md.mesh;
+  const int nblk = (int)((m.E + EPB - 1) / EPB);
+  hipLaunchKernelGGL((k_grad<KIND, D, P1, float, false, true>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), m.tabf,
+                     md.dev(), u, q, (const double*)nullptr, du);
+  LDG_TRY(hipGetLastError());
+  return LDG_OK;
+}
+
+template <int KIND, int D, int P1>
+static ldg_status launch_resid_ext(const Model& md, const TimeDev& t, const double* u, const float* q, float* F,
+                                   double* out, hipStream_t s) {
+  constexpr int NN = ResidCfg<KIND, D, P1, float, 0>::NN, EPB = ResidCfg<KIND, D, P1, float, 0>::EPB;
+  const Mesh& m = *md.mesh;
+  const int nblk = (int)((m.E + EPB - 1) / EPB);
+  hipLaunchKernelGGL((k_resid<KIND, D, P1, float, 0, true>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), m.tabf,
+                     md.dev(), t, u, q, (const double*)nullptr, (const float*)nullptr, (const double*)nullptr, out, F);
+  LDG_TRY(hipGetLastError());
+  return LDG_OK;
+}
+
+// dispatch over (nd, p+1) for one model kind
+template <int KI, template <int, int, int> class F, class... Args>
+static ldg_status dispatch_kind(int nd, int p1, Args&&... args) {
+#define LDG_CASE(DD, PP) \
+  if (nd == DD && p1 == PP) return F<KI, DD, PP>::run(args...);
+  LDG_CASE(2, 2) LDG_CASE(2, 3) LDG_CASE(2, 4) LDG_CASE(2, 5) LDG_CASE(3, 2) LDG_CASE(3, 3) LDG_CASE(3, 4)
+#undef LDG_CASE
+  set_error("no compiled kernel for this (model, nd, p)");
+  return LDG_EUNSUPPORTED;
+}
+
+template <int KI, int DD, int PP>
+struct GradOp {
+  static ldg_status run(const Model& md, const double* u, void* q, bool fp32, bool with_data, hipStream_t s) {
+    if constexpr (KI == K_EULER) {
+      return LDG_OK;
+    } else {
+      if (fp32) return launch_grad<KI, DD, PP, float>(md, u, q, with_data, s);
+      return launch_grad<KI, DD, PP, double>(md, u, q, with_data, s);
+    }
+  }
+};
+
+template <int KI, int DD, int PP>
+struct ResidOp {
+  static ldg_status run(const Model& md, const TimeDev& t, const double* u, const void* q, double* out, bool fp32,
+                        bool with_data, hipStream_t s) {
+    if constexpr (KI <= K_CONVDIFF) {
+      const double* dt = with_data ? md.d_dterm : nullptr;
+      if (fp32) return launch_resid<KI, DD, PP, float, 0>(md, t, u, q, nullptr, nullptr, dt, out, s);
+      return launch_resid<KI, DD, PP, double, 0>(md, t, u, q, nullptr, nullptr, dt, out, s);
+    } else {
+      if (fp32) return launch_resid<KI, DD, PP, float, 1>(md, t, u, q, nullptr, nullptr, nullptr, out, s);
+      return launch_resid<KI, DD, PP, double, 1>(md, t, u, q, nullptr, nullptr, nullptr, out, s);
+    }
+  }
+};
+
+template <int KI, int DD, int PP>
+struct TangentOp {
+  static ldg_status run(const Model& md, const TimeDev& t, const double* u, const void* q, const double* v,
+                        const void* dq, double* out, bool fp32, hipStream_t s) {
+    if constexpr (KI <= K_CONVDIFF) {
+      set_error("tangent kernel requested for a linear model");
+      return LDG_EINVAL;
+    } else {
+      if (fp32) return launch_resid<KI, DD, PP, float, 2>(md, t, u, q, v, dq, nullptr, out, s);
+      return launch_resid<KI, DD, PP, double, 2>(md, t, u, q, v, dq, nullptr, out, s);
+    }
+  }
+};
+
+template <int KI, int DD, int PP>
+struct GradExtOp {
+  static ldg_status run(const Model& md, const double* u, const float* du, float* q, hipStream_t s) {
+    if constexpr (KI <= K_CONVDIFF) return launch_grad_ext<KI, DD, PP>(md, u, du, q, s);
+    else { set_error("external contractions are for the linear models"); return LDG_EUNSUPPORTED; }
+  }
+};
+template <int KI, int DD, int PP>
+struct ResidExtOp {
+  static ldg_status run(const Model& md, const TimeDev& t, const double* u, const float* q, float* F, double* out,
+                        hipStream_t s) {
+    if constexpr (KI <= K_CONVDIFF) return launch_resid_ext<KI, DD, PP>(md, t, u, q, F, out, s);
+    else { set_error("external contractions are for the linear models"); return LDG_EUNSUPPORTED; }
+  }
+};
+
+// per-kind entry points, defined in ldg_op_<kind>.hip
+template <int KI> struct KindOps {
+  static ldg_status grad(const Model& md, const double* u, void* q, bool fp32, bool with_data, hipStream_t s);
+  static ldg_status resid(const Model& md, const TimeDev& t, const double* u, const void* q, double* out, bool fp32,
+                          bool with_data, hipStream_t s);
+  static ldg_status tangent(const Model& md, const TimeDev& t, const double* u, const void* q, const double* v,
+                            const void* dq, double* out, bool fp32, hipStream_t s);
+  static ldg_status grad_ext(const Model& md, const double* u, const float* du, float* q, hipStream_t s);
+  static ldg_status resid_ext(const Model& md, const TimeDev& t, const double* u, const float* q, float* F,
+                              double* out, hipStream_t s);
+};
+
+#define LDG_DEFINE_KIND_OPS(KI)                                                                                  \
+  template <> ldg_status KindOps<KI>::grad(const Model& md, const double* u, void* q, bool fp32, bool with_data,  \
+                                           hipStream_t s) {                                                      \
+    return dispatch_kind<KI, GradOp>(md.mesh->nd, md.mesh->p1, md, u, q, fp32, with_data, s);                    \
+  }                                                                                                              \
+  template <> ldg_status KindOps<KI>::resid(const Model& md, const TimeDev& t, const double* u, const void* q,   \
+                                            double* out, bool fp32, bool with_data, hipStream_t s) {             \
+    return dispatch_kind<KI, ResidOp>(md.mesh->nd, md.mesh->p1, md, t, u, q, out, fp32, with_data, s);           \
+  }                                                                                                              \
+  template <> ldg_status KindOps<KI>::tangent(const Model& md, const TimeDev& t, const double* u, const void* q, \
+                                              const double* v, const void* dq, double* out, bool fp32,           \
+                                              hipStream_t s) {                                                   \
+    return dispatch_kind<KI, TangentOp>(md.mesh->nd, md.mesh->p1, md, t, u, q, v, dq, out, fp32, s);             \
+  }                                                                                                              \
+  template <> ldg_status KindOps<KI>::grad_ext(const Model& md, const double* u, const float* du, float* q,      \
+                                               hipStream_t s) {                                                  \
+    return dispatch_kind<KI, GradExtOp>(md.mesh->nd, md.mesh->p1, md, u, du, q, s);                              \
+  }                                                                                                              \
+  template <> ldg_status KindOps<KI>::resid_ext(const Model& md, const TimeDev& t, const double* u, const float* q, \
+                                                float* F, double* out, hipStream_t s) {                          \
+    return dispatch_kind<KI, ResidExtOp>(md.mesh->nd, md.mesh->p1, md, t, u, q, F, out, s);                      \
+  }
+
+}  // namespace ldg
