@@ -12,6 +12,8 @@ Newton-GMRES time-to-1e-8 for the plain FP64 block-Jacobi form and the mixed
 forms, and the oracle on a bounded sample of elements on the host (1 core).
 """
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -27,6 +29,33 @@ HBM_PEAK_GBS = 8000.0
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sources_sha256():
+    """Hash of the library's kernel sources (names and contents, sorted)."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2205_07824_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(n):
+    """HBM bytes per JVP launch from the committed TCC counter summary, or None
+    when the kernels changed since the counters were taken (or for another size)."""
+    path = os.path.join(ROOT, "profiles", "jvp_poisson3d_p3_32cube_hbm_counters.md")
+    if n != 32 or not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "sources_sha256"):
+                k, v = line.split(":", 1)
+                kv[k] = v.strip()
+    if kv.get("sources_sha256") != kernel_sources_sha256() or "traffic_bytes_per_launch" not in kv:
+        return None
+    return int(kv["traffic_bytes_per_launch"])
 
 
 def build_workload(ldg, I, n=32, p=3):
@@ -173,7 +202,7 @@ def main():
                    "dof": N, "elements": m.E, "p": 3, "quadrature": "collocated Gauss-Legendre 4^3"},
         "roofline": {"bound": "hbm", "kernel": "ldg_jvp (k_grad + k_resid, FP64)", "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "alg_bytes_per_launch": alg_bytes,
+                     "traffic": recorded_traffic(args.n), "alg_bytes_per_launch": alg_bytes,
                      "launch_us": round(e_jvp * 1e6, 3)},
     }
     if args.profile_jvp_only:

@@ -212,7 +212,7 @@ ldg_status ldg_mlp_train_step(ldg_mlp net, const float* X, const float* Y, int64
 /* Patch features of the listed elements (elem_idx DEVICE int32 [B], or NULL =
  * all elements in order) of a 2D scalar model: the element and its four face
  * neighbours (-x, +x, -y, +y; zeros outside the domain) give
- * X[B][20 nn] = [r/s (5 nn) | log kappa (5 nn) | b_x, b_y per patch element (10 nn)],
+ * X[B][20 nn] = [r/s (5 nn) | log kappa (5 nn) | b_x/100, b_y/100 per patch element (10 nn)],
  * s = ||r on the patch||_2 + 1e-300 (S[B], DEVICE double, optional), and when
  * e_target is given Y[B][nn] = e on the element / s. */
 ldg_status ldg_mlp_gather_patches(ldg_model model, const double* r, const double* e_target, const int32_t* elem_idx,

@@ -371,9 +371,10 @@ __global__ void k_gather_patches(int64_t B, const int32_t* __restrict__ elems, i
     if (el >= 0) {
       rv = (float)(r[el * nn + j] / sc);
       if (naux >= 3) {
+        // velocity features scaled by 1/100 (the workload's |b| <= 100)
         lk = (float)log(aux[(el * naux + 0) * nn + j]);
-        bx = (float)aux[(el * naux + 1) * nn + j];
-        by = (float)aux[(el * naux + 2) * nn + j];
+        bx = (float)(0.01 * aux[(el * naux + 1) * nn + j]);
+        by = (float)(0.01 * aux[(el * naux + 2) * nn + j]);
       }
     }
     Xr[t] = rv;

@@ -115,8 +115,8 @@ def test_patch_features(L):
         assert np.abs(X[row, :5 * nn] - rp / s).max() < 1e-6
         lk = np.concatenate([np.log(c.aux[k, 0]) if k >= 0 else np.zeros(nn) for k in patch])
         assert np.abs(X[row, 5 * nn:10 * nn] - lk).max() < 1e-5
-        bxy = np.concatenate([np.concatenate([c.aux[k, 1], c.aux[k, 2]]) if k >= 0 else np.zeros(2 * nn)
-                              for k in patch])
+        bxy = 0.01 * np.concatenate([np.concatenate([c.aux[k, 1], c.aux[k, 2]]) if k >= 0 else np.zeros(2 * nn)
+                                     for k in patch])
         assert np.abs(X[row, 10 * nn:] - bxy).max() < 1e-4 * (1 + np.abs(bxy).max())
         assert np.abs(Y[row] - e.reshape(m.E, nn)[K] / s).max() < 1e-6
 
