@@ -2,6 +2,7 @@
 // vector kernels, the block-wise multi-dot / update pair of classical
 // Gram-Schmidt with one re-orthogonalization pass (CGS2), Givens rotations on
 // the device, restarted flexible GMRES, and Newton's method.
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <cmath>
@@ -99,35 +100,139 @@ ldg_status vec_norm2(int64_t n, const double* x, double* part, double* host_out,
   return LDG_OK;
 }
 
-// ------------------------------------------------------- Gram-Schmidt pair ---
-// h_i = V_i . w for i = 0..j (one pass over w, j+1 basis vectors), block partials
-// part[i * nblk + b].
+// ------------------------------------------------------- Gram-Schmidt sweeps ---
+// Classical Gram-Schmidt with one re-orthogonalization (CGS2), as three streaming
+// sweeps over the basis V per Arnoldi step, each reading every basis vector once:
+//   A  h1 = V^T w, ||w||^2                       (k_cgs_dots)
+//   B  w -= V h1 ; h2 = V^T w                    (k_cgs_update_dots, nv <= 32)
+//   C  w -= V h2 ; ||w||^2                       (k_cgs_update)
+// Each work-group owns a contiguous chunk of the vectors; a thread keeps up to G
+// basis values and G dot accumulators in registers, so all loads of one element
+// index are independent.  Block partials go to part[i * nblk + b] and are reduced
+// by k_reduce_rows (deterministic, no atomics).
 constexpr int MAXM = 128;
-__global__ void __launch_bounds__(VB) k_multidot(int64_t n, int nv, const double* __restrict__ V, int64_t ldv,
-                                                 const double* __restrict__ w, double* __restrict__ part) {
-  __shared__ double sh[16];
+
+__device__ inline void chunk_of(int64_t n, int64_t* lo, int64_t* hi) {
   const int nblk = gridDim.x;
-  // each block owns a contiguous chunk; w is read once into registers per chunk pass
   const int64_t chunk = ((n + nblk - 1) / nblk + VB - 1) / VB * VB;
-  const int64_t lo = (int64_t)blockIdx.x * chunk;
-  const int64_t hi = lo + chunk < n ? lo + chunk : n;
-  for (int i0 = 0; i0 < nv; i0 += 4) {
-    double s[4] = {0, 0, 0, 0};
-    const int ni = nv - i0 < 4 ? nv - i0 : 4;
-    for (int64_t t = lo + threadIdx.x; t < hi; t += VB) {
-      const double wt = w[t];
+  *lo = (int64_t)blockIdx.x * chunk;
+  *hi = *lo + chunk < n ? *lo + chunk : n;
+}
+
+// block reduction of nr <= G values per thread; threads 0..nr-1 return the sums
+template <int G>
+__device__ inline double block_sum_many(const double (&s)[G], int nr, double (*sh)[G]) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (r < ni) s[r] += V[(int64_t)(i0 + r) * ldv + t] * wt;
-    }
+  for (int r = 0; r < G; ++r) {
+    if (r < nr) {
+      double v = s[r];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      if (r < ni) {
-        double tot = block_sum(s[r], sh);
-        if (threadIdx.x == 0) part[(int64_t)(i0 + r) * nblk + blockIdx.x] = tot;
-      }
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+      if (lane == 0) sh[wid][r] = v;
     }
   }
+  __syncthreads();
+  double t = 0.0;
+  if ((int)threadIdx.x < nr)
+    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) t += sh[w][threadIdx.x];
+  __syncthreads();
+  return t;
+}
+
+// A: part rows i < nv: V_i . w; row nv: w . w
+template <int G>
+__global__ void __launch_bounds__(VB) k_cgs_dots(int64_t n, int nv, const double* __restrict__ V, int64_t ldv,
+                                                 const double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double sh[VB / 64][G + 1];
+  int64_t lo, hi;
+  chunk_of(n, &lo, &hi);
+  const int nblk = gridDim.x;
+  for (int i0 = 0; i0 < nv; i0 += G) {
+    const int ni = nv - i0 < G ? nv - i0 : G;
+    double s[G + 1];
+#pragma unroll
+    for (int r = 0; r <= G; ++r) s[r] = 0.0;
+    for (int64_t t = lo + threadIdx.x; t < hi; t += VB) {
+      const double wt = w[t];
+      double v[G];
+#pragma unroll
+      for (int r = 0; r < G; ++r) v[r] = (r < ni) ? V[(int64_t)(i0 + r) * ldv + t] : 0.0;
+#pragma unroll
+      for (int r = 0; r < G; ++r) s[r] += v[r] * wt;
+      s[G] += wt * wt;
+    }
+    // the norm rides in slot ni of the first group
+    const int nr = (i0 == 0) ? ni + 1 : ni;
+    if (i0 == 0) {
+#pragma unroll
+      for (int r = 0; r < G; ++r)
+        if (r == ni) s[r] = s[G];
+    }
+    const double tot = block_sum_many<G + 1>(s, nr, sh);
+    if ((int)threadIdx.x < nr) {
+      const int row = (i0 == 0 && (int)threadIdx.x == ni) ? nv : i0 + (int)threadIdx.x;
+      part[(int64_t)row * nblk + blockIdx.x] = tot;
+    }
+  }
+}
+
+// B: w -= V h ; part rows i < nv: V_i . w  (nv <= G)
+template <int G>
+__global__ void __launch_bounds__(VB) k_cgs_update_dots(int64_t n, int nv, const double* __restrict__ V, int64_t ldv,
+                                                        const double* __restrict__ h, double* __restrict__ w,
+                                                        double* __restrict__ part) {
+  __shared__ double sh[VB / 64][G];
+  __shared__ double hs[G];
+  for (int i = threadIdx.x; i < G; i += blockDim.x) hs[i] = i < nv ? h[i] : 0.0;
+  __syncthreads();
+  int64_t lo, hi;
+  chunk_of(n, &lo, &hi);
+  double s[G];
+#pragma unroll
+  for (int r = 0; r < G; ++r) s[r] = 0.0;
+  for (int64_t t = lo + threadIdx.x; t < hi; t += VB) {
+    double v[G];
+#pragma unroll
+    for (int r = 0; r < G; ++r) v[r] = (r < nv) ? V[(int64_t)r * ldv + t] : 0.0;
+    double acc = w[t];
+#pragma unroll
+    for (int r = 0; r < G; ++r) acc -= hs[r] * v[r];
+    w[t] = acc;
+#pragma unroll
+    for (int r = 0; r < G; ++r) s[r] += v[r] * acc;
+  }
+  const double tot = block_sum_many<G>(s, nv, sh);
+  if ((int)threadIdx.x < nv) part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = tot;
+}
+
+// C: w -= V h (any nv, groups of G) ; npart (nullable) = block partials of w . w
+template <int G>
+__global__ void __launch_bounds__(VB) k_cgs_update(int64_t n, int nv, const double* __restrict__ V, int64_t ldv,
+                                                   const double* __restrict__ h, double* __restrict__ w,
+                                                   double* __restrict__ npart) {
+  __shared__ double sh[VB / 64][1];
+  __shared__ double hs[MAXM + 1];
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) hs[i] = h[i];
+  __syncthreads();
+  int64_t lo, hi;
+  chunk_of(n, &lo, &hi);
+  double ss[1] = {0.0};
+  for (int64_t t = lo + threadIdx.x; t < hi; t += VB) {
+    double acc = w[t];
+    for (int i0 = 0; i0 < nv; i0 += G) {
+      double v[G];
+#pragma unroll
+      for (int r = 0; r < G; ++r) v[r] = (i0 + r < nv) ? V[(int64_t)(i0 + r) * ldv + t] : 0.0;
+#pragma unroll
+      for (int r = 0; r < G; ++r)
+        if (i0 + r < nv) acc -= hs[i0 + r] * v[r];
+    }
+    w[t] = acc;
+    ss[0] += acc * acc;
+  }
+  const double tot = block_sum_many<1>(ss, 1, sh);
+  if (threadIdx.x == 0 && npart) npart[blockIdx.x] = tot;
 }
 
 // reduce the partials of nv dot products into h[0..nv) (one block per dot)
@@ -138,67 +243,6 @@ __global__ void k_reduce_rows(int nv, int nblk, const double* __restrict__ part,
   for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += part[(int64_t)i * nblk + b];
   s = block_sum(s, sh);
   if (threadIdx.x == 0 && i < nv) h[i] = s;
-}
-
-// w -= sum_i h_i V_i ; optionally the partial sums of ||w||^2 after the update
-__global__ void __launch_bounds__(VB) k_update(int64_t n, int nv, const double* __restrict__ V, int64_t ldv,
-                                               const double* __restrict__ h, double* __restrict__ w,
-                                               double* __restrict__ npart) {
-  __shared__ double sh[16];
-  __shared__ double hs[MAXM + 1];
-  for (int i = threadIdx.x; i < nv; i += blockDim.x) hs[i] = h[i];
-  __syncthreads();
-  double ss = 0.0;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
-    double acc = w[t];
-    for (int i = 0; i < nv; ++i) acc -= hs[i] * V[(int64_t)i * ldv + t];
-    w[t] = acc;
-    ss += acc * acc;
-  }
-  if (npart) {
-    ss = block_sum(ss, sh);
-    if (threadIdx.x == 0) npart[blockIdx.x] = ss;
-  }
-}
-
-// Fused: w -= sum_i h_i V_i, then the block partials of V_i . w (second CGS pass)
-// in the same sweep over V (the second read of V[i][t] hits L2).
-__global__ void __launch_bounds__(VB) k_update_multidot(int64_t n, int nv, const double* __restrict__ V, int64_t ldv,
-                                                        const double* __restrict__ h, double* __restrict__ w,
-                                                        double* __restrict__ part) {
-  __shared__ double sh[16];
-  __shared__ double hs[MAXM + 1];
-  for (int i = threadIdx.x; i < nv; i += blockDim.x) hs[i] = h[i];
-  __syncthreads();
-  const int nblk = gridDim.x;
-  const int64_t chunk = ((n + nblk - 1) / nblk + VB - 1) / VB * VB;
-  const int64_t lo = (int64_t)blockIdx.x * chunk;
-  const int64_t hi = lo + chunk < n ? lo + chunk : n;
-  for (int i0 = 0; i0 < nv; i0 += 8) {
-    // (the update is applied in the first group sweep only)
-    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const int ni = nv - i0 < 8 ? nv - i0 : 8;
-    for (int64_t t = lo + threadIdx.x; t < hi; t += VB) {
-      double acc;
-      if (i0 == 0) {
-        acc = w[t];
-        for (int i = 0; i < nv; ++i) acc -= hs[i] * V[(int64_t)i * ldv + t];
-        w[t] = acc;
-      } else {
-        acc = w[t];
-      }
-#pragma unroll
-      for (int r = 0; r < 8; ++r)
-        if (r < ni) s[r] += V[(int64_t)(i0 + r) * ldv + t] * acc;
-    }
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      if (r < ni) {
-        double tot = block_sum(s[r], sh);
-        if (threadIdx.x == 0) part[(int64_t)(i0 + r) * nblk + blockIdx.x] = tot;
-      }
-    }
-  }
 }
 
 // x += sum_i y_i Z_i
@@ -227,6 +271,7 @@ struct ArnoldiState {
   int breakdown;
 };
 
+// h1[j + 1] holds ||w||^2 before the orthogonalization
 __global__ void k_givens(ArnoldiState* st, int j, int nblk, const double* __restrict__ h1, const double* __restrict__ h2,
                          const double* __restrict__ npart) {
   __shared__ double sh[16];
@@ -234,6 +279,7 @@ __global__ void k_givens(ArnoldiState* st, int j, int nblk, const double* __rest
   for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += npart[b];
   s = block_sum(s, sh);
   if (threadIdx.x != 0) return;
+  st->wnorm0 = sqrt(h1[j + 1]);
   const int ld = MAXM + 1;
   double* col = st->H + (int64_t)j * ld;
   for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
@@ -254,15 +300,6 @@ __global__ void k_givens(ArnoldiState* st, int j, int nblk, const double* __rest
   st->g[j + 1] = -st->sn[j] * st->g[j];
   st->g[j] = st->cs[j] * st->g[j];
   st->resid = fabs(st->g[j + 1]);
-}
-
-// ||w|| before orthogonalization (for the breakdown test)
-__global__ void k_store_norm(ArnoldiState* st, int nblk, const double* __restrict__ npart) {
-  __shared__ double sh[16];
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += npart[b];
-  s = block_sum(s, sh);
-  if (threadIdx.x == 0) st->wnorm0 = sqrt(s);
 }
 
 __global__ void k_arnoldi_start(ArnoldiState* st, int nblk, const double* __restrict__ npart) {
@@ -364,6 +401,38 @@ inline int nblk_for(int64_t n) {
 
 namespace ldg {
 
+// The three CGS2 sweeps.  Register tiles: the dot sweep keeps at most 16
+// accumulators (more cost occupancy than they save in re-reads of w), the
+// update-only sweep reads the basis 8 vectors at a time, and the fused
+// update + dot sweep keeps all nv <= 32 basis values of an element index live.
+// At most 512 work-groups: fewer, longer chunks measured faster for these
+// streaming sweeps.
+template <int GB>
+static void cgs2_launch(int64_t n, int nv, int nb, Workspace& ws, hipStream_t s) {
+  if (nv <= 8) hipLaunchKernelGGL((k_cgs_dots<8>), dim3(nb), dim3(VB), 0, s, n, nv, ws.V, n, ws.w, ws.part);
+  else hipLaunchKernelGGL((k_cgs_dots<16>), dim3(nb), dim3(VB), 0, s, n, nv, ws.V, n, ws.w, ws.part);
+  hipLaunchKernelGGL(k_reduce_rows, dim3(nv + 1), dim3(VB), 0, s, nv + 1, nb, ws.part, ws.h1);
+  if (nv <= GB) {
+    hipLaunchKernelGGL((k_cgs_update_dots<GB>), dim3(nb), dim3(VB), 0, s, n, nv, ws.V, n, ws.h1, ws.w, ws.part);
+  } else {
+    hipLaunchKernelGGL((k_cgs_update<8>), dim3(nb), dim3(VB), 0, s, n, nv, ws.V, n, ws.h1, ws.w, (double*)nullptr);
+    hipLaunchKernelGGL((k_cgs_dots<16>), dim3(nb), dim3(VB), 0, s, n, nv, ws.V, n, ws.w, ws.part);
+  }
+  hipLaunchKernelGGL(k_reduce_rows, dim3(nv), dim3(VB), 0, s, nv, nb, ws.part, ws.h2);
+  hipLaunchKernelGGL((k_cgs_update<8>), dim3(nb), dim3(VB), 0, s, n, nv, ws.V, n, ws.h2, ws.w, ws.npart);
+}
+
+inline int cgs_blocks(int64_t n) { return std::min(nblk_for(n), 512); }
+
+static ldg_status cgs2(int64_t n, int nv, Workspace& ws, hipStream_t s) {
+  const int nb = cgs_blocks(n);
+  if (nv <= 8) cgs2_launch<8>(n, nv, nb, ws, s);
+  else if (nv <= 16) cgs2_launch<16>(n, nv, nb, ws, s);
+  else cgs2_launch<32>(n, nv, nb, ws, s);
+  LDG_TRY(hipGetLastError());
+  return LDG_OK;
+}
+
 // w = b - J x  -> ws.r ; returns ||r|| on the host
 static ldg_status true_residual(Model& md, const ldg_time* t, const double* u, const double* b, const double* x,
                                 ldg_precision prec, Workspace& ws, double* out_norm, hipStream_t s) {
@@ -424,10 +493,41 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
     hipLaunchKernelGGL(k_scale_dev, dim3(gV), dim3(VB), 0, s, n, &ws.st->inv_hnext, ws.r, ws.V);
     int k = 0;
     bool stop = false;
+    // Without the learned preconditioner's host-side watch, step j + 1 is queued
+    // before the host reads step j's residual estimate, so the GPU never waits for
+    // the host.  A queued step after convergence or breakdown only touches
+    // column j + 1 of H, g[j + 1..j + 2] and V[j + 2]; the solution update uses
+    // the first k columns only (a step after a breakdown works on a zero vector).
+    const bool pipelined = !watch;
+    int queued = -1;                  // last queued step whose result is unread
+    // read step jj's result (slot jj & 1); true when the cycle ends there
+    auto finish = [&](int jj) -> bool {
+      const int sl = jj & 1;
+      if (hipEventSynchronize(ws.ev[4 * sl + 3]) != hipSuccess) { result = LDG_EDEVICE; set_error("event synchronization failed"); return true; }
+      if (hipEventElapsedTime(&ms, ws.ev[4 * sl + 0], ws.ev[4 * sl + 1]) == hipSuccess) S.t_pc += ms * 1e-3;
+      if (hipEventElapsedTime(&ms, ws.ev[4 * sl + 1], ws.ev[4 * sl + 2]) == hipSuccess) S.t_jvp += ms * 1e-3;
+      if (hipEventElapsedTime(&ms, ws.ev[4 * sl + 2], ws.ev[4 * sl + 3]) == hipSuccess) S.t_orth += ms * 1e-3;
+      k = jj + 1;
+      const double res = ws.pinned[2 * sl];
+      int brk = 0;
+      std::memcpy(&brk, ws.pinned + 2 * sl + 1, sizeof(int));
+      S.res_est = res;
+      if (!std::isfinite(res)) { result = LDG_EBREAKDOWN; return true; }
+      if (watch && pc_cur == o.pc) {
+        if (watch_ref < 0) { watch_ref = res; watch_it = 0; }
+        if (++watch_it >= 10) {
+          if (res > 0.99 * watch_ref && precond_fallback(o.pc)) { pc_cur = precond_fallback(o.pc); S.fell_back = 1; }
+          watch_ref = res;
+          watch_it = 0;
+        }
+      }
+      return res <= tol || brk;
+    };
     for (int j = 0; j < m && its < o.maxit; ++j) {
+      const int sl = j & 1;
       double* vj = ws.V + (int64_t)j * n;
       double* zj = use_pc ? ws.Z + (int64_t)j * n : vj;
-      hipEventRecord(ws.ev[0], s);
+      hipEventRecord(ws.ev[4 * sl + 0], s);
       if (use_pc) {
         st = precond_apply_impl(pc_cur, vj, zj, s);
         if (st != LDG_OK) return st;
@@ -446,47 +546,37 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
           }
         }
       }
-      hipEventRecord(ws.ev[1], s);
+      hipEventRecord(ws.ev[4 * sl + 1], s);
       st = jvp_impl(md, t, u_lin, zj, ws.w, jp, true, s);
       if (st != LDG_OK) return st;
-      hipEventRecord(ws.ev[2], s);
-      // ||w|| before orthogonalization
-      hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(VB), 0, s, n, ws.w, ws.w, ws.npart);
-      hipLaunchKernelGGL(k_store_norm, dim3(1), dim3(VB), 0, s, ws.st, nb, ws.npart);
-      // CGS2: two passes of (h = V^T w ; w -= V h)
-      hipLaunchKernelGGL(k_multidot, dim3(nb), dim3(VB), 0, s, n, j + 1, ws.V, n, ws.w, ws.part);
-      hipLaunchKernelGGL(k_reduce_rows, dim3(j + 1), dim3(VB), 0, s, j + 1, nb, ws.part, ws.h1);
-      hipLaunchKernelGGL(k_update_multidot, dim3(nb), dim3(VB), 0, s, n, j + 1, ws.V, n, ws.h1, ws.w, ws.part);
-      hipLaunchKernelGGL(k_reduce_rows, dim3(j + 1), dim3(VB), 0, s, j + 1, nb, ws.part, ws.h2);
-      hipLaunchKernelGGL(k_update, dim3(gV), dim3(VB), 0, s, n, j + 1, ws.V, n, ws.h2, ws.w, ws.npart);
-      hipLaunchKernelGGL(k_givens, dim3(1), dim3(VB), 0, s, ws.st, j, gV, ws.h1, ws.h2, ws.npart);
+      hipEventRecord(ws.ev[4 * sl + 2], s);
+      // CGS2: h1 = V^T w (+ ||w||^2), w -= V h1, h2 = V^T w, w -= V h2 (+ ||w||^2)
+      st = cgs2(n, j + 1, ws, s);
+      if (st != LDG_OK) return st;
+      hipLaunchKernelGGL(k_givens, dim3(1), dim3(VB), 0, s, ws.st, j, cgs_blocks(n), ws.h1, ws.h2, ws.npart);
       hipLaunchKernelGGL(k_scale_dev, dim3(gV), dim3(VB), 0, s, n, &ws.st->inv_hnext, ws.w,
                          ws.V + (int64_t)(j + 1) * n);
       LDG_TRY(hipGetLastError());
-      hipEventRecord(ws.ev[3], s);
-      LDG_TRY(hipMemcpyAsync(ws.pinned, &ws.st->resid, sizeof(double), hipMemcpyDeviceToHost, s));
-      LDG_TRY(hipMemcpyAsync(ws.pinned + 1, &ws.st->breakdown, sizeof(int), hipMemcpyDeviceToHost, s));
-      LDG_TRY(hipStreamSynchronize(s));
-      if (hipEventElapsedTime(&ms, ws.ev[0], ws.ev[1]) == hipSuccess) S.t_pc += ms * 1e-3;
-      if (hipEventElapsedTime(&ms, ws.ev[1], ws.ev[2]) == hipSuccess) S.t_jvp += ms * 1e-3;
-      if (hipEventElapsedTime(&ms, ws.ev[2], ws.ev[3]) == hipSuccess) S.t_orth += ms * 1e-3;
+      LDG_TRY(hipMemcpyAsync(ws.pinned + 2 * sl, &ws.st->resid, sizeof(double), hipMemcpyDeviceToHost, s));
+      LDG_TRY(hipMemcpyAsync(ws.pinned + 2 * sl + 1, &ws.st->breakdown, sizeof(int), hipMemcpyDeviceToHost, s));
+      hipEventRecord(ws.ev[4 * sl + 3], s);
       ++its;
-      k = j + 1;
-      const double res = ws.pinned[0];
-      int brk = 0;
-      std::memcpy(&brk, ws.pinned + 1, sizeof(int));
-      S.res_est = res;
-      if (!std::isfinite(res)) { stop = true; result = LDG_EBREAKDOWN; break; }
-      if (watch && pc_cur == o.pc) {
-        if (watch_ref < 0) { watch_ref = res; watch_it = 0; }
-        if (++watch_it >= 10) {
-          if (res > 0.99 * watch_ref && precond_fallback(o.pc)) { pc_cur = precond_fallback(o.pc); S.fell_back = 1; }
-          watch_ref = res;
-          watch_it = 0;
-        }
+      if (!pipelined) {
+        if (finish(j)) { stop = true; break; }
+        continue;
       }
-      if (res <= tol || brk) { stop = true; break; }
+      const int prev = queued;
+      queued = j;
+      if (prev >= 0 && finish(prev)) {
+        // step j was queued past the end of the cycle: not counted
+        --its;
+        queued = -1;
+        stop = true;
+        break;
+      }
     }
+    if (queued >= 0 && result == LDG_OK) stop = finish(queued);
+    if (result == LDG_EDEVICE) return result;
     // x += Z y
     if (k > 0 && result == LDG_OK) {
       hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, s, ws.st, k);

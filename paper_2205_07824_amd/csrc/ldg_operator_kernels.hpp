@@ -32,10 +32,11 @@ template <class R> struct TabOf;
 template <> struct TabOf<double> { using T = BasisTab; };
 template <> struct TabOf<float> { using T = BasisTabF; };
 
-// Elements per work-group: fill 256 threads, bounded by an LDS budget per group.
+// Elements per work-group: fill 256 threads (2D) or 128 threads (3D elements,
+// where fewer waves per barrier measured faster), bounded by an LDS budget.
 template <int NN, int BYTES_PER_ELEM>
 constexpr int pick_epb() {
-  int e = 256 / NN;
+  int e = (NN >= 27 ? 128 : 256) / NN;
   if (e < 1) e = 1;
   while (e > 1 && e * BYTES_PER_ELEM > 40 * 1024) --e;
   return e;
@@ -156,10 +157,120 @@ __device__ inline int face_index_of_node(const int* a, int dir) {
   return f;
 }
 
+template <int D, int P1>
+struct GeoTab {
+  static constexpr int NFP = ipow(P1, D - 1), NF = 2 * D;
+  static constexpr int NVC = D * NFP;                       // volume columns
+  static constexpr int NFC = (D == 3) ? NF * 2 * P1 : NF;   // face columns
+  static constexpr int NCOL = NVC + NFC;
+  static constexpr int SIZE = NCOL * D;
+};
+
+// Column tables of one element, evaluated by its nl lanes:
+//   entry t < NVC:  column j = t / NFP at the tangential tuple t % NFP (lower direction fastest)
+//   3D face column (F, h, idx): h = 0 column A = (dir+1)%3 with xi_B = x[idx],
+//                               h = 1 column B = (dir+2)%3 with xi_A = x[idx], xi_dir = -1/+1
+//   2D face column F: column 1-dir at xi_dir = -1/+1 (constant along the edge)
+// A column j is bilinear (3D) or linear (2D) in the other coordinates, taken in
+// increasing direction order (va, vb); the code is the same for every lane.
+template <int D, int P1, class R>
+__device__ inline void build_geo(const double* c, const R* tx, R* g, int lane, int nl) {
+  using G = GeoTab<D, P1>;
+  for (int t = lane; t < G::NCOL; t += nl) {
+    int j;
+    R va;
+    if constexpr (D == 3) {
+      R vb;
+      if (t < G::NVC) {
+        j = t / G::NFP;
+        const int r = t % G::NFP;
+        va = tx[r % P1];
+        vb = tx[r / P1];
+      } else {
+        const int uu = t - G::NVC;
+        const int F = uu / (2 * P1), h = (uu / P1) & 1, idx = uu % P1;
+        const int dir = F >> 1;
+        const int A = (dir + 1) % 3, B = (dir + 2) % 3;
+        const R sd = (F & 1) ? R(1) : R(-1);
+        j = h ? B : A;
+        const int other = h ? A : B;
+        if (dir < other) { va = sd; vb = tx[idx]; } else { va = tx[idx]; vb = sd; }
+      }
+      const int o0 = (j == 0) ? 1 : 0, o1 = (j == 2) ? 1 : 2;
+      const int m0 = 1 << j, m1 = m0 | (1 << o0), m2 = m0 | (1 << o1), m3 = m1 | (1 << o1);
+      const R vab = va * vb;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        g[t * 3 + k] = R(c[m0 * 3 + k]) + R(c[m1 * 3 + k]) * va + R(c[m2 * 3 + k]) * vb + R(c[m3 * 3 + k]) * vab;
+    } else {
+      if (t < G::NVC) {
+        j = t / P1;
+        va = tx[t % P1];
+      } else {
+        const int F = t - G::NVC;
+        j = 1 - (F >> 1);
+        va = (F & 1) ? R(1) : R(-1);
+      }
+      const int m0 = 1 << j, m1 = m0 | (1 << (1 - j));
+#pragma unroll
+      for (int k = 0; k < 2; ++k) g[t * 2 + k] = R(c[m0 * 2 + k]) + R(c[m1 * 2 + k]) * va;
+    }
+  }
+}
+
+// Jacobian at node a[] from the tables (or the constant columns of an affine map)
+template <int D, int P1, class R, bool AFF>
+__device__ inline void geo_jac(const R* g, const double* __restrict__ c, const int* a, R J[D][D]) {
+  if constexpr (AFF) {
+    R xi0[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) xi0[k] = R(0);
+    jac_full<D, R, true>(c, xi0, J);
+  } else {
+    constexpr int NFP = GeoTab<D, P1>::NFP;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const R* col = g + (j * NFP + face_index_of_node<D, P1>(a, j)) * D;
+#pragma unroll
+      for (int k = 0; k < D; ++k) J[k][j] = col[k];
+    }
+  }
+}
+
+// scaled outward normal N = ds n at face point (t0, t1) of face (DIR, side)
+template <int D, int P1, int DIR, class R, bool AFF>
+__device__ inline void geo_normal(const R* g, const double* __restrict__ c, int side, int t0, int t1, R* N) {
+  if constexpr (AFF) {
+    R xi0[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) xi0[k] = R(0);
+    face_normal<D, DIR, R, true>(c, xi0, side, N);
+  } else {
+    using G = GeoTab<D, P1>;
+    const int F = 2 * DIR + side;
+    const R s = side ? R(1) : R(-1);
+    if constexpr (D == 2) {
+      const R* col = g + (G::NVC + F) * 2;
+      if constexpr (DIR == 0) { N[0] = s * col[1]; N[1] = -s * col[0]; }
+      else { N[0] = -s * col[1]; N[1] = s * col[0]; }
+    } else {
+      constexpr int A = (DIR + 1) % 3, B = (DIR + 2) % 3;
+      constexpr int T0 = Tang<3, DIR>::T0;
+      const int iB = (B == T0) ? t0 : t1;
+      const int iA = (A == T0) ? t0 : t1;
+      const R* a = g + (G::NVC + (F * 2 + 0) * P1 + iB) * 3;
+      const R* b = g + (G::NVC + (F * 2 + 1) * P1 + iA) * 3;
+      N[0] = s * (a[1] * b[2] - a[2] * b[1]);
+      N[1] = s * (a[2] * b[0] - a[0] * b[2]);
+      N[2] = s * (a[0] * b[1] - a[1] * b[0]);
+    }
+  }
+}
+
 template <int KIND, int D, int P1, class R>
 struct GradCfg {
   static constexpr int NCU = Phys<KIND, D>::NCU, NN = ipow(P1, D), NFP = ipow(P1, D - 1), NF = 2 * D, NV = 1 << D;
-  static constexpr int BYTES = sizeof(R) * (NCU * NN + NF * NCU * D * NFP) + 8 * NV * D;
+  static constexpr int BYTES = sizeof(R) * (NCU * NN + NF * NCU * D * NFP + GeoTab<D, P1>::SIZE) + 8 * NV * D;
   static constexpr int EPB = pick_epb<NN, BYTES>();
 };
 
@@ -171,7 +282,7 @@ struct ResidCfg {
   static constexpr bool HASQ = PH::HASQ;
   static constexpr int NQ = HASQ ? NCU * D : 1;
   static constexpr int BYTES = sizeof(V) * (NCU * NN + (HASQ ? NCU * D * NN : 0)) +
-                               sizeof(R) * (NCU * D * NN + NF * NCU * NFP) + 8 * NV * D;
+                               sizeof(R) * (NCU * D * NN + NF * NCU * NFP + GeoTab<D, P1>::SIZE) + 8 * NV * D;
   static constexpr int EPB = pick_epb<NN, BYTES>();
 };
 
@@ -193,6 +304,8 @@ k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const double* __restric
   __shared__ R s_u[EPB][NCU][NN];
   __shared__ R s_L[EPB][NF][NCU][D][NFP];
   __shared__ double s_c[EPB][NV * D];
+  __shared__ R s_g[EPB][AFF ? 1 : GeoTab<D, P1>::SIZE];
+  __shared__ R s_lfw[2 * P1];
 
   const int64_t eb = xcd_block(blockIdx.x, gridDim.x);
   const int el = threadIdx.x / NN, i = threadIdx.x % NN;
@@ -204,11 +317,15 @@ k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const double* __restric
     for (int c = 0; c < NCU; ++c) s_u[el][c][i] = R(u[(K * NCU + c) * NN + i]);
     for (int t = i; t < NV * D; t += NN) s_c[el][t] = m.coef[K * NV * D + t];
   }
+  for (int t = threadIdx.x; t < 2 * P1; t += blockDim.x) s_lfw[t] = R(tab.lf[t / P1][t % P1] / tab.w[t % P1]);
   __syncthreads();
   const R* tx = s_tab + L::X;
-  const R* tw = s_tab + L::W;
   const R* tD = s_tab + L::DM;
   const R* tl = s_tab + L::LF;
+  if constexpr (!AFF) {
+    if (active) build_geo<D, P1, R>(s_c[el], tx, s_g[el], i, NN);
+    __syncthreads();
+  }
 
   // ---- faces, one reference direction at a time
   auto face_dir = [&](auto dirc, const int it) {
@@ -256,12 +373,8 @@ k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const double* __restric
             uh[c] = um[c];
         }
       }
-      R xi[D];
-      xi[DIR] = side ? R(1) : R(-1);
-      xi[T0] = tx[t0];
-      if constexpr (D == 3) xi[T1] = tx[t1];
       R N[D];
-      face_normal<D, DIR, R, AFF>(s_c[e], xi, side, N);
+      geo_normal<D, P1, DIR, R, AFF>(s_g[e], s_c[e], side, t0, t1, N);
 #pragma unroll
       for (int c = 0; c < NCU; ++c)
 #pragma unroll
@@ -281,17 +394,14 @@ k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const double* __restric
 
   int a[D];
   node_index<D, P1>(i, a);
-  R xi[D];
-#pragma unroll
-  for (int k = 0; k < D; ++k) xi[k] = tx[a[k]];
   R J[D][D], adj[D][D];
-  jac_full<D, R, AFF>(s_c[el], xi, J);
+  geo_jac<D, P1, R, AFF>(s_g[el], s_c[el], a, J);
   const R det = adjugate<D, R>(J, adj);
   const R idet = R(1) / det;
   R liftw[NF];      // l_{a_dir}(side) / (w_{a_dir} det)
   int fidx[D];
 #pragma unroll
-  for (int F = 0; F < NF; ++F) liftw[F] = tl[(F & 1) * P1 + a[F >> 1]] / tw[a[F >> 1]] * idet;
+  for (int F = 0; F < NF; ++F) liftw[F] = s_lfw[(F & 1) * P1 + a[F >> 1]] * idet;
 #pragma unroll
   for (int dd = 0; dd < D; ++dd) fidx[dd] = face_index_of_node<D, P1>(a, dd);
 #pragma unroll
@@ -354,6 +464,7 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const doub
   __shared__ R s_F[EPB][NCU][D][NN];
   __shared__ R s_Fh[EPB][NF][NCU][NFP];
   __shared__ double s_c[EPB][NV * D];
+  __shared__ R s_g[EPB][AFF ? 1 : GeoTab<D, P1>::SIZE];
 
   const int64_t eb = xcd_block(blockIdx.x, gridDim.x);
   const int el = threadIdx.x / NN, i = threadIdx.x % NN;
@@ -384,6 +495,10 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const doub
   const R* tw = s_tab + L::W;
   const R* tD = s_tab + L::DM;
   const R* tl = s_tab + L::LF;
+  if constexpr (!AFF) {
+    if (active) build_geo<D, P1, R>(s_c[el], tx, s_g[el], i, NN);
+    __syncthreads();
+  }
 
   // ---- faces: numerical flux times w ds, to LDS, one reference direction at a time
   auto face_dir = [&](auto dirc, const int it) {
@@ -427,12 +542,8 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const doub
         }
         am[t] = sacc;
       }
-      R xi2[D];
-      xi2[DIR] = side ? R(1) : R(-1);
-      xi2[T0] = tx[t0];
-      if constexpr (D == 3) xi2[T1] = tx[t1];
       R N[D], n[D];
-      face_normal<D, DIR, R, AFF>(s_c[e], xi2, side, N);
+      geo_normal<D, P1, DIR, R, AFF>(s_g[e], s_c[e], side, t0, t1, N);
       R ds = R(0);
 #pragma unroll
       for (int k = 0; k < D; ++k) ds += N[k] * N[k];
@@ -532,11 +643,8 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const doub
   int a[D];
   node_index<D, P1>(i, a);
   if (active) {
-    R xi[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) xi[k] = tx[a[k]];
     R J[D][D], adj[D][D];
-    jac_full<D, R, AFF>(s_c[el], xi, J);
+    geo_jac<D, P1, R, AFF>(s_g[el], s_c[el], a, J);
     const R det = adjugate<D, R>(J, adj);
     R wi = R(1);
 #pragma unroll

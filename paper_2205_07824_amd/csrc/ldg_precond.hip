@@ -125,21 +125,37 @@ __global__ void __launch_bounds__(256) k_gj_invert(int nb, double* __restrict__ 
   }
 }
 
-// z_b = B_b^-1 r_b with the transposed inverse; one thread per row, BPB blocks per group
-template <class S>
-__global__ void __launch_bounds__(256) k_bj_apply(int nb, int64_t nblocks, int bpb, const S* __restrict__ inv,
+// z_b = B_b^-1 r_b with the transposed inverse (M[j][i] = inverse[i][j]): one
+// thread per row, bpb blocks per work-group, r_b staged in LDS.  For each j the
+// threads of a block read one contiguous row of M; four partial sums keep four
+// loads in flight per thread.  NB > 0: block size fixed at compile time (loop
+// fully unrolled); NB = 0: any block size.
+template <class S, int NB>
+__global__ void __launch_bounds__(1024) k_bj_apply(int nb_rt, int64_t nblocks, int bpb, const S* __restrict__ inv,
                                                   const double* __restrict__ r, double* __restrict__ z) {
   extern __shared__ double rs[];
+  const int nb = NB > 0 ? NB : nb_rt;
   const int lb = threadIdx.x / nb, i = threadIdx.x % nb;
   const int64_t b = (int64_t)blockIdx.x * bpb + lb;
   const bool act = lb < bpb && b < nblocks;
   if (act) rs[lb * nb + i] = r[b * nb + i];
   __syncthreads();
   if (!act) return;
-  const S* M = inv + b * (int64_t)nb * nb;
-  double acc = 0.0;
-  for (int j = 0; j < nb; ++j) acc += (double)M[j * nb + i] * rs[lb * nb + j];
-  z[b * nb + i] = acc;
+  const S* M = inv + b * (int64_t)nb * nb + i;
+  const double* rb = rs + lb * nb;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if constexpr (NB > 0) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[j & 3] += (double)M[j * NB] * rb[j];
+  } else {
+    int j = 0;
+    for (; j + 4 <= nb; j += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += (double)M[(j + u) * nb] * rb[j + u];
+    }
+    for (; j < nb; ++j) acc[0] += (double)M[j * nb] * rb[j];
+  }
+  z[b * nb + i] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
 static ldg_status assemble_blocks(Model& md, const ldg_time* t, const double* u_lin, int per_variable,
@@ -215,12 +231,19 @@ ldg_status precond_apply_impl(ldg_precond_s* pc, const double* r, double* z, hip
   if (bpb < 1) bpb = 1;
   const unsigned grid = (unsigned)((pc->nblocks + bpb - 1) / bpb);
   const size_t sh = (size_t)bpb * nb * sizeof(double);
-  if (pc->prec == LDG_FP32)
-    hipLaunchKernelGGL(k_bj_apply<float>, dim3(grid), dim3(bpb * nb), sh, s, nb, pc->nblocks, bpb,
-                       (const float*)pc->inv, r, z);
-  else
-    hipLaunchKernelGGL(k_bj_apply<double>, dim3(grid), dim3(bpb * nb), sh, s, nb, pc->nblocks, bpb,
-                       (const double*)pc->inv, r, z);
+  const dim3 thr(bpb * nb);
+  if (nb > 1024) { set_error("block-Jacobi blocks larger than 1024 rows"); return LDG_EUNSUPPORTED; }
+  if (pc->prec == LDG_FP32) {
+    if (nb == 64)
+      hipLaunchKernelGGL((k_bj_apply<float, 64>), dim3(grid), thr, sh, s, nb, pc->nblocks, bpb, (const float*)pc->inv, r, z);
+    else
+      hipLaunchKernelGGL((k_bj_apply<float, 0>), dim3(grid), thr, sh, s, nb, pc->nblocks, bpb, (const float*)pc->inv, r, z);
+  } else {
+    if (nb == 64)
+      hipLaunchKernelGGL((k_bj_apply<double, 64>), dim3(grid), thr, sh, s, nb, pc->nblocks, bpb, (const double*)pc->inv, r, z);
+    else
+      hipLaunchKernelGGL((k_bj_apply<double, 0>), dim3(grid), thr, sh, s, nb, pc->nblocks, bpb, (const double*)pc->inv, r, z);
+  }
   LDG_TRY(hipGetLastError());
   return LDG_OK;
 }
