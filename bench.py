@@ -128,6 +128,50 @@ def other_workloads(ldg, I, log):
     log("ns", res)
     del md, m, u, v, Jv
     torch.cuda.empty_cache()
+    # the Poisson workload scaled to 96^3 (N = 56.6M, vectors larger than the 256 MB last-level cache)
+    box, m, md = build_workload(ldg, I, n=96)
+    v = torch.as_tensor(np.random.default_rng(2).uniform(-1, 1, md.N), device="cuda")
+    Jv = md.empty()
+    for nm, pr in (("fp64", ldg.FP64), ("fp32", ldg.FP32)):
+        md.jvp(None, v, out=Jv, prec=pr)
+        e = event_time(lambda: md.jvp(None, v, out=Jv, prec=pr), 20)
+        res[f"poisson3d_p3_96cube_jvp_{nm}_gdofs"] = round(md.N / e / 1e9, 3)
+        res[f"poisson3d_p3_96cube_jvp_{nm}_us"] = round(e * 1e6, 1)
+    res["poisson3d_p3_96cube_dof"] = md.N
+    log("poisson 96^3", res)
+    del md, m, v, Jv, box
+    torch.cuda.empty_cache()
+    return res
+
+
+def implicit_steps(ldg, I, log, nsteps=5):
+    """2D Euler, four isentropic vortices, 256^2 p=4 periodic: BDF1 then BDF2 steps at CFL 10, each solved by
+    Newton-GMRES(50) + block-Jacobi (rebuilt per Newton iterate), eta = 1e-3, ||G|| <= 1e-8 ||G0||."""
+    import torch
+    from paper_2205_07824_amd import timestep as TS
+    box = I.box_mesh(2, 256, lo=(0, 0), hi=(20, 20), periodic=(True, True))
+    m = ldg.Mesh(box, 4)
+    xn, _, _, _ = m.points()
+    Ut = I.isentropic_vortices(xn, I.vortex_centres(4, 20.0, 5.0, 0)).transpose(0, 2, 1)
+    dt = TS.euler_cfl_dt(Ut, 2, 20.0 / 256, 10.0)
+    md = ldg.Model(m, ldg.MODEL_EULER, 4, [1.4])
+    u0 = torch.as_tensor(np.ascontiguousarray(Ut).reshape(-1), device="cuda")
+    res = {"workload": "2D Euler p=4, 256^2 periodic [0,20]^2, 4 isentropic vortices, BDF2 at CFL 10",
+           "dof": md.N, "dt": dt, "steps": nsteps}
+    for name, jp, bp in (("fp64_jvp+fp64_bj", ldg.FP64, ldg.FP64), ("fp32_jvp+fp32_bj", ldg.FP32, ldg.FP32)):
+        _, stats = TS.bdf_steps(md, u0, dt, nsteps, restart=50, eta=1e-3, rtol=1e-8, jvp_prec=jp, bj_prec=bp,
+                                log=log)
+        later = stats[1:] if len(stats) > 1 else stats
+        res[name] = {"seconds_per_step_2_to_%d" % nsteps: round(float(np.mean([r["seconds"] for r in later])), 4),
+                     "all_converged": all(r["converged"] for r in stats) and len(stats) == nsteps,
+                     "newton_iters": [r["newton_iters"] for r in stats],
+                     "gmres_iters": [r["gmres_iters"] for r in stats],
+                     "t_jvp_s": round(sum(r["t_jvp"] for r in later), 4),
+                     "t_pc_s": round(sum(r["t_pc"] for r in later), 4),
+                     "t_orth_s": round(sum(r["t_orth"] for r in later), 4)}
+        log(name, res[name])
+    del md, m, u0
+    torch.cuda.empty_cache()
     return res
 
 
@@ -140,7 +184,9 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra-workloads", action="store_true",
-                    help="skip the 2D Euler and 3D Navier-Stokes JVP throughput legs")
+                    help="skip the 2D Euler, 3D Navier-Stokes and 96^3 Poisson JVP throughput legs")
+    ap.add_argument("--no-implicit", action="store_true",
+                    help="skip the 2D Euler BDF2 Newton-GMRES steps")
     ap.add_argument("--profile-jvp-only", action="store_true",
                     help="only the timed JVP steps (for counter collection)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -259,6 +305,10 @@ def main():
     if not args.no_extra_workloads:
         out["other_workloads"] = other_workloads(ldg, I, log)
 
+    # implicit time steps on the 2D Euler workload (seconds per step averaged over steps 2..5)
+    if not args.no_implicit:
+        out["implicit_steps"] = implicit_steps(ldg, I, log)
+
     # oracle on a bounded sample of elements, host, one core
     if not args.no_cpu:
         try:
@@ -271,7 +321,7 @@ def main():
                           bdata=ub.reshape(om.nbf, 1, om.nqf), bc_kind=[0])
             vv = v.cpu().numpy()
             uu = np.zeros(N)
-            sel = np.arange(0, om.E, max(1, om.E // 4096), dtype=np.int64)[:4096]
+            sel = np.arange(0, om.E, max(1, om.E // 12288), dtype=np.int64)[:12288]
             t0 = time.process_time()
             _, Jv_s = om.sample(omd, uu, vv, sel)
             tc = time.process_time() - t0

@@ -215,6 +215,35 @@ def test_newton_euler_bdf2_step_matches_oracle(L):
     assert rel(u.cpu().numpy(), u_ref) < 1e-8
 
 
+def test_bdf_steps_match_oracle(L):
+    """Three implicit steps (backward Euler, then BDF2) of the Euler vortex case against the oracle's Newton
+    with sparse direct solves on the same step sequence."""
+    import scipy.sparse.linalg as spla
+    import oracle as O
+    from paper_2205_07824_amd import timestep as TS
+    c = CS.c3_euler2d(n=4, p=3)
+    _say("case c3 bdf steps")
+    m, md, t, dev = build_gpu(L, c)
+    base = c.oracle_model()
+    dt, nsteps = 0.5, 3
+    u = c.u.copy()
+    u_prev = None
+    for k in range(nsteps):
+        un = u.copy()
+        if k == 0:
+            om = base.replace(a0=1.0 / dt, r=un / dt)
+        else:
+            om = base.replace(a0=1.5 / dt, r=(2.0 / dt) * un - (0.5 / dt) * u_prev)
+        G = lambda x, om=om: c.om.residual(om, x)
+        solve = lambda x, rhs, om=om: spla.spsolve(c.om.jacobian(om, x).tocsc(), rhs)
+        u, info = O.newton(G, solve, un.copy(), rtol=1e-13, maxit=12)
+        u_prev = un
+    ug, stats = TS.bdf_steps(md, dev(c.u.copy()), dt, nsteps, restart=50, eta=1e-10, rtol=1e-12, newton_maxit=12)
+    _say("bdf stats", stats)
+    assert len(stats) == nsteps and all(s["converged"] for s in stats)
+    assert rel(ug.cpu().numpy(), u) < 1e-8
+
+
 def test_gmres_failure_paths(L):
     c = CS.c1_poisson2d()
     _say("case c1 failure paths")
