@@ -233,6 +233,7 @@ typedef struct {
   ldg_precision jvp_prec; /* precision of the Jacobian-vector products            */
   ldg_precond pc;         /* NULL = no preconditioner                             */
   int inject_fault;       /* test hook: 1 = poison the preconditioner output with NaN */
+  int orth;               /* 0 = CGS2 (three streaming sweeps over the basis), 1 = modified Gram-Schmidt */
 } ldg_gmres_opts;
 
 typedef struct {
@@ -242,8 +243,9 @@ typedef struct {
 } ldg_gmres_stats;
 
 /* Solves J(u_lin) x = b by restarted (F)GMRES with classical Gram-Schmidt and
- * one re-orthogonalization pass (CGS2) in FP64, Givens rotations in FP64 on the
- * host.  x holds the initial guess on entry and the solution on exit.
+ * one re-orthogonalization pass (CGS2, or modified Gram-Schmidt with orth = 1)
+ * in FP64, Givens rotations in FP64 on the device.  x holds the initial guess on
+ * entry and the solution on exit.
  * Returns LDG_ENOCONV if maxit is reached, LDG_EBREAKDOWN on a non-finite
  * value. */
 ldg_status ldg_gmres_solve(ldg_model model, const ldg_time* t, const double* u_lin, const double* b, double* x,

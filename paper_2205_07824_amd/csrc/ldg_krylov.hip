@@ -35,6 +35,14 @@ __global__ void k_scale_dev(int64_t n, const double* __restrict__ sc, const doub
     y[i] = a * x[i];
 }
 
+// y -= a[0] x (a on the device)
+__global__ void k_axmy_dev(int64_t n, const double* __restrict__ a, const double* __restrict__ x,
+                           double* __restrict__ y) {
+  const double c = *a;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] -= c * x[i];
+}
+
 __device__ inline double block_sum(double v, double* sh) {
   // wave64 shuffle reduction, then across waves through LDS
 #pragma unroll
@@ -433,6 +441,25 @@ static ldg_status cgs2(int64_t n, int nv, Workspace& ws, hipStream_t s) {
   return LDG_OK;
 }
 
+// Modified Gram-Schmidt (one pass): for i = 0..nv-1, h1_i = V_i . w, w -= h1_i V_i.
+// Leaves h2 = 0, h1[nv] = ||w||^2 before the orthogonalization and the block
+// partials of the final ||w||^2 in npart, as the CGS2 path does.
+static ldg_status mgs(int64_t n, int nv, Workspace& ws, hipStream_t s) {
+  const int nb = cgs_blocks(n);
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(VB), 0, s, (int64_t)(MAXM + 1), 0.0, ws.h2);
+  hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(VB), 0, s, n, ws.w, ws.w, ws.part);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(VB), 0, s, nb, ws.part, ws.h1 + nv);
+  for (int i = 0; i < nv; ++i) {
+    const double* vi = ws.V + (int64_t)i * n;
+    hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(VB), 0, s, n, vi, ws.w, ws.part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(VB), 0, s, nb, ws.part, ws.h1 + i);
+    hipLaunchKernelGGL(k_axmy_dev, dim3(nb), dim3(VB), 0, s, n, ws.h1 + i, vi, ws.w);
+  }
+  hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(VB), 0, s, n, ws.w, ws.w, ws.npart);
+  LDG_TRY(hipGetLastError());
+  return LDG_OK;
+}
+
 // w = b - J x  -> ws.r ; returns ||r|| on the host
 static ldg_status true_residual(Model& md, const ldg_time* t, const double* u, const double* b, const double* x,
                                 ldg_precision prec, Workspace& ws, double* out_norm, hipStream_t s) {
@@ -453,6 +480,7 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
   const int64_t n = (int64_t)md.N();
   const int m = o.restart;
   if (m < 1 || m > MAXM) { set_error("restart must be in [1, 128]"); return LDG_EINVAL; }
+  if (o.orth != 0 && o.orth != 1) { set_error("orth must be 0 (CGS2) or 1 (MGS)"); return LDG_EINVAL; }
   if (!g_ws_ptr) g_ws_ptr = new Workspace();
   Workspace& ws = *g_ws_ptr;
   ldg_status st = ws.ensure(n, m);
@@ -550,8 +578,8 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
       st = jvp_impl(md, t, u_lin, zj, ws.w, jp, true, s);
       if (st != LDG_OK) return st;
       hipEventRecord(ws.ev[4 * sl + 2], s);
-      // CGS2: h1 = V^T w (+ ||w||^2), w -= V h1, h2 = V^T w, w -= V h2 (+ ||w||^2)
-      st = cgs2(n, j + 1, ws, s);
+      // CGS2: h1 = V^T w (+ ||w||^2), w -= V h1, h2 = V^T w, w -= V h2 (+ ||w||^2); or MGS
+      st = o.orth == 1 ? mgs(n, j + 1, ws, s) : cgs2(n, j + 1, ws, s);
       if (st != LDG_OK) return st;
       hipLaunchKernelGGL(k_givens, dim3(1), dim3(VB), 0, s, ws.st, j, cgs_blocks(n), ws.h1, ws.h2, ws.npart);
       hipLaunchKernelGGL(k_scale_dev, dim3(gV), dim3(VB), 0, s, n, &ws.st->inv_hnext, ws.w,

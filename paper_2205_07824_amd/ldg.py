@@ -43,7 +43,8 @@ class _ModelDesc(C.Structure):
 
 class GmresOpts(C.Structure):
     _fields_ = [("restart", C.c_int), ("maxit", C.c_int), ("flexible", C.c_int), ("rtol", C.c_double),
-                ("atol", C.c_double), ("jvp_prec", C.c_int), ("pc", C.c_void_p), ("inject_fault", C.c_int)]
+                ("atol", C.c_double), ("jvp_prec", C.c_int), ("pc", C.c_void_p), ("inject_fault", C.c_int),
+                ("orth", C.c_int)]
 
 
 class GmresStats(C.Structure):
@@ -348,8 +349,13 @@ class LearnedPrecond:
             self.h = None
 
 
-def gmres_opts(restart=30, maxit=1000, rtol=1e-8, atol=0.0, jvp_prec=FP64, pc=None, flexible=True, inject_fault=0):
-    return GmresOpts(restart, maxit, int(flexible), rtol, atol, jvp_prec, None if pc is None else pc.h, inject_fault)
+ORTH_CGS2, ORTH_MGS = 0, 1
+
+
+def gmres_opts(restart=30, maxit=1000, rtol=1e-8, atol=0.0, jvp_prec=FP64, pc=None, flexible=True, inject_fault=0,
+               orth=ORTH_CGS2):
+    return GmresOpts(restart, maxit, int(flexible), rtol, atol, jvp_prec, None if pc is None else pc.h, inject_fault,
+                     orth)
 
 
 def gmres(model, b, x=None, u_lin=None, time=None, check=True, **kw):

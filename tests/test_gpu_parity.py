@@ -196,6 +196,21 @@ def test_gmres_without_preconditioner_and_cgs2_orthogonality(L):
     assert L.norm(r) <= 1.01e-9 * L.norm(b)
 
 
+def test_gmres_modified_gram_schmidt_matches_cgs2(L):
+    c = CS.c5_convdiff2d()
+    _say("case c5 gmres mgs vs cgs2")
+    m, md, t, dev = build_gpu(L, c)
+    N = c.om.size(1)
+    b = dev(np.random.default_rng(9).uniform(-1, 1, N))
+    pc = L.BlockJacobi(md)
+    x1, s1, st1 = L.gmres(md, b, pc=pc, restart=40, rtol=1e-10, maxit=4000, orth=L.ORTH_CGS2)
+    x2, s2, st2 = L.gmres(md, b, pc=pc, restart=40, rtol=1e-10, maxit=4000, orth=L.ORTH_MGS)
+    _say("cgs2", s1["iters"], "mgs", s2["iters"])
+    assert st1 == st2 == L.LDG_OK
+    assert abs(s1["iters"] - s2["iters"]) <= 2
+    assert (x1 - x2).norm().item() <= 1e-7 * x1.norm().item()
+
+
 def test_newton_euler_bdf2_step_matches_oracle(L):
     import scipy.sparse.linalg as spla
     import torch
