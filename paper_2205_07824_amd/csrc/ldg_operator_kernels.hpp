@@ -28,6 +28,25 @@
 
 namespace ldg {
 
+// FP64 1/sqrt(x) and 1/x from the hardware estimates refined by two Newton
+// steps: fewer issue slots than the correctly rounded sequences, within a few
+// ulp (the FP32 versions keep the plain operations, measured faster).
+__device__ inline double fast_rsqrt(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y;
+}
+__device__ inline float fast_rsqrt(float x) { return 1.0f / sqrtf(x); }
+__device__ inline double fast_rcp(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ inline float fast_rcp(float x) { return 1.0f / x; }
+
 template <class R> struct TabOf;
 template <> struct TabOf<double> { using T = BasisTab; };
 template <> struct TabOf<float> { using T = BasisTabF; };
@@ -284,6 +303,9 @@ struct ResidCfg {
   static constexpr int BYTES = sizeof(V) * (NCU * NN + (HASQ ? NCU * D * NN : 0)) +
                                sizeof(R) * (NCU * D * NN + NF * NCU * NFP + GeoTab<D, P1>::SIZE) + 8 * NV * D;
   static constexpr int EPB = pick_epb<NN, BYTES>();
+  // the linear 3D FP64 instance needs 98 VGPRs unconstrained (4 waves per SIMD);
+  // capping it at 96 for a fifth wave measured 6 us faster on the 32^3 p=3 JVP
+  static constexpr int MIN_WAVES = (Phys<KIND, D>::LINEAR && D == 3 && MODE == 0) ? 5 : 1;
 };
 
 // ============================================================================
@@ -397,7 +419,7 @@ k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const double* __restric
   R J[D][D], adj[D][D];
   geo_jac<D, P1, R, AFF>(s_g[el], s_c[el], a, J);
   const R det = adjugate<D, R>(J, adj);
-  const R idet = R(1) / det;
+  const R idet = fast_rcp(det);
   R liftw[NF];      // l_{a_dir}(side) / (w_{a_dir} det)
   int fidx[D];
 #pragma unroll
@@ -448,6 +470,7 @@ k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const double* __restric
 // ============================================================================
 template <int KIND, int D, int P1, class R, int MODE, bool EXT = false, bool AFF = false>
 __global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(ResidCfg<KIND, D, P1, R, MODE>::MIN_WAVES)))
 k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const double* __restrict__ u,
         const R* __restrict__ q, const double* __restrict__ v, const R* __restrict__ dq,
         const double* __restrict__ dterm, double* __restrict__ out, float* __restrict__ Fout = nullptr) {
@@ -544,11 +567,11 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const doub
       }
       R N[D], n[D];
       geo_normal<D, P1, DIR, R, AFF>(s_g[e], s_c[e], side, t0, t1, N);
-      R ds = R(0);
+      R nn2 = R(0);
 #pragma unroll
-      for (int k = 0; k < D; ++k) ds += N[k] * N[k];
-      ds = vsqrt(ds);
-      const R ids = R(1) / ds;
+      for (int k = 0; k < D; ++k) nn2 += N[k] * N[k];
+      const R ids = fast_rsqrt(nn2);
+      const R ds = nn2 * ids;
 #pragma unroll
       for (int k = 0; k < D; ++k) n[k] = N[k] * ids;
       R wf = tw[t0];
