@@ -1,0 +1,61 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark
+times, on sampled elements the oracle evaluates one by one (needs an MI355X).
+
+The GPU evaluates R(u) (with the time wrapper and data terms) and J(u)v over the
+whole mesh; the oracle computes G_K and (Jv)_K on a seeded sample of elements
+(each from its own neighbourhood).  Tolerances: relative 2-norm over the sample,
+1e-12 in FP64 and 1e-5 in FP32.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from tests import cases as CS
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    from paper_2205_07824_amd import ldg
+    assert torch.cuda.is_available()
+    ldg.lib()
+    return ldg
+
+
+# (case, size, sampled elements): the 32^3 Poisson, 256^2 Euler, 128^2 convection-diffusion and
+# 64^3 Navier-Stokes workloads
+@pytest.mark.parametrize("name,n,nsamp", [("c2", 32, 512), ("c3", 256, 256), ("c5", 128, 512), ("c4", 64, 48)])
+def test_full_size_sampled_parity(L, name, n, nsamp):
+    import torch
+    _say("full-size case", name, "n", n)
+    c = CS.ALL[name](n=n)
+    m = L.Mesh(c.box, c.p, c.nq)
+    md = L.Model(m, c.kind, c.ncu, c.mu, aux=c.aux, src=c.src, bdata=c.bdata, bc_kind=c.bc_kind)
+    dev = lambda a: None if a is None else torch.as_tensor(a, dtype=torch.float64, device="cuda").contiguous()
+    t = None
+    if c.a0 or c.r1 is not None:
+        t = L.Time(a0=c.a0, r1=dev(c.r1), c1=c.c1, r2=dev(c.r2), c2=c.c2)
+    sel = np.sort(np.random.default_rng(5).choice(m.E, nsamp, replace=False)).astype(np.int64)
+    G_ref, Jv_ref = c.om.sample(c.oracle_model(), c.u, c.v, sel)
+    u, v = dev(c.u), dev(c.v)
+    nb = c.ncu * m.nn
+    for prec, tol in ((L.FP64, 1e-12), (L.FP32, 1e-5)):
+        G = md.residual(u, time=t, prec=prec).cpu().numpy().reshape(m.E, nb)[sel]
+        Jv = md.jvp(u, v, time=t, prec=prec).cpu().numpy().reshape(m.E, nb)[sel]
+        eg, ej = rel(G, G_ref), rel(Jv, Jv_ref)
+        _say(name, "prec", prec, "residual rel err", eg, "jvp rel err", ej)
+        assert eg < tol and ej < tol
+    del md, m
+    torch.cuda.empty_cache()
