@@ -103,7 +103,8 @@ const char* ldg_last_error(void);
  * matching, boundary-face list and tags, distance-2 element colouring (used to
  * probe Jacobian diagonal blocks), multilinear geometry.  Section 3.2 (mesh
  * module for simple geometries).
- *   nd in {2,3}; p in [1,5]; nq1d >= p+1
+ *   nd in {2,3}; p in [1,5]; nq1d >= p+1 (the operator kernels exist for quads with
+ *             p <= 4 and hexes with p <= 3: ldg_model_create rejects other orders)
  *   vert      HOST [nvert][nd]
  *   elem_vert HOST [nelem][2^nd], lexicographic corners
  *   period    HOST [nd], >0 marks a periodic direction of that length (vertices

@@ -362,6 +362,14 @@ ldg_status ldg_mesh_destroy(ldg_mesh m) {
 ldg_status ldg_model_create(ldg_mesh m, const ldg_model_desc* d, void* stream, ldg_model* out) {
   LDG_ENTER();
   CHECK_ARG(m && d && out, "null argument");
+  {
+    // operator kernels are compiled for quads with p <= 4 and hexes with p <= 3
+    const ldg::Mesh& mm = *m;
+    if ((mm.nd == 2 && mm.p1 > 5) || (mm.nd == 3 && mm.p1 > 4)) {
+      set_error("no operator kernels for this order: quads take p <= 4, hexes p <= 3");
+      return LDG_EUNSUPPORTED;
+    }
+  }
   CHECK_ARG(d->kind >= 0 && d->kind <= 3, "unknown model kind");
   const int want_ncu = d->kind <= 1 ? 1 : m->nd + 2;
   CHECK_ARG(d->ncu == want_ncu, "ncu inconsistent with the model");

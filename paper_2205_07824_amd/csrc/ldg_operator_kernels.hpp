@@ -30,14 +30,13 @@ namespace ldg {
 
 // FP64 1/sqrt(x) and 1/x from the hardware estimates refined by two Newton
 // steps: fewer issue slots than the correctly rounded sequences, within a few
-// ulp (the FP32 versions keep the plain operations, measured faster).
+// ulp (the FP32 kernels keep the plain operations, measured faster there).
 __device__ inline double fast_rsqrt(double x) {
   double y = __builtin_amdgcn_rsq(x);
   y = y * (1.5 - 0.5 * x * y * y);
   y = y * (1.5 - 0.5 * x * y * y);
   return y;
 }
-__device__ inline float fast_rsqrt(float x) { return 1.0f / sqrtf(x); }
 __device__ inline double fast_rcp(double x) {
   double y = __builtin_amdgcn_rcp(x);
   double e = fma(-x, y, 1.0);
@@ -45,7 +44,6 @@ __device__ inline double fast_rcp(double x) {
   e = fma(-x, y, 1.0);
   return fma(y, e, y);
 }
-__device__ inline float fast_rcp(float x) { return 1.0f / x; }
 
 template <class R> struct TabOf;
 template <> struct TabOf<double> { using T = BasisTab; };
@@ -305,7 +303,8 @@ struct ResidCfg {
   static constexpr int EPB = pick_epb<NN, BYTES>();
   // the linear 3D FP64 instance needs 98 VGPRs unconstrained (4 waves per SIMD);
   // capping it at 96 for a fifth wave measured 6 us faster on the 32^3 p=3 JVP
-  static constexpr int MIN_WAVES = (Phys<KIND, D>::LINEAR && D == 3 && MODE == 0) ? 5 : 1;
+  static constexpr int MIN_WAVES =
+      (Phys<KIND, D>::LINEAR && D == 3 && MODE == 0 && std::is_same<R, double>::value) ? 5 : 1;
 };
 
 // ============================================================================
@@ -419,7 +418,7 @@ k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const double* __restric
   R J[D][D], adj[D][D];
   geo_jac<D, P1, R, AFF>(s_g[el], s_c[el], a, J);
   const R det = adjugate<D, R>(J, adj);
-  const R idet = fast_rcp(det);
+  const R idet = std::is_same<R, double>::value ? R(fast_rcp(double(det))) : R(1) / det;
   R liftw[NF];      // l_{a_dir}(side) / (w_{a_dir} det)
   int fidx[D];
 #pragma unroll
@@ -570,8 +569,14 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const doub
       R nn2 = R(0);
 #pragma unroll
       for (int k = 0; k < D; ++k) nn2 += N[k] * N[k];
-      const R ids = fast_rsqrt(nn2);
-      const R ds = nn2 * ids;
+      R ds, ids;
+      if constexpr (std::is_same<R, double>::value) {
+        ids = fast_rsqrt(nn2);
+        ds = nn2 * ids;
+      } else {
+        ds = vsqrt(nn2);
+        ids = R(1) / ds;
+      }
 #pragma unroll
       for (int k = 0; k < D; ++k) n[k] = N[k] * ids;
       R wf = tw[t0];

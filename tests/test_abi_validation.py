@@ -33,6 +33,12 @@ def test_bad_dimensions_and_orders():
     assert _create(2, 2, 2, box.vert, box.elem_vert)[0] == 1   # fewer quadrature points than nodes
 
 
+def test_empty_mesh_rejected():
+    box = I.box_mesh(2, 2)
+    st, msg = _create(2, 1, 2, box.vert, box.elem_vert[:0])
+    assert st == 1 and "sizes" in msg
+
+
 def test_vertex_index_out_of_range():
     box = I.box_mesh(2, 2)
     ev = box.elem_vert.copy()

@@ -259,6 +259,47 @@ def test_bdf_steps_match_oracle(L):
     assert rel(ug.cpu().numpy(), u) < 1e-8
 
 
+@pytest.mark.parametrize("nd,p", [(2, 2), (3, 3), (3, 1)])
+def test_single_element_mesh(L, nd, p):
+    """One element, every face a Dirichlet boundary: residual and JVP against the oracle."""
+    import torch
+    from tests.util import poisson_setup, penalty
+    from paper_2205_07824_amd import inputs as I
+    mms = I.mms_sin2d if nd == 2 else I.mms_expsin3d
+    box, om, omd = poisson_setup(nd, 1, p, mms)
+    m = L.Mesh(box, p)
+    xn, xq, xb, _ = m.points()
+    _, _, f = mms(xq)
+    ub, _, _ = mms(xb)
+    md = L.Model(m, L.MODEL_POISSON, 1, [1.0, penalty(p, 1.0), 0.0], src=f.reshape(m.E, 1, m.nqv),
+                 bdata=ub.reshape(m.nbf, 1, m.nqf), bc_kind=(0,))
+    rng = np.random.default_rng(4)
+    u = rng.uniform(-1, 1, m.E * m.nn)
+    v = rng.uniform(-1, 1, m.E * m.nn)
+    G = md.residual(torch.as_tensor(u, device="cuda")).cpu().numpy()
+    Jv = md.jvp(None, torch.as_tensor(v, device="cuda")).cpu().numpy()
+    assert rel(G, om.residual(omd, u)) < 1e-12
+    assert rel(Jv, om.jvp(omd, u, v)) < 1e-12
+
+
+def test_unsupported_order_rejected(L):
+    from paper_2205_07824_amd import inputs as I
+    m = L.Mesh(I.box_mesh(3, 2), 4)
+    with pytest.raises(L.LDGError) as e:
+        L.Model(m, L.MODEL_POISSON, 1, [1.0, 25.0, 0.0], bc_kind=(0,))
+    assert "order" in str(e.value)
+
+
+def test_zero_direction_gives_zero_jvp(L):
+    import torch
+    for name in ("c2", "c3"):
+        c = CS.ALL[name]()
+        m, md, t, dev = build_gpu(L, c)
+        z = torch.zeros(md.N, dtype=torch.float64, device="cuda")
+        Jv = md.jvp(dev(c.u), z, time=t)
+        assert Jv.abs().max().item() == 0.0
+
+
 def test_gmres_failure_paths(L):
     c = CS.c1_poisson2d()
     _say("case c1 failure paths")
