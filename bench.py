@@ -184,6 +184,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=32)
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--orth", choices=("dcgs2", "cgs2"), default="dcgs2",
+                    help="Gram-Schmidt variant of the Newton-GMRES legs")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra-workloads", action="store_true",
                     help="skip the 2D Euler, 3D Navier-Stokes and 96^3 Poisson JVP throughput legs")
@@ -280,6 +282,7 @@ def main():
     # Newton-GMRES to ||G|| <= 1e-8 ||G(u0)||, u0 = 0, GMRES(30) + block Jacobi
     if not args.no_solve:
         forms = {}
+        orth = ldg.ORTH_DCGS2 if args.orth == "dcgs2" else ldg.ORTH_CGS2
         for name, jp, bp, eta in (("fp64_jvp+fp64_bj", ldg.FP64, ldg.FP64, 1e-9),
                                   ("fp64_jvp+fp32_bj", ldg.FP64, ldg.FP32, 1e-9),
                                   ("fp32_jvp+fp32_bj", ldg.FP32, ldg.FP32, 1e-4)):
@@ -290,7 +293,7 @@ def main():
             t_bj = time.perf_counter() - t0
             x = torch.zeros(N, dtype=torch.float64, device="cuda")
             x, st, status = ldg.newton(md, x, rtol=1e-8, eta=eta, maxit=8, pc=pc, restart=30, lin_maxit=4000,
-                                       jvp_prec=jp, check=False)
+                                       jvp_prec=jp, orth=orth, check=False)
             torch.cuda.synchronize()
             t_all = time.perf_counter() - t0
             forms[name] = {"time_to_1e-8_s": round(t_all, 4), "bj_build_s": round(t_bj, 4),

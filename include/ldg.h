@@ -234,7 +234,8 @@ typedef struct {
   ldg_precision jvp_prec; /* precision of the Jacobian-vector products            */
   ldg_precond pc;         /* NULL = no preconditioner                             */
   int inject_fault;       /* test hook: 1 = poison the preconditioner output with NaN */
-  int orth;               /* 0 = CGS2 (three streaming sweeps over the basis), 1 = modified Gram-Schmidt */
+  int orth;               /* 0 = CGS2 (three streaming sweeps over the basis), 1 = modified Gram-Schmidt,
+                             2 = CGS2 with the re-orthogonalization delayed to the next step (two sweeps) */
 } ldg_gmres_opts;
 
 typedef struct {

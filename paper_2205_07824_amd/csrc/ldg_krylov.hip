@@ -334,6 +334,162 @@ __global__ void k_backsolve(ArnoldiState* st, int k) {
   }
 }
 
+// ------------------------------------------- delayed re-orthogonalization ---
+// Flexible GMRES with classical Gram-Schmidt whose second (re-orthogonalization)
+// pass is delayed by one step and folded into the next step's sweeps, so that
+// each Arnoldi step reads the basis twice instead of three times.  At step j,
+// U is the previous step's once-orthogonalized, unnormalized vector and
+// W = A z_j with z_j = M(U) (FGMRES allows any z_j as long as A z_j is expanded
+// in the final orthonormal basis):
+//   sweep 1 (k_dc_dots):   a = V^T U, b = V^T W, U.U, U.W, W.W     (V = v_0..v_{j-1})
+//   scalars (k_dc_scalar): s = a, alpha = sqrt(U.U - |s|^2), v_j = (U - V s)/alpha,
+//                          column j-1 of H = [h1_{j-1} + s ; alpha] -> Givens,
+//                          h1_j = [b ; c], c = v_j.W = (U.W - s.b)/alpha
+//   sweep 2 (k_dc_update): v_j = (U - V s)/alpha, U <- W - V h1_j
+//                          = W - (c/alpha) U - V (b - (c/alpha) s)
+// Column j-1 of H is final one step late; a closing sweep 1 (without W) finalizes
+// the last column of a cycle.  At j = 0, U = r and alpha = ||r|| (g_0 = alpha).
+
+// rows of part: [0, j) U.V_i, [j, 2j) W.V_i, 2j U.U, 2j+1 U.W, 2j+2 W.W (W nullable)
+template <int G>
+__global__ void __launch_bounds__(VB) k_dc_dots(int64_t n, int j, const double* __restrict__ V, int64_t ldv,
+                                                const double* __restrict__ U, const double* __restrict__ W,
+                                                double* __restrict__ part) {
+  __shared__ double sh[VB / 64][2 * G + 3];
+  int64_t lo, hi;
+  chunk_of(n, &lo, &hi);
+  const int nblk = gridDim.x;
+  const bool hw = W != nullptr;
+  const int ngroups = j > 0 ? (j + G - 1) / G : 1;
+  for (int gi = 0; gi < ngroups; ++gi) {
+    const int i0 = gi * G;
+    const int ni = j - i0 < G ? (j - i0 > 0 ? j - i0 : 0) : G;
+    double s[2 * G + 3];
+#pragma unroll
+    for (int r = 0; r < 2 * G + 3; ++r) s[r] = 0.0;
+    for (int64_t t = lo + threadIdx.x; t < hi; t += VB) {
+      const double ut = U[t];
+      const double wt = hw ? W[t] : 0.0;
+#pragma unroll
+      for (int r = 0; r < G; ++r) {
+        const double v = (r < ni) ? V[(int64_t)(i0 + r) * ldv + t] : 0.0;
+        s[r] += v * ut;
+        s[G + r] += v * wt;
+      }
+      s[2 * G] += ut * ut;
+      s[2 * G + 1] += ut * wt;
+      s[2 * G + 2] += wt * wt;
+    }
+    const double tot = block_sum_many<2 * G + 3>(s, 2 * G + 3, sh);
+    const int q = threadIdx.x;
+    int row = -1;
+    if (q < G) {
+      if (q < ni) row = i0 + q;
+    } else if (q < 2 * G) {
+      if (q - G < ni) row = j + i0 + (q - G);
+    } else if (q < 2 * G + 3 && gi == 0) {
+      row = 2 * j + (q - 2 * G);
+    }
+    if (row >= 0) part[(int64_t)row * nblk + blockIdx.x] = tot;
+  }
+}
+
+// coefficient block of sweep 2: [0, MAXM) s, [MAXM, 2 MAXM) gamma, 2 MAXM: 1/alpha, 2 MAXM + 1: c/alpha
+constexpr int DC_COEF = 2 * MAXM + 2;
+
+// dots[0..2j+3) as laid out by k_dc_dots; h1p holds h1_{j-1} on entry and h1_j on exit
+__global__ void k_dc_scalar(ArnoldiState* st, int j, int closing, const double* __restrict__ dots,
+                            double* __restrict__ h1p, double* __restrict__ coef) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double* a = dots;
+  const double* b = dots + j;
+  const double uu = dots[2 * j], uw = dots[2 * j + 1], ww = dots[2 * j + 2];
+  double ss = 0.0;
+  for (int i = 0; i < j; ++i) ss += a[i] * a[i];
+  double al2 = uu - ss;
+  const double al = al2 > 0.0 ? sqrt(al2) : 0.0;
+  int brk = 0;
+  if (j == 0) {
+    for (int i = 0; i <= MAXM; ++i) st->g[i] = 0.0;
+    st->g[0] = al;
+    st->resid = al;
+  } else {
+    const int ld = MAXM + 1;
+    const int c = j - 1;
+    double* col = st->H + (int64_t)c * ld;
+    for (int i = 0; i < j; ++i) col[i] = h1p[i] + a[i];
+    col[j] = al;
+    brk = (al <= 1e-14 * st->wnorm0) ? 1 : 0;
+    for (int i = 0; i < c; ++i) {
+      const double t = st->cs[i] * col[i] + st->sn[i] * col[i + 1];
+      col[i + 1] = -st->sn[i] * col[i] + st->cs[i] * col[i + 1];
+      col[i] = t;
+    }
+    const double d = hypot(col[c], col[c + 1]);
+    st->cs[c] = d > 0 ? col[c] / d : 1.0;
+    st->sn[c] = d > 0 ? col[c + 1] / d : 0.0;
+    col[c] = d;
+    col[c + 1] = 0.0;
+    st->g[c + 1] = -st->sn[c] * st->g[c];
+    st->g[c] = st->cs[c] * st->g[c];
+    st->resid = fabs(st->g[c + 1]);
+  }
+  st->breakdown = brk;
+  if (closing) return;
+  const double inva = (al > 0.0 && !brk) ? 1.0 / al : 0.0;
+  double sb = 0.0;
+  for (int i = 0; i < j; ++i) sb += a[i] * b[i];
+  const double cc = (uw - sb) * inva;
+  const double dl = cc * inva;
+  for (int i = 0; i < j; ++i) {
+    coef[i] = a[i];
+    coef[MAXM + i] = b[i] - dl * a[i];
+    h1p[i] = b[i];
+  }
+  h1p[j] = cc;
+  coef[2 * MAXM] = inva;
+  coef[2 * MAXM + 1] = dl;
+  st->wnorm0 = sqrt(ww);
+}
+
+// v_j = (U - V s)/alpha -> Vj ; U <- W - (c/alpha) U - V gamma
+template <int G>
+__global__ void __launch_bounds__(VB) k_dc_update(int64_t n, int j, const double* __restrict__ V, int64_t ldv,
+                                                  const double* __restrict__ coef, double* __restrict__ U,
+                                                  const double* __restrict__ W, double* __restrict__ Vj) {
+  __shared__ double cs_[2 * MAXM + 2];
+  for (int i = threadIdx.x; i < j; i += blockDim.x) {
+    cs_[i] = coef[i];
+    cs_[MAXM + i] = coef[MAXM + i];
+  }
+  if (threadIdx.x == 0) {
+    cs_[2 * MAXM] = coef[2 * MAXM];
+    cs_[2 * MAXM + 1] = coef[2 * MAXM + 1];
+  }
+  __syncthreads();
+  const double inva = cs_[2 * MAXM], dl = cs_[2 * MAXM + 1];
+  int64_t lo, hi;
+  chunk_of(n, &lo, &hi);
+  for (int64_t t = lo + threadIdx.x; t < hi; t += VB) {
+    const double ut = U[t];
+    double va = ut, ua = W[t] - dl * ut;
+    for (int i0 = 0; i0 < j; i0 += G) {
+      double v[G];
+#pragma unroll
+      for (int r = 0; r < G; ++r) v[r] = (i0 + r < j) ? V[(int64_t)(i0 + r) * ldv + t] : 0.0;
+#pragma unroll
+      for (int r = 0; r < G; ++r) {
+        if (i0 + r < j) {
+          va -= cs_[i0 + r] * v[r];
+          ua -= cs_[MAXM + i0 + r] * v[r];
+        }
+      }
+    }
+    Vj[t] = va * inva;
+    U[t] = ua;
+  }
+}
+
 // NaN injection for the failure-handling tests
 __global__ void k_poison(int64_t n, double* z) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -362,10 +518,13 @@ struct Workspace {
   double* Z = nullptr;     // [m][n]
   double* w = nullptr;
   double* r = nullptr;
-  double* part = nullptr;  // [(MAXM+1) * RED_BLOCKS]
+  double* part = nullptr;  // [(2 MAXM + 3) * RED_BLOCKS] block partials
   double* npart = nullptr; // [RED_BLOCKS]
   double* h1 = nullptr;
   double* h2 = nullptr;
+  double* U = nullptr;     // delayed re-orthogonalization: the pending vector
+  double* dots = nullptr;  // [2 MAXM + 3]
+  double* coef = nullptr;  // [DC_COEF]
   ArnoldiState* st = nullptr;
   double* pinned = nullptr;  // host scalars
   hipEvent_t ev[8];
@@ -373,6 +532,7 @@ struct Workspace {
   void release() {
     if (!ok) return;
     hipFree(V); hipFree(Z); hipFree(w); hipFree(r); hipFree(part); hipFree(npart); hipFree(h1); hipFree(h2);
+    hipFree(U); hipFree(dots); hipFree(coef);
     hipFree(st); hipHostFree(pinned);
     for (auto& e : ev) hipEventDestroy(e);
     ok = false;
@@ -385,10 +545,13 @@ struct Workspace {
     LDG_TRY(hipMalloc((void**)&Z, sizeof(double) * m * n));
     LDG_TRY(hipMalloc((void**)&w, sizeof(double) * n));
     LDG_TRY(hipMalloc((void**)&r, sizeof(double) * n));
-    LDG_TRY(hipMalloc((void**)&part, sizeof(double) * (MAXM + 1) * RED_BLOCKS));
+    LDG_TRY(hipMalloc((void**)&part, sizeof(double) * (2 * MAXM + 3) * RED_BLOCKS));
     LDG_TRY(hipMalloc((void**)&npart, sizeof(double) * RED_BLOCKS));
     LDG_TRY(hipMalloc((void**)&h1, sizeof(double) * (MAXM + 1)));
     LDG_TRY(hipMalloc((void**)&h2, sizeof(double) * (MAXM + 1)));
+    LDG_TRY(hipMalloc((void**)&U, sizeof(double) * n));
+    LDG_TRY(hipMalloc((void**)&dots, sizeof(double) * (2 * MAXM + 3)));
+    LDG_TRY(hipMalloc((void**)&coef, sizeof(double) * DC_COEF));
     LDG_TRY(hipMalloc((void**)&st, sizeof(ArnoldiState)));
     LDG_TRY(hipHostMalloc((void**)&pinned, sizeof(double) * 8, hipHostMallocDefault));
     for (auto& e : ev) LDG_TRY(hipEventCreate(&e));
@@ -473,6 +636,127 @@ static ldg_status true_residual(Model& md, const ldg_time* t, const double* u, c
   return st;
 }
 
+// One restart cycle of FGMRES with the delayed re-orthogonalization (orth = 2):
+// k returns the number of final columns of H, stop whether the cycle ended on
+// convergence or breakdown.  ws.r holds the cycle's residual on entry.
+static ldg_status dcgs2_cycle(Model& md, const ldg_time* t, const double* u_lin, ldg_precision jp,
+                              const ldg_gmres_opts& o, Workspace& ws, ldg_precond_s*& pc_cur, bool watch,
+                              double& watch_ref, int& watch_it, double tol, int& its, int& k, bool& stop,
+                              ldg_status& result, ldg_gmres_stats& S, hipStream_t s) {
+  const int64_t n = ws.n;
+  const int m = o.restart;
+  const int nbc = cgs_blocks(n);
+  const bool use_pc = o.pc != nullptr;
+  const bool pipelined = !watch;
+  float ms = 0.0f;
+  ldg_status st;
+  LDG_TRY(hipMemcpyAsync(ws.U, ws.r, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  auto sweep1 = [&](int j, const double* Wp) {
+    if (j <= 8) hipLaunchKernelGGL((k_dc_dots<8>), dim3(nbc), dim3(VB), 0, s, n, j, ws.V, n, ws.U, Wp, ws.part);
+    else hipLaunchKernelGGL((k_dc_dots<16>), dim3(nbc), dim3(VB), 0, s, n, j, ws.V, n, ws.U, Wp, ws.part);
+    hipLaunchKernelGGL(k_reduce_rows, dim3(2 * j + 3), dim3(VB), 0, s, 2 * j + 3, nbc, ws.part, ws.dots);
+  };
+  // read step jj's result: after it, columns 0..jj-1 of H are final
+  auto finish = [&](int jj) -> bool {
+    const int sl = jj & 1;
+    if (hipEventSynchronize(ws.ev[4 * sl + 3]) != hipSuccess) {
+      result = LDG_EDEVICE;
+      set_error("event synchronization failed");
+      return true;
+    }
+    if (hipEventElapsedTime(&ms, ws.ev[4 * sl + 0], ws.ev[4 * sl + 1]) == hipSuccess) S.t_pc += ms * 1e-3;
+    if (hipEventElapsedTime(&ms, ws.ev[4 * sl + 1], ws.ev[4 * sl + 2]) == hipSuccess) S.t_jvp += ms * 1e-3;
+    if (hipEventElapsedTime(&ms, ws.ev[4 * sl + 2], ws.ev[4 * sl + 3]) == hipSuccess) S.t_orth += ms * 1e-3;
+    k = jj;
+    if (jj == 0) return false;
+    const double res = ws.pinned[2 * sl];
+    int brk = 0;
+    std::memcpy(&brk, ws.pinned + 2 * sl + 1, sizeof(int));
+    S.res_est = res;
+    if (!std::isfinite(res)) { result = LDG_EBREAKDOWN; return true; }
+    if (watch && pc_cur == o.pc) {
+      if (watch_ref < 0) { watch_ref = res; watch_it = 0; }
+      if (++watch_it >= 10) {
+        if (res > 0.99 * watch_ref && precond_fallback(o.pc)) { pc_cur = precond_fallback(o.pc); S.fell_back = 1; }
+        watch_ref = res;
+        watch_it = 0;
+      }
+    }
+    return res <= tol || brk;
+  };
+  int queued = -1, done = 0;
+  for (int j = 0; j < m && its < o.maxit; ++j) {
+    const int sl = j & 1;
+    double* zj = ws.Z + (int64_t)j * n;
+    hipEventRecord(ws.ev[4 * sl + 0], s);
+    if (use_pc) {
+      st = precond_apply_impl(pc_cur, ws.U, zj, s);
+      if (st != LDG_OK) return st;
+      if (o.inject_fault == 1) hipLaunchKernelGGL(k_poison, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, zj);
+      if (watch && pc_cur == o.pc) {
+        int bad = 0;
+        st = precond_count_nonfinite(pc_cur, zj, n, &bad, s);
+        if (st != LDG_OK) return st;
+        if (bad) {
+          ldg_precond_s* fb = precond_fallback(o.pc);
+          if (!fb) { result = LDG_EBREAKDOWN; break; }
+          pc_cur = fb;
+          S.fell_back = 1;
+          st = precond_apply_impl(pc_cur, ws.U, zj, s);
+          if (st != LDG_OK) return st;
+        }
+      }
+    } else {
+      LDG_TRY(hipMemcpyAsync(zj, ws.U, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    hipEventRecord(ws.ev[4 * sl + 1], s);
+    st = jvp_impl(md, t, u_lin, zj, ws.w, jp, true, s);
+    if (st != LDG_OK) return st;
+    hipEventRecord(ws.ev[4 * sl + 2], s);
+    sweep1(j, ws.w);
+    hipLaunchKernelGGL(k_dc_scalar, dim3(1), dim3(64), 0, s, ws.st, j, 0, ws.dots, ws.h1, ws.coef);
+    if (j <= 8)
+      hipLaunchKernelGGL((k_dc_update<8>), dim3(nbc), dim3(VB), 0, s, n, j, ws.V, n, ws.coef, ws.U, ws.w,
+                         ws.V + (int64_t)j * n);
+    else
+      hipLaunchKernelGGL((k_dc_update<16>), dim3(nbc), dim3(VB), 0, s, n, j, ws.V, n, ws.coef, ws.U, ws.w,
+                         ws.V + (int64_t)j * n);
+    LDG_TRY(hipGetLastError());
+    LDG_TRY(hipMemcpyAsync(ws.pinned + 2 * sl, &ws.st->resid, sizeof(double), hipMemcpyDeviceToHost, s));
+    LDG_TRY(hipMemcpyAsync(ws.pinned + 2 * sl + 1, &ws.st->breakdown, sizeof(int), hipMemcpyDeviceToHost, s));
+    hipEventRecord(ws.ev[4 * sl + 3], s);
+    ++its;
+    done = j + 1;
+    if (!pipelined) {
+      if (finish(j)) { stop = true; break; }
+      continue;
+    }
+    const int prev = queued;
+    queued = j;
+    if (prev >= 0 && finish(prev)) {
+      // step j was queued past the end of the cycle: not counted
+      --its;
+      queued = -1;
+      stop = true;
+      break;
+    }
+  }
+  if (queued >= 0 && result == LDG_OK) stop = finish(queued);
+  if (result != LDG_OK) return LDG_OK;
+  if (!stop && done > 0) {
+    // close the cycle: re-orthogonalize the pending vector to finalize column done-1
+    sweep1(done, nullptr);
+    hipLaunchKernelGGL(k_dc_scalar, dim3(1), dim3(64), 0, s, ws.st, done, 1, ws.dots, ws.h1, ws.coef);
+    LDG_TRY(hipGetLastError());
+    LDG_TRY(hipMemcpyAsync(ws.pinned, &ws.st->resid, sizeof(double), hipMemcpyDeviceToHost, s));
+    LDG_TRY(hipStreamSynchronize(s));
+    k = done;
+    S.res_est = ws.pinned[0];
+    if (!std::isfinite(S.res_est)) result = LDG_EBREAKDOWN;
+  }
+  return LDG_OK;
+}
+
 ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const double* b, double* x,
                       const ldg_gmres_opts& o, ldg_gmres_stats* stats, hipStream_t s) {
   auto T0 = std::chrono::steady_clock::now();
@@ -480,7 +764,7 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
   const int64_t n = (int64_t)md.N();
   const int m = o.restart;
   if (m < 1 || m > MAXM) { set_error("restart must be in [1, 128]"); return LDG_EINVAL; }
-  if (o.orth != 0 && o.orth != 1) { set_error("orth must be 0 (CGS2) or 1 (MGS)"); return LDG_EINVAL; }
+  if (o.orth < 0 || o.orth > 2) { set_error("orth must be 0 (CGS2), 1 (MGS) or 2 (delayed CGS2)"); return LDG_EINVAL; }
   if (!g_ws_ptr) g_ws_ptr = new Workspace();
   Workspace& ws = *g_ws_ptr;
   ldg_status st = ws.ensure(n, m);
@@ -515,100 +799,107 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
   float ms = 0.0f;
   while (beta > tol && its < o.maxit) {
     if (!std::isfinite(beta)) { result = LDG_EBREAKDOWN; break; }
-    // V0 = r / beta
-    hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(VB), 0, s, n, ws.r, ws.r, ws.npart);
-    hipLaunchKernelGGL(k_arnoldi_start, dim3(1), dim3(VB), 0, s, ws.st, nb, ws.npart);
-    hipLaunchKernelGGL(k_scale_dev, dim3(gV), dim3(VB), 0, s, n, &ws.st->inv_hnext, ws.r, ws.V);
     int k = 0;
     bool stop = false;
-    // Without the learned preconditioner's host-side watch, step j + 1 is queued
-    // before the host reads step j's residual estimate, so the GPU never waits for
-    // the host.  A queued step after convergence or breakdown only touches
-    // column j + 1 of H, g[j + 1..j + 2] and V[j + 2]; the solution update uses
-    // the first k columns only (a step after a breakdown works on a zero vector).
-    const bool pipelined = !watch;
-    int queued = -1;                  // last queued step whose result is unread
-    // read step jj's result (slot jj & 1); true when the cycle ends there
-    auto finish = [&](int jj) -> bool {
-      const int sl = jj & 1;
-      if (hipEventSynchronize(ws.ev[4 * sl + 3]) != hipSuccess) { result = LDG_EDEVICE; set_error("event synchronization failed"); return true; }
-      if (hipEventElapsedTime(&ms, ws.ev[4 * sl + 0], ws.ev[4 * sl + 1]) == hipSuccess) S.t_pc += ms * 1e-3;
-      if (hipEventElapsedTime(&ms, ws.ev[4 * sl + 1], ws.ev[4 * sl + 2]) == hipSuccess) S.t_jvp += ms * 1e-3;
-      if (hipEventElapsedTime(&ms, ws.ev[4 * sl + 2], ws.ev[4 * sl + 3]) == hipSuccess) S.t_orth += ms * 1e-3;
-      k = jj + 1;
-      const double res = ws.pinned[2 * sl];
-      int brk = 0;
-      std::memcpy(&brk, ws.pinned + 2 * sl + 1, sizeof(int));
-      S.res_est = res;
-      if (!std::isfinite(res)) { result = LDG_EBREAKDOWN; return true; }
-      if (watch && pc_cur == o.pc) {
-        if (watch_ref < 0) { watch_ref = res; watch_it = 0; }
-        if (++watch_it >= 10) {
-          if (res > 0.99 * watch_ref && precond_fallback(o.pc)) { pc_cur = precond_fallback(o.pc); S.fell_back = 1; }
-          watch_ref = res;
-          watch_it = 0;
-        }
-      }
-      return res <= tol || brk;
-    };
-    for (int j = 0; j < m && its < o.maxit; ++j) {
-      const int sl = j & 1;
-      double* vj = ws.V + (int64_t)j * n;
-      double* zj = use_pc ? ws.Z + (int64_t)j * n : vj;
-      hipEventRecord(ws.ev[4 * sl + 0], s);
-      if (use_pc) {
-        st = precond_apply_impl(pc_cur, vj, zj, s);
-        if (st != LDG_OK) return st;
-        if (o.inject_fault == 1) hipLaunchKernelGGL(k_poison, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, zj);
+    if (o.orth == 2) {
+      st = dcgs2_cycle(md, t, u_lin, jp, o, ws, pc_cur, watch, watch_ref, watch_it, tol, its, k, stop, result, S, s);
+      if (st != LDG_OK) return st;
+      if (result == LDG_EDEVICE) return result;
+    } else {
+      // V0 = r / beta
+      hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(VB), 0, s, n, ws.r, ws.r, ws.npart);
+      hipLaunchKernelGGL(k_arnoldi_start, dim3(1), dim3(VB), 0, s, ws.st, nb, ws.npart);
+      hipLaunchKernelGGL(k_scale_dev, dim3(gV), dim3(VB), 0, s, n, &ws.st->inv_hnext, ws.r, ws.V);
+      // Without the learned preconditioner's host-side watch, step j + 1 is queued
+      // before the host reads step j's residual estimate, so the GPU never waits for
+      // the host.  A queued step after convergence or breakdown only touches
+      // column j + 1 of H, g[j + 1..j + 2] and V[j + 2]; the solution update uses
+      // the first k columns only (a step after a breakdown works on a zero vector).
+      const bool pipelined = !watch;
+      int queued = -1;                  // last queued step whose result is unread
+      // read step jj's result (slot jj & 1); true when the cycle ends there
+      auto finish = [&](int jj) -> bool {
+        const int sl = jj & 1;
+        if (hipEventSynchronize(ws.ev[4 * sl + 3]) != hipSuccess) { result = LDG_EDEVICE; set_error("event synchronization failed"); return true; }
+        if (hipEventElapsedTime(&ms, ws.ev[4 * sl + 0], ws.ev[4 * sl + 1]) == hipSuccess) S.t_pc += ms * 1e-3;
+        if (hipEventElapsedTime(&ms, ws.ev[4 * sl + 1], ws.ev[4 * sl + 2]) == hipSuccess) S.t_jvp += ms * 1e-3;
+        if (hipEventElapsedTime(&ms, ws.ev[4 * sl + 2], ws.ev[4 * sl + 3]) == hipSuccess) S.t_orth += ms * 1e-3;
+        k = jj + 1;
+        const double res = ws.pinned[2 * sl];
+        int brk = 0;
+        std::memcpy(&brk, ws.pinned + 2 * sl + 1, sizeof(int));
+        S.res_est = res;
+        if (!std::isfinite(res)) { result = LDG_EBREAKDOWN; return true; }
         if (watch && pc_cur == o.pc) {
-          int bad = 0;
-          st = precond_count_nonfinite(pc_cur, zj, n, &bad, s);
-          if (st != LDG_OK) return st;
-          if (bad) {
-            ldg_precond_s* fb = precond_fallback(o.pc);
-            if (!fb) { result = LDG_EBREAKDOWN; break; }
-            pc_cur = fb;
-            S.fell_back = 1;
-            st = precond_apply_impl(pc_cur, vj, zj, s);
-            if (st != LDG_OK) return st;
+          if (watch_ref < 0) { watch_ref = res; watch_it = 0; }
+          if (++watch_it >= 10) {
+            if (res > 0.99 * watch_ref && precond_fallback(o.pc)) { pc_cur = precond_fallback(o.pc); S.fell_back = 1; }
+            watch_ref = res;
+            watch_it = 0;
           }
         }
+        return res <= tol || brk;
+      };
+      for (int j = 0; j < m && its < o.maxit; ++j) {
+        const int sl = j & 1;
+        double* vj = ws.V + (int64_t)j * n;
+        double* zj = use_pc ? ws.Z + (int64_t)j * n : vj;
+        hipEventRecord(ws.ev[4 * sl + 0], s);
+        if (use_pc) {
+          st = precond_apply_impl(pc_cur, vj, zj, s);
+          if (st != LDG_OK) return st;
+          if (o.inject_fault == 1) hipLaunchKernelGGL(k_poison, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, zj);
+          if (watch && pc_cur == o.pc) {
+            int bad = 0;
+            st = precond_count_nonfinite(pc_cur, zj, n, &bad, s);
+            if (st != LDG_OK) return st;
+            if (bad) {
+              ldg_precond_s* fb = precond_fallback(o.pc);
+              if (!fb) { result = LDG_EBREAKDOWN; break; }
+              pc_cur = fb;
+              S.fell_back = 1;
+              st = precond_apply_impl(pc_cur, vj, zj, s);
+              if (st != LDG_OK) return st;
+            }
+          }
+        }
+        hipEventRecord(ws.ev[4 * sl + 1], s);
+        st = jvp_impl(md, t, u_lin, zj, ws.w, jp, true, s);
+        if (st != LDG_OK) return st;
+        hipEventRecord(ws.ev[4 * sl + 2], s);
+        // CGS2: h1 = V^T w (+ ||w||^2), w -= V h1, h2 = V^T w, w -= V h2 (+ ||w||^2); or MGS
+        st = o.orth == 1 ? mgs(n, j + 1, ws, s) : cgs2(n, j + 1, ws, s);
+        if (st != LDG_OK) return st;
+        hipLaunchKernelGGL(k_givens, dim3(1), dim3(VB), 0, s, ws.st, j, cgs_blocks(n), ws.h1, ws.h2, ws.npart);
+        hipLaunchKernelGGL(k_scale_dev, dim3(gV), dim3(VB), 0, s, n, &ws.st->inv_hnext, ws.w,
+                           ws.V + (int64_t)(j + 1) * n);
+        LDG_TRY(hipGetLastError());
+        LDG_TRY(hipMemcpyAsync(ws.pinned + 2 * sl, &ws.st->resid, sizeof(double), hipMemcpyDeviceToHost, s));
+        LDG_TRY(hipMemcpyAsync(ws.pinned + 2 * sl + 1, &ws.st->breakdown, sizeof(int), hipMemcpyDeviceToHost, s));
+        hipEventRecord(ws.ev[4 * sl + 3], s);
+        ++its;
+        if (!pipelined) {
+          if (finish(j)) { stop = true; break; }
+          continue;
+        }
+        const int prev = queued;
+        queued = j;
+        if (prev >= 0 && finish(prev)) {
+          // step j was queued past the end of the cycle: not counted
+          --its;
+          queued = -1;
+          stop = true;
+          break;
+        }
       }
-      hipEventRecord(ws.ev[4 * sl + 1], s);
-      st = jvp_impl(md, t, u_lin, zj, ws.w, jp, true, s);
-      if (st != LDG_OK) return st;
-      hipEventRecord(ws.ev[4 * sl + 2], s);
-      // CGS2: h1 = V^T w (+ ||w||^2), w -= V h1, h2 = V^T w, w -= V h2 (+ ||w||^2); or MGS
-      st = o.orth == 1 ? mgs(n, j + 1, ws, s) : cgs2(n, j + 1, ws, s);
-      if (st != LDG_OK) return st;
-      hipLaunchKernelGGL(k_givens, dim3(1), dim3(VB), 0, s, ws.st, j, cgs_blocks(n), ws.h1, ws.h2, ws.npart);
-      hipLaunchKernelGGL(k_scale_dev, dim3(gV), dim3(VB), 0, s, n, &ws.st->inv_hnext, ws.w,
-                         ws.V + (int64_t)(j + 1) * n);
-      LDG_TRY(hipGetLastError());
-      LDG_TRY(hipMemcpyAsync(ws.pinned + 2 * sl, &ws.st->resid, sizeof(double), hipMemcpyDeviceToHost, s));
-      LDG_TRY(hipMemcpyAsync(ws.pinned + 2 * sl + 1, &ws.st->breakdown, sizeof(int), hipMemcpyDeviceToHost, s));
-      hipEventRecord(ws.ev[4 * sl + 3], s);
-      ++its;
-      if (!pipelined) {
-        if (finish(j)) { stop = true; break; }
-        continue;
-      }
-      const int prev = queued;
-      queued = j;
-      if (prev >= 0 && finish(prev)) {
-        // step j was queued past the end of the cycle: not counted
-        --its;
-        queued = -1;
-        stop = true;
-        break;
-      }
+      if (queued >= 0 && result == LDG_OK) stop = finish(queued);
+      if (result == LDG_EDEVICE) return result;
     }
-    if (queued >= 0 && result == LDG_OK) stop = finish(queued);
-    if (result == LDG_EDEVICE) return result;
     // x += Z y
     if (k > 0 && result == LDG_OK) {
       hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, s, ws.st, k);
-      hipLaunchKernelGGL(k_combine, dim3(gV), dim3(VB), 0, s, n, k, use_pc ? ws.Z : ws.V, n, ws.st->y, x);
+      hipLaunchKernelGGL(k_combine, dim3(gV), dim3(VB), 0, s, n, k, (use_pc || o.orth == 2) ? ws.Z : ws.V, n,
+                         ws.st->y, x);
       LDG_TRY(hipGetLastError());
     }
     ++S.restarts;

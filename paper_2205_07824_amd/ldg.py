@@ -349,11 +349,11 @@ class LearnedPrecond:
             self.h = None
 
 
-ORTH_CGS2, ORTH_MGS = 0, 1
+ORTH_CGS2, ORTH_MGS, ORTH_DCGS2 = 0, 1, 2
 
 
 def gmres_opts(restart=30, maxit=1000, rtol=1e-8, atol=0.0, jvp_prec=FP64, pc=None, flexible=True, inject_fault=0,
-               orth=ORTH_CGS2):
+               orth=ORTH_DCGS2):
     return GmresOpts(restart, maxit, int(flexible), rtol, atol, jvp_prec, None if pc is None else pc.h, inject_fault,
                      orth)
 

@@ -30,7 +30,7 @@ def euler_cfl_dt(U, nd, h, cfl, gamma=1.4):
 
 
 def bdf_steps(model, u0, dt, nsteps, restart=50, eta=1e-3, rtol=1e-8, jvp_prec=ldg.FP64, bj_prec=ldg.FP64,
-              per_variable=False, newton_maxit=10, lin_maxit=5000, log=None):
+              per_variable=False, newton_maxit=10, lin_maxit=5000, orth=ldg.ORTH_DCGS2, log=None):
     """Advance u0 by nsteps implicit steps; returns (u, per-step statistics)."""
     u = u0.clone()
     u_prev = None
@@ -48,7 +48,7 @@ def bdf_steps(model, u0, dt, nsteps, restart=50, eta=1e-3, rtol=1e-8, jvp_prec=l
         t0 = time.perf_counter()
         u, st, status = ldg.newton(model, u, time=t, rtol=rtol, eta=eta, maxit=newton_maxit, bj_refresh=True,
                                    bj_per_variable=per_variable, bj_prec=bj_prec, pc=pc, restart=restart,
-                                   lin_maxit=lin_maxit, jvp_prec=jvp_prec, check=False)
+                                   lin_maxit=lin_maxit, jvp_prec=jvp_prec, orth=orth, check=False)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         rec = {"step": k + 1, "seconds": el, "converged": status == ldg.LDG_OK, "newton_iters": st["iters"],

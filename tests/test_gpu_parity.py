@@ -196,19 +196,59 @@ def test_gmres_without_preconditioner_and_cgs2_orthogonality(L):
     assert L.norm(r) <= 1.01e-9 * L.norm(b)
 
 
-def test_gmres_modified_gram_schmidt_matches_cgs2(L):
+@pytest.mark.parametrize("orth", ["mgs", "dcgs2"])
+@pytest.mark.parametrize("use_pc,restart", [(True, 40), (False, 12)])
+def test_gmres_orthogonalization_variants_match_cgs2(L, orth, use_pc, restart):
     c = CS.c5_convdiff2d()
-    _say("case c5 gmres mgs vs cgs2")
+    _say("case c5 gmres", orth, "vs cgs2, pc", use_pc, "restart", restart)
     m, md, t, dev = build_gpu(L, c)
     N = c.om.size(1)
     b = dev(np.random.default_rng(9).uniform(-1, 1, N))
-    pc = L.BlockJacobi(md)
-    x1, s1, st1 = L.gmres(md, b, pc=pc, restart=40, rtol=1e-10, maxit=4000, orth=L.ORTH_CGS2)
-    x2, s2, st2 = L.gmres(md, b, pc=pc, restart=40, rtol=1e-10, maxit=4000, orth=L.ORTH_MGS)
-    _say("cgs2", s1["iters"], "mgs", s2["iters"])
+    pc = L.BlockJacobi(md) if use_pc else None
+    o = L.ORTH_MGS if orth == "mgs" else L.ORTH_DCGS2
+    x1, s1, st1 = L.gmres(md, b, pc=pc, restart=restart, rtol=1e-10, maxit=6000, orth=L.ORTH_CGS2)
+    x2, s2, st2 = L.gmres(md, b, pc=pc, restart=restart, rtol=1e-10, maxit=6000, orth=o)
+    _say("cgs2", s1["iters"], orth, s2["iters"], "res", s1["res_true"], s2["res_true"])
     assert st1 == st2 == L.LDG_OK
-    assert abs(s1["iters"] - s2["iters"]) <= 2
-    assert (x1 - x2).norm().item() <= 1e-7 * x1.norm().item()
+    assert s2["res_true"] <= 1.01e-10 * s2["res0"]
+    if use_pc:
+        # well-conditioned: the iteration counts agree; without a preconditioner the
+        # thousands of restarted iterations amplify rounding differences in the count
+        assert abs(s1["iters"] - s2["iters"]) <= 2
+    assert (x1 - x2).norm().item() <= 1e-6 * x1.norm().item()
+
+
+def test_gmres_dcgs2_c1_matches_oracle_solution(L):
+    import scipy.sparse.linalg as spla
+    import torch
+    c = CS.c1_poisson2d()
+    m, md, t, dev = build_gpu(L, c)
+    om = c.oracle_model()
+    N = c.om.size(1)
+    x_ref = spla.spsolve(c.om.jacobian(om, np.zeros(N)).tocsc(), -c.om.residual(om, np.zeros(N)))
+    bg = -md.residual(torch.zeros(N, dtype=torch.float64, device="cuda"))
+    x, st, status = L.gmres(md, bg, pc=L.BlockJacobi(md), restart=30, rtol=1e-10, maxit=500, orth=L.ORTH_DCGS2)
+    _say("dcgs2 c1", st)
+    assert status == L.LDG_OK
+    assert rel(x.cpu().numpy(), x_ref) < 1e-8
+
+
+def test_newton_euler_with_dcgs2(L):
+    import scipy.sparse.linalg as spla
+    import oracle as O
+    c = CS.c3_euler2d(n=4, p=3)
+    m, md, t, dev = build_gpu(L, c)
+    om = c.oracle_model()
+    G = lambda u: c.om.residual(om, u)
+    solve = lambda u, rhs: spla.spsolve(c.om.jacobian(om, u).tocsc(), rhs)
+    u_ref, info = O.newton(G, solve, c.r1.copy(), rtol=1e-13, maxit=10)
+    u = dev(c.r1.copy())
+    pc = L.BlockJacobi(md, u_lin=u, time=t)
+    u, st, status = L.newton(md, u, time=t, rtol=1e-12, eta=1e-10, maxit=12, bj_refresh=True, pc=pc, restart=50,
+                             orth=L.ORTH_DCGS2)
+    _say("newton dcgs2", st)
+    assert status == L.LDG_OK
+    assert rel(u.cpu().numpy(), u_ref) < 1e-8
 
 
 def test_newton_euler_bdf2_step_matches_oracle(L):
@@ -314,6 +354,12 @@ def test_gmres_failure_paths(L):
     pc = L.BlockJacobi(md)
     x, st, status = L.gmres(md, b, pc=pc, restart=10, rtol=1e-12, maxit=50, inject_fault=1, check=False)
     assert status == L.LDG_EBREAKDOWN
+    for orth in (L.ORTH_DCGS2,):
+        x, st, status = L.gmres(md, b, restart=5, rtol=1e-12, maxit=3, check=False, orth=orth)
+        assert status == L.LDG_ENOCONV and st["iters"] == 3
+        x, st, status = L.gmres(md, b, pc=pc, restart=10, rtol=1e-12, maxit=50, inject_fault=1, check=False,
+                                orth=orth)
+        assert status == L.LDG_EBREAKDOWN
 
 
 @pytest.mark.parametrize("name", ["c1", "c2", "c5", "mixed2d", "mixed3d"])
