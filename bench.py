@@ -146,6 +146,47 @@ def other_workloads(ldg, I, log):
     return res
 
 
+def other_solves(ldg, I, log):
+    """Newton-GMRES time-to-tolerance on the 2D Poisson p=2 8x8 workload (Newton 1 step, GMRES(30) + block-Jacobi
+    to 1e-10) and one held-out 2D convection-diffusion instance at 128^2 p=3 (FGMRES(30) + block-Jacobi to 1e-8,
+    FP64 and FP32 factors)."""
+    import torch
+    from paper_2205_07824_amd import learned as LP
+    res = {}
+    box = I.box_mesh(2, 8)
+    m = ldg.Mesh(box, 2, 5)
+    xn, xq, xb, _ = m.points()
+    _, _, f = I.mms_sin2d(xq)
+    ub, _, _ = I.mms_sin2d(xb)
+    md = ldg.Model(m, ldg.MODEL_POISSON, 1, [1.0, 9.0 * 8, 0.0], src=f.reshape(m.E, 1, m.nqv),
+                   bdata=ub.reshape(m.nbf, 1, m.nqf), bc_kind=(0,))
+    for rep in range(2):   # the first solve also allocates the solver workspace
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pc = ldg.BlockJacobi(md)
+        u = torch.zeros(md.N, dtype=torch.float64, device="cuda")
+        u, st, status = ldg.newton(md, u, rtol=1e-10, eta=1e-11, maxit=4, pc=pc, restart=30, lin_maxit=500,
+                                   check=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+    res["poisson2d_p2_8x8"] = {"time_to_1e-10_s": round(el, 5), "converged": status == ldg.LDG_OK,
+                               "gmres_iters": st["gmres_iters"], "dof": md.N}
+    log("poisson 8x8", res["poisson2d_p2_8x8"])
+    inst = LP.c5_instance(100000, n=128, p=3)
+    cd = {"dof": inst["model"].N, "A": round(inst["A"], 3)}
+    for name, bp in (("fp64_bj", ldg.FP64), ("fp32_bj", ldg.FP32)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pc = ldg.BlockJacobi(inst["model"], prec=bp)
+        x, st, status = ldg.gmres(inst["model"], inst["b"], pc=pc, restart=30, rtol=1e-8, maxit=6000, check=False)
+        torch.cuda.synchronize()
+        cd[name] = {"time_to_1e-8_s": round(time.perf_counter() - t0, 4), "converged": status == ldg.LDG_OK,
+                    "iters": st["iters"], "res_ratio": st["res_true"] / max(st["res0"], 1e-300)}
+    res["convdiff2d_p3_128sq_seed100000"] = cd
+    log("convdiff 128^2", cd)
+    return res
+
+
 def implicit_steps(ldg, I, log, nsteps=5):
     """2D Euler, four isentropic vortices, 256^2 p=4 periodic: BDF1 then BDF2 steps at CFL 10, each solved by
     Newton-GMRES(50) + block-Jacobi (rebuilt per Newton iterate), eta = 1e-3, ||G|| <= 1e-8 ||G0||."""
@@ -309,6 +350,9 @@ def main():
     # JVP throughput on the other workload shapes (FP64 and FP32, HIP events)
     if not args.no_extra_workloads:
         out["other_workloads"] = other_workloads(ldg, I, log)
+
+    if not args.no_solve:
+        out["other_solves"] = other_solves(ldg, I, log)
 
     # implicit time steps on the 2D Euler workload (seconds per step averaged over steps 2..5)
     if not args.no_implicit:
