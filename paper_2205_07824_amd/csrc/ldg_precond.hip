@@ -128,8 +128,10 @@ __global__ void __launch_bounds__(256) k_gj_invert(int nb, double* __restrict__ 
 // z_b = B_b^-1 r_b with the transposed inverse (M[j][i] = inverse[i][j]): one
 // thread per row, bpb blocks per work-group, r_b staged in LDS.  For each j the
 // threads of a block read one contiguous row of M; four partial sums keep four
-// loads in flight per thread.  NB > 0: block size fixed at compile time (loop
-// fully unrolled); NB = 0: any block size.
+// loads in flight per thread.  The inverses are streamed once per apply (far
+// larger than the caches), so they are read with nontemporal loads.
+// NB > 0: block size fixed at compile time (loop fully unrolled); NB = 0: any
+// block size.
 template <class S, int NB>
 __global__ void __launch_bounds__(1024) k_bj_apply(int nb_rt, int64_t nblocks, int bpb, const S* __restrict__ inv,
                                                   const double* __restrict__ r, double* __restrict__ z) {
@@ -146,14 +148,14 @@ __global__ void __launch_bounds__(1024) k_bj_apply(int nb_rt, int64_t nblocks, i
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if constexpr (NB > 0) {
 #pragma unroll
-    for (int j = 0; j < NB; ++j) acc[j & 3] += (double)M[j * NB] * rb[j];
+    for (int j = 0; j < NB; ++j) acc[j & 3] += (double)__builtin_nontemporal_load(M + j * NB) * rb[j];
   } else {
     int j = 0;
     for (; j + 4 <= nb; j += 4) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] += (double)M[(j + u) * nb] * rb[j + u];
+      for (int u = 0; u < 4; ++u) acc[u] += (double)__builtin_nontemporal_load(M + (j + u) * nb) * rb[j + u];
     }
-    for (; j < nb; ++j) acc[0] += (double)M[j * nb] * rb[j];
+    for (; j < nb; ++j) acc[0] += (double)__builtin_nontemporal_load(M + j * nb) * rb[j];
   }
   z[b * nb + i] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
