@@ -183,8 +183,8 @@ ldg_status ldg_jacobian_blocks(ldg_model model, const ldg_time* t, const double*
                                double* blocks, void* stream);
 
 /* Block-Jacobi preconditioner: the blocks above, inverted by Gauss-Jordan
- * elimination with partial pivoting, stored in FP64 or FP32 (factor_prec).
- * Apply: z_K = B_K^{-1} r_K. */
+ * elimination with partial pivoting, stored in FP64 or FP32 (factor_prec; with
+ * FP32 storage the probing JVPs also run in FP32).  Apply: z_K = B_K^{-1} r_K. */
 ldg_status ldg_precond_block_jacobi(ldg_model model, const ldg_time* t, const double* u_lin, int per_variable,
                                     ldg_precision factor_prec, void* stream, ldg_precond* out);
 ldg_status ldg_precond_apply(ldg_precond pc, const double* r, double* z, void* stream);

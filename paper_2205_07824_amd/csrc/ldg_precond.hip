@@ -129,7 +129,9 @@ __global__ void __launch_bounds__(256) k_gj_invert(int nb, double* __restrict__ 
 // thread per row, bpb blocks per work-group, r_b staged in LDS.  For each j the
 // threads of a block read one contiguous row of M; four partial sums keep four
 // loads in flight per thread.  The inverses are streamed once per apply (far
-// larger than the caches), so they are read with nontemporal loads.
+// larger than the caches): with nb = 64 every row of M fills whole cache lines
+// and is read with nontemporal loads; for other sizes consecutive rows share
+// lines, which plain loads reuse (nontemporal ones measured slower there).
 // NB > 0: block size fixed at compile time (loop fully unrolled); NB = 0: any
 // block size.
 template <class S, int NB>
@@ -153,15 +155,17 @@ __global__ void __launch_bounds__(1024) k_bj_apply(int nb_rt, int64_t nblocks, i
     int j = 0;
     for (; j + 4 <= nb; j += 4) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] += (double)__builtin_nontemporal_load(M + (j + u) * nb) * rb[j + u];
+      for (int u = 0; u < 4; ++u) acc[u] += (double)M[(j + u) * nb] * rb[j + u];
     }
-    for (; j < nb; ++j) acc[0] += (double)__builtin_nontemporal_load(M + j * nb) * rb[j];
+    for (; j < nb; ++j) acc[0] += (double)M[j * nb] * rb[j];
   }
   z[b * nb + i] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
+// probe = LDG_FP32 for blocks that are stored in FP32 anyway (the probing JVPs
+// then run in FP32 too)
 static ldg_status assemble_blocks(Model& md, const ldg_time* t, const double* u_lin, int per_variable,
-                                  double* blocks, hipStream_t s) {
+                                  double* blocks, ldg_precision probe, hipStream_t s) {
   Mesh& m = *md.mesh;
   const int NB = md.ncu * m.nn;
   const int64_t n = (int64_t)md.N();
@@ -169,6 +173,10 @@ static ldg_status assemble_blocks(Model& md, const ldg_time* t, const double* u_
   if (!md.linear && md.kind != LDG_MODEL_EULER) {
     st = op_grad(md, u_lin, md.d_q, false, true, s);
     if (st != LDG_OK) return st;
+    if (probe == LDG_FP32) {
+      st = op_grad(md, u_lin, md.d_q32, true, true, s);
+      if (st != LDG_OK) return st;
+    }
   }
   double* v = md.d_tmp;
   double* Jv = md.d_tmp2;
@@ -179,7 +187,7 @@ static ldg_status assemble_blocks(Model& md, const ldg_time* t, const double* u_
     const int32_t* list = m.d_color_list + m.color_off[c];
     for (int j = 0; j < NB; ++j) {
       hipLaunchKernelGGL(k_probe_set, dim3((cnt + 255) / 256), dim3(256), 0, s, cnt, list, NB, j, 1.0, v);
-      st = jvp_impl(md, t, u_lin, v, Jv, LDG_FP64, true, s);
+      st = jvp_impl(md, t, u_lin, v, Jv, probe, true, s);
       if (st != LDG_OK) return st;
       const int64_t tot = per_variable ? (int64_t)cnt * m.nn : (int64_t)cnt * NB;
       hipLaunchKernelGGL(k_probe_gather, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, cnt, list, NB, m.nn, j,
@@ -217,7 +225,8 @@ ldg_status precond_rebuild(ldg_precond_s* pc, const ldg_time* t, const double* u
     set_error("the learned preconditioner is rebuilt through its block-Jacobi part");
     return LDG_EINVAL;
   }
-  ldg_status st = assemble_blocks(*pc->md, t, u_lin, pc->per_variable, pc->scratch, s);
+  ldg_status st = assemble_blocks(*pc->md, t, u_lin, pc->per_variable, pc->scratch,
+                                  pc->prec == LDG_FP32 ? LDG_FP32 : LDG_FP64, s);
   if (st != LDG_OK) return st;
   return invert_blocks(pc, s);
 }
@@ -276,7 +285,7 @@ ldg_status ldg_jacobian_blocks(ldg_model md, const ldg_time* t, const double* u_
   LDG_ENTER();
   if (!md || !blocks) { set_error("null argument"); return LDG_EINVAL; }
   if (!md->linear && !u_lin) { set_error("nonlinear model needs u_lin"); return LDG_EINVAL; }
-  return assemble_blocks(*md, t, u_lin, per_variable, blocks, (hipStream_t)stream);
+  return assemble_blocks(*md, t, u_lin, per_variable, blocks, LDG_FP64, (hipStream_t)stream);
 }
 
 ldg_status ldg_precond_block_jacobi(ldg_model md, const ldg_time* t, const double* u_lin, int per_variable,
