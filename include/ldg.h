@@ -257,7 +257,8 @@ typedef struct {
   int maxit;             /* Newton iteration cap                                       */
   double rtol, atol;     /* stop when ||G(u_k)|| <= max(rtol ||G(u_0)||, atol)          */
   double eta;            /* linear solve relative tolerance (forcing term)              */
-  int bj_refresh;        /* rebuild a block-Jacobi preconditioner at every iterate      */
+  int bj_refresh;        /* rebuild the block-Jacobi preconditioner: 0 never, 1 at every
+                            iterate, 2 at the first iterate only (lagged)               */
   int bj_per_variable;   /* for bj_refresh                                              */
   ldg_precision bj_prec; /* storage precision of the refreshed blocks                   */
   ldg_gmres_opts lin;    /* inner solver options (rtol is replaced by eta)              */

@@ -960,7 +960,7 @@ ldg_status ldg_newton_solve(ldg_model md, const ldg_time* t, double* u, const ld
   while (gn > std::max(opts->rtol * g0, opts->atol)) {
     if (S.iters >= opts->maxit) { result = LDG_ENOCONV; set_error("Newton did not converge"); break; }
     if (!std::isfinite(gn)) { result = LDG_EBREAKDOWN; set_error("non-finite Newton residual"); break; }
-    if (opts->bj_refresh && lin.pc) {
+    if (lin.pc && (opts->bj_refresh == 1 || (opts->bj_refresh == 2 && S.iters == 0))) {
       st = precond_rebuild(lin.pc, t, u, s);
       if (st != LDG_OK) { result = st; break; }
     }

@@ -64,6 +64,8 @@ __global__ void __launch_bounds__(256) k_gj_invert(int nb, double* __restrict__ 
   double* A = use_lds ? lds : G;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int nn2 = nb * nb;
+  const int rpp = nt / nb;                 // rows per pass of the update (nb <= 128 < nt)
+  const int jc = tid % nb, r0 = tid / nb;
   if (use_lds)
     for (int t = tid; t < nn2; t += nt) A[t] = G[t];
   __syncthreads();
@@ -99,11 +101,14 @@ __global__ void __launch_bounds__(256) k_gj_invert(int nb, double* __restrict__ 
     __syncthreads();
     for (int j = tid; j < nb; j += nt) A[k * nb + j] = (j == k ? 1.0 : A[k * nb + j]) * ipv;
     __syncthreads();
-    for (int t = tid; t < nn2; t += nt) {
-      const int i = t / nb, j = t % nb;
-      if (i == k) continue;
-      const double base = (j == k) ? 0.0 : A[t];
-      A[t] = base - fcol[i] * A[k * nb + j];
+    // rank-1 update of the other rows: thread (r0, j) owns column j of rows r0, r0 + rpp, ...
+    if (r0 < rpp) {
+      const double akj = A[k * nb + jc];
+      for (int i = r0; i < nb; i += rpp) {
+        if (i == k) continue;
+        const double base = (jc == k) ? 0.0 : A[i * nb + jc];
+        A[i * nb + jc] = base - fcol[i] * akj;
+      }
     }
     __syncthreads();
   }
@@ -119,10 +124,8 @@ __global__ void __launch_bounds__(256) k_gj_invert(int nb, double* __restrict__ 
     __syncthreads();
   }
   S* out = inv + b * (int64_t)nb * nb;
-  for (int t = tid; t < nn2; t += nt) {
-    const int j = t / nb, i = t % nb;   // out[j][i] = A[i][j]
-    out[t] = (S)A[i * nb + j];
-  }
+  if (r0 < rpp)
+    for (int j = r0; j < nb; j += rpp) out[j * nb + jc] = (S)A[jc * nb + j];   // out[j][i] = A[i][j]
 }
 
 // z_b = B_b^-1 r_b with the transposed inverse (M[j][i] = inverse[i][j]): one
@@ -202,7 +205,24 @@ static ldg_status assemble_blocks(Model& md, const ldg_time* t, const double* u_
 static ldg_status invert_blocks(ldg_precond_s* pc, hipStream_t s) {
   const int nb = pc->nb;
   const size_t bytes = (size_t)nb * nb * sizeof(double);
-  const int use_lds = bytes <= 48 * 1024 ? 1 : 0;   // plus ~1.5 KB of static LDS
+  // the block in LDS when it fits beside the kernel's ~1.6 KB of static LDS
+  static int lds_limit = -1;
+  if (lds_limit < 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      v = 64 * 1024;
+    lds_limit = v;
+    (void)hipGetLastError();
+  }
+  const int use_lds = bytes + 2048 <= (size_t)lds_limit ? 1 : 0;
+  if (use_lds && bytes > 48 * 1024) {
+    if (pc->prec == LDG_FP32)
+      (void)hipFuncSetAttribute((const void*)k_gj_invert<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    else
+      (void)hipFuncSetAttribute((const void*)k_gj_invert<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    (void)hipGetLastError();
+  }
   if (nb > 128) { set_error("block size above 128"); return LDG_EUNSUPPORTED; }
   if (zero_int(pc->info, s) != LDG_OK) return LDG_EDEVICE;
   const int threads = 256;
