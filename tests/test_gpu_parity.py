@@ -218,6 +218,34 @@ def test_gmres_orthogonalization_variants_match_cgs2(L, orth, use_pc, restart):
     assert (x1 - x2).norm().item() <= 1e-6 * x1.norm().item()
 
 
+@pytest.mark.parametrize("orth", ["cgs2", "mgs", "dcgs2"])
+@pytest.mark.parametrize("restart", [1, 2, 128])
+def test_gmres_restart_extremes(L, orth, restart):
+    """Restart lengths 1, 2 and the maximum 128 with every orthogonalization: the true FP64 residual meets the
+    tolerance (or, for GMRES(1)/(2), decreases monotonically over the cycles)."""
+    import torch
+    c = CS.c1_poisson2d()
+    m, md, t, dev = build_gpu(L, c)
+    N = c.om.size(1)
+    b = dev(np.random.default_rng(21).uniform(-1, 1, N))
+    o = {"cgs2": L.ORTH_CGS2, "mgs": L.ORTH_MGS, "dcgs2": L.ORTH_DCGS2}[orth]
+    pc = L.BlockJacobi(md)
+    if restart == 128:
+        x, st, status = L.gmres(md, b, pc=pc, restart=restart, rtol=1e-10, maxit=400, orth=o)
+        assert status == L.LDG_OK and st["res_true"] <= 1.01e-10 * st["res0"]
+        assert st["iters"] < 128   # no restart needed on this system
+    else:
+        x = torch.zeros_like(b)
+        prev = L.norm(b)
+        for _ in range(5):
+            x, st, status = L.gmres(md, b, x=x, pc=pc, restart=restart, rtol=0.0, atol=0.0, maxit=restart * 4,
+                                    orth=o, check=False)
+            assert status == L.LDG_ENOCONV
+            r = L.norm(b - md.jvp(None, x))
+            assert r <= prev * (1 + 1e-12)
+            prev = r
+
+
 def test_gmres_dcgs2_c1_matches_oracle_solution(L):
     import scipy.sparse.linalg as spla
     import torch
