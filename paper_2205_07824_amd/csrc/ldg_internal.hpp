@@ -263,7 +263,6 @@ ldg_status jvp_impl(Model& md, const ldg_time* t, const double* u, const double*
 
 // vector kernels (ldg_krylov.hip)
 ldg_status vec_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s);
-ldg_status vec_scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t s);
 ldg_status vec_fill(int64_t n, double a, double* y, hipStream_t s);
 // host result of sum(x*x); uses a small device scratch owned by the caller
 ldg_status vec_norm2(int64_t n, const double* x, double* partial, double* host_out, hipStream_t s);

@@ -94,9 +94,6 @@ ldg_status vec_fill(int64_t n, double a, double* y, hipStream_t s) {
   LDG_TRY(hipGetLastError());
   return LDG_OK;
 }
-ldg_status vec_scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t s) {
-  return vec_axpby(n, a, x, 0.0, y, s);
-}
 // sum(x^2) to the host; part needs >= RED_BLOCKS + 1 doubles
 ldg_status vec_norm2(int64_t n, const double* x, double* part, double* host_out, hipStream_t s) {
   const int g = grid_for(n);
