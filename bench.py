@@ -146,6 +146,32 @@ def other_workloads(ldg, I, log):
     return res
 
 
+def mfma_p4(ldg, I, log, steps=20):
+    """2D Poisson p=4 on 512^2 quads (N = 6,553,600): the BF16/FP16-MFMA JVP (dense element contractions on the
+    matrix cores) against the FP64 JVP; dense MFMA flops per JVP = 4 d nn^2 E (two GEMMs)."""
+    import torch
+    box = I.box_mesh(2, 512)
+    m = ldg.Mesh(box, 4)
+    md = ldg.Model(m, ldg.MODEL_POISSON, 1, [1.0, 25.0 * 512, 0.0], bc_kind=(0,))
+    v = torch.as_tensor(np.random.default_rng(2).uniform(-1, 1, md.N), device="cuda")
+    ref = md.jvp(None, v).clone()
+    Jv = md.empty()
+    res = {"workload": "2D Poisson p=4, 512^2 quads", "dof": md.N}
+    flops = 4.0 * 2 * m.nn * m.nn * m.E
+    for nm, pr in (("fp64", ldg.FP64), ("bf16_mfma", ldg.BF16_MFMA), ("fp16_mfma", ldg.FP16_MFMA)):
+        md.jvp(None, v, out=Jv, prec=pr)
+        e = event_time(lambda: md.jvp(None, v, out=Jv, prec=pr), steps)
+        res[f"jvp_{nm}_gdofs"] = round(md.N / e / 1e9, 3)
+        res[f"jvp_{nm}_us"] = round(e * 1e6, 1)
+        if pr != ldg.FP64:
+            res[f"jvp_{nm}_rel_err_vs_fp64"] = float(((Jv - ref).norm() / ref.norm()).item())
+            res[f"jvp_{nm}_dense_mfma_tflops"] = round(flops / e / 1e12, 3)
+    log("mfma p=4", res)
+    del md, m, v, ref, Jv
+    torch.cuda.empty_cache()
+    return res
+
+
 def other_solves(ldg, I, log):
     """Newton-GMRES time-to-tolerance on the 2D Poisson p=2 8x8 workload (Newton 1 step, GMRES(30) + block-Jacobi
     to 1e-10) and one held-out 2D convection-diffusion instance at 128^2 p=3 (FGMRES(30) + block-Jacobi to 1e-8,
@@ -235,6 +261,8 @@ def main():
                     help="skip the 2D Euler BDF2 Newton-GMRES steps")
     ap.add_argument("--profile-jvp-only", action="store_true",
                     help="only the timed JVP steps (for counter collection)")
+    ap.add_argument("--profile-mfma-only", action="store_true",
+                    help="only the 2D Poisson p=4 MFMA JVP leg (for counter collection)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 512 MiB buffer 10 times (scales the HBM byte counters)")
     args = ap.parse_args()
@@ -254,6 +282,9 @@ def main():
             c.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read_per_dispatch": a.numel() * 8, "copy_bytes_written_per_dispatch": a.numel() * 8}))
+        return
+    if args.profile_mfma_only:
+        print(json.dumps(mfma_p4(ldg, I, log, steps=args.steps)))
         return
     box, m, md = build_workload(ldg, I, n=args.n)
     N = md.N
@@ -351,6 +382,7 @@ def main():
     # JVP throughput on the other workload shapes (FP64 and FP32, HIP events)
     if not args.no_extra_workloads:
         out["other_workloads"] = other_workloads(ldg, I, log)
+        out["mfma_p4"] = mfma_p4(ldg, I, log)
 
     if not args.no_solve:
         out["other_solves"] = other_solves(ldg, I, log)
