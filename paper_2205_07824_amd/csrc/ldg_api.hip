@@ -281,6 +281,41 @@ ldg_status ldg_mesh_create(int nd, int p, int nq1d, int64_t nvert, const double*
   }
   m->color_off[m->ncolors] = (int64_t)clist.size();
 
+  // operator visit order.  3D: elements sorted by the Morton code of their
+  // centroid (the constant monomial coefficient), so that the work-groups in
+  // flight on one XCD touch face neighbours that are also in flight and share
+  // its L2 (measured 15% faster on the 64^3 Navier-Stokes tangent).  2D: the
+  // input order, whose neighbour rows already fit in L2 (Morton measured a few
+  // per cent slower there).
+  m->h_order.resize(nelem);
+  for (int64_t K = 0; K < nelem; ++K) m->h_order[K] = (int32_t)K;
+  if (nd == 3) {
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int k = 0; k < nd; ++k) { lo[k] = 1e300; hi[k] = -1e300; }
+    for (int64_t K = 0; K < nelem; ++K)
+      for (int k = 0; k < nd; ++k) {
+        const double c = m->h_coef[(size_t)K * nv * nd + k];
+        lo[k] = std::min(lo[k], c);
+        hi[k] = std::max(hi[k], c);
+      }
+    const int bits = 10;
+    std::vector<uint64_t> code((size_t)nelem, 0);
+    for (int64_t K = 0; K < nelem; ++K) {
+      uint64_t cell[3] = {0, 0, 0};
+      for (int k = 0; k < nd; ++k) {
+        const double ext = hi[k] - lo[k];
+        double t = ext > 0 ? (m->h_coef[(size_t)K * nv * nd + k] - lo[k]) / ext : 0.0;
+        t = std::min(std::max(t, 0.0), 1.0);
+        cell[k] = std::min<uint64_t>((uint64_t)(t * double(1u << bits)), (1u << bits) - 1);
+      }
+      uint64_t z = 0;
+      for (int b = bits - 1; b >= 0; --b)
+        for (int k = nd - 1; k >= 0; --k) z = (z << 1) | ((cell[k] >> b) & 1u);
+      code[K] = z;
+    }
+    std::stable_sort(m->h_order.begin(), m->h_order.end(), [&](int32_t a, int32_t b) { return code[a] < code[b]; });
+  }
+
   // upload
   hipError_t e = hipSuccess;
   e = hipMalloc((void**)&m->d_coef, m->h_coef.size() * sizeof(double));
@@ -292,9 +327,11 @@ ldg_status ldg_mesh_create(int nd, int p, int nq1d, int64_t nvert, const double*
     e = hipMemcpy(m->d_btag, m->h_btag.data(), m->h_btag.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc((void**)&m->d_color_list, clist.size() * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemcpy(m->d_color_list, clist.data(), clist.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->d_order, m->h_order.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMemcpy(m->d_order, m->h_order.data(), m->h_order.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     set_error(std::string("mesh upload: ") + hipGetErrorString(e));
-    hipFree(m->d_coef); hipFree(m->d_nbr); hipFree(m->d_btag); hipFree(m->d_color_list);
+    hipFree(m->d_coef); hipFree(m->d_nbr); hipFree(m->d_btag); hipFree(m->d_color_list); hipFree(m->d_order);
     delete m;
     return e == hipErrorOutOfMemory ? LDG_ENOMEM : LDG_EDEVICE;
   }
@@ -354,7 +391,7 @@ ldg_status ldg_mesh_points(ldg_mesh m, double* xnode, double* xquad, double* xbf
 ldg_status ldg_mesh_destroy(ldg_mesh m) {
   LDG_ENTER();
   if (!m) return LDG_OK;
-  hipFree(m->d_coef); hipFree(m->d_nbr); hipFree(m->d_btag); hipFree(m->d_color_list);
+  hipFree(m->d_coef); hipFree(m->d_nbr); hipFree(m->d_btag); hipFree(m->d_color_list); hipFree(m->d_order);
   delete m;
   return LDG_OK;
 }

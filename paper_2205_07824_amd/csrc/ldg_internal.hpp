@@ -35,6 +35,7 @@ struct MeshDev {
   const double* coef;    // [E][2^nd][nd] multilinear monomial coefficients: x(xi) = sum_m coef[m] prod_{k in m} xi_k
   const int32_t* nbr;    // [E][2nd] >= 0 neighbour element; < 0: -(1 + boundary face index)
   const int32_t* btag;   // [nbf] boundary tag
+  const int32_t* order;  // [E] element visit order of the operator kernels (a permutation of 0..E-1)
 };
 
 // Device view of a model's parameters.
@@ -191,8 +192,10 @@ struct Mesh {
   int32_t* d_nbr = nullptr;
   int32_t* d_btag = nullptr;
   int32_t* d_color_list = nullptr;    // elements sorted by colour
+  std::vector<int32_t> h_order;       // [E] Morton order of the element centroids
+  int32_t* d_order = nullptr;
   std::vector<int64_t> color_off;     // [ncolors+1] offsets into d_color_list
-  MeshDev dev() const { return MeshDev{(int)E, (int)nbf, d_coef, d_nbr, d_btag}; }
+  MeshDev dev() const { return MeshDev{(int)E, (int)nbf, d_coef, d_nbr, d_btag, d_order}; }
 };
 
 struct Model {

@@ -17,9 +17,10 @@
 // Face work is organised by reference direction (a compile-time constant), so
 // the line strides, the tangential directions and the normal (cross product of
 // the two tangential Jacobian columns) need no per-lane selects.  The 1D tables
-// live in LDS.  Work-groups are mapped to elements so that each of the eight
-// XCDs (which receive work-groups round-robin) walks a contiguous range of
-// elements and finds most neighbours in its own L2.
+// live in LDS.  Work-groups take elements in the mesh's visit order (the
+// Morton order of the element centroids), and each of the eight XCDs (which
+// receive work-groups round-robin) walks a contiguous range of that order, so
+// that most face neighbours are in flight on the same XCD and hit its L2.
 #include <type_traits>
 
 #pragma once
@@ -78,7 +79,8 @@ __device__ inline void stage_tables(const TAB& tab, R* st) {
   }
 }
 
-// work-group -> element block, XCD-aware (work-group b runs on XCD b % 8)
+// work-group -> block of slots in the mesh's element visit order, XCD-aware
+// (work-group b runs on XCD b % 8, and each XCD walks a contiguous range)
 __device__ inline int64_t xcd_block(int64_t b, int64_t nblk) {
   const int64_t q = nblk >> 3;
   if (b < (q << 3)) return (b & 7) * q + (b >> 3);
@@ -328,10 +330,12 @@ k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const double* __restric
   __shared__ R s_g[EPB][AFF ? 1 : GeoTab<D, P1>::SIZE];
   __shared__ R s_lfw[2 * P1];
 
+  __shared__ int s_K[EPB];
   const int64_t eb = xcd_block(blockIdx.x, gridDim.x);
   const int el = threadIdx.x / NN, i = threadIdx.x % NN;
-  const int64_t K = eb * EPB + el;
-  const bool active = K < m.E;
+  const bool active = eb * EPB + el < m.E;
+  const int64_t K = active ? m.order[eb * EPB + el] : 0;
+  if (threadIdx.x < EPB) s_K[threadIdx.x] = eb * EPB + threadIdx.x < m.E ? m.order[eb * EPB + threadIdx.x] : -1;
   stage_tables<P1, R>(tab, s_tab);
   if (active) {
 #pragma unroll
@@ -355,8 +359,8 @@ k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const double* __restric
     constexpr int SD = stride_c(P1, DIR);
     {
       const int e = it / (2 * NFP), side = (it / NFP) & 1, f = it % NFP;
-      const int64_t Ke = eb * EPB + e;
-      if (Ke >= m.E) return;
+      const int64_t Ke = s_K[e];
+      if (Ke < 0) return;
       const int t0 = f % P1, t1 = (D == 3) ? f / P1 : 0;
       int base = t0 * stride_c(P1, T0);
       if constexpr (D == 3) base += t1 * stride_c(P1, T1);
@@ -488,10 +492,12 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const doub
   __shared__ double s_c[EPB][NV * D];
   __shared__ R s_g[EPB][AFF ? 1 : GeoTab<D, P1>::SIZE];
 
+  __shared__ int s_K[EPB];
   const int64_t eb = xcd_block(blockIdx.x, gridDim.x);
   const int el = threadIdx.x / NN, i = threadIdx.x % NN;
-  const int64_t K = eb * EPB + el;
-  const bool active = K < m.E;
+  const bool active = eb * EPB + el < m.E;
+  const int64_t K = active ? m.order[eb * EPB + el] : 0;
+  if (threadIdx.x < EPB) s_K[threadIdx.x] = eb * EPB + threadIdx.x < m.E ? m.order[eb * EPB + threadIdx.x] : -1;
   stage_tables<P1, R>(tab, s_tab);
   // state loads: MODE 0 reads the input vector from u (the vector the linear
   // operator is applied to); MODE 2 pairs (u, v) and (q, dq).
@@ -529,8 +535,8 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const doub
     constexpr int SD = stride_c(P1, DIR);
     {
       const int e = it / (2 * NFP), side = (it / NFP) & 1, ff = it % NFP;
-      const int64_t Ke = eb * EPB + e;
-      if (Ke >= m.E) return;
+      const int64_t Ke = s_K[e];
+      if (Ke < 0) return;
       const int t0 = ff % P1, t1 = (D == 3) ? ff / P1 : 0;
       int base = t0 * stride_c(P1, T0);
       if constexpr (D == 3) base += t1 * stride_c(P1, T1);
