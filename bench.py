@@ -228,7 +228,8 @@ def implicit_steps(ldg, I, log, nsteps=5):
     u0 = torch.as_tensor(np.ascontiguousarray(Ut).reshape(-1), device="cuda")
     res = {"workload": "2D Euler p=4, 256^2 periodic [0,20]^2, 4 isentropic vortices, BDF2 at CFL 10",
            "dof": md.N, "dt": dt, "steps": nsteps}
-    for name, jp, bp, rf in (("fp64_jvp+fp64_bj", ldg.FP64, ldg.FP64, 1), ("fp32_jvp+fp32_bj", ldg.FP32, ldg.FP32, 1)):
+    for name, jp, bp, rf in (("fp64_jvp+fp64_bj", ldg.FP64, ldg.FP64, 1), ("fp32_jvp+fp32_bj", ldg.FP32, ldg.FP32, 1),
+                             ("fp32_jvp+fp16_bj", ldg.FP32, ldg.FP16, 1)):
         _, stats = TS.bdf_steps(md, u0, dt, nsteps, restart=50, eta=1e-3, rtol=1e-8, jvp_prec=jp, bj_prec=bp,
                                 bj_refresh=rf, log=log)
         later = stats[1:] if len(stats) > 1 else stats
@@ -358,7 +359,10 @@ def main():
         orth = ldg.ORTH_DCGS2 if args.orth == "dcgs2" else ldg.ORTH_CGS2
         for name, jp, bp, eta in (("fp64_jvp+fp64_bj", ldg.FP64, ldg.FP64, 1e-9),
                                   ("fp64_jvp+fp32_bj", ldg.FP64, ldg.FP32, 1e-9),
-                                  ("fp32_jvp+fp32_bj", ldg.FP32, ldg.FP32, 1e-4)):
+                                  ("fp64_jvp+fp16_bj", ldg.FP64, ldg.FP16, 1e-9),
+                                  ("fp32_jvp+fp32_bj", ldg.FP32, ldg.FP32, 1e-4),
+                                  ("fp32_jvp+fp16_bj", ldg.FP32, ldg.FP16, 1e-4),
+                                  ("fp32_jvp+bf16_bj", ldg.FP32, ldg.BF16, 1e-4)):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             pc = ldg.BlockJacobi(md, prec=bp)

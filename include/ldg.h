@@ -65,7 +65,9 @@ typedef enum {
   LDG_FP32 = 1,
   LDG_BF16_MFMA = 2,   /* derivative/test contractions on MFMA, bf16 operands, fp32 accumulation */
   LDG_FP16_MFMA = 3,   /* same with fp16 operands                                              */
-  LDG_JVP_FD = 4       /* finite-difference JVP: (R(u + eps v) - R(u)) / eps in FP64             */
+  LDG_JVP_FD = 4,      /* finite-difference JVP: (R(u + eps v) - R(u)) / eps in FP64             */
+  LDG_BF16 = 5,        /* storage only (block-Jacobi factors): bf16 codes, FP64 arithmetic       */
+  LDG_FP16 = 6         /* storage only (block-Jacobi factors): fp16 codes, FP64 arithmetic       */
 } ldg_precision;
 
 /* Built-in PDE models (Section 2.1 classes): diffusion (Poisson/heat,
@@ -183,8 +185,12 @@ ldg_status ldg_jacobian_blocks(ldg_model model, const ldg_time* t, const double*
                                double* blocks, void* stream);
 
 /* Block-Jacobi preconditioner: the blocks above, inverted by Gauss-Jordan
- * elimination with partial pivoting, stored in FP64 or FP32 (factor_prec; with
- * FP32 storage the probing JVPs also run in FP32).  Apply: z_K = B_K^{-1} r_K. */
+ * elimination with partial pivoting, stored in FP64, FP32, BF16 or FP16
+ * (factor_prec; with any storage below FP64 the probing JVPs run in FP32).  The
+ * 16-bit forms store each row of B_K^{-1} divided by a power of two >= its
+ * largest magnitude (so every code lies in (-1, 1) and the scaling is exact)
+ * and apply in FP64 arithmetic.  Apply: z_K = B_K^{-1} r_K.  Other factor_prec
+ * values: LDG_EINVAL. */
 ldg_status ldg_precond_block_jacobi(ldg_model model, const ldg_time* t, const double* u_lin, int per_variable,
                                     ldg_precision factor_prec, void* stream, ldg_precond* out);
 ldg_status ldg_precond_apply(ldg_precond pc, const double* r, double* z, void* stream);

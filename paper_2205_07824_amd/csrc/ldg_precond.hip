@@ -2,8 +2,10 @@
 // probing (one JVP per element colour and local unknown; elements of one colour
 // are at face-graph distance >= 3, beyond the reach of the LDG stencil), batched
 // Gauss-Jordan inversion with partial pivoting, and a batched block-matrix
-// vector product as the apply (FP64 or FP32 storage).
+// vector product as the apply (FP64, FP32, or 16-bit storage: bf16 or fp16 with
+// a power-of-two scale per row and FP64 accumulation).
 #include <cmath>
+#include <cstdint>
 
 #include "ldg_internal.hpp"
 
@@ -15,7 +17,11 @@ struct ldg_precond_s {
   ldg_precision prec;     // storage precision of the inverse blocks
   int nb;                 // block size
   int64_t nblocks;        // E (full) or E * ncu (per variable)
-  void* inv = nullptr;    // [nblocks][nb][nb], transposed: inv[b][j][i] = (B_b^-1)[i][j]
+  void* inv = nullptr;    // FP64/FP32: [nblocks][nb][nb], transposed: inv[b][j][i] = (B_b^-1)[i][j]
+                          // 16-bit: [nblocks][ng][nb][4], inv[b][g][i][k] = (B_b^-1)[i][4g+k] / scale[b][i]
+                          // (zero for 4g+k >= nb)
+  float* scale = nullptr; // 16-bit: [nblocks][nb] power-of-two row scales
+  int ng = 0;             // 16-bit: column groups of four, ceil(nb / 4)
   double* scratch = nullptr;  // assembled blocks [nblocks][nb][nb] row-major
   int* info = nullptr;        // singular-block counter (device)
   double a0 = 0.0;
@@ -48,12 +54,29 @@ __global__ void k_probe_gather(int n, const int32_t* __restrict__ list, int NB, 
   }
 }
 
+// 16-bit codes: bf16 by round-to-nearest-even of the FP32 value; fp16 by the
+// hardware conversion
+__device__ inline uint16_t to_bf16(double x) {
+  uint32_t u = __float_as_uint((float)x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline uint16_t to_fp16(double x) {
+  const _Float16 h = (_Float16)(float)x;
+  return __builtin_bit_cast(uint16_t, h);
+}
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ inline double from_bf16(uint32_t c) { return (double)__uint_as_float(c << 16); }
+__device__ inline double from_fp16(uint32_t c) { return (double)(float)__builtin_bit_cast(_Float16, (uint16_t)c); }
+
 // In-place Gauss-Jordan inversion with row pivoting of one nb x nb block per
 // work-group (A in LDS when it fits, otherwise in global memory), written out
-// transposed in the storage precision.
-template <class S>
+// transposed in the storage precision.  H = 0: S-typed entries; H = 1 (bf16) or
+// 2 (fp16): the grouped 16-bit layout with row scales.
+template <class S, int H>
 __global__ void __launch_bounds__(256) k_gj_invert(int nb, double* __restrict__ blocks, S* __restrict__ inv,
-                                                   int use_lds, int* __restrict__ info) {
+                                                   float* __restrict__ scale, int use_lds, int* __restrict__ info) {
   extern __shared__ double lds[];
   __shared__ int piv[128];
   __shared__ double fcol[128];
@@ -123,9 +146,29 @@ __global__ void __launch_bounds__(256) k_gj_invert(int nb, double* __restrict__ 
       }
     __syncthreads();
   }
-  S* out = inv + b * (int64_t)nb * nb;
-  if (r0 < rpp)
-    for (int j = r0; j < nb; j += rpp) out[j * nb + jc] = (S)A[jc * nb + j];   // out[j][i] = A[i][j]
+  if constexpr (H == 0) {
+    S* out = inv + b * (int64_t)nb * nb;
+    if (r0 < rpp)
+      for (int j = r0; j < nb; j += rpp) out[j * nb + jc] = (S)A[jc * nb + j];   // out[j][i] = A[i][j]
+  } else {
+    // row i scaled by the power of two 2^e >= max_j |A[i][j]| (exact), so every code is in (-1, 1)
+    const int ng = (nb + 3) / 4;
+    for (int i = tid; i < nb; i += nt) {
+      double mx = 0.0;
+      for (int j = 0; j < nb; ++j) mx = fmax(mx, fabs(A[i * nb + j]));
+      int e = 0;
+      if (mx > 0.0) (void)frexp(mx, &e);
+      fcol[i] = ldexp(1.0, -e);
+      scale[b * nb + i] = (float)ldexp(1.0, e);
+    }
+    __syncthreads();
+    S* out = inv + b * (int64_t)ng * nb * 4;
+    for (int t = tid; t < ng * nb * 4; t += nt) {
+      const int g = t / (nb * 4), i = (t / 4) % nb, j = 4 * g + (t & 3);
+      const double a = j < nb ? A[i * nb + j] * fcol[i] : 0.0;
+      out[t] = H == 1 ? to_bf16(a) : to_fp16(a);
+    }
+  }
 }
 
 // z_b = B_b^-1 r_b with the transposed inverse (M[j][i] = inverse[i][j]): one
@@ -164,6 +207,83 @@ __global__ void __launch_bounds__(1024) k_bj_apply(int nb_rt, int64_t nblocks, i
   }
   z[b * nb + i] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
+
+// z_b = B_b^-1 r_b from the 16-bit grouped layout: one thread per row, one
+// 8-byte load per group of four columns (a wave reads 512 contiguous bytes),
+// decoded and accumulated in FP64, times the row scale.  H = 1 bf16, 2 fp16.
+template <int H>
+__device__ inline void decode4(u32x2 w, double* e) {
+  if constexpr (H == 1) {
+    e[0] = from_bf16(w.x & 0xffffu); e[1] = from_bf16(w.x >> 16); e[2] = from_bf16(w.y & 0xffffu); e[3] = from_bf16(w.y >> 16);
+  } else {
+    e[0] = from_fp16(w.x & 0xffffu); e[1] = from_fp16(w.x >> 16); e[2] = from_fp16(w.y & 0xffffu); e[3] = from_fp16(w.y >> 16);
+  }
+}
+
+template <int H, int NG>
+__global__ void __launch_bounds__(1024) k_bj_apply16(int nb, int ng_rt, int64_t nblocks, int bpb,
+                                                    const uint16_t* __restrict__ inv, const float* __restrict__ scale,
+                                                    const double* __restrict__ r, double* __restrict__ z) {
+  extern __shared__ double rs[];
+  const int ng = NG > 0 ? NG : ng_rt;
+  const int lb = threadIdx.x / nb, i = threadIdx.x % nb;
+  const int64_t b = (int64_t)blockIdx.x * bpb + lb;
+  const bool act = lb < bpb && b < nblocks;
+  const u32x2* M = reinterpret_cast<const u32x2*>(inv + (act ? b : 0) * (int64_t)ng * nb * 4) + i;
+  u32x2 w[NG > 0 ? NG : 1];
+  if constexpr (NG > 0) {
+    // group count fixed at compile time: the (at most two per thread) entries
+    // of r are requested first, then the whole row of codes, so that waiting
+    // for r (the oldest loads) does not wait for the codes.  Loads use clamped
+    // in-bounds indices (threads past the last block read block 0's codes,
+    // unused); padding entries are zeroed by the selects.
+    const int tot = bpb * NG * 4;
+    double rv[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int t = threadIdx.x + h * blockDim.x;
+      const int l = t / (NG * 4), j = t % (NG * 4);
+      const int64_t bb = (int64_t)blockIdx.x * bpb + l;
+      const bool ok = t < tot && j < nb && bb < nblocks;
+      const double x = r[(ok ? bb : 0) * nb + (ok ? j : 0)];
+      rv[h] = ok ? x : 0.0;
+    }
+#pragma unroll
+    for (int g = 0; g < NG; ++g) w[g] = __builtin_nontemporal_load(M + g * nb);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      if (threadIdx.x + h * blockDim.x < tot) rs[threadIdx.x + h * blockDim.x] = rv[h];
+  } else {
+    // r_b staged with zeros up to 4 ng
+    for (int t = threadIdx.x; t < bpb * ng * 4; t += blockDim.x) {
+      const int l = t / (ng * 4), j = t % (ng * 4);
+      const int64_t bb = (int64_t)blockIdx.x * bpb + l;
+      rs[t] = (j < nb && bb < nblocks) ? r[bb * nb + j] : 0.0;
+    }
+  }
+  __syncthreads();
+  if (!act) return;
+  const double* rb = rs + lb * ng * 4;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  auto group = [&](int g, u32x2 wg) {
+    double e[4];
+    decode4<H>(wg, e);
+    double t = acc[g & 3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t = fma(e[k], rb[4 * g + k], t);
+    acc[g & 3] = t;
+  };
+  if constexpr (NG > 0) {
+#pragma unroll
+    for (int g = 0; g < NG; ++g) group(g, w[g]);
+  } else {
+#pragma unroll 4
+    for (int g = 0; g < ng; ++g) group(g, __builtin_nontemporal_load(M + (int64_t)g * nb));
+  }
+  z[b * nb + i] = (double)scale[b * nb + i] * ((acc[0] + acc[1]) + (acc[2] + acc[3]));
+}
+
+static bool is16(ldg_precision p) { return p == LDG_BF16 || p == LDG_FP16; }
 
 // probe = LDG_FP32 for blocks that are stored in FP32 anyway (the probing JVPs
 // then run in FP32 too)
@@ -217,21 +337,30 @@ static ldg_status invert_blocks(ldg_precond_s* pc, hipStream_t s) {
   }
   const int use_lds = bytes + 2048 <= (size_t)lds_limit ? 1 : 0;
   if (use_lds && bytes > 48 * 1024) {
-    if (pc->prec == LDG_FP32)
-      (void)hipFuncSetAttribute((const void*)k_gj_invert<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    else
-      (void)hipFuncSetAttribute((const void*)k_gj_invert<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    const void* f = pc->prec == LDG_FP32   ? (const void*)k_gj_invert<float, 0>
+                    : pc->prec == LDG_BF16 ? (const void*)k_gj_invert<uint16_t, 1>
+                    : pc->prec == LDG_FP16 ? (const void*)k_gj_invert<uint16_t, 2>
+                                           : (const void*)k_gj_invert<double, 0>;
+    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     (void)hipGetLastError();
   }
   if (nb > 128) { set_error("block size above 128"); return LDG_EUNSUPPORTED; }
   if (zero_int(pc->info, s) != LDG_OK) return LDG_EDEVICE;
   const int threads = 256;
+  const size_t lds = use_lds ? bytes : 0;
+  const dim3 grid((unsigned)pc->nblocks);
   if (pc->prec == LDG_FP32)
-    hipLaunchKernelGGL(k_gj_invert<float>, dim3((unsigned)pc->nblocks), dim3(threads), use_lds ? bytes : 0, s, nb,
-                       pc->scratch, (float*)pc->inv, use_lds, pc->info);
+    hipLaunchKernelGGL((k_gj_invert<float, 0>), grid, dim3(threads), lds, s, nb, pc->scratch, (float*)pc->inv,
+                       pc->scale, use_lds, pc->info);
+  else if (pc->prec == LDG_BF16)
+    hipLaunchKernelGGL((k_gj_invert<uint16_t, 1>), grid, dim3(threads), lds, s, nb, pc->scratch, (uint16_t*)pc->inv,
+                       pc->scale, use_lds, pc->info);
+  else if (pc->prec == LDG_FP16)
+    hipLaunchKernelGGL((k_gj_invert<uint16_t, 2>), grid, dim3(threads), lds, s, nb, pc->scratch, (uint16_t*)pc->inv,
+                       pc->scale, use_lds, pc->info);
   else
-    hipLaunchKernelGGL(k_gj_invert<double>, dim3((unsigned)pc->nblocks), dim3(threads), use_lds ? bytes : 0, s, nb,
-                       pc->scratch, (double*)pc->inv, use_lds, pc->info);
+    hipLaunchKernelGGL((k_gj_invert<double, 0>), grid, dim3(threads), lds, s, nb, pc->scratch, (double*)pc->inv,
+                       pc->scale, use_lds, pc->info);
   LDG_TRY(hipGetLastError());
   int h_info = 0;
   LDG_TRY(hipMemcpyAsync(&h_info, pc->info, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -246,7 +375,7 @@ ldg_status precond_rebuild(ldg_precond_s* pc, const ldg_time* t, const double* u
     return LDG_EINVAL;
   }
   ldg_status st = assemble_blocks(*pc->md, t, u_lin, pc->per_variable, pc->scratch,
-                                  pc->prec == LDG_FP32 ? LDG_FP32 : LDG_FP64, s);
+                                  pc->prec == LDG_FP64 ? LDG_FP64 : LDG_FP32, s);
   if (st != LDG_OK) return st;
   return invert_blocks(pc, s);
 }
@@ -264,7 +393,30 @@ ldg_status precond_apply_impl(ldg_precond_s* pc, const double* r, double* z, hip
   const size_t sh = (size_t)bpb * nb * sizeof(double);
   const dim3 thr(bpb * nb);
   if (nb > 1024) { set_error("block-Jacobi blocks larger than 1024 rows"); return LDG_EUNSUPPORTED; }
-  if (pc->prec == LDG_FP32) {
+  if (is16(pc->prec)) {
+    const size_t sh16 = (size_t)bpb * pc->ng * 4 * sizeof(double);
+    const uint16_t* inv = (const uint16_t*)pc->inv;
+    // compile-time group counts for the common block sizes: 16 (nb 64), 25
+    // (nb 100), 7 (nb 25, 27), 4 (nb 16)
+#define LDG_APPLY16(HH, NGC)                                                                                         \
+  hipLaunchKernelGGL((k_bj_apply16<HH, NGC>), dim3(grid), thr, sh16, s, nb, pc->ng, pc->nblocks, bpb, inv, pc->scale, \
+                     r, z)
+#define LDG_APPLY16_ALL(HH)                     \
+  switch (pc->ng) {                             \
+    case 16: LDG_APPLY16(HH, 16); break;        \
+    case 25: LDG_APPLY16(HH, 25); break;        \
+    case 7: LDG_APPLY16(HH, 7); break;          \
+    case 4: LDG_APPLY16(HH, 4); break;          \
+    default: LDG_APPLY16(HH, 0); break;         \
+  }
+    if (pc->prec == LDG_BF16) {
+      LDG_APPLY16_ALL(1)
+    } else {
+      LDG_APPLY16_ALL(2)
+    }
+#undef LDG_APPLY16_ALL
+#undef LDG_APPLY16
+  } else if (pc->prec == LDG_FP32) {
     if (nb == 64)
       hipLaunchKernelGGL((k_bj_apply<float, 64>), dim3(grid), thr, sh, s, nb, pc->nblocks, bpb, (const float*)pc->inv, r, z);
     else
@@ -312,7 +464,10 @@ ldg_status ldg_precond_block_jacobi(ldg_model md, const ldg_time* t, const doubl
                                     ldg_precision factor_prec, void* stream, ldg_precond* out) {
   LDG_ENTER();
   if (!md || !out) { set_error("null argument"); return LDG_EINVAL; }
-  if (factor_prec != LDG_FP64 && factor_prec != LDG_FP32) { set_error("factor precision must be FP64 or FP32"); return LDG_EINVAL; }
+  if (factor_prec != LDG_FP64 && factor_prec != LDG_FP32 && !is16(factor_prec)) {
+    set_error("factor precision must be FP64, FP32, BF16 or FP16");
+    return LDG_EINVAL;
+  }
   if (!md->linear && !u_lin) { set_error("nonlinear model needs u_lin"); return LDG_EINVAL; }
   auto* pc = new ldg_precond_s();
   pc->md = md;
@@ -323,18 +478,22 @@ ldg_status ldg_precond_block_jacobi(ldg_model md, const ldg_time* t, const doubl
   pc->a0 = t ? t->a0 : 0.0;
   if (pc->nb > 128) { delete pc; set_error("block size above 128"); return LDG_EUNSUPPORTED; }
   const size_t nel = (size_t)pc->nblocks * pc->nb * pc->nb;
+  pc->ng = (pc->nb + 3) / 4;
+  const size_t inv_bytes = is16(factor_prec) ? (size_t)pc->nblocks * pc->ng * 4 * pc->nb * sizeof(uint16_t)
+                                             : nel * (factor_prec == LDG_FP32 ? sizeof(float) : sizeof(double));
   hipError_t e = hipMalloc((void**)&pc->scratch, nel * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&pc->inv, nel * (factor_prec == LDG_FP32 ? sizeof(float) : sizeof(double)));
+  if (e == hipSuccess) e = hipMalloc(&pc->inv, inv_bytes);
+  if (e == hipSuccess && is16(factor_prec)) e = hipMalloc((void**)&pc->scale, (size_t)pc->nblocks * pc->nb * sizeof(float));
   if (e == hipSuccess) e = hipMalloc((void**)&pc->info, sizeof(int));
   if (e != hipSuccess) {
-    hipFree(pc->scratch); hipFree(pc->inv); hipFree(pc->info);
+    hipFree(pc->scratch); hipFree(pc->inv); hipFree(pc->scale); hipFree(pc->info);
     delete pc;
     set_error(std::string("block-Jacobi allocation: ") + hipGetErrorString(e));
     return LDG_ENOMEM;
   }
   ldg_status st = precond_rebuild(pc, t, u_lin, (hipStream_t)stream);
   if (st != LDG_OK) {
-    hipFree(pc->scratch); hipFree(pc->inv); hipFree(pc->info);
+    hipFree(pc->scratch); hipFree(pc->inv); hipFree(pc->scale); hipFree(pc->info);
     delete pc;
     return st;
   }
@@ -369,7 +528,7 @@ ldg_status ldg_precond_destroy(ldg_precond pc) {
   LDG_ENTER();
   if (!pc) return LDG_OK;
   if (pc->kind == 1) { mlp_precond_destroy(pc->mlp_data); delete pc; return LDG_OK; }
-  hipFree(pc->scratch); hipFree(pc->inv); hipFree(pc->info);
+  hipFree(pc->scratch); hipFree(pc->inv); hipFree(pc->scale); hipFree(pc->info);
   delete pc;
   return LDG_OK;
 }

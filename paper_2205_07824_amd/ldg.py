@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libldg.so")
 
 LDG_OK, LDG_EINVAL, LDG_EUNSUPPORTED, LDG_EDEVICE, LDG_ENOMEM, LDG_ENOCONV, LDG_EBREAKDOWN = range(7)
-FP64, FP32, BF16_MFMA, FP16_MFMA, JVP_FD = range(5)
+FP64, FP32, BF16_MFMA, FP16_MFMA, JVP_FD, BF16, FP16 = range(7)
 MODEL_POISSON, MODEL_CONVDIFF, MODEL_EULER, MODEL_NS = range(4)
 BC_DIRICHLET, BC_NEUMANN, BC_EXTRAP = range(3)
 

@@ -28,3 +28,19 @@ def test_binding_names_match_header():
     from paper_2205_07824_amd import ldg
     assert sorted(ldg.EXPORTED) == [n for n in declared_functions() if n in ldg.EXPORTED]
     assert set(declared_functions()) == set(ldg.EXPORTED)
+
+
+def header_enum(name):
+    src = open(os.path.join(ROOT, "include", "ldg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"typedef enum \{([^}]*)\}\s*" + name + r"\s*;", src).group(1)
+    return {k: int(v) for k, v in re.findall(r"\b(LDG_[A-Z0-9_]+)\s*=\s*(\d+)", body)}
+
+
+def test_binding_precision_constants_match_header():
+    from paper_2205_07824_amd import ldg
+    e = header_enum("ldg_precision")
+    for py, c in (("FP64", "LDG_FP64"), ("FP32", "LDG_FP32"), ("BF16_MFMA", "LDG_BF16_MFMA"),
+                  ("FP16_MFMA", "LDG_FP16_MFMA"), ("JVP_FD", "LDG_JVP_FD"), ("BF16", "LDG_BF16"), ("FP16", "LDG_FP16")):
+        assert getattr(ldg, py) == e[c], (py, c)
+    assert len(e) == 7

@@ -161,6 +161,53 @@ def test_block_jacobi_apply_inverts_blocks(L):
         assert rel(back, r) < tol * 100
 
 
+@pytest.mark.parametrize("name", ["bf16", "fp16"])
+def test_block_jacobi_16bit_factors_rounding_bound(L, name):
+    # 16-bit factors differ from the FP32 ones (same FP32-probed blocks, same
+    # FP64 inversion) only by the rounding of each entry of the row-scaled
+    # inverse: |z16 - z32|_i <= (u + 2^-24) sum_j |A_ij r_j| + (fp16 subnormal
+    # floor) 2^-24 max_j |A_ij| sum_j |r_j|, with u = 2^-8 (bf16), 2^-11 (fp16)
+    prec, u = {"bf16": (L.BF16, 2.0 ** -8), "fp16": (L.FP16, 2.0 ** -11)}[name]
+    for case in ("c2", "c3"):
+        c = CS.c2_poisson3d() if case == "c2" else CS.c3_euler2d(n=4)
+        _say("case", case, "block-Jacobi", name, "factors")
+        m, md, t, dev = build_gpu(L, c)
+        u_lin = dev(c.u) if case == "c3" else None
+        p32 = L.BlockJacobi(md, u_lin=u_lin, time=t, prec=L.FP32)
+        p16 = L.BlockJacobi(md, u_lin=u_lin, time=t, prec=prec)
+        r = np.random.default_rng(11).uniform(-1, 1, c.om.size(c.ncu))
+        z32 = p32.apply(dev(r)).cpu().numpy().reshape(c.om.E, -1)
+        z16 = p16.apply(dev(r)).cpu().numpy().reshape(c.om.E, -1)
+        Ainv = np.linalg.inv(c.om.blocks(c.oracle_model(), c.u))
+        rb = r.reshape(c.om.E, -1)
+        mag = np.einsum("eij,ej->ei", np.abs(Ainv), np.abs(rb))
+        floor = 2.0 ** -24 * np.abs(Ainv).max(axis=2) * np.abs(rb).sum(axis=1)[:, None]
+        err = np.abs(z16 - z32)
+        bound = 1.02 * (u + 2.0 ** -24) * mag + 1.02 * floor
+        assert np.all(err <= bound), float((err / bound).max())
+        # and the rounding is visible (the path really stores 16-bit codes)
+        assert err.max() > 1e-3 * u * mag.max()
+
+
+@pytest.mark.parametrize("prec_name", ["bf16", "fp16"])
+def test_gmres_16bit_block_jacobi_reaches_fp64_solution(L, prec_name):
+    c = CS.c1_poisson2d()
+    _say("case c1 gmres with", prec_name, "block-Jacobi factors")
+    m, md, t, dev = build_gpu(L, c)
+    import torch
+    N = c.om.size(1)
+    zero = torch.zeros(N, dtype=torch.float64, device="cuda")
+    bg = -md.residual(zero)
+    x64, st64, s64 = L.gmres(md, bg, pc=L.BlockJacobi(md), restart=30, rtol=1e-11, maxit=500)
+    prec = L.BF16 if prec_name == "bf16" else L.FP16
+    x16, st16, s16 = L.gmres(md, bg, pc=L.BlockJacobi(md, prec=prec), restart=30, rtol=1e-11, maxit=500)
+    _say("iterations fp64", st64["iters"], prec_name, st16["iters"])
+    assert s64 == L.LDG_OK and s16 == L.LDG_OK
+    assert st16["res_true"] <= 1e-11 * st16["res0"] * 1.01
+    assert rel(x16.cpu().numpy(), x64.cpu().numpy()) < 1e-8
+    assert st16["iters"] <= 2 * st64["iters"] + 5
+
+
 def test_gmres_block_jacobi_c1_matches_oracle_solution(L):
     import scipy.sparse.linalg as spla
     c = CS.c1_poisson2d()
