@@ -4,6 +4,7 @@
 // the device, restarted flexible GMRES, and Newton's method.
 #include <algorithm>
 #include <chrono>
+#include <cstddef>
 #include <cstring>
 #include <cmath>
 
@@ -272,9 +273,12 @@ struct ArnoldiState {
   double cs[MAXM], sn[MAXM], g[MAXM + 1], y[MAXM];
   double inv_hnext;
   double resid;                  // |g_{j+1}|
+  int breakdown;                 // directly after resid: one 16-byte copy reads both
+  int pad_;
   double wnorm0;                 // ||w|| before orthogonalization
-  int breakdown;
 };
+static_assert(offsetof(ArnoldiState, breakdown) == offsetof(ArnoldiState, resid) + sizeof(double),
+              "resid and breakdown are copied to the host together");
 
 // h1[j + 1] holds ||w||^2 before the orthogonalization
 __global__ void k_givens(ArnoldiState* st, int j, int nblk, const double* __restrict__ h1, const double* __restrict__ h2,
@@ -394,59 +398,84 @@ __global__ void __launch_bounds__(VB) k_dc_dots(int64_t n, int j, const double* 
 // coefficient block of sweep 2: [0, MAXM) s, [MAXM, 2 MAXM) gamma, 2 MAXM: 1/alpha, 2 MAXM + 1: c/alpha
 constexpr int DC_COEF = 2 * MAXM + 2;
 
-// dots[0..2j+3) as laid out by k_dc_dots; h1p holds h1_{j-1} on entry and h1_j on exit
-__global__ void k_dc_scalar(ArnoldiState* st, int j, int closing, const double* __restrict__ dots,
-                            double* __restrict__ h1p, double* __restrict__ coef) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One work-group of 1024 threads.  The block partials of sweep 1 (rows laid out
+// as by k_dc_dots, nblk partials each) are first reduced into LDS, one row per
+// wave at a time (fixed order: deterministic); thread 0 then does the sequential part;
+// the coefficient writes are spread over the threads.  h1p holds h1_{j-1} on
+// entry and h1_j on exit.
+constexpr int DC_SCALAR_THREADS = 1024;
+__global__ void __launch_bounds__(DC_SCALAR_THREADS) k_dc_scalar(ArnoldiState* st, int j, int closing,
+                                                  const double* __restrict__ part, int nblk,
+                                                  double* __restrict__ h1p, double* __restrict__ coef) {
+  __shared__ double dots[2 * MAXM + 3];
+  __shared__ double bc[3];   // 1/alpha, c/alpha, c
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int row = wid; row < 2 * j + 3; row += nw) {
+    double v = 0.0;
+#pragma unroll 8
+    for (int b = lane; b < nblk; b += 64) v += part[(int64_t)row * nblk + b];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) dots[row] = v;
+  }
+  __syncthreads();
   const double* a = dots;
   const double* b = dots + j;
-  const double uu = dots[2 * j], uw = dots[2 * j + 1], ww = dots[2 * j + 2];
-  double ss = 0.0;
-  for (int i = 0; i < j; ++i) ss += a[i] * a[i];
-  double al2 = uu - ss;
-  const double al = al2 > 0.0 ? sqrt(al2) : 0.0;
-  int brk = 0;
-  if (j == 0) {
-    for (int i = 0; i <= MAXM; ++i) st->g[i] = 0.0;
-    st->g[0] = al;
-    st->resid = al;
-  } else {
-    const int ld = MAXM + 1;
-    const int c = j - 1;
-    double* col = st->H + (int64_t)c * ld;
-    for (int i = 0; i < j; ++i) col[i] = h1p[i] + a[i];
-    col[j] = al;
-    brk = (al <= 1e-14 * st->wnorm0) ? 1 : 0;
-    for (int i = 0; i < c; ++i) {
-      const double t = st->cs[i] * col[i] + st->sn[i] * col[i + 1];
-      col[i + 1] = -st->sn[i] * col[i] + st->cs[i] * col[i + 1];
-      col[i] = t;
+  if (threadIdx.x == 0) {
+    const double uu = dots[2 * j], uw = dots[2 * j + 1], ww = dots[2 * j + 2];
+    double ss = 0.0;
+    for (int i = 0; i < j; ++i) ss += a[i] * a[i];
+    double al2 = uu - ss;
+    const double al = al2 > 0.0 ? sqrt(al2) : 0.0;
+    int brk = 0;
+    if (j == 0) {
+      for (int i = 0; i <= MAXM; ++i) st->g[i] = 0.0;
+      st->g[0] = al;
+      st->resid = al;
+    } else {
+      const int ld = MAXM + 1;
+      const int c = j - 1;
+      double* col = st->H + (int64_t)c * ld;
+      for (int i = 0; i < j; ++i) col[i] = h1p[i] + a[i];
+      col[j] = al;
+      brk = (al <= 1e-14 * st->wnorm0) ? 1 : 0;
+      for (int i = 0; i < c; ++i) {
+        const double t = st->cs[i] * col[i] + st->sn[i] * col[i + 1];
+        col[i + 1] = -st->sn[i] * col[i] + st->cs[i] * col[i + 1];
+        col[i] = t;
+      }
+      const double d = hypot(col[c], col[c + 1]);
+      st->cs[c] = d > 0 ? col[c] / d : 1.0;
+      st->sn[c] = d > 0 ? col[c + 1] / d : 0.0;
+      col[c] = d;
+      col[c + 1] = 0.0;
+      st->g[c + 1] = -st->sn[c] * st->g[c];
+      st->g[c] = st->cs[c] * st->g[c];
+      st->resid = fabs(st->g[c + 1]);
     }
-    const double d = hypot(col[c], col[c + 1]);
-    st->cs[c] = d > 0 ? col[c] / d : 1.0;
-    st->sn[c] = d > 0 ? col[c + 1] / d : 0.0;
-    col[c] = d;
-    col[c + 1] = 0.0;
-    st->g[c + 1] = -st->sn[c] * st->g[c];
-    st->g[c] = st->cs[c] * st->g[c];
-    st->resid = fabs(st->g[c + 1]);
+    st->breakdown = brk;
+    const double inva = (al > 0.0 && !brk) ? 1.0 / al : 0.0;
+    double sb = 0.0;
+    for (int i = 0; i < j; ++i) sb += a[i] * b[i];
+    const double cc = (uw - sb) * inva;
+    bc[0] = inva;
+    bc[1] = cc * inva;
+    bc[2] = cc;
+    if (!closing) st->wnorm0 = sqrt(ww);
   }
-  st->breakdown = brk;
   if (closing) return;
-  const double inva = (al > 0.0 && !brk) ? 1.0 / al : 0.0;
-  double sb = 0.0;
-  for (int i = 0; i < j; ++i) sb += a[i] * b[i];
-  const double cc = (uw - sb) * inva;
-  const double dl = cc * inva;
-  for (int i = 0; i < j; ++i) {
+  __syncthreads();
+  const double dl = bc[1];
+  for (int i = threadIdx.x; i < j; i += blockDim.x) {
     coef[i] = a[i];
     coef[MAXM + i] = b[i] - dl * a[i];
     h1p[i] = b[i];
   }
-  h1p[j] = cc;
-  coef[2 * MAXM] = inva;
-  coef[2 * MAXM + 1] = dl;
-  st->wnorm0 = sqrt(ww);
+  if (threadIdx.x == 0) {
+    h1p[j] = bc[2];
+    coef[2 * MAXM] = bc[0];
+    coef[2 * MAXM + 1] = dl;
+  }
 }
 
 // v_j = (U - V s)/alpha -> Vj ; U <- W - (c/alpha) U - V gamma
@@ -520,7 +549,6 @@ struct Workspace {
   double* h1 = nullptr;
   double* h2 = nullptr;
   double* U = nullptr;     // delayed re-orthogonalization: the pending vector
-  double* dots = nullptr;  // [2 MAXM + 3]
   double* coef = nullptr;  // [DC_COEF]
   ArnoldiState* st = nullptr;
   double* pinned = nullptr;  // host scalars
@@ -529,7 +557,7 @@ struct Workspace {
   void release() {
     if (!ok) return;
     hipFree(V); hipFree(Z); hipFree(w); hipFree(r); hipFree(part); hipFree(npart); hipFree(h1); hipFree(h2);
-    hipFree(U); hipFree(dots); hipFree(coef);
+    hipFree(U); hipFree(coef);
     hipFree(st); hipHostFree(pinned);
     for (auto& e : ev) hipEventDestroy(e);
     ok = false;
@@ -547,7 +575,6 @@ struct Workspace {
     LDG_TRY(hipMalloc((void**)&h1, sizeof(double) * (MAXM + 1)));
     LDG_TRY(hipMalloc((void**)&h2, sizeof(double) * (MAXM + 1)));
     LDG_TRY(hipMalloc((void**)&U, sizeof(double) * n));
-    LDG_TRY(hipMalloc((void**)&dots, sizeof(double) * (2 * MAXM + 3)));
     LDG_TRY(hipMalloc((void**)&coef, sizeof(double) * DC_COEF));
     LDG_TRY(hipMalloc((void**)&st, sizeof(ArnoldiState)));
     LDG_TRY(hipHostMalloc((void**)&pinned, sizeof(double) * 8, hipHostMallocDefault));
@@ -648,10 +675,10 @@ static ldg_status dcgs2_cycle(Model& md, const ldg_time* t, const double* u_lin,
   float ms = 0.0f;
   ldg_status st;
   LDG_TRY(hipMemcpyAsync(ws.U, ws.r, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  // sweep 1 (block partials; k_dc_scalar reduces them)
   auto sweep1 = [&](int j, const double* Wp) {
     if (j <= 8) hipLaunchKernelGGL((k_dc_dots<8>), dim3(nbc), dim3(VB), 0, s, n, j, ws.V, n, ws.U, Wp, ws.part);
     else hipLaunchKernelGGL((k_dc_dots<16>), dim3(nbc), dim3(VB), 0, s, n, j, ws.V, n, ws.U, Wp, ws.part);
-    hipLaunchKernelGGL(k_reduce_rows, dim3(2 * j + 3), dim3(VB), 0, s, 2 * j + 3, nbc, ws.part, ws.dots);
   };
   // read step jj's result: after it, columns 0..jj-1 of H are final
   auto finish = [&](int jj) -> bool {
@@ -711,7 +738,7 @@ static ldg_status dcgs2_cycle(Model& md, const ldg_time* t, const double* u_lin,
     if (st != LDG_OK) return st;
     hipEventRecord(ws.ev[4 * sl + 2], s);
     sweep1(j, ws.w);
-    hipLaunchKernelGGL(k_dc_scalar, dim3(1), dim3(64), 0, s, ws.st, j, 0, ws.dots, ws.h1, ws.coef);
+    hipLaunchKernelGGL(k_dc_scalar, dim3(1), dim3(DC_SCALAR_THREADS), 0, s, ws.st, j, 0, ws.part, nbc, ws.h1, ws.coef);
     if (j <= 8)
       hipLaunchKernelGGL((k_dc_update<8>), dim3(nbc), dim3(VB), 0, s, n, j, ws.V, n, ws.coef, ws.U, ws.w,
                          ws.V + (int64_t)j * n);
@@ -719,8 +746,7 @@ static ldg_status dcgs2_cycle(Model& md, const ldg_time* t, const double* u_lin,
       hipLaunchKernelGGL((k_dc_update<16>), dim3(nbc), dim3(VB), 0, s, n, j, ws.V, n, ws.coef, ws.U, ws.w,
                          ws.V + (int64_t)j * n);
     LDG_TRY(hipGetLastError());
-    LDG_TRY(hipMemcpyAsync(ws.pinned + 2 * sl, &ws.st->resid, sizeof(double), hipMemcpyDeviceToHost, s));
-    LDG_TRY(hipMemcpyAsync(ws.pinned + 2 * sl + 1, &ws.st->breakdown, sizeof(int), hipMemcpyDeviceToHost, s));
+    LDG_TRY(hipMemcpyAsync(ws.pinned + 2 * sl, &ws.st->resid, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     hipEventRecord(ws.ev[4 * sl + 3], s);
     ++its;
     done = j + 1;
@@ -743,7 +769,7 @@ static ldg_status dcgs2_cycle(Model& md, const ldg_time* t, const double* u_lin,
   if (!stop && done > 0) {
     // close the cycle: re-orthogonalize the pending vector to finalize column done-1
     sweep1(done, nullptr);
-    hipLaunchKernelGGL(k_dc_scalar, dim3(1), dim3(64), 0, s, ws.st, done, 1, ws.dots, ws.h1, ws.coef);
+    hipLaunchKernelGGL(k_dc_scalar, dim3(1), dim3(DC_SCALAR_THREADS), 0, s, ws.st, done, 1, ws.part, nbc, ws.h1, ws.coef);
     LDG_TRY(hipGetLastError());
     LDG_TRY(hipMemcpyAsync(ws.pinned, &ws.st->resid, sizeof(double), hipMemcpyDeviceToHost, s));
     LDG_TRY(hipStreamSynchronize(s));
@@ -871,8 +897,7 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
         hipLaunchKernelGGL(k_scale_dev, dim3(gV), dim3(VB), 0, s, n, &ws.st->inv_hnext, ws.w,
                            ws.V + (int64_t)(j + 1) * n);
         LDG_TRY(hipGetLastError());
-        LDG_TRY(hipMemcpyAsync(ws.pinned + 2 * sl, &ws.st->resid, sizeof(double), hipMemcpyDeviceToHost, s));
-        LDG_TRY(hipMemcpyAsync(ws.pinned + 2 * sl + 1, &ws.st->breakdown, sizeof(int), hipMemcpyDeviceToHost, s));
+        LDG_TRY(hipMemcpyAsync(ws.pinned + 2 * sl, &ws.st->resid, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
         hipEventRecord(ws.ev[4 * sl + 3], s);
         ++its;
         if (!pipelined) {
