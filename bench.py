@@ -246,6 +246,36 @@ def implicit_steps(ldg, I, log, nsteps=5):
     return res
 
 
+# Newton-GMRES forms on the Poisson workload: (JVP precision, block-Jacobi factor
+# storage, Newton forcing eta)
+NEWTON_FORMS = {"fp64_jvp+fp64_bj": ("FP64", "FP64", 1e-9), "fp64_jvp+fp32_bj": ("FP64", "FP32", 1e-9),
+                "fp64_jvp+fp16_bj": ("FP64", "FP16", 1e-9), "fp32_jvp+fp32_bj": ("FP32", "FP32", 1e-4),
+                "fp32_jvp+fp16_bj": ("FP32", "FP16", 1e-4), "fp32_jvp+bf16_bj": ("FP32", "BF16", 1e-4)}
+
+
+def newton_form(ldg, md, name, orth, log):
+    """Block-Jacobi build + Newton-GMRES(30) from u = 0 to ||G|| <= 1e-8 ||G(0)||, timed end to end."""
+    import torch
+    jp, bp, eta = NEWTON_FORMS[name]
+    jp, bp = getattr(ldg, jp), getattr(ldg, bp)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pc = ldg.BlockJacobi(md, prec=bp)
+    torch.cuda.synchronize()
+    t_bj = time.perf_counter() - t0
+    x = torch.zeros(md.N, dtype=torch.float64, device="cuda")
+    x, st, status = ldg.newton(md, x, rtol=1e-8, eta=eta, maxit=8, pc=pc, restart=30, lin_maxit=4000,
+                               jvp_prec=jp, orth=orth, check=False)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t0
+    rec = {"time_to_1e-8_s": round(t_all, 4), "bj_build_s": round(t_bj, 4),
+           "converged": status == ldg.LDG_OK, "newton_iters": st["iters"], "gmres_iters": st["gmres_iters"],
+           "res_ratio": st["res_final"] / max(st["res0"], 1e-300),
+           "t_jvp_s": round(st["t_jvp"], 4), "t_pc_s": round(st["t_pc"], 4), "t_orth_s": round(st["t_orth"], 4)}
+    log(name, rec)
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,6 +294,8 @@ def main():
                     help="only the timed JVP steps (for counter collection)")
     ap.add_argument("--profile-mfma-only", action="store_true",
                     help="only the 2D Poisson p=4 MFMA JVP leg (for counter collection)")
+    ap.add_argument("--profile-solve-only", choices=sorted(NEWTON_FORMS), default=None,
+                    help="only one Newton-GMRES form on the Poisson workload (for a kernel trace)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 512 MiB buffer 10 times (scales the HBM byte counters)")
     args = ap.parse_args()
@@ -289,6 +321,10 @@ def main():
         return
     box, m, md = build_workload(ldg, I, n=args.n)
     N = md.N
+    if args.profile_solve_only:
+        orth = ldg.ORTH_DCGS2 if args.orth == "dcgs2" else ldg.ORTH_CGS2
+        print(json.dumps(newton_form(ldg, md, args.profile_solve_only, orth, log)))
+        return
     log(f"workload: E={m.E} nn={m.nn} N={N} colours={m.ncolors}")
     v = torch.as_tensor(np.random.default_rng(2).uniform(-1, 1, N), device="cuda")
     u = torch.as_tensor(np.random.default_rng(1).uniform(-1, 1, N), device="cuda")
@@ -355,33 +391,8 @@ def main():
 
     # Newton-GMRES to ||G|| <= 1e-8 ||G(u0)||, u0 = 0, GMRES(30) + block Jacobi
     if not args.no_solve:
-        forms = {}
         orth = ldg.ORTH_DCGS2 if args.orth == "dcgs2" else ldg.ORTH_CGS2
-        for name, jp, bp, eta in (("fp64_jvp+fp64_bj", ldg.FP64, ldg.FP64, 1e-9),
-                                  ("fp64_jvp+fp32_bj", ldg.FP64, ldg.FP32, 1e-9),
-                                  ("fp64_jvp+fp16_bj", ldg.FP64, ldg.FP16, 1e-9),
-                                  ("fp32_jvp+fp32_bj", ldg.FP32, ldg.FP32, 1e-4),
-                                  ("fp32_jvp+fp16_bj", ldg.FP32, ldg.FP16, 1e-4),
-                                  ("fp32_jvp+bf16_bj", ldg.FP32, ldg.BF16, 1e-4)):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            pc = ldg.BlockJacobi(md, prec=bp)
-            torch.cuda.synchronize()
-            t_bj = time.perf_counter() - t0
-            x = torch.zeros(N, dtype=torch.float64, device="cuda")
-            x, st, status = ldg.newton(md, x, rtol=1e-8, eta=eta, maxit=8, pc=pc, restart=30, lin_maxit=4000,
-                                       jvp_prec=jp, orth=orth, check=False)
-            torch.cuda.synchronize()
-            t_all = time.perf_counter() - t0
-            forms[name] = {"time_to_1e-8_s": round(t_all, 4), "bj_build_s": round(t_bj, 4),
-                           "converged": status == ldg.LDG_OK, "newton_iters": st["iters"],
-                           "gmres_iters": st["gmres_iters"],
-                           "res_ratio": st["res_final"] / max(st["res0"], 1e-300),
-                           "t_jvp_s": round(st["t_jvp"], 4), "t_pc_s": round(st["t_pc"], 4),
-                           "t_orth_s": round(st["t_orth"], 4)}
-            log(name, forms[name])
-            del pc
-        out["newton_gmres"] = forms
+        out["newton_gmres"] = {name: newton_form(ldg, md, name, orth, log) for name in NEWTON_FORMS}
 
     # JVP throughput on the other workload shapes (FP64 and FP32, HIP events)
     if not args.no_extra_workloads:
