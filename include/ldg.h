@@ -247,7 +247,10 @@ typedef struct {
 typedef struct {
   int iters, restarts, fell_back;
   double res0, res_est, res_true;          /* ||b - J x0||, Givens estimate, true ||b - J x|| */
-  double t_jvp, t_pc, t_orth, t_total;     /* seconds per phase                             */
+  double t_jvp, t_pc, t_orth, t_total;     /* seconds per phase: the preconditioner, JVP and
+                                              orthogonalization times are measured on every
+                                              8th Arnoldi step and scaled to all steps;
+                                              t_total is the wall time of the call       */
 } ldg_gmres_stats;
 
 /* Solves J(u_lin) x = b by restarted (F)GMRES with classical Gram-Schmidt and

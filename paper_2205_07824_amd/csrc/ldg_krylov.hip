@@ -552,7 +552,8 @@ struct Workspace {
   double* coef = nullptr;  // [DC_COEF]
   ArnoldiState* st = nullptr;
   double* pinned = nullptr;  // host scalars
-  hipEvent_t ev[8];
+  hipEvent_t ev[8];        // phase timing events of the sampled steps, two slots of four
+  hipEvent_t evs[2];       // step-end events of the other steps (no timing)
   bool ok = false;
   void release() {
     if (!ok) return;
@@ -560,6 +561,7 @@ struct Workspace {
     hipFree(U); hipFree(coef);
     hipFree(st); hipHostFree(pinned);
     for (auto& e : ev) hipEventDestroy(e);
+    for (auto& e : evs) hipEventDestroy(e);
     ok = false;
   }
   ldg_status ensure(int64_t nn, int mm) {
@@ -579,6 +581,7 @@ struct Workspace {
     LDG_TRY(hipMalloc((void**)&st, sizeof(ArnoldiState)));
     LDG_TRY(hipHostMalloc((void**)&pinned, sizeof(double) * 8, hipHostMallocDefault));
     for (auto& e : ev) LDG_TRY(hipEventCreate(&e));
+    for (auto& e : evs) LDG_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     ok = true;
     return LDG_OK;
   }
@@ -586,6 +589,45 @@ struct Workspace {
 
 // per-thread solver workspace, kept until the process ends
 thread_local Workspace* g_ws_ptr = nullptr;
+
+// Phase times (preconditioner, JVP, orthogonalization) are taken with timing
+// events on every PHASE_SAMPLE-th Arnoldi step only and scaled to all steps:
+// each timing event record left the GPU idle for 5-10 us, about 8% of a step.
+// The other steps record one event without timing for the host's wait.
+constexpr int PHASE_SAMPLE = 8;
+
+struct PhaseClock {
+  double pc = 0.0, jvp = 0.0, orth = 0.0;
+  int64_t timed = 0, steps = 0;
+  bool slot_timed[2] = {false, false};
+  // before queuing a step into slot sl
+  bool begin(int its, int sl) { return slot_timed[sl] = (its % PHASE_SAMPLE) == 0; }
+  void mark(Workspace& ws, int sl, int k, hipStream_t s) const {
+    if (slot_timed[sl]) hipEventRecord(ws.ev[4 * sl + k], s);
+  }
+  void end(Workspace& ws, int sl, hipStream_t s) const {
+    hipEventRecord(slot_timed[sl] ? ws.ev[4 * sl + 3] : ws.evs[sl], s);
+  }
+  // wait for the step in slot sl and account for it
+  bool wait(Workspace& ws, int sl) {
+    if (hipEventSynchronize(slot_timed[sl] ? ws.ev[4 * sl + 3] : ws.evs[sl]) != hipSuccess) return false;
+    ++steps;
+    if (slot_timed[sl]) {
+      float ms = 0.0f;
+      ++timed;
+      if (hipEventElapsedTime(&ms, ws.ev[4 * sl + 0], ws.ev[4 * sl + 1]) == hipSuccess) pc += ms * 1e-3;
+      if (hipEventElapsedTime(&ms, ws.ev[4 * sl + 1], ws.ev[4 * sl + 2]) == hipSuccess) jvp += ms * 1e-3;
+      if (hipEventElapsedTime(&ms, ws.ev[4 * sl + 2], ws.ev[4 * sl + 3]) == hipSuccess) orth += ms * 1e-3;
+    }
+    return true;
+  }
+  void report(ldg_gmres_stats& S) const {
+    const double f = timed ? double(steps) / double(timed) : 0.0;
+    S.t_pc = pc * f;
+    S.t_jvp = jvp * f;
+    S.t_orth = orth * f;
+  }
+};
 
 inline int nblk_for(int64_t n) {
   int64_t g = (n + VB - 1) / VB;
@@ -666,13 +708,12 @@ static ldg_status true_residual(Model& md, const ldg_time* t, const double* u, c
 static ldg_status dcgs2_cycle(Model& md, const ldg_time* t, const double* u_lin, ldg_precision jp,
                               const ldg_gmres_opts& o, Workspace& ws, ldg_precond_s*& pc_cur, bool watch,
                               double& watch_ref, int& watch_it, double tol, int& its, int& k, bool& stop,
-                              ldg_status& result, ldg_gmres_stats& S, hipStream_t s) {
+                              ldg_status& result, ldg_gmres_stats& S, PhaseClock& clk, hipStream_t s) {
   const int64_t n = ws.n;
   const int m = o.restart;
   const int nbc = cgs_blocks(n);
   const bool use_pc = o.pc != nullptr;
   const bool pipelined = !watch;
-  float ms = 0.0f;
   ldg_status st;
   LDG_TRY(hipMemcpyAsync(ws.U, ws.r, n * sizeof(double), hipMemcpyDeviceToDevice, s));
   // sweep 1 (block partials; k_dc_scalar reduces them)
@@ -683,14 +724,11 @@ static ldg_status dcgs2_cycle(Model& md, const ldg_time* t, const double* u_lin,
   // read step jj's result: after it, columns 0..jj-1 of H are final
   auto finish = [&](int jj) -> bool {
     const int sl = jj & 1;
-    if (hipEventSynchronize(ws.ev[4 * sl + 3]) != hipSuccess) {
+    if (!clk.wait(ws, sl)) {
       result = LDG_EDEVICE;
       set_error("event synchronization failed");
       return true;
     }
-    if (hipEventElapsedTime(&ms, ws.ev[4 * sl + 0], ws.ev[4 * sl + 1]) == hipSuccess) S.t_pc += ms * 1e-3;
-    if (hipEventElapsedTime(&ms, ws.ev[4 * sl + 1], ws.ev[4 * sl + 2]) == hipSuccess) S.t_jvp += ms * 1e-3;
-    if (hipEventElapsedTime(&ms, ws.ev[4 * sl + 2], ws.ev[4 * sl + 3]) == hipSuccess) S.t_orth += ms * 1e-3;
     k = jj;
     if (jj == 0) return false;
     const double res = ws.pinned[2 * sl];
@@ -712,7 +750,8 @@ static ldg_status dcgs2_cycle(Model& md, const ldg_time* t, const double* u_lin,
   for (int j = 0; j < m && its < o.maxit; ++j) {
     const int sl = j & 1;
     double* zj = ws.Z + (int64_t)j * n;
-    hipEventRecord(ws.ev[4 * sl + 0], s);
+    clk.begin(its, sl);
+    clk.mark(ws, sl, 0, s);
     if (use_pc) {
       st = precond_apply_impl(pc_cur, ws.U, zj, s);
       if (st != LDG_OK) return st;
@@ -733,10 +772,10 @@ static ldg_status dcgs2_cycle(Model& md, const ldg_time* t, const double* u_lin,
     } else {
       LDG_TRY(hipMemcpyAsync(zj, ws.U, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
-    hipEventRecord(ws.ev[4 * sl + 1], s);
+    clk.mark(ws, sl, 1, s);
     st = jvp_impl(md, t, u_lin, zj, ws.w, jp, true, s);
     if (st != LDG_OK) return st;
-    hipEventRecord(ws.ev[4 * sl + 2], s);
+    clk.mark(ws, sl, 2, s);
     sweep1(j, ws.w);
     hipLaunchKernelGGL(k_dc_scalar, dim3(1), dim3(DC_SCALAR_THREADS), 0, s, ws.st, j, 0, ws.part, nbc, ws.h1, ws.coef);
     if (j <= 8)
@@ -747,7 +786,7 @@ static ldg_status dcgs2_cycle(Model& md, const ldg_time* t, const double* u_lin,
                          ws.V + (int64_t)j * n);
     LDG_TRY(hipGetLastError());
     LDG_TRY(hipMemcpyAsync(ws.pinned + 2 * sl, &ws.st->resid, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-    hipEventRecord(ws.ev[4 * sl + 3], s);
+    clk.end(ws, sl, s);
     ++its;
     done = j + 1;
     if (!pipelined) {
@@ -819,13 +858,13 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
   double beta = r0;
   int its = 0;
   ldg_status result = LDG_OK;
-  float ms = 0.0f;
+  PhaseClock clk;
   while (beta > tol && its < o.maxit) {
     if (!std::isfinite(beta)) { result = LDG_EBREAKDOWN; break; }
     int k = 0;
     bool stop = false;
     if (o.orth == 2) {
-      st = dcgs2_cycle(md, t, u_lin, jp, o, ws, pc_cur, watch, watch_ref, watch_it, tol, its, k, stop, result, S, s);
+      st = dcgs2_cycle(md, t, u_lin, jp, o, ws, pc_cur, watch, watch_ref, watch_it, tol, its, k, stop, result, S, clk, s);
       if (st != LDG_OK) return st;
       if (result == LDG_EDEVICE) return result;
     } else {
@@ -843,10 +882,7 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
       // read step jj's result (slot jj & 1); true when the cycle ends there
       auto finish = [&](int jj) -> bool {
         const int sl = jj & 1;
-        if (hipEventSynchronize(ws.ev[4 * sl + 3]) != hipSuccess) { result = LDG_EDEVICE; set_error("event synchronization failed"); return true; }
-        if (hipEventElapsedTime(&ms, ws.ev[4 * sl + 0], ws.ev[4 * sl + 1]) == hipSuccess) S.t_pc += ms * 1e-3;
-        if (hipEventElapsedTime(&ms, ws.ev[4 * sl + 1], ws.ev[4 * sl + 2]) == hipSuccess) S.t_jvp += ms * 1e-3;
-        if (hipEventElapsedTime(&ms, ws.ev[4 * sl + 2], ws.ev[4 * sl + 3]) == hipSuccess) S.t_orth += ms * 1e-3;
+        if (!clk.wait(ws, sl)) { result = LDG_EDEVICE; set_error("event synchronization failed"); return true; }
         k = jj + 1;
         const double res = ws.pinned[2 * sl];
         int brk = 0;
@@ -867,7 +903,8 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
         const int sl = j & 1;
         double* vj = ws.V + (int64_t)j * n;
         double* zj = use_pc ? ws.Z + (int64_t)j * n : vj;
-        hipEventRecord(ws.ev[4 * sl + 0], s);
+        clk.begin(its, sl);
+        clk.mark(ws, sl, 0, s);
         if (use_pc) {
           st = precond_apply_impl(pc_cur, vj, zj, s);
           if (st != LDG_OK) return st;
@@ -886,10 +923,10 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
             }
           }
         }
-        hipEventRecord(ws.ev[4 * sl + 1], s);
+        clk.mark(ws, sl, 1, s);
         st = jvp_impl(md, t, u_lin, zj, ws.w, jp, true, s);
         if (st != LDG_OK) return st;
-        hipEventRecord(ws.ev[4 * sl + 2], s);
+        clk.mark(ws, sl, 2, s);
         // CGS2: h1 = V^T w (+ ||w||^2), w -= V h1, h2 = V^T w, w -= V h2 (+ ||w||^2); or MGS
         st = o.orth == 1 ? mgs(n, j + 1, ws, s) : cgs2(n, j + 1, ws, s);
         if (st != LDG_OK) return st;
@@ -898,7 +935,7 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
                            ws.V + (int64_t)(j + 1) * n);
         LDG_TRY(hipGetLastError());
         LDG_TRY(hipMemcpyAsync(ws.pinned + 2 * sl, &ws.st->resid, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-        hipEventRecord(ws.ev[4 * sl + 3], s);
+        clk.end(ws, sl, s);
         ++its;
         if (!pipelined) {
           if (finish(j)) { stop = true; break; }
@@ -937,6 +974,7 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
     result = LDG_ENOCONV;
   }
   if (!std::isfinite(beta)) result = LDG_EBREAKDOWN;
+  clk.report(S);
   S.t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - T0).count();
   if (stats) *stats = S;
   if (result == LDG_ENOCONV) set_error("GMRES did not reach the tolerance");
