@@ -161,32 +161,41 @@ def test_block_jacobi_apply_inverts_blocks(L):
         assert rel(back, r) < tol * 100
 
 
+# block sizes 64 (16 groups of four columns), 100 (25), 16 (4), per-variable 27 (7, padded)
+BJ16_CASES = [("c2", False, None), ("c3", False, None), ("c5", False, None), ("c4p2", True, 6)]
+
+
 @pytest.mark.parametrize("name", ["bf16", "fp16"])
-def test_block_jacobi_16bit_factors_rounding_bound(L, name):
+@pytest.mark.parametrize("case,per_variable,ncheck", BJ16_CASES)
+def test_block_jacobi_16bit_factors_rounding_bound(L, name, case, per_variable, ncheck):
     # 16-bit factors differ from the FP32 ones (same FP32-probed blocks, same
     # FP64 inversion) only by the rounding of each entry of the row-scaled
     # inverse: |z16 - z32|_i <= (u + 2^-24) sum_j |A_ij r_j| + (fp16 subnormal
     # floor) 2^-24 max_j |A_ij| sum_j |r_j|, with u = 2^-8 (bf16), 2^-11 (fp16)
     prec, u = {"bf16": (L.BF16, 2.0 ** -8), "fp16": (L.FP16, 2.0 ** -11)}[name]
-    for case in ("c2", "c3"):
-        c = CS.c2_poisson3d() if case == "c2" else CS.c3_euler2d(n=4)
-        _say("case", case, "block-Jacobi", name, "factors")
-        m, md, t, dev = build_gpu(L, c)
-        u_lin = dev(c.u) if case == "c3" else None
-        p32 = L.BlockJacobi(md, u_lin=u_lin, time=t, prec=L.FP32)
-        p16 = L.BlockJacobi(md, u_lin=u_lin, time=t, prec=prec)
-        r = np.random.default_rng(11).uniform(-1, 1, c.om.size(c.ncu))
-        z32 = p32.apply(dev(r)).cpu().numpy().reshape(c.om.E, -1)
-        z16 = p16.apply(dev(r)).cpu().numpy().reshape(c.om.E, -1)
-        Ainv = np.linalg.inv(c.om.blocks(c.oracle_model(), c.u))
-        rb = r.reshape(c.om.E, -1)
-        mag = np.einsum("eij,ej->ei", np.abs(Ainv), np.abs(rb))
-        floor = 2.0 ** -24 * np.abs(Ainv).max(axis=2) * np.abs(rb).sum(axis=1)[:, None]
-        err = np.abs(z16 - z32)
-        bound = 1.02 * (u + 2.0 ** -24) * mag + 1.02 * floor
-        assert np.all(err <= bound), float((err / bound).max())
-        # and the rounding is visible (the path really stores 16-bit codes)
-        assert err.max() > 1e-3 * u * mag.max()
+    c = {"c2": lambda: CS.c2_poisson3d(), "c3": lambda: CS.c3_euler2d(n=4), "c5": lambda: CS.c5_convdiff2d(),
+         "c4p2": lambda: CS.c4_ns3d(n=3, p=2)}[case]()
+    _say("case", case, "per-variable" if per_variable else "full", "block-Jacobi", name, "factors")
+    m, md, t, dev = build_gpu(L, c)
+    u_lin = None if c.kind in (CS.O.MODEL_POISSON, CS.O.MODEL_CONVDIFF) else dev(c.u)
+    p32 = L.BlockJacobi(md, u_lin=u_lin, time=t, per_variable=per_variable, prec=L.FP32)
+    p16 = L.BlockJacobi(md, u_lin=u_lin, time=t, per_variable=per_variable, prec=prec)
+    r = np.random.default_rng(11).uniform(-1, 1, c.om.size(c.ncu))
+    nb = c.om.nn if per_variable else c.ncu * c.om.nn
+    z32 = p32.apply(dev(r)).cpu().numpy().reshape(-1, nb)
+    z16 = p16.apply(dev(r)).cpu().numpy().reshape(-1, nb)
+    elems = np.arange(ncheck) if ncheck else None
+    Bref = c.om.blocks(c.oracle_model(), c.u, elems=elems, per_variable=per_variable)
+    Ainv = np.linalg.inv(np.asarray(Bref).reshape(-1, nb, nb))
+    nblk = Ainv.shape[0]
+    rb = r.reshape(-1, nb)[:nblk]
+    mag = np.einsum("eij,ej->ei", np.abs(Ainv), np.abs(rb))
+    floor = 2.0 ** -24 * np.abs(Ainv).max(axis=2) * np.abs(rb).sum(axis=1)[:, None]
+    err = np.abs(z16[:nblk] - z32[:nblk])
+    bound = 1.02 * (u + 2.0 ** -24) * mag + 1.02 * floor
+    assert np.all(err <= bound), float((err / bound).max())
+    # and the rounding is visible (the path really stores 16-bit codes)
+    assert err.max() > 1e-3 * u * mag.max()
 
 
 @pytest.mark.parametrize("prec_name", ["bf16", "fp16"])
