@@ -241,6 +241,17 @@ def implicit_steps(ldg, I, log, nsteps=5):
                      "t_pc_s": round(sum(r["t_pc"] for r in later), 4),
                      "t_orth_s": round(sum(r["t_orth"] for r in later), 4)}
         log(name, res[name])
+    # the paper's integrator family: three steps of the L-stable three-stage DIRK(3,3) (each stage a
+    # Newton-GMRES solve like one BDF2 step), mixed-precision form
+    name = "fp32_jvp+fp16_bj_dirk33"
+    _, stats = TS.dirk_steps(md, u0, dt, 3, scheme="dirk33", restart=50, eta=1e-3, rtol=1e-8, jvp_prec=ldg.FP32,
+                             bj_prec=ldg.FP16, bj_refresh=1, log=log)
+    later = stats[1:]
+    res[name] = {"seconds_per_step_2_to_3": round(float(np.mean([r["seconds"] for r in later])), 4),
+                 "all_converged": all(r["converged"] for r in stats) and len(stats) == 3,
+                 "newton_iters": [r["newton_iters"] for r in stats],
+                 "gmres_iters": [r["gmres_iters"] for r in stats]}
+    log(name, res[name])
     del md, m, u0
     torch.cuda.empty_cache()
     return res

@@ -391,6 +391,65 @@ def newton(G, solve, u0, rtol=1e-8, atol=0.0, maxit=20, history=None):
 
 
 # ----------------------------------------------------------------------------
+# O11b: diagonally implicit Runge-Kutta time stepping of M du/dt + R(u) = 0
+# (Section 2: the paper's DIRK discretization in time, schemes after Alexander
+# 1977).  Written from the stage equations themselves:
+#   M (U_i - u_n) / dt + sum_{j<=i} a_ij R(U_j) = 0,   i = 1..s,
+#   u_{n+1} = u_n + dt sum_j b_j k_j,   k_j = -M^{-1} R(U_j),
+# each stage solved by Newton with sparse direct solves of
+# M/dt + a_ii dR/du.  M is diagonal for the collocated nodal basis.
+# ----------------------------------------------------------------------------
+def dirk_tableau(name):
+    """(A, b) of implicit Euler ("be"), Alexander's L-stable two- and three-stage schemes of orders 2 and 3
+    ("dirk22", "dirk33", with b the last row of A) and the three-stage fourth-order A-stable scheme ("dirk34")."""
+    if name == "be":
+        return np.array([[1.0]]), np.array([1.0])
+    if name == "dirk22":
+        g = (2.0 - np.sqrt(2.0)) / 2.0
+        return np.array([[g, 0.0], [1.0 - g, g]]), np.array([1.0 - g, g])
+    if name == "dirk33":
+        roots = np.roots([1.0, -3.0, 1.5, -1.0 / 6.0])
+        g = float(next(r.real for r in roots if abs(r.imag) < 1e-12 and 1.0 / 6.0 < r.real < 0.5))
+        t2 = (1.0 + g) / 2.0
+        b1 = -(6.0 * g ** 2 - 16.0 * g + 1.0) / 4.0
+        b2 = (6.0 * g ** 2 - 20.0 * g + 5.0) / 4.0
+        A = np.array([[g, 0.0, 0.0], [t2 - g, g, 0.0], [b1, b2, g]])
+        return A, A[2].copy()
+    if name == "dirk34":
+        g = 0.5 + np.cos(np.pi / 18.0) / np.sqrt(3.0)
+        d = 1.0 / (6.0 * (2.0 * g - 1.0) ** 2)
+        return (np.array([[g, 0.0, 0.0], [0.5 - g, g, 0.0], [2.0 * g, 1.0 - 4.0 * g, g]]),
+                np.array([d, 1.0 - 2.0 * d, d]))
+    raise ValueError(name)
+
+
+def dirk_step(mesh, model, un, dt, A, b, rtol=1e-13, maxit=12):
+    """One DIRK step of M du/dt + R(u) = 0 from un; model is the steady model (its R).  Returns u_{n+1}."""
+    import scipy.sparse.linalg as spla
+    ncu = model.ncu
+    Mdiag = mesh.mass_apply(ncu, np.ones_like(un))
+    s = len(b)
+    R = []
+    U = un.copy()
+    for i in range(s):
+        rest = sum((A[i, j] * R[j] for j in range(i)), np.zeros_like(un))
+
+        def F(x, i=i, rest=rest):
+            return mesh.mass_apply(ncu, x - un) / dt + rest + A[i, i] * mesh.residual(model, x)
+
+        # dF/du = M/dt + a_ii dR/du = a_ii (a0 M + dR/du) with a0 = 1/(a_ii dt)
+        mj = model.replace(a0=1.0 / (A[i, i] * dt), r=None)
+
+        def solve(x, rhs, i=i, mj=mj):
+            return spla.spsolve((A[i, i] * mesh.jacobian(mj, x)).tocsc(), rhs)
+
+        U, info = newton(F, solve, U, rtol=rtol, maxit=maxit)
+        R.append(mesh.residual(model, U))
+    k = [-Rj / Mdiag for Rj in R]
+    return un + dt * sum(b[j] * k[j] for j in range(s))
+
+
+# ----------------------------------------------------------------------------
 # O12: the element-patch MLP in FP64: y = W3 relu(W2 relu(W1 x + b1) + b2) + b3,
 # hand-written backward pass and Adam.
 # ----------------------------------------------------------------------------

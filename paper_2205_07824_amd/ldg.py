@@ -380,6 +380,13 @@ def newton(model, u, time=None, maxit=20, rtol=1e-8, atol=0.0, eta=1e-3, bj_refr
     return u, st.as_dict(), status
 
 
+def axpby(a, x, b, y):
+    """y = a x + b y on the device (FP64 vectors of equal length)."""
+    assert x.numel() == y.numel()
+    _check(lib().ldg_axpby(x.numel(), C.c_double(a), _ptr(x), C.c_double(b), _ptr(y), _stream()), "ldg_axpby")
+    return y
+
+
 def norm(x):
     out = C.c_double()
     _check(lib().ldg_norm2(x.numel(), _ptr(x), C.byref(out), _stream()), "ldg_norm2")

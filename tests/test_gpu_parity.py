@@ -383,6 +383,28 @@ def test_bdf_steps_match_oracle(L):
     assert rel(ug.cpu().numpy(), u) < 1e-8
 
 
+@pytest.mark.parametrize("scheme", ["dirk22", "dirk33", "dirk34"])
+def test_dirk_steps_match_oracle(L, scheme):
+    """Two DIRK steps of the Euler vortex case: the library's stages (time wrapper with the stage
+    combination, Newton-GMRES) against the oracle's stage equations solved with sparse direct solves."""
+    import oracle as O
+    from paper_2205_07824_amd import timestep as TS
+    c = CS.c3_euler2d(n=4, p=3)
+    _say("case c3 dirk steps", scheme)
+    m, md, t, dev = build_gpu(L, c)
+    steady = c.oracle_model().replace(a0=0.0, r=None)
+    A, b = O.dirk_tableau(scheme)
+    dt, nsteps = 0.5, 2
+    u = c.u.copy()
+    for _ in range(nsteps):
+        u = O.dirk_step(c.om, steady, u, dt, A, b)
+    ug, stats = TS.dirk_steps(md, dev(c.u.copy()), dt, nsteps, scheme=scheme, restart=50, eta=1e-10, rtol=1e-12,
+                              newton_maxit=12)
+    _say("dirk stats", stats)
+    assert len(stats) == nsteps and all(s["converged"] for s in stats)
+    assert rel(ug.cpu().numpy(), u) < 1e-8
+
+
 @pytest.mark.parametrize("nd,p", [(2, 2), (3, 3), (3, 1)])
 def test_single_element_mesh(L, nd, p):
     """One element, every face a Dirichlet boundary: residual and JVP against the oracle."""

@@ -412,6 +412,44 @@ def test_bdf2_recurrence_reaction():
         s_nm1, s_n = s_n, s_new
 
 
+# ---------------------------------------------------------------- P13b DIRK
+def _reaction_mesh_model(lam):
+    box = I.box_mesh(2, 3, periodic=(True, True))
+    m = O.Mesh(box, 1)
+    return m, O.Model(O.MODEL_POISSON, 1, [1.0, 4.0, lam])
+
+
+@pytest.mark.parametrize("scheme", ["be", "dirk22", "dirk33", "dirk34"])
+def test_dirk_step_reaction_matches_stability_function(scheme):
+    # constant state, no spatial coupling: M du/dt + lam M u = 0, so one step multiplies u by the scheme's
+    # stability function R(z) = 1 + z b^T (I - z A)^-1 1 at z = -lam dt (a resolvent of the tableau, not the
+    # stage-by-stage Newton solves of the oracle)
+    lam, dt = 0.7, 0.3
+    m, md = _reaction_mesh_model(lam)
+    A, b = O.dirk_tableau(scheme)
+    u1 = O.dirk_step(m, md, np.full(m.size(1), 1.0), dt, A, b)
+    z = -lam * dt
+    Rz = 1.0 + z * b @ np.linalg.solve(np.eye(len(b)) - z * A, np.ones(len(b)))
+    assert np.abs(u1 - Rz).max() < 1e-13
+
+
+@pytest.mark.parametrize("scheme,order", [("be", 1), ("dirk22", 2), ("dirk33", 3), ("dirk34", 4)])
+def test_dirk_convergence_order_on_reaction(scheme, order):
+    # u' = -lam u to T = 1 against exp(-lam T): halving dt divides the error by 2^order (the tableau's order
+    # conditions; a wrong coefficient or stage equation breaks the rate)
+    lam, T = 1.0, 1.0
+    m, md = _reaction_mesh_model(lam)
+    A, b = O.dirk_tableau(scheme)
+    errs = []
+    for n in (8, 16):
+        u = np.full(m.size(1), 1.0)
+        for _ in range(n):
+            u = O.dirk_step(m, md, u, T / n, A, b)
+        errs.append(np.abs(u - np.exp(-lam * T)).max())
+    rate = np.log2(errs[0] / errs[1])
+    assert abs(rate - order) < 0.25, (errs, rate)
+
+
 # ---------------------------------------------------------------- P14 Newton
 def test_newton_quadratic_on_euler_implicit_step():
     box = I.box_mesh(2, 4, lo=(0, 0), hi=(20, 20), periodic=(True, True))
