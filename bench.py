@@ -30,7 +30,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-JVP_KERNEL_SOURCES = ("ldg_internal.hpp", "ldg_physics.hpp", "ldg_operator_kernels.hpp", "ldg_op_poisson.hip")
+JVP_KERNEL_SOURCES = ("ldg_device.hpp", "ldg_physics.hpp", "ldg_operator_kernels.hpp", "ldg_operator_launch.hpp",
+                      "ldg_op_poisson.hip")
 
 
 def kernel_sources_sha256():

@@ -4,6 +4,7 @@
 #include <cstring>
 #include <unordered_map>
 
+#include "ldg_internal.hpp"
 #include "ldg_physics.hpp"
 
 namespace ldg {

@@ -1,5 +1,5 @@
 // Operator kernels instantiated for one model kind (poisson).
-#include "ldg_operator_kernels.hpp"
+#include "ldg_operator_launch.hpp"
 
 namespace ldg {
 LDG_DEFINE_KIND_OPS(0)

@@ -1,6 +1,6 @@
 // Model-kind dispatch of the operator kernels, and the set-up kernel that
 // integrates the data terms of the linear models.
-#include "ldg_operator_kernels.hpp"
+#include "ldg_operator_launch.hpp"
 
 namespace ldg {
 

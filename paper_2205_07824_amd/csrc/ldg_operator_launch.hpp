@@ -1,0 +1,187 @@
+// Host launchers of the operator kernels and the per-kind entry points.
+#pragma once
+
+#include "ldg_internal.hpp"
+#include "ldg_operator_kernels.hpp"
+
+namespace ldg {
+
+// ============================================================================
+// host dispatch
+// ============================================================================
+template <int KIND, int D, int P1, class R>
+static ldg_status launch_grad(const Model& md, const double* u, void* q, bool with_data, hipStream_t s) {
+  // linear models: homogeneous kernel + boundary-data offset; nonlinear: data in the kernel
+  const bool in_kernel_data = with_data && !Phys<KIND, D>::LINEAR;
+  const double* qoff = (with_data && Phys<KIND, D>::LINEAR) ? md.d_qg : nullptr;
+  constexpr int NN = GradCfg<KIND, D, P1, R>::NN, EPB = GradCfg<KIND, D, P1, R>::EPB;
+  const Mesh& m = *md.mesh;
+  const int nblk = (int)((m.E + EPB - 1) / EPB);
+  typename TabOf<R>::T tab;
+  if constexpr (std::is_same<R, double>::value) tab = m.tab; else tab = m.tabf;
+  const float* nodu = nullptr;
+  if (in_kernel_data) {
+    if (m.affine)
+      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, true, false, true>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), tab,
+                         md.dev(), u, (R*)q, qoff, nodu);
+    else
+      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, true, false, false>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), tab,
+                         md.dev(), u, (R*)q, qoff, nodu);
+  } else {
+    if (m.affine)
+      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, false, false, true>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), tab,
+                         md.dev(), u, (R*)q, qoff, nodu);
+    else
+      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, false, false, false>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), tab,
+                         md.dev(), u, (R*)q, qoff, nodu);
+  }
+  LDG_TRY(hipGetLastError());
+  return LDG_OK;
+}
+
+template <int KIND, int D, int P1, class R, int MODE>
+static ldg_status launch_resid(const Model& md, const TimeDev& t, const double* u, const void* q, const double* v,
+                               const void* dq, const double* dterm, double* out, hipStream_t s) {
+  constexpr int NN = ResidCfg<KIND, D, P1, R, MODE>::NN, EPB = ResidCfg<KIND, D, P1, R, MODE>::EPB;
+  const Mesh& m = *md.mesh;
+  const int nblk = (int)((m.E + EPB - 1) / EPB);
+  typename TabOf<R>::T tab;
+  if constexpr (std::is_same<R, double>::value) tab = m.tab; else tab = m.tabf;
+  float* noF = nullptr;
+  if (m.affine)
+    hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, true>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), tab,
+                       md.dev(), t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
+  else
+    hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, false>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), tab,
+                       md.dev(), t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
+  LDG_TRY(hipGetLastError());
+  return LDG_OK;
+}
+
+template <int KIND, int D, int P1>
+static ldg_status launch_grad_ext(const Model& md, const double* u, const float* du, float* q, hipStream_t s) {
+  constexpr int NN = GradCfg<KIND, D, P1, float>::NN, EPB = GradCfg<KIND, D, P1, float>::EPB;
+  const Mesh& m = *md.mesh;
+  const int nblk = (int)((m.E + EPB - 1) / EPB);
+  hipLaunchKernelGGL((k_grad<KIND, D, P1, float, false, true>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), m.tabf,
+                     md.dev(), u, q, (const double*)nullptr, du);
+  LDG_TRY(hipGetLastError());
+  return LDG_OK;
+}
+
+template <int KIND, int D, int P1>
+static ldg_status launch_resid_ext(const Model& md, const TimeDev& t, const double* u, const float* q, float* F,
+                                   double* out, hipStream_t s) {
+  constexpr int NN = ResidCfg<KIND, D, P1, float, 0>::NN, EPB = ResidCfg<KIND, D, P1, float, 0>::EPB;
+  const Mesh& m = *md.mesh;
+  const int nblk = (int)((m.E + EPB - 1) / EPB);
+  hipLaunchKernelGGL((k_resid<KIND, D, P1, float, 0, true>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), m.tabf,
+                     md.dev(), t, u, q, (const double*)nullptr, (const float*)nullptr, (const double*)nullptr, out, F);
+  LDG_TRY(hipGetLastError());
+  return LDG_OK;
+}
+
+// dispatch over (nd, p+1) for one model kind
+template <int KI, template <int, int, int> class F, class... Args>
+static ldg_status dispatch_kind(int nd, int p1, Args&&... args) {
+#define LDG_CASE(DD, PP) \
+  if (nd == DD && p1 == PP) return F<KI, DD, PP>::run(args...);
+  LDG_CASE(2, 2) LDG_CASE(2, 3) LDG_CASE(2, 4) LDG_CASE(2, 5) LDG_CASE(3, 2) LDG_CASE(3, 3) LDG_CASE(3, 4)
+#undef LDG_CASE
+  set_error("no compiled kernel for this (model, nd, p)");
+  return LDG_EUNSUPPORTED;
+}
+
+template <int KI, int DD, int PP>
+struct GradOp {
+  static ldg_status run(const Model& md, const double* u, void* q, bool fp32, bool with_data, hipStream_t s) {
+    if constexpr (KI == K_EULER) {
+      return LDG_OK;
+    } else {
+      if (fp32) return launch_grad<KI, DD, PP, float>(md, u, q, with_data, s);
+      return launch_grad<KI, DD, PP, double>(md, u, q, with_data, s);
+    }
+  }
+};
+
+template <int KI, int DD, int PP>
+struct ResidOp {
+  static ldg_status run(const Model& md, const TimeDev& t, const double* u, const void* q, double* out, bool fp32,
+                        bool with_data, hipStream_t s) {
+    if constexpr (KI <= K_CONVDIFF) {
+      const double* dt = with_data ? md.d_dterm : nullptr;
+      if (fp32) return launch_resid<KI, DD, PP, float, 0>(md, t, u, q, nullptr, nullptr, dt, out, s);
+      return launch_resid<KI, DD, PP, double, 0>(md, t, u, q, nullptr, nullptr, dt, out, s);
+    } else {
+      if (fp32) return launch_resid<KI, DD, PP, float, 1>(md, t, u, q, nullptr, nullptr, nullptr, out, s);
+      return launch_resid<KI, DD, PP, double, 1>(md, t, u, q, nullptr, nullptr, nullptr, out, s);
+    }
+  }
+};
+
+template <int KI, int DD, int PP>
+struct TangentOp {
+  static ldg_status run(const Model& md, const TimeDev& t, const double* u, const void* q, const double* v,
+                        const void* dq, double* out, bool fp32, hipStream_t s) {
+    if constexpr (KI <= K_CONVDIFF) {
+      set_error("tangent kernel requested for a linear model");
+      return LDG_EINVAL;
+    } else {
+      if (fp32) return launch_resid<KI, DD, PP, float, 2>(md, t, u, q, v, dq, nullptr, out, s);
+      return launch_resid<KI, DD, PP, double, 2>(md, t, u, q, v, dq, nullptr, out, s);
+    }
+  }
+};
+
+template <int KI, int DD, int PP>
+struct GradExtOp {
+  static ldg_status run(const Model& md, const double* u, const float* du, float* q, hipStream_t s) {
+    if constexpr (KI <= K_CONVDIFF) return launch_grad_ext<KI, DD, PP>(md, u, du, q, s);
+    else { set_error("external contractions are for the linear models"); return LDG_EUNSUPPORTED; }
+  }
+};
+template <int KI, int DD, int PP>
+struct ResidExtOp {
+  static ldg_status run(const Model& md, const TimeDev& t, const double* u, const float* q, float* F, double* out,
+                        hipStream_t s) {
+    if constexpr (KI <= K_CONVDIFF) return launch_resid_ext<KI, DD, PP>(md, t, u, q, F, out, s);
+    else { set_error("external contractions are for the linear models"); return LDG_EUNSUPPORTED; }
+  }
+};
+
+// per-kind entry points, defined in ldg_op_<kind>.hip
+template <int KI> struct KindOps {
+  static ldg_status grad(const Model& md, const double* u, void* q, bool fp32, bool with_data, hipStream_t s);
+  static ldg_status resid(const Model& md, const TimeDev& t, const double* u, const void* q, double* out, bool fp32,
+                          bool with_data, hipStream_t s);
+  static ldg_status tangent(const Model& md, const TimeDev& t, const double* u, const void* q, const double* v,
+                            const void* dq, double* out, bool fp32, hipStream_t s);
+  static ldg_status grad_ext(const Model& md, const double* u, const float* du, float* q, hipStream_t s);
+  static ldg_status resid_ext(const Model& md, const TimeDev& t, const double* u, const float* q, float* F,
+                              double* out, hipStream_t s);
+};
+
+#define LDG_DEFINE_KIND_OPS(KI)                                                                                  \
+  template <> ldg_status KindOps<KI>::grad(const Model& md, const double* u, void* q, bool fp32, bool with_data,  \
+                                           hipStream_t s) {                                                      \
+    return dispatch_kind<KI, GradOp>(md.mesh->nd, md.mesh->p1, md, u, q, fp32, with_data, s);                    \
+  }                                                                                                              \
+  template <> ldg_status KindOps<KI>::resid(const Model& md, const TimeDev& t, const double* u, const void* q,   \
+                                            double* out, bool fp32, bool with_data, hipStream_t s) {             \
+    return dispatch_kind<KI, ResidOp>(md.mesh->nd, md.mesh->p1, md, t, u, q, out, fp32, with_data, s);           \
+  }                                                                                                              \
+  template <> ldg_status KindOps<KI>::tangent(const Model& md, const TimeDev& t, const double* u, const void* q, \
+                                              const double* v, const void* dq, double* out, bool fp32,           \
+                                              hipStream_t s) {                                                   \
+    return dispatch_kind<KI, TangentOp>(md.mesh->nd, md.mesh->p1, md, t, u, q, v, dq, out, fp32, s);             \
+  }                                                                                                              \
+  template <> ldg_status KindOps<KI>::grad_ext(const Model& md, const double* u, const float* du, float* q,      \
+                                               hipStream_t s) {                                                  \
+    return dispatch_kind<KI, GradExtOp>(md.mesh->nd, md.mesh->p1, md, u, du, q, s);                              \
+  }                                                                                                              \
+  template <> ldg_status KindOps<KI>::resid_ext(const Model& md, const TimeDev& t, const double* u, const float* q, \
+                                                float* F, double* out, hipStream_t s) {                          \
+    return dispatch_kind<KI, ResidExtOp>(md.mesh->nd, md.mesh->p1, md, t, u, q, F, out, s);                      \
+  }
+
+}  // namespace ldg

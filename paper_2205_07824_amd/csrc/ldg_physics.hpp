@@ -4,7 +4,7 @@
 // exactly the arithmetic of the residual kernels.
 #pragma once
 
-#include "ldg_internal.hpp"
+#include "ldg_device.hpp"
 
 namespace ldg {
 
