@@ -83,7 +83,13 @@ typedef enum {
  *   sigma = 1/2 max(|v.n| + c) (Euler), + tau / Re (NS);
  * numerical trace uhat = (u- + u+)/2.  tau is the interior-penalty parameter
  * chosen by the caller (the tests use (p+1)^2 / h). */
-typedef enum { LDG_MODEL_POISSON = 0, LDG_MODEL_CONVDIFF = 1, LDG_MODEL_EULER = 2, LDG_MODEL_NS = 3 } ldg_model_kind;
+typedef enum {
+  LDG_MODEL_POISSON = 0,
+  LDG_MODEL_CONVDIFF = 1,
+  LDG_MODEL_EULER = 2,
+  LDG_MODEL_NS = 3,
+  LDG_MODEL_USER = 4   /* physics from a source compiled at run time (ldg_model_create_user) */
+} ldg_model_kind;
 
 /* Boundary condition per boundary tag.
  *   DIRICHLET: uhat = g, u+ = g, q+ = q- in the interior flux formula
@@ -151,6 +157,41 @@ typedef struct {
  * compiled kernel for this (nd, p, model)). */
 ldg_status ldg_model_create(ldg_mesh mesh, const ldg_model_desc* desc, void* stream, ldg_model* out);
 ldg_status ldg_model_destroy(ldg_model model);
+
+/* Model with run-time compiled physics.  The paper generates the flux, source
+ * and boundary code of each PDE from its description (Section 3); here the
+ * caller passes the pointwise physics as C++ source, compiled with hipRTC for
+ * gfx950 together with the library's operator kernels for this mesh's element
+ * type and order (one-off, a few seconds).  The source defines
+ *
+ *   struct LdgUser {
+ *     static constexpr int NCU = ...;      conserved variables (= desc->ncu)
+ *     static constexpr bool HASQ = ...;    the flux depends on q = -grad u (= has_q)
+ *     static constexpr int NAUX = ...;     aux fields read (upper bound of desc->naux)
+ *     template <int D, class V, class R> __device__ static void
+ *       flux(const double* mu, int naux, const V* u, const V (*q)[D], const R* a, V (*f)[D]);
+ *     template <int D, class V, class R> __device__ static void
+ *       numflux(const double* mu, int naux, const V* uL, const V (*qL)[D], const R* aL,
+ *               const V* uR, const V (*qR)[D], const R* aR, const R* n, V* Fh);
+ *   };
+ *
+ * R is double or float; V is R or the dual number ldg::Dl<R> (value and
+ * tangent), so the same source yields exact Jacobian-vector products.  Helpers
+ * from the library's device header are in scope (ldg::VT<V>::mk, vsqrt, vabs,
+ * vmax).  f is the physical flux [NCU][D] (R = -(f, grad phi) + <Fh, phi> -
+ * (src, phi)), Fh the numerical flux along the unit normal n (interior faces,
+ * Dirichlet faces with uR = g, qR = qL); Neumann and extrapolation tags behave
+ * as for the built-in models.  desc->kind must be LDG_MODEL_USER; the source
+ * term is the data field desc->src.  The model is nonlinear: JVPs need u.
+ * Errors: LDG_EINVAL with the compiler's log in ldg_last_error() when the
+ * source does not compile; otherwise as ldg_model_create. */
+ldg_status ldg_model_create_user(ldg_mesh mesh, const ldg_model_desc* desc, const char* physics_source, int has_q,
+                                 void* stream, ldg_model* out);
+
+/* Compiles a physics source as ldg_model_create_user would for (nd, p, ncu,
+ * has_q), on the host only (no device needed): LDG_OK, or LDG_EINVAL with the
+ * compiler's log in ldg_last_error(). */
+ldg_status ldg_user_physics_check(const char* physics_source, int nd, int p, int ncu, int has_q);
 
 /* Implicit time wrapper (the configurations use BDF1/BDF2; DIRK stages have the
  * same form): G(u) = a0 M u - M (c1 r1 + c2 r2) + R(u).  r1, r2 are DEVICE

@@ -397,8 +397,8 @@ ldg_status ldg_mesh_destroy(ldg_mesh m) {
   return LDG_OK;
 }
 
-ldg_status ldg_model_create(ldg_mesh m, const ldg_model_desc* d, void* stream, ldg_model* out) {
-  LDG_ENTER();
+static ldg_status model_create(ldg_mesh m, const ldg_model_desc* d, const char* user_source, int has_q, void* stream,
+                               ldg_model* out) {
   CHECK_ARG(m && d && out, "null argument");
   {
     // operator kernels are compiled for quads with p <= 4 and hexes with p <= 3
@@ -408,15 +408,21 @@ ldg_status ldg_model_create(ldg_mesh m, const ldg_model_desc* d, void* stream, l
       return LDG_EUNSUPPORTED;
     }
   }
-  CHECK_ARG(d->kind >= 0 && d->kind <= 3, "unknown model kind");
-  const int want_ncu = d->kind <= 1 ? 1 : m->nd + 2;
-  CHECK_ARG(d->ncu == want_ncu, "ncu inconsistent with the model");
+  const bool user = user_source != nullptr;
+  if (user) {
+    CHECK_ARG(d->kind == LDG_MODEL_USER, "a physics source needs kind LDG_MODEL_USER");
+    CHECK_ARG(d->ncu >= 1 && d->ncu <= 8, "ncu must be in [1, 8]");
+  } else {
+    CHECK_ARG(d->kind >= 0 && d->kind <= 3, "unknown model kind (LDG_MODEL_USER needs ldg_model_create_user)");
+    const int want_ncu = d->kind <= 1 ? 1 : m->nd + 2;
+    CHECK_ARG(d->ncu == want_ncu, "ncu inconsistent with the model");
+  }
   CHECK_ARG(d->nmu >= 0 && d->nmu <= MAXMU && (d->nmu == 0 || d->mu), "bad mu");
   CHECK_ARG(d->nbc >= 1 && d->nbc <= MAXTAG && d->bc_kind, "need 1..8 boundary kinds");
   CHECK_ARG(d->naux >= 0 && (d->naux == 0 || d->aux), "bad aux");
   if (d->kind == LDG_MODEL_CONVDIFF) CHECK_ARG(d->naux == 1 + m->nd, "convection-diffusion needs aux = [kappa, b]");
   if (d->kind == LDG_MODEL_POISSON) CHECK_ARG(d->naux <= 1, "Poisson takes at most one aux field");
-  if (d->kind >= 2) CHECK_ARG(d->naux == 0, "Euler / NS take no aux fields");
+  if (d->kind == LDG_MODEL_EULER || d->kind == LDG_MODEL_NS) CHECK_ARG(d->naux == 0, "Euler / NS take no aux fields");
   for (int i = 0; i < d->nbc; ++i) CHECK_ARG(d->bc_kind[i] >= 0 && d->bc_kind[i] <= 2, "bad bc kind");
   if (m->nq1 != m->p1) {
     if (!(d->kind == LDG_MODEL_POISSON && d->naux == 0 && m->affine)) {
@@ -430,7 +436,9 @@ ldg_status ldg_model_create(ldg_mesh m, const ldg_model_desc* d, void* stream, l
   md->kind = d->kind; md->ncu = d->ncu; md->nmu = d->nmu; md->naux = d->naux;
   for (int i = 0; i < MAXMU; ++i) md->mu[i] = i < d->nmu ? d->mu[i] : 0.0;
   // defaults for missing parameters
-  if (d->kind <= 1) {
+  if (user) {
+    // no defaults: the physics source reads mu as given
+  } else if (d->kind <= 1) {
     if (d->nmu < 1) md->mu[0] = 1.0;
     if (d->nmu < 2) md->mu[1] = 1.0;
   } else {
@@ -445,6 +453,7 @@ ldg_status ldg_model_create(ldg_mesh m, const ldg_model_desc* d, void* stream, l
   for (int i = 0; i < MAXTAG; ++i) md->bc_kind[i] = i < d->nbc ? d->bc_kind[i] : d->bc_kind[d->nbc - 1];
   md->aux = d->aux; md->src = d->src; md->bdata = d->bdata;
   md->linear = d->kind <= 1;
+  md->hasq = user ? has_q != 0 : d->kind != LDG_MODEL_EULER;
   const size_t N = md->N();
   const size_t NQ = N * m->nd;
   hipError_t e = hipSuccess;
@@ -470,14 +479,40 @@ ldg_status ldg_model_create(ldg_mesh m, const ldg_model_desc* d, void* stream, l
   } else {
     md->d_srcn = const_cast<double*>(d->src);   // collocated: quadrature points are the nodes
   }
+  if (user) {
+    ldg_status st = jit_build(*md, user_source);
+    if (st != LDG_OK) { ldg_model_destroy(md); return st; }
+  }
   *out = md;
   return LDG_OK;
+}
+
+ldg_status ldg_model_create(ldg_mesh m, const ldg_model_desc* d, void* stream, ldg_model* out) {
+  LDG_ENTER();
+  return model_create(m, d, nullptr, 1, stream, out);
+}
+
+ldg_status ldg_model_create_user(ldg_mesh m, const ldg_model_desc* d, const char* physics_source, int has_q,
+                                 void* stream, ldg_model* out) {
+  LDG_ENTER();
+  CHECK_ARG(physics_source, "null physics source");
+  return model_create(m, d, physics_source, has_q, stream, out);
+}
+
+ldg_status ldg_user_physics_check(const char* physics_source, int nd, int p, int ncu, int has_q) {
+  LDG_ENTER();
+  CHECK_ARG(physics_source, "null physics source");
+  CHECK_ARG((nd == 2 && p >= 1 && p <= 4) || (nd == 3 && p >= 1 && p <= 3),
+            "operator kernels exist for quads with p <= 4 and hexes with p <= 3");
+  CHECK_ARG(ncu >= 1 && ncu <= 8, "ncu must be in [1, 8]");
+  return jit_check(physics_source, nd, p + 1, ncu, has_q != 0);
 }
 
 ldg_status ldg_model_destroy(ldg_model md) {
   LDG_ENTER();
   if (!md) return LDG_OK;
   mfma_release(*md);
+  jit_release(*md);
   hipFree(md->d_q); hipFree(md->d_q32); hipFree(md->d_qres); hipFree(md->d_dq); hipFree(md->d_tmp); hipFree(md->d_tmp2); hipFree(md->d_red);
   hipFree(md->d_qg); hipFree(md->d_dterm);
   delete md;
@@ -511,7 +546,7 @@ ldg_status residual_impl(Model& md, const ldg_time* t, const double* u, double* 
   if (st != LDG_OK) return st;
   st = op_resid(md, make_time(t, true), u, qbuf, G, fp32, true, s);
   if (st != LDG_OK) return st;
-  if (q_out && qbuf != q_out && md.kind != LDG_MODEL_EULER) {
+  if (q_out && qbuf != q_out && md.hasq) {
     const int64_t n = (int64_t)md.N() * md.mesh->nd;
     hipLaunchKernelGGL(k_f32_to_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, (const float*)qbuf, q_out);
     LDG_TRY(hipGetLastError());
@@ -564,11 +599,11 @@ ldg_status jvp_impl(Model& md, const ldg_time* t, const double* u, const double*
   }
   ldg_status st;
   void* qc = fp32 ? (void*)md.d_q32 : (void*)md.d_q;
-  if (!prepared && md.kind != LDG_MODEL_EULER) {
+  if (!prepared && md.hasq) {
     st = op_grad(md, u, qc, fp32, true, s);
     if (st != LDG_OK) return st;
   }
-  if (md.kind != LDG_MODEL_EULER) {
+  if (md.hasq) {
     st = op_grad(md, v, md.d_dq, fp32, false, s);
     if (st != LDG_OK) return st;
   }

@@ -19,6 +19,9 @@ using __hip_internal::uint64_t;
 
 namespace ldg {
 
+// boundary condition kinds, the values of the ABI's ldg_bc_kind
+enum BcKind { BC_DIRICHLET = 0, BC_NEUMANN = 1, BC_EXTRAP = 2 };
+
 constexpr int MAXP1 = 6;        // p <= 5
 constexpr int MAXTAG = 8;
 constexpr int MAXMU = 8;

@@ -12,6 +12,9 @@
 
 namespace ldg {
 
+static_assert(BC_DIRICHLET == LDG_BC_DIRICHLET && BC_NEUMANN == LDG_BC_NEUMANN && BC_EXTRAP == LDG_BC_EXTRAP,
+              "device boundary kinds are the ABI's");
+
 // --------------------------------------------------------------------------
 // Host-side objects
 // --------------------------------------------------------------------------
@@ -40,6 +43,8 @@ struct Mesh {
   MeshDev dev() const { return MeshDev{(int)E, (int)nbf, d_coef, d_nbr, d_btag, d_order}; }
 };
 
+struct JitOps;   // run-time compiled physics (ldg_jit.hip)
+
 struct Model {
   Mesh* mesh;
   int kind, ncu, nmu, naux;
@@ -50,6 +55,8 @@ struct Model {
   const double* src;
   const double* bdata;
   bool linear;
+  bool hasq = true;           // the model's flux depends on q (all but Euler)
+  JitOps* jit = nullptr;      // kernels of a model compiled at run time
   double* d_qg = nullptr;     // linear models: q offset from boundary data  [E][ncu][nd][nn]
   double* d_dterm = nullptr;  // linear models: data terms of the residual   [E][ncu][nn]
   double* d_srcn = nullptr;   // nonlinear models: source at nodes          [E][ncu][nn]
@@ -98,6 +105,14 @@ ldg_status op_jvp_nonlinear(const Model& md, const TimeDev& t, const double* u, 
 ldg_status op_data_terms(Model& md, hipStream_t s);
 ldg_status op_mfma_jvp(const Model& md, const TimeDev& t, const double* v, double* out, bool fp16, hipStream_t s);
 void mfma_release(const Model& md);
+
+// run-time compiled physics (ldg_jit.hip)
+ldg_status jit_build(Model& md, const char* user_source);
+void jit_release(Model& md);
+ldg_status jit_check(const char* user_source, int nd, int p1, int ncu, bool hasq);
+ldg_status jit_grad(const Model& md, const double* u, void* q, bool fp32, bool with_data, hipStream_t s);
+ldg_status jit_resid(const Model& md, const TimeDev& t, const double* u, const void* q, const double* v,
+                     const void* dq, double* out, bool fp32, bool tangent, hipStream_t s);
 
 // shared host helpers (ldg_api.hip)
 TimeDev make_time(const ldg_time* t, bool with_rhs);

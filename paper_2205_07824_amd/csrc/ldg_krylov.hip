@@ -834,7 +834,7 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
   const int nb = nblk_for(n);
   const int gV = nb;
   // linearization point: q(u_lin) for the nonlinear models, once per solve
-  if (!md.linear && md.kind != LDG_MODEL_EULER) {
+  if (!md.linear && md.hasq) {
     st = op_grad(md, u_lin, md.d_q, false, true, s);
     if (st != LDG_OK) return st;
     if (o.jvp_prec == LDG_FP32) {

@@ -141,18 +141,21 @@ static ldg_status by_kind(int kind, F0 f0, F1 f1, F2 f2, F3 f3, Args&&... args) 
 }
 
 ldg_status op_grad(const Model& md, const double* u, void* q, bool fp32, bool with_data, hipStream_t s) {
+  if (md.kind == LDG_MODEL_USER) return jit_grad(md, u, q, fp32, with_data, s);
   return by_kind(md.kind, KindOps<0>::grad, KindOps<1>::grad, KindOps<2>::grad, KindOps<3>::grad, md, u, q, fp32,
                  with_data, s);
 }
 
 ldg_status op_resid(const Model& md, const TimeDev& t, const double* u, const void* q, double* out, bool fp32,
                     bool with_data, hipStream_t s) {
+  if (md.kind == LDG_MODEL_USER) return jit_resid(md, t, u, q, nullptr, nullptr, out, fp32, false, s);
   return by_kind(md.kind, KindOps<0>::resid, KindOps<1>::resid, KindOps<2>::resid, KindOps<3>::resid, md, t, u, q,
                  out, fp32, with_data, s);
 }
 
 ldg_status op_jvp_nonlinear(const Model& md, const TimeDev& t, const double* u, const void* q, const double* v,
                             const void* dq, double* out, bool fp32, hipStream_t s) {
+  if (md.kind == LDG_MODEL_USER) return jit_resid(md, t, u, q, v, dq, out, fp32, true, s);
   return by_kind(md.kind, KindOps<0>::tangent, KindOps<1>::tangent, KindOps<2>::tangent, KindOps<3>::tangent, md, t,
                  u, q, v, dq, out, fp32, s);
 }

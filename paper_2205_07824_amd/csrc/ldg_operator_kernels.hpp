@@ -50,12 +50,27 @@ template <> struct TabOf<float> { using T = BasisTabF; };
 
 // Elements per work-group: fill 256 threads (2D) or 128 threads (3D elements,
 // where fewer waves per barrier measured faster), bounded by an LDS budget.
-template <int NN, int BYTES_PER_ELEM>
-constexpr int pick_epb() {
-  int e = (NN >= 27 ? 128 : 256) / NN;
+// Plain constexpr functions of the sizes, so that the launcher of kernels
+// compiled at run time computes the same numbers.
+__host__ __device__ constexpr int pick_epb_n(int nn, int bytes_per_elem) {
+  int e = (nn >= 27 ? 128 : 256) / nn;
   if (e < 1) e = 1;
-  while (e > 1 && e * BYTES_PER_ELEM > 40 * 1024) --e;
+  while (e > 1 && e * bytes_per_elem > 40 * 1024) --e;
   return e;
+}
+template <int NN, int BYTES_PER_ELEM>
+constexpr int pick_epb() { return pick_epb_n(NN, BYTES_PER_ELEM); }
+
+__host__ __device__ constexpr int geo_tab_size(int d, int p1) {
+  return (d * ipow(p1, d - 1) + ((d == 3) ? 2 * d * 2 * p1 : 2 * d)) * d;
+}
+// LDS bytes per element of the gradient and residual kernels (rsz = sizeof(R))
+__host__ __device__ constexpr int grad_bytes(int ncu, int d, int p1, int rsz) {
+  return rsz * (ncu * ipow(p1, d) + 2 * d * ncu * d * ipow(p1, d - 1) + geo_tab_size(d, p1)) + 8 * (1 << d) * d;
+}
+__host__ __device__ constexpr int resid_bytes(int ncu, bool hasq, int mode, int d, int p1, int rsz) {
+  return (mode == 2 ? 2 * rsz : rsz) * (ncu * ipow(p1, d) + (hasq ? ncu * d * ipow(p1, d) : 0)) +
+         rsz * (ncu * d * ipow(p1, d) + 2 * d * ncu * ipow(p1, d - 1) + geo_tab_size(d, p1)) + 8 * (1 << d) * d;
 }
 
 template <int P1>
@@ -288,6 +303,7 @@ template <int KIND, int D, int P1, class R>
 struct GradCfg {
   static constexpr int NCU = Phys<KIND, D>::NCU, NN = ipow(P1, D), NFP = ipow(P1, D - 1), NF = 2 * D, NV = 1 << D;
   static constexpr int BYTES = sizeof(R) * (NCU * NN + NF * NCU * D * NFP + GeoTab<D, P1>::SIZE) + 8 * NV * D;
+  static_assert(BYTES == grad_bytes(NCU, D, P1, sizeof(R)), "one formula for the host and the kernels");
   static constexpr int EPB = pick_epb<NN, BYTES>();
 };
 
@@ -300,6 +316,7 @@ struct ResidCfg {
   static constexpr int NQ = HASQ ? NCU * D : 1;
   static constexpr int BYTES = sizeof(V) * (NCU * NN + (HASQ ? NCU * D * NN : 0)) +
                                sizeof(R) * (NCU * D * NN + NF * NCU * NFP + GeoTab<D, P1>::SIZE) + 8 * NV * D;
+  static_assert(BYTES == resid_bytes(NCU, HASQ, MODE, D, P1, sizeof(R)), "one formula for the host and the kernels");
   static constexpr int EPB = pick_epb<NN, BYTES>();
   // the linear 3D FP64 instance needs 98 VGPRs unconstrained (4 waves per SIMD);
   // capping it at 96 for a fifth wave measured 6 us faster on the 32^3 p=3 JVP
@@ -390,7 +407,7 @@ k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const double* __restric
         const int kind = md.bc_kind[tag];
 #pragma unroll
         for (int c = 0; c < NCU; ++c) {
-          if (kind == LDG_BC_DIRICHLET)
+          if (kind == BC_DIRICHLET)
             uh[c] = (DATA && md.bdata) ? R(md.bdata[((int64_t)b * NCU + c) * NFP + f]) : R(0);
           else
             uh[c] = um[c];
@@ -632,14 +649,14 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const doub
         int tag = m.btag[b];
         tag = tag < 0 ? 0 : (tag >= md.nbc ? md.nbc - 1 : tag);
         const int kind = md.bc_kind[tag];
-        if (kind == LDG_BC_DIRICHLET) {
+        if (kind == BC_DIRICHLET) {
           // the state outside is the data g (zero tangent); the linear operator (MODE 0) sees g = 0
           V ub[NCU];
 #pragma unroll
           for (int c = 0; c < NCU; ++c)
             ub[c] = (MODE != 0 && md.bdata) ? T::mk(R(md.bdata[((int64_t)b * NCU + c) * NFP + ff])) : T::mk(R(0));
           num_flux<KIND, D, V, R>(md.mu, md.naux, um, qm, am, ub, qm, am, n, Fh);
-        } else if (kind == LDG_BC_NEUMANN) {
+        } else if (kind == BC_NEUMANN) {
 #pragma unroll
           for (int c = 0; c < NCU; ++c)
             Fh[c] = (MODE == 1 && md.bdata) ? T::mk(R(md.bdata[((int64_t)b * NCU + c) * NFP + ff])) : T::mk(R(0));

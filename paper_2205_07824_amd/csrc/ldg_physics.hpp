@@ -8,7 +8,7 @@
 
 namespace ldg {
 
-enum { K_POISSON = 0, K_CONVDIFF = 1, K_EULER = 2, K_NS = 3 };
+enum { K_POISSON = 0, K_CONVDIFF = 1, K_EULER = 2, K_NS = 3, K_USER = 4 };
 
 template <int KIND, int D>
 struct Phys {
@@ -17,6 +17,20 @@ struct Phys {
   static constexpr bool LINEAR = (KIND <= 1);
   static constexpr int NAUX = (KIND == K_CONVDIFF) ? 1 + D : (KIND == K_POISSON ? 1 : 0);
 };
+
+// User physics (a model compiled at run time): the source defines a struct
+// LdgUser with NCU, HASQ, NAUX and the templates flux<D>(mu, naux, u, q, a, f)
+// and numflux<D>(mu, naux, uL, qL, aL, uR, qR, aR, n, Fh), written once for
+// plain values and dual numbers like the built-in models below.
+#ifdef LDG_USER_PHYSICS
+template <int D>
+struct Phys<K_USER, D> {
+  static constexpr int NCU = ::LdgUser::NCU;
+  static constexpr bool HASQ = ::LdgUser::HASQ;
+  static constexpr bool LINEAR = false;
+  static constexpr int NAUX = ::LdgUser::NAUX;
+};
+#endif
 
 // physical flux; a = aux at the point (R), naux = number of aux fields present
 template <int KIND, int D, class V, class R>
@@ -27,7 +41,13 @@ __device__ inline void phys_flux(const double* mu, int naux, const V* u, const V
     R kap = R(mu[0]) * (naux >= 1 ? a[0] : R(1));
 #pragma unroll
     for (int k = 0; k < D; ++k) f[0][k] = kap * q[0][k];
-  } else if constexpr (KIND == K_CONVDIFF) {
+  }
+#ifdef LDG_USER_PHYSICS
+  else if constexpr (KIND == K_USER) {
+    ::LdgUser::template flux<D, V, R>(mu, naux, u, q, a, f);
+  }
+#endif
+  else if constexpr (KIND == K_CONVDIFF) {
     R kap = R(mu[0]) * a[0];
 #pragma unroll
     for (int k = 0; k < D; ++k) f[0][k] = kap * q[0][k] + a[1 + k] * u[0];
@@ -102,6 +122,12 @@ __device__ inline V wave_speed(R gam, const V* u, const R* n) {
 template <int KIND, int D, class V, class R>
 __device__ inline void num_flux(const double* mu, int naux, const V* uL, const V (*qL)[D], const R* aL,
                                 const V* uR, const V (*qR)[D], const R* aR, const R* n, V* Fh) {
+#ifdef LDG_USER_PHYSICS
+  if constexpr (KIND == K_USER) {
+    ::LdgUser::template numflux<D, V, R>(mu, naux, uL, qL, aL, uR, qR, aR, n, Fh);
+  } else
+#endif
+  {
   constexpr int NCU = Phys<KIND, D>::NCU;
   V fL[NCU][D], fR[NCU][D];
   phys_flux<KIND, D, V, R>(mu, naux, uL, qL, aL, fL);
@@ -131,6 +157,7 @@ __device__ inline void num_flux(const double* mu, int naux, const V* uL, const V
     if constexpr (KIND == K_NS) sig = sig + R(mu[3] / mu[1]);
 #pragma unroll
     for (int c = 0; c < NCU; ++c) Fh[c] += sig * (uL[c] - uR[c]);
+  }
   }
 }
 

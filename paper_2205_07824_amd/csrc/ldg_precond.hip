@@ -293,7 +293,7 @@ static ldg_status assemble_blocks(Model& md, const ldg_time* t, const double* u_
   const int NB = md.ncu * m.nn;
   const int64_t n = (int64_t)md.N();
   ldg_status st;
-  if (!md.linear && md.kind != LDG_MODEL_EULER) {
+  if (!md.linear && md.hasq) {
     st = op_grad(md, u_lin, md.d_q, false, true, s);
     if (st != LDG_OK) return st;
     if (probe == LDG_FP32) {

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libldg.so")
 
 LDG_OK, LDG_EINVAL, LDG_EUNSUPPORTED, LDG_EDEVICE, LDG_ENOMEM, LDG_ENOCONV, LDG_EBREAKDOWN = range(7)
 FP64, FP32, BF16_MFMA, FP16_MFMA, JVP_FD, BF16, FP16 = range(7)
-MODEL_POISSON, MODEL_CONVDIFF, MODEL_EULER, MODEL_NS = range(4)
+MODEL_POISSON, MODEL_CONVDIFF, MODEL_EULER, MODEL_NS, MODEL_USER = range(5)
 BC_DIRICHLET, BC_NEUMANN, BC_EXTRAP = range(3)
 
 _STATUS = {0: "OK", 1: "EINVAL", 2: "EUNSUPPORTED", 3: "EDEVICE", 4: "ENOMEM", 5: "ENOCONV", 6: "EBREAKDOWN"}
@@ -77,7 +77,7 @@ EXPORTED = ["ldg_last_error", "ldg_mesh_create", "ldg_mesh_info", "ldg_mesh_poin
             "ldg_precond_block_jacobi", "ldg_precond_apply", "ldg_precond_destroy", "ldg_gmres_solve",
             "ldg_newton_solve", "ldg_axpby", "ldg_norm2", "ldg_mlp_create", "ldg_mlp_destroy", "ldg_mlp_set_params",
             "ldg_mlp_get_params", "ldg_mlp_forward", "ldg_mlp_train_step", "ldg_mlp_gather_patches",
-            "ldg_precond_mlp"]
+            "ldg_precond_mlp", "ldg_model_create_user", "ldg_user_physics_check"]
 
 
 def lib():
@@ -116,6 +116,8 @@ def lib():
         "ldg_mlp_train_step": [vp, vp, vp, C.c_int64, C.c_float, C.POINTER(C.c_float), vp],
         "ldg_mlp_gather_patches": [vp, vp, vp, vp, C.c_int64, vp, vp, vp, vp],
         "ldg_precond_mlp": [vp, vp, vp, C.c_int, C.POINTER(vp)],
+        "ldg_model_create_user": [vp, C.POINTER(_ModelDesc), C.c_char_p, C.c_int, vp, C.POINTER(vp)],
+        "ldg_user_physics_check": [C.c_char_p, C.c_int, C.c_int, C.c_int, C.c_int],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -203,7 +205,11 @@ def _time(t):
 
 
 class Model:
-    def __init__(self, mesh, kind, ncu, mu, aux=None, src=None, bdata=None, bc_kind=(0,)):
+    """A model bound to a mesh.  kind = MODEL_USER takes physics_source (the LdgUser struct, compiled at run time
+    by the library) and has_q."""
+
+    def __init__(self, mesh, kind, ncu, mu, aux=None, src=None, bdata=None, bc_kind=(0,), physics_source=None,
+                 has_q=True):
         self.mesh, self.kind, self.ncu = mesh, kind, ncu
         dev = torch.device("cuda")
         to = lambda a: None if a is None else torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64).to(dev).contiguous()
@@ -216,7 +222,11 @@ class Model:
                        _ptr(self.aux), _ptr(self.src), _ptr(self.bdata), len(self._bc),
                        self._bc.ctypes.data_as(C.POINTER(C.c_int32)))
         h = C.c_void_p()
-        _check(lib().ldg_model_create(mesh.h, C.byref(d), _stream(), C.byref(h)), "ldg_model_create")
+        if physics_source is not None:
+            _check(lib().ldg_model_create_user(mesh.h, C.byref(d), physics_source.encode(), int(has_q), _stream(),
+                                               C.byref(h)), "ldg_model_create_user")
+        else:
+            _check(lib().ldg_model_create(mesh.h, C.byref(d), _stream(), C.byref(h)), "ldg_model_create")
         self.h = h
         self.N = mesh.size(ncu)
 
@@ -378,6 +388,11 @@ def newton(model, u, time=None, maxit=20, rtol=1e-8, atol=0.0, eta=1e-3, bj_refr
     if check and status != LDG_OK:
         _check(status, "ldg_newton_solve")
     return u, st.as_dict(), status
+
+
+def user_physics_check(source, nd, p, ncu, has_q=True):
+    """Compile a physics source on the host only (no device); raises LDGError with the compiler's log."""
+    _check(lib().ldg_user_physics_check(source.encode(), nd, p, ncu, int(has_q)), "ldg_user_physics_check")
 
 
 def axpby(a, x, b, y):

@@ -1,0 +1,34 @@
+"""Run-time compiled physics: host-side compile checks (no GPU needed)."""
+import pytest
+
+from tests import user_physics as U
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2205_07824_amd import ldg
+    ldg.lib()
+    return ldg
+
+
+@pytest.mark.parametrize("src,nd,p,ncu,has_q", [(U.EULER_2D, 2, 4, 4, False), (U.NONLINEAR_DIFFUSION, 3, 2, 1, True)])
+def test_physics_sources_compile(L, src, nd, p, ncu, has_q):
+    L.user_physics_check(src, nd, p, ncu, has_q)
+
+
+def test_broken_source_returns_the_compiler_log(L):
+    with pytest.raises(L.LDGError) as e:
+        L.user_physics_check(U.BROKEN, 2, 3, 1, True)
+    assert e.value.status == 1 and "physics_source:6" in str(e.value) and "error" in str(e.value)
+
+
+@pytest.mark.parametrize("ncu,has_q", [(5, False), (4, True)])
+def test_declared_sizes_must_match_the_source(L, ncu, has_q):
+    with pytest.raises(L.LDGError) as e:
+        L.user_physics_check(U.EULER_2D, 2, 4, ncu, has_q)
+    assert "differs" in str(e.value)
+
+
+def test_orders_without_kernels_rejected(L):
+    with pytest.raises(L.LDGError):
+        L.user_physics_check(U.EULER_2D, 3, 4, 4, False)

@@ -1,0 +1,88 @@
+"""Physics sources for run-time compiled models (test inputs).
+
+EULER_2D re-states the compressible Euler flux and the local Lax-Friedrichs
+flux in the user format, so that a compiled model can be compared with the
+built-in Euler model.  NONLINEAR_DIFFUSION is a model the library does not
+have: f = kappa(u) q with kappa(u) = mu0 (1 + mu2 u^2), central flux plus an
+interior penalty mu1 mu0 (u- - u+); with mu2 = 0 it is the built-in Poisson
+operator without reaction.
+"""
+
+EULER_2D = r"""
+struct LdgUser {
+  static constexpr int NCU = 4;
+  static constexpr bool HASQ = false;
+  static constexpr int NAUX = 0;
+  template <int D, class V, class R>
+  __device__ static void flux(const double* mu, int, const V* u, const V (*)[D], const R*, V (*f)[D]) {
+    const R gam = R(mu[0]);
+    const V rho = u[0], E = u[D + 1];
+    const V rinv = VT<V>::mk(R(1)) / rho;
+    V vel[D];
+    V ke = VT<V>::mk(R(0));
+    for (int k = 0; k < D; ++k) { vel[k] = u[1 + k] * rinv; ke += u[1 + k] * vel[k]; }
+    const V p = (gam - R(1)) * (E - R(0.5) * ke);
+    for (int k = 0; k < D; ++k) {
+      f[0][k] = u[1 + k];
+      for (int i = 0; i < D; ++i) {
+        f[1 + i][k] = u[1 + i] * vel[k];
+        if (i == k) f[1 + i][k] += p;
+      }
+      f[D + 1][k] = (E + p) * vel[k];
+    }
+  }
+  template <int D, class V, class R>
+  __device__ static V speed(R gam, const V* u, const R* n) {
+    const V rinv = VT<V>::mk(R(1)) / u[0];
+    V vn = VT<V>::mk(R(0)), ke = VT<V>::mk(R(0));
+    for (int k = 0; k < D; ++k) { vn += (u[1 + k] * rinv) * n[k]; ke += u[1 + k] * u[1 + k] * rinv; }
+    const V p = (gam - R(1)) * (u[D + 1] - R(0.5) * ke);
+    return vabs(vn) + vsqrt(gam * p * rinv);
+  }
+  template <int D, class V, class R>
+  __device__ static void numflux(const double* mu, int naux, const V* uL, const V (*qL)[D], const R* aL,
+                                 const V* uR, const V (*qR)[D], const R* aR, const R* n, V* Fh) {
+    V fL[NCU][D], fR[NCU][D];
+    flux<D, V, R>(mu, naux, uL, qL, aL, fL);
+    flux<D, V, R>(mu, naux, uR, qR, aR, fR);
+    const V sig = R(0.5) * vmax(speed<D, V, R>(R(mu[0]), uL, n), speed<D, V, R>(R(mu[0]), uR, n));
+    for (int c = 0; c < NCU; ++c) {
+      V s = R(0.5) * (fL[c][0] + fR[c][0]) * n[0];
+      for (int k = 1; k < D; ++k) s += R(0.5) * (fL[c][k] + fR[c][k]) * n[k];
+      Fh[c] = s + sig * (uL[c] - uR[c]);
+    }
+  }
+};
+"""
+
+NONLINEAR_DIFFUSION = r"""
+struct LdgUser {
+  static constexpr int NCU = 1;
+  static constexpr bool HASQ = true;
+  static constexpr int NAUX = 0;
+  template <int D, class V, class R>
+  __device__ static void flux(const double* mu, int, const V* u, const V (*q)[D], const R*, V (*f)[D]) {
+    const V kap = R(mu[0]) * (VT<V>::mk(R(1)) + R(mu[2]) * u[0] * u[0]);
+    for (int k = 0; k < D; ++k) f[0][k] = kap * q[0][k];
+  }
+  template <int D, class V, class R>
+  __device__ static void numflux(const double* mu, int naux, const V* uL, const V (*qL)[D], const R* aL,
+                                 const V* uR, const V (*qR)[D], const R* aR, const R* n, V* Fh) {
+    V fL[1][D], fR[1][D];
+    flux<D, V, R>(mu, naux, uL, qL, aL, fL);
+    flux<D, V, R>(mu, naux, uR, qR, aR, fR);
+    V s = R(0.5) * (fL[0][0] + fR[0][0]) * n[0];
+    for (int k = 1; k < D; ++k) s += R(0.5) * (fL[0][k] + fR[0][k]) * n[k];
+    Fh[0] = s + R(mu[1] * mu[0]) * (uL[0] - uR[0]);
+  }
+};
+"""
+
+BROKEN = r"""
+struct LdgUser {
+  static constexpr int NCU = 1;
+  static constexpr bool HASQ = true;
+  static constexpr int NAUX = 0;
+  this is not C++;
+};
+"""
