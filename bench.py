@@ -105,8 +105,18 @@ def other_workloads(ldg, I, log):
         e = event_time(lambda: md.jvp(u, v, time=t, out=Jv, prec=pr), 20)
         res[f"euler2d_p4_256sq_jvp_{nm}_gdofs"] = round(md.N / e / 1e9, 3)
     res["euler2d_p4_256sq_dof"] = md.N
+    # the same physics as a run-time compiled model (user source, hipRTC at model creation)
+    sys.path.insert(0, ROOT)
+    from tests import user_physics as UP
+    t0 = time.perf_counter()
+    mu_ = ldg.Model(m, ldg.MODEL_USER, 4, [1.4], physics_source=UP.EULER_2D, has_q=False)
+    res["euler2d_p4_user_physics_compile_s"] = round(time.perf_counter() - t0, 2)
+    for nm, pr in (("fp64", ldg.FP64), ("fp32", ldg.FP32)):
+        mu_.jvp(u, v, time=t, out=Jv, prec=pr)
+        e = event_time(lambda: mu_.jvp(u, v, time=t, out=Jv, prec=pr), 20)
+        res[f"euler2d_p4_256sq_user_physics_jvp_{nm}_gdofs"] = round(md.N / e / 1e9, 3)
     log("euler", res)
-    del md, m, u, v, Jv
+    del md, mu_, m, u, v, Jv
     torch.cuda.empty_cache()
     # 3D Navier-Stokes Taylor-Green vortex, p=3, periodic 64^3 on (0, 2 pi)^3, Re 1600, Mach 0.1, Pr 0.71
     L = 2 * np.pi
