@@ -419,6 +419,7 @@ static OMesh* build_mesh(int nd, int p, int nq, long nvert, const double* vert, 
 // kind 1: convection-diff.  f = kappa q + b u,           s = src
 // kind 2: Euler             f = inviscid flux,           s = src
 // kind 3: Navier-Stokes     f = inviscid - viscous(u, grad u = -q)
+// kind 4: shallow water     f = (h v, h v v^T + g h^2/2 I), g = mu[0]
 // mu: Poisson [kappa0, tau, lambda]; conv-diff [kappa0, tau];
 //     Euler [gamma]; NS [gamma, Re, Pr, tau]
 // aux (nodal): Poisson [kappa-factor]; conv-diff [kappa, b_1..b_nd]
@@ -447,6 +448,15 @@ static void phys_flux(const OModel& md, const T* u, const T* q, const double* a,
   } else if (md.kind == 1) {
     double kap = mu_or(md, 0, 1.0) * a[0];
     for (int k = 0; k < nd; ++k) f[k] = kap * q[k] + a[1 + k] * u[0];
+  } else if (md.kind == 4) {
+    // shallow water, u = (h, h v): f = (h v, h v v^T + g h^2 / 2 I), g = mu[0]
+    const double g = mu_or(md, 0, 1.0);
+    T h = u[0];
+    T half_gh2 = 0.5 * g * h * h;
+    for (int k = 0; k < nd; ++k) {
+      f[0 * nd + k] = u[1 + k];
+      for (int i = 0; i < nd; ++i) f[(1 + i) * nd + k] = u[1 + i] * u[1 + k] / h + (i == k ? half_gh2 : T(0.0));
+    }
   } else {
     const double gam = mu_or(md, 0, 1.4);
     const int ne = nd + 1;
@@ -498,6 +508,12 @@ static void phys_flux(const OModel& md, const T* u, const T* q, const double* a,
 template <class T>
 static T wave_speed(const OModel& md, const T* u, const double* n) {
   const int nd = md.nd;
+  if (md.kind == 4) {
+    // shallow water: |v.n| + sqrt(g h)
+    T vn = T(0.0);
+    for (int k = 0; k < nd; ++k) vn += u[1 + k] / u[0] * n[k];
+    return fabs(vn) + sqrt(mu_or(md, 0, 1.0) * u[0]);
+  }
   const double gam = mu_or(md, 0, 1.4);
   T rho = u[0], E = u[nd + 1];
   T vn = T(0.0), ke = T(0.0);
@@ -687,7 +703,7 @@ static void compute_q(const OMesh& M, const OModel& md, const T* u, long K, T* q
   for (size_t i = 0; i < b.size(); ++i) qK[i] = b[i];
 }
 
-static bool model_has_q(const OModel& md) { return md.kind != 2; }
+static bool model_has_q(const OModel& md) { return md.kind != 2 && md.kind != 4; }
 
 // O6 + O7: residual G_K of element K given q on K and on its face neighbours
 template <class T>
@@ -842,8 +858,9 @@ static OModel to_model(const OMesh& M, const ldgo_model_desc* d) {
   md.aux = d->aux; md.src = d->src; md.bdata = d->bdata;
   md.bc_kind.assign(d->bc_kind, d->bc_kind + d->nbc);
   md.a0 = d->a0; md.r = d->r;
-  if (md.kind < 0 || md.kind > 3) throw std::runtime_error("unknown model");
-  if ((md.kind <= 1 && md.ncu != 1) || (md.kind >= 2 && md.ncu != M.nd + 2))
+  if (md.kind < 0 || md.kind > 4) throw std::runtime_error("unknown model");
+  if ((md.kind <= 1 && md.ncu != 1) || ((md.kind == 2 || md.kind == 3) && md.ncu != M.nd + 2) ||
+      (md.kind == 4 && md.ncu != M.nd + 1))
     throw std::runtime_error("ncu inconsistent with the model");
   if (md.kind == 1 && md.naux != 1 + M.nd) throw std::runtime_error("convection-diffusion needs aux = [kappa, b]");
   return md;

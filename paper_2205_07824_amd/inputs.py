@@ -13,6 +13,7 @@ Workload shapes follow the configurations the method is exercised on:
   manufactured exp(x+y+z) sin(pi x y z);
 * 2D Euler, periodic [0,20]^2, superposed isentropic vortices;
 * 3D Navier-Stokes Taylor-Green vortex on the periodic (0,2 pi)^3 box;
+* shallow-water Bickley jet on the periodic (-2 pi, 2 pi)^2 box;
 * 2D convection-diffusion with a log-normal random kappa and a
   divergence-free velocity.
 """
@@ -209,6 +210,30 @@ def isentropic_vortices(x, centres, L=20.0, gamma=1.4, beta=5.0, mach=0.5):
     vy = dv
     E = p / (gamma - 1.0) + 0.5 * rho * (vx * vx + vy * vy)
     return np.stack([rho, rho * vx, rho * vy, E], axis=-1)
+
+
+def bickley_jet(x, seed=0, eps=0.01, nmodes=4, L=4.0 * math.pi):
+    """Shallow-water Bickley jet on the periodic box (-L/2, L/2)^2 (the paper's second convection workload).
+
+    Depth h = 1 and velocity u = sech^2(y), v = 0, plus a slight seeded
+    perturbation of the velocity: eps times a sum of nmodes x-periodic modes
+    (wavenumbers 1..nmodes in units of 2 pi / L, random phases and amplitudes)
+    localized on the jet by exp(-y^2).  Returns [.., 3] = (h, h u, h v)."""
+    X, Y = x[..., 0], x[..., 1]
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0.0, 2.0 * np.pi, (2, nmodes))
+    amp = rng.uniform(0.5, 1.0, (2, nmodes))
+    env = np.exp(-Y * Y)
+    du = np.zeros(X.shape)
+    dv = np.zeros(X.shape)
+    for k in range(nmodes):
+        w = 2.0 * np.pi * (k + 1) / L
+        du += amp[0, k] * np.cos(w * X + ph[0, k])
+        dv += amp[1, k] * np.sin(w * X + ph[1, k])
+    h = np.ones(X.shape)
+    vx = 1.0 / np.cosh(Y) ** 2 + eps * env * du
+    vy = eps * env * dv
+    return np.stack([h, h * vx, h * vy], axis=-1)
 
 
 def taylor_green(x, gamma=1.4, mach=0.1):

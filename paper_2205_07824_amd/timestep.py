@@ -43,7 +43,7 @@ def euler_cfl_dt(U, nd, h, cfl, gamma=1.4):
 
 def bdf_steps(model, u0, dt, nsteps, restart=50, eta=1e-3, rtol=1e-8, jvp_prec=ldg.FP64, bj_prec=ldg.FP64,
               per_variable=False, newton_maxit=10, lin_maxit=5000, orth=ldg.ORTH_DCGS2, bj_refresh=1,
-              log=None):
+              log=None, atol=0.0):
     """Advance u0 by nsteps implicit steps; returns (u, per-step statistics).  bj_refresh: 1 rebuilds the
     block-Jacobi preconditioner at every Newton iterate, 2 once per step (at its first iterate)."""
     u = u0.clone()
@@ -60,7 +60,8 @@ def bdf_steps(model, u0, dt, nsteps, restart=50, eta=1e-3, rtol=1e-8, jvp_prec=l
             pc = ldg.BlockJacobi(model, u_lin=u, time=t, per_variable=per_variable, prec=bj_prec)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        u, st, status = ldg.newton(model, u, time=t, rtol=rtol, eta=eta, maxit=newton_maxit, bj_refresh=bj_refresh,
+        u, st, status = ldg.newton(model, u, time=t, rtol=rtol, atol=atol, eta=eta, maxit=newton_maxit,
+                                   bj_refresh=bj_refresh,
                                    bj_per_variable=per_variable, bj_prec=bj_prec, pc=pc, restart=restart,
                                    lin_maxit=lin_maxit, jvp_prec=jvp_prec, orth=orth, check=False)
         torch.cuda.synchronize()
@@ -105,9 +106,9 @@ def dirk_tableau(name):
 
 def dirk_steps(model, u0, dt, nsteps, scheme="dirk33", restart=50, eta=1e-3, rtol=1e-8, jvp_prec=ldg.FP64,
                bj_prec=ldg.FP64, per_variable=False, newton_maxit=10, lin_maxit=5000, orth=ldg.ORTH_DCGS2,
-               bj_refresh=1, log=None):
+               bj_refresh=1, log=None, atol=0.0):
     """Advance u0 by nsteps steps of a DIRK scheme (dirk_tableau); returns (u, per-step statistics).  Each
-    stage starts Newton from the previous stage value."""
+    stage starts Newton from the previous stage value and stops at ||G|| <= max(rtol ||G_0||, atol)."""
     A, b = dirk_tableau(scheme)
     s = len(b)
     Ainv = np.linalg.inv(np.asarray(A, dtype=np.float64))
@@ -132,7 +133,7 @@ def dirk_steps(model, u0, dt, nsteps, scheme="dirk33", restart=50, eta=1e-3, rto
                 pc = ldg.BlockJacobi(model, u_lin=U, time=t, per_variable=per_variable, prec=bj_prec)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            U, st, status = ldg.newton(model, U, time=t, rtol=rtol, eta=eta, maxit=newton_maxit,
+            U, st, status = ldg.newton(model, U, time=t, rtol=rtol, atol=atol, eta=eta, maxit=newton_maxit,
                                        bj_refresh=bj_refresh, bj_per_variable=per_variable, bj_prec=bj_prec, pc=pc,
                                        restart=restart, lin_maxit=lin_maxit, jvp_prec=jvp_prec, orth=orth,
                                        check=False)

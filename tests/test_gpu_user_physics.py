@@ -2,6 +2,9 @@
 
 * A user source re-stating the Euler equations against the built-in Euler
   model and the oracle: residual and JVP in FP64 and FP32, and one implicit step.
+* The shallow-water system as a user source (the paper's second convection
+  workload, a Bickley jet) against the oracle's shallow-water model: residual
+  and JVP in FP64 and FP32, and a DIRK(3,3) step.
 * A model the library does not have (nonlinear diffusion, kappa(u) =
   mu0 (1 + mu2 u^2)): at mu2 = 0 against the built-in Poisson operator; at
   mu2 > 0 discrete conservation on a periodic mesh (the fluxes are
@@ -116,3 +119,50 @@ def test_user_diffusion_conservation_and_tangent(L):
     # the nonlinearity is active: the tangent differs from the frozen-coefficient operator
     _, lin, _ = _diffusion(L, 0.0)
     assert rel(Jv, lin.jvp(dev(u0), dev(v0)).cpu().numpy()) > 1e-2
+
+
+def _jet_case(n=4, p=3, g=100.0, seed=3):
+    import oracle as O
+    L = 4.0 * np.pi
+    box = I.box_mesh(2, n, lo=(-L / 2, -L / 2), hi=(L / 2, L / 2), periodic=(True, True))
+    om = O.Mesh(box, p)
+    xn, _, _, _ = om.points()
+    U0 = I.bickley_jet(xn, seed=seed, eps=0.05).transpose(0, 2, 1).reshape(-1)
+    rng = np.random.default_rng(seed)
+    u = U0 + 0.02 * rng.uniform(-1, 1, U0.shape)   # generic (off the symmetric state)
+    return box, om, U0, u, rng.uniform(-1, 1, U0.shape)
+
+
+def test_user_shallow_water_matches_oracle(L):
+    import oracle as O
+    g, dt = 100.0, 0.05
+    box, om, U0, u, v = _jet_case(g=g)
+    _say("case shallow-water jet")
+    m = L.Mesh(box, 3)
+    md = L.Model(m, L.MODEL_USER, 3, [g], bc_kind=(0,), physics_source=U.SHALLOW_WATER_2D, has_q=False)
+    r1 = U0.copy()
+    t = L.Time(a0=1.0 / dt, r1=dev(r1), c1=1.0 / dt)
+    omd = O.Model(O.MODEL_SHALLOW_WATER, 3, [g], a0=1.0 / dt, r=r1 / dt)
+    G_ref, Jv_ref = om.residual(omd, u), om.jvp(omd, u, v)
+    for prec, tol in ((L.FP64, 1e-12), (L.FP32, 1e-5)):
+        G = md.residual(dev(u), time=t, prec=prec).cpu().numpy()
+        Jv = md.jvp(dev(u), dev(v), time=t, prec=prec).cpu().numpy()
+        _say("prec", prec, "residual", rel(G, G_ref), "jvp", rel(Jv, Jv_ref))
+        assert rel(G, G_ref) < tol and rel(Jv, Jv_ref) < tol
+
+
+def test_user_shallow_water_dirk_step_matches_oracle(L):
+    import oracle as O
+    from paper_2205_07824_amd import timestep as TS
+    g, dt = 100.0, 0.05
+    box, om, U0, u, v = _jet_case(g=g)
+    _say("case shallow-water jet dirk33")
+    m = L.Mesh(box, 3)
+    md = L.Model(m, L.MODEL_USER, 3, [g], bc_kind=(0,), physics_source=U.SHALLOW_WATER_2D, has_q=False)
+    A, b = O.dirk_tableau("dirk33")
+    u_ref = O.dirk_step(om, O.Model(O.MODEL_SHALLOW_WATER, 3, [g]), U0.copy(), dt, A, b)
+    ug, stats = TS.dirk_steps(md, dev(U0.copy()), dt, 1, scheme="dirk33", restart=50, eta=1e-10, rtol=1e-12,
+                              newton_maxit=12)
+    _say("dirk stats", stats)
+    assert stats[0]["converged"]
+    assert rel(ug.cpu().numpy(), u_ref) < 1e-8

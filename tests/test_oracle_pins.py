@@ -328,6 +328,54 @@ def test_euler_flux_closed_form():
     assert np.abs(f - expect).max() < 1e-14
 
 
+# ---------------------------------------------------------------- shallow water (second convection model)
+def test_shallow_water_flux_closed_form():
+    # h = 2, v = (1, -0.5), g = 10: f = (h v, h v v^T + g h^2/2 I) with g h^2 / 2 = 20
+    md = O.Model(O.MODEL_SHALLOW_WATER, 3, [10.0])
+    f = O.point_flux(md, 2, [2.0, 2.0, -1.0], np.zeros(6), np.zeros(4))
+    expect = np.array([[2.0, -1.0], [22.0, -1.0], [-1.0, 20.5]])
+    assert np.abs(f - expect).max() < 1e-14
+
+
+def test_shallow_water_lax_friedrichs_flux():
+    md = O.Model(O.MODEL_SHALLOW_WATER, 3, [9.0])
+    uL, uR, n = np.array([1.0, 0.5, 0.0]), np.array([4.0, 0.0, 2.0]), np.array([0.6, 0.8])
+    fL = O.point_flux(md, 2, uL, np.zeros(6), np.zeros(4))
+    fR = O.point_flux(md, 2, uR, np.zeros(6), np.zeros(4))
+    # |v.n| + sqrt(g h): left 0.5*0.6 + 3 = 3.3, right 0.5*0.8 + 6 = 6.4
+    expect = 0.5 * (fL + fR) @ n + 0.5 * 6.4 * (uL - uR)
+    F = O.point_numflux(md, 2, uL, np.zeros(6), np.zeros(4), uR, np.zeros(6), np.zeros(4), n)
+    assert np.abs(F - expect).max() < 1e-14
+    F2 = O.point_numflux(md, 2, uR, np.zeros(6), np.zeros(4), uL, np.zeros(6), np.zeros(4), -n)
+    assert np.abs(F + F2).max() < 1e-14
+
+
+@pytest.mark.parametrize("state", [(1.0, 0.0, 0.0), (1.3, 0.4, -0.2)])
+def test_shallow_water_free_stream_perturbed_periodic(state):
+    # a constant state (lake at rest, uniform flow) is steady on perturbed periodic quads
+    box = I.box_mesh(2, 3, periodic=(True, True), perturb=0.05, seed=4)
+    m = O.Mesh(box, 3)
+    md = O.Model(O.MODEL_SHALLOW_WATER, 3, [100.0])
+    u = np.broadcast_to(np.array(state)[None, :, None], (m.E, 3, m.nn)).reshape(-1).copy()
+    assert np.abs(m.residual(md, u)).max() < 1e-11
+
+
+def test_conservation_shallow_water_periodic():
+    box = I.box_mesh(2, 4, periodic=(True, True), perturb=0.05, seed=6)
+    m = O.Mesh(box, 3)
+    md = O.Model(O.MODEL_SHALLOW_WATER, 3, [50.0])
+    rng = np.random.default_rng(2)
+    u = np.zeros((m.E, 3, m.nn))
+    u[:, 0] = 1 + 0.2 * rng.uniform(-1, 1, (m.E, m.nn))
+    u[:, 1:] = 0.3 * rng.uniform(-1, 1, (m.E, 2, m.nn))
+    R = m.residual(md, u.reshape(-1)).reshape(m.E, 3, m.nn)
+    v = rng.uniform(-1, 1, u.shape)
+    Jv = m.jvp(md, u.reshape(-1), v.reshape(-1)).reshape(m.E, 3, m.nn)
+    for c in range(3):
+        assert abs(R[:, c].sum()) < 1e-12 * np.abs(R[:, c]).sum()
+        assert abs(Jv[:, c].sum()) < 1e-12 * np.abs(Jv[:, c]).sum()
+
+
 def test_ns_viscous_flux_couette():
     # simple shear u = (a y, 0), constant rho, p: viscous x-momentum flux in y is mu * a
     md = O.Model(O.MODEL_NS, 4, [1.4, 10.0, 0.72, 1.0])

@@ -5,7 +5,8 @@ flux in the user format, so that a compiled model can be compared with the
 built-in Euler model.  NONLINEAR_DIFFUSION is a model the library does not
 have: f = kappa(u) q with kappa(u) = mu0 (1 + mu2 u^2), central flux plus an
 interior penalty mu1 mu0 (u- - u+); with mu2 = 0 it is the built-in Poisson
-operator without reaction.
+operator without reaction.  SHALLOW_WATER_2D is the shallow-water system
+(h, h v) with the local Lax-Friedrichs flux (speed |v.n| + sqrt(g h)).
 """
 
 EULER_2D = r"""
@@ -74,6 +75,45 @@ struct LdgUser {
     V s = R(0.5) * (fL[0][0] + fR[0][0]) * n[0];
     for (int k = 1; k < D; ++k) s += R(0.5) * (fL[0][k] + fR[0][k]) * n[k];
     Fh[0] = s + R(mu[1] * mu[0]) * (uL[0] - uR[0]);
+  }
+};
+"""
+
+SHALLOW_WATER_2D = r"""
+struct LdgUser {
+  static constexpr int NCU = 3;
+  static constexpr bool HASQ = false;
+  static constexpr int NAUX = 0;
+  // u = (h, h v); g = mu[0]
+  template <int D, class V, class R>
+  __device__ static void flux(const double* mu, int, const V* u, const V (*)[D], const R*, V (*f)[D]) {
+    const V hinv = VT<V>::mk(R(1)) / u[0];
+    const V pg = R(0.5 * mu[0]) * u[0] * u[0];
+    for (int k = 0; k < D; ++k) {
+      f[0][k] = u[1 + k];
+      const V vk = u[1 + k] * hinv;
+      for (int i = 0; i < D; ++i) f[1 + i][k] = u[1 + i] * vk + (i == k ? pg : VT<V>::mk(R(0)));
+    }
+  }
+  template <int D, class V, class R>
+  __device__ static V speed(R g, const V* u, const R* n) {
+    const V hinv = VT<V>::mk(R(1)) / u[0];
+    V vn = VT<V>::mk(R(0));
+    for (int k = 0; k < D; ++k) vn += (u[1 + k] * hinv) * n[k];
+    return vabs(vn) + vsqrt(g * u[0]);
+  }
+  template <int D, class V, class R>
+  __device__ static void numflux(const double* mu, int naux, const V* uL, const V (*qL)[D], const R* aL,
+                                 const V* uR, const V (*qR)[D], const R* aR, const R* n, V* Fh) {
+    V fL[NCU][D], fR[NCU][D];
+    flux<D, V, R>(mu, naux, uL, qL, aL, fL);
+    flux<D, V, R>(mu, naux, uR, qR, aR, fR);
+    const V sig = R(0.5) * vmax(speed<D, V, R>(R(mu[0]), uL, n), speed<D, V, R>(R(mu[0]), uR, n));
+    for (int c = 0; c < NCU; ++c) {
+      V s = R(0.5) * (fL[c][0] + fR[c][0]) * n[0];
+      for (int k = 1; k < D; ++k) s += R(0.5) * (fL[c][k] + fR[c][k]) * n[k];
+      Fh[c] = s + sig * (uL[c] - uR[c]);
+    }
   }
 };
 """
