@@ -3,9 +3,9 @@
 EULER_2D re-states the compressible Euler flux and the local Lax-Friedrichs
 flux in the user format, so that a compiled model can be compared with the
 built-in Euler model.  NONLINEAR_DIFFUSION is a model the library does not
-have: f = kappa(u) q with kappa(u) = mu0 (1 + mu2 u^2), central flux plus an
-interior penalty mu1 mu0 (u- - u+); with mu2 = 0 it is the built-in Poisson
-operator without reaction.  SHALLOW_WATER_2D is the shallow-water system
+have: f = kappa q with kappa = mu0 kappa(x) (1 + mu2 u^2) (kappa(x) an optional
+aux field), central flux plus an interior penalty mu1 mu0 {kappa(x)} (u- - u+);
+with mu2 = 0 it is the built-in Poisson operator without reaction.  SHALLOW_WATER_2D is the shallow-water system
 (h, h v) with the local Lax-Friedrichs flux (speed |v.n| + sqrt(g h)).
 """
 
@@ -60,10 +60,11 @@ NONLINEAR_DIFFUSION = r"""
 struct LdgUser {
   static constexpr int NCU = 1;
   static constexpr bool HASQ = true;
-  static constexpr int NAUX = 0;
+  static constexpr int NAUX = 1;   // optional kappa(x) field
   template <int D, class V, class R>
-  __device__ static void flux(const double* mu, int, const V* u, const V (*q)[D], const R*, V (*f)[D]) {
-    const V kap = R(mu[0]) * (VT<V>::mk(R(1)) + R(mu[2]) * u[0] * u[0]);
+  __device__ static void flux(const double* mu, int naux, const V* u, const V (*q)[D], const R* a, V (*f)[D]) {
+    const R kx = naux >= 1 ? a[0] : R(1);
+    const V kap = (R(mu[0]) * kx) * (VT<V>::mk(R(1)) + R(mu[2]) * u[0] * u[0]);
     for (int k = 0; k < D; ++k) f[0][k] = kap * q[0][k];
   }
   template <int D, class V, class R>
@@ -74,7 +75,8 @@ struct LdgUser {
     flux<D, V, R>(mu, naux, uR, qR, aR, fR);
     V s = R(0.5) * (fL[0][0] + fR[0][0]) * n[0];
     for (int k = 1; k < D; ++k) s += R(0.5) * (fL[0][k] + fR[0][k]) * n[k];
-    Fh[0] = s + R(mu[1] * mu[0]) * (uL[0] - uR[0]);
+    const R kbar = naux >= 1 ? R(0.5) * (aL[0] + aR[0]) : R(1);
+    Fh[0] = s + (R(mu[1]) * R(mu[0]) * kbar) * (uL[0] - uR[0]);
   }
 };
 """
