@@ -436,6 +436,18 @@ def main():
         print(json.dumps(out))
         return
 
+    # measured HBM copy bandwidth on this GPU in the same run (512 MiB device-to-device copy, read + write
+    # bytes per second), reported beside the 8 TB/s datasheet peak the roofline fraction uses
+    a_ = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    c_ = torch.empty_like(a_)
+    c_.copy_(a_)
+    e_copy = event_time(lambda: c_.copy_(a_), 20)
+    copy_gbs = 2.0 * a_.numel() * 8 / e_copy / 1e9
+    out["roofline"]["measured_copy_gbs"] = round(copy_gbs, 1)
+    out["roofline"]["frac_of_measured_copy"] = round(achieved / copy_gbs, 4)
+    del a_, c_
+    torch.cuda.empty_cache()
+
     # other precisions / operator evaluations (events, outside the timed steps)
     extra = {}
     e32 = event_time(lambda: md.jvp(None, v, out=Jv, prec=ldg.FP32), 50)
