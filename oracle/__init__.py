@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ldg_oracle.cpp")
 _LIB = os.path.join(_HERE, "libldg_oracle.so")
 
-MODEL_POISSON, MODEL_CONVDIFF, MODEL_EULER, MODEL_NS, MODEL_SHALLOW_WATER = 0, 1, 2, 3, 4
+MODEL_POISSON, MODEL_CONVDIFF, MODEL_EULER, MODEL_NS, MODEL_SHALLOW_WATER, MODEL_WAVE = 0, 1, 2, 3, 4, 5
 BC_DIRICHLET, BC_NEUMANN, BC_EXTRAP = 0, 1, 2
 
 

@@ -420,6 +420,7 @@ static OMesh* build_mesh(int nd, int p, int nq, long nvert, const double* vert, 
 // kind 2: Euler             f = inviscid flux,           s = src
 // kind 3: Navier-Stokes     f = inviscid - viscous(u, grad u = -q)
 // kind 4: shallow water     f = (h v, h v v^T + g h^2/2 I), g = mu[0]
+// kind 5: wave (first order) state (u, q): f = (c^2 q, u I), c^2 = mu[0]
 // mu: Poisson [kappa0, tau, lambda]; conv-diff [kappa0, tau];
 //     Euler [gamma]; NS [gamma, Re, Pr, tau]
 // aux (nodal): Poisson [kappa-factor]; conv-diff [kappa, b_1..b_nd]
@@ -448,6 +449,14 @@ static void phys_flux(const OModel& md, const T* u, const T* q, const double* a,
   } else if (md.kind == 1) {
     double kap = mu_or(md, 0, 1.0) * a[0];
     for (int k = 0; k < nd; ++k) f[k] = kap * q[k] + a[1 + k] * u[0];
+  } else if (md.kind == 5) {
+    // wave model as a first-order system, state (u, q): u_t + div(c^2 q) = 0, q_t + grad u = 0,
+    // i.e. f = (c^2 q, u I), c^2 = mu[0]
+    const double c2 = mu_or(md, 0, 1.0);
+    for (int k = 0; k < nd; ++k) {
+      f[0 * nd + k] = c2 * u[1 + k];
+      for (int i = 0; i < nd; ++i) f[(1 + i) * nd + k] = (i == k) ? u[0] : T(0.0);
+    }
   } else if (md.kind == 4) {
     // shallow water, u = (h, h v): f = (h v, h v v^T + g h^2 / 2 I), g = mu[0]
     const double g = mu_or(md, 0, 1.0);
@@ -508,6 +517,7 @@ static void phys_flux(const OModel& md, const T* u, const T* q, const double* a,
 template <class T>
 static T wave_speed(const OModel& md, const T* u, const double* n) {
   const int nd = md.nd;
+  if (md.kind == 5) return T(std::sqrt(mu_or(md, 0, 1.0)));   // wave speed c
   if (md.kind == 4) {
     // shallow water: |v.n| + sqrt(g h)
     T vn = T(0.0);
@@ -703,7 +713,7 @@ static void compute_q(const OMesh& M, const OModel& md, const T* u, long K, T* q
   for (size_t i = 0; i < b.size(); ++i) qK[i] = b[i];
 }
 
-static bool model_has_q(const OModel& md) { return md.kind != 2 && md.kind != 4; }
+static bool model_has_q(const OModel& md) { return md.kind <= 1 || md.kind == 3; }
 
 // O6 + O7: residual G_K of element K given q on K and on its face neighbours
 template <class T>
@@ -858,9 +868,9 @@ static OModel to_model(const OMesh& M, const ldgo_model_desc* d) {
   md.aux = d->aux; md.src = d->src; md.bdata = d->bdata;
   md.bc_kind.assign(d->bc_kind, d->bc_kind + d->nbc);
   md.a0 = d->a0; md.r = d->r;
-  if (md.kind < 0 || md.kind > 4) throw std::runtime_error("unknown model");
+  if (md.kind < 0 || md.kind > 5) throw std::runtime_error("unknown model");
   if ((md.kind <= 1 && md.ncu != 1) || ((md.kind == 2 || md.kind == 3) && md.ncu != M.nd + 2) ||
-      (md.kind == 4 && md.ncu != M.nd + 1))
+      ((md.kind == 4 || md.kind == 5) && md.ncu != M.nd + 1))
     throw std::runtime_error("ncu inconsistent with the model");
   if (md.kind == 1 && md.naux != 1 + M.nd) throw std::runtime_error("convection-diffusion needs aux = [kappa, b]");
   return md;

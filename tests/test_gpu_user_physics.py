@@ -190,3 +190,34 @@ def test_user_diffusion_with_aux_and_dirichlet_data_matches_builtin_poisson(L):
     ej = rel(user.jvp(u, v).cpu().numpy(), built.jvp(None, v).cpu().numpy())
     _say("user vs built-in with data: residual", eg, "jvp", ej)
     assert eg < 1e-12 and ej < 1e-12
+
+
+def test_user_wave_model_matches_oracle(L):
+    """The paper's wave model (q_t + grad u = 0, u_t + div(c^2 q) = 0) as a compiled first-order system
+    against the oracle's: residual and JVP in FP64 and FP32, and a DIRK(3,3) step of a plane wave."""
+    import oracle as O
+    from paper_2205_07824_amd import timestep as TS
+    c2, n, p, dt = 2.0, 4, 3, 0.02
+    box = I.box_mesh(2, n, periodic=(True, True), perturb=0.05, seed=2)
+    om = O.Mesh(box, p)
+    k = 2 * np.pi * np.array([1.0, 2.0])
+    th = om.points()[0] @ k
+    U0 = np.stack([-np.cos(th), -k[0] * np.cos(th), -k[1] * np.cos(th)], axis=1).reshape(-1)
+    rng = np.random.default_rng(6)
+    u, v = U0 + 0.1 * rng.uniform(-1, 1, U0.shape), rng.uniform(-1, 1, U0.shape)
+    m = L.Mesh(box, p)
+    md = L.Model(m, L.MODEL_USER, 3, [c2], bc_kind=(0,), physics_source=U.WAVE_2D, has_q=False)
+    t = L.Time(a0=1.0 / dt, r1=dev(U0), c1=1.0 / dt)
+    omd = O.Model(O.MODEL_WAVE, 3, [c2], a0=1.0 / dt, r=U0 / dt)
+    G_ref, Jv_ref = om.residual(omd, u), om.jvp(omd, u, v)
+    for prec, tol in ((L.FP64, 1e-12), (L.FP32, 1e-5)):
+        G = md.residual(dev(u), time=t, prec=prec).cpu().numpy()
+        Jv = md.jvp(dev(u), dev(v), time=t, prec=prec).cpu().numpy()
+        _say("wave prec", prec, "residual", rel(G, G_ref), "jvp", rel(Jv, Jv_ref))
+        assert rel(G, G_ref) < tol and rel(Jv, Jv_ref) < tol
+    A, b = O.dirk_tableau("dirk33")
+    u_ref = O.dirk_step(om, O.Model(O.MODEL_WAVE, 3, [c2]), U0.copy(), dt, A, b)
+    ug, stats = TS.dirk_steps(md, dev(U0.copy()), dt, 1, scheme="dirk33", restart=50, eta=1e-10, rtol=1e-12,
+                              newton_maxit=6)
+    assert stats[0]["converged"]
+    assert rel(ug.cpu().numpy(), u_ref) < 1e-8

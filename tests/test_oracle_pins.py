@@ -376,6 +376,42 @@ def test_conservation_shallow_water_periodic():
         assert abs(Jv[:, c].sum()) < 1e-12 * np.abs(Jv[:, c]).sum()
 
 
+# ---------------------------------------------------------------- wave model (first-order system)
+def test_wave_flux_closed_form():
+    # c^2 = 4, u = 0.5, q = (1, -2): f = (c^2 q, u I)
+    md = O.Model(O.MODEL_WAVE, 3, [4.0])
+    f = O.point_flux(md, 2, [0.5, 1.0, -2.0], np.zeros(6), np.zeros(4))
+    assert np.abs(f - np.array([[4.0, -8.0], [0.5, 0.0], [0.0, 0.5]])).max() < 1e-15
+
+
+def test_wave_free_stream_perturbed_periodic():
+    box = I.box_mesh(2, 3, periodic=(True, True), perturb=0.05, seed=4)
+    m = O.Mesh(box, 3)
+    md = O.Model(O.MODEL_WAVE, 3, [2.0])
+    u = np.broadcast_to(np.array([0.7, -0.3, 0.4])[None, :, None], (m.E, 3, m.nn)).reshape(-1).copy()
+    assert np.abs(m.residual(md, u)).max() < 1e-12
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_wave_plane_wave_consistency_rate(p):
+    # w = sin(k.x - c|k| t): u = w_t, q = -grad w solve u_t + div(c^2 q) = 0, q_t + grad u = 0.  The discrete
+    # time derivative -M^-1 R(I U) of the interpolated wave matches I(U_t) to O(h^p) at the nodes
+    c2 = 1.0
+    k = 2 * np.pi * np.array([1.0, 1.0])
+    om = np.sqrt(c2) * np.linalg.norm(k)
+    errs = []
+    for n in (8, 16):
+        m = O.Mesh(I.box_mesh(2, n, periodic=(True, True)), p)
+        th = m.points()[0] @ k
+        U = np.stack([-om * np.cos(th), -k[0] * np.cos(th), -k[1] * np.cos(th)], axis=1)
+        Ut = np.stack([-om ** 2 * np.sin(th), -k[0] * om * np.sin(th), -k[1] * om * np.sin(th)], axis=1)
+        R = m.residual(O.Model(O.MODEL_WAVE, 3, [c2]), U.reshape(-1))
+        e = R / m.mass_apply(3, np.ones(U.size)) + Ut.reshape(-1)
+        errs.append(np.abs(e).max() / np.abs(Ut).max())
+    assert errs[1] < 0.05
+    assert abs(np.log2(errs[0] / errs[1]) - p) < 0.2
+
+
 def test_ns_viscous_flux_couette():
     # simple shear u = (a y, 0), constant rho, p: viscous x-momentum flux in y is mu * a
     md = O.Model(O.MODEL_NS, 4, [1.4, 10.0, 0.72, 1.0])

@@ -12,7 +12,7 @@ def L():
 
 
 @pytest.mark.parametrize("src,nd,p,ncu,has_q", [(U.EULER_2D, 2, 4, 4, False), (U.NONLINEAR_DIFFUSION, 3, 2, 1, True),
-                                                (U.SHALLOW_WATER_2D, 2, 4, 3, False)])
+                                                (U.SHALLOW_WATER_2D, 2, 4, 3, False), (U.WAVE_2D, 2, 3, 3, False)])
 def test_physics_sources_compile(L, src, nd, p, ncu, has_q):
     L.user_physics_check(src, nd, p, ncu, has_q)
 

@@ -6,7 +6,9 @@ built-in Euler model.  NONLINEAR_DIFFUSION is a model the library does not
 have: f = kappa q with kappa = mu0 kappa(x) (1 + mu2 u^2) (kappa(x) an optional
 aux field), central flux plus an interior penalty mu1 mu0 {kappa(x)} (u- - u+);
 with mu2 = 0 it is the built-in Poisson operator without reaction.  SHALLOW_WATER_2D is the shallow-water system
-(h, h v) with the local Lax-Friedrichs flux (speed |v.n| + sqrt(g h)).
+(h, h v) with the local Lax-Friedrichs flux (speed |v.n| + sqrt(g h)).  WAVE_2D
+is the paper's wave model written as a first-order system in (u, q) with the
+upwind (Lax-Friedrichs, speed c) flux.
 """
 
 EULER_2D = r"""
@@ -111,6 +113,35 @@ struct LdgUser {
     flux<D, V, R>(mu, naux, uL, qL, aL, fL);
     flux<D, V, R>(mu, naux, uR, qR, aR, fR);
     const V sig = R(0.5) * vmax(speed<D, V, R>(R(mu[0]), uL, n), speed<D, V, R>(R(mu[0]), uR, n));
+    for (int c = 0; c < NCU; ++c) {
+      V s = R(0.5) * (fL[c][0] + fR[c][0]) * n[0];
+      for (int k = 1; k < D; ++k) s += R(0.5) * (fL[c][k] + fR[c][k]) * n[k];
+      Fh[c] = s + sig * (uL[c] - uR[c]);
+    }
+  }
+};
+"""
+
+WAVE_2D = r"""
+struct LdgUser {
+  static constexpr int NCU = 3;      // state (u, q1, q2)
+  static constexpr bool HASQ = false;
+  static constexpr int NAUX = 0;
+  // u_t + div(c^2 q) = 0, q_t + grad u = 0: f = (c^2 q, u I), c^2 = mu[0]
+  template <int D, class V, class R>
+  __device__ static void flux(const double* mu, int, const V* u, const V (*)[D], const R*, V (*f)[D]) {
+    for (int k = 0; k < D; ++k) {
+      f[0][k] = R(mu[0]) * u[1 + k];
+      for (int i = 0; i < D; ++i) f[1 + i][k] = (i == k) ? u[0] : VT<V>::mk(R(0));
+    }
+  }
+  template <int D, class V, class R>
+  __device__ static void numflux(const double* mu, int naux, const V* uL, const V (*qL)[D], const R* aL,
+                                 const V* uR, const V (*qR)[D], const R* aR, const R* n, V* Fh) {
+    V fL[NCU][D], fR[NCU][D];
+    flux<D, V, R>(mu, naux, uL, qL, aL, fL);
+    flux<D, V, R>(mu, naux, uR, qR, aR, fR);
+    const R sig = R(0.5) * R(sqrt(mu[0]));
     for (int c = 0; c < NCU; ++c) {
       V s = R(0.5) * (fL[c][0] + fR[c][0]) * n[0];
       for (int k = 1; k < D; ++k) s += R(0.5) * (fL[c][k] + fR[c][k]) * n[k];
