@@ -104,6 +104,19 @@ def dirk_tableau(name):
     raise ValueError(f"unknown DIRK scheme {name!r}")
 
 
+def dirk_stage_coefficients(A, b):
+    """For the stage form used by dirk_steps: c[i][l] (l < i), the weights of the earlier stage increments
+    Y_l = U_l - u_n in stage i's right-hand side, and e = b^T A^-1, the weights of the step's final update."""
+    A = np.asarray(A, dtype=np.float64)
+    s = A.shape[0]
+    Ainv = np.linalg.inv(A)
+    c = np.zeros((s, s))
+    for i in range(s):
+        for l in range(i):
+            c[i, l] = sum(A[i, j] * Ainv[j, l] for j in range(l, i))
+    return c, np.asarray(b, dtype=np.float64) @ Ainv
+
+
 def dirk_steps(model, u0, dt, nsteps, scheme="dirk33", restart=50, eta=1e-3, rtol=1e-8, jvp_prec=ldg.FP64,
                bj_prec=ldg.FP64, per_variable=False, newton_maxit=10, lin_maxit=5000, orth=ldg.ORTH_DCGS2,
                bj_refresh=1, log=None, atol=0.0):
@@ -111,8 +124,7 @@ def dirk_steps(model, u0, dt, nsteps, scheme="dirk33", restart=50, eta=1e-3, rto
     stage starts Newton from the previous stage value and stops at ||G|| <= max(rtol ||G_0||, atol)."""
     A, b = dirk_tableau(scheme)
     s = len(b)
-    Ainv = np.linalg.inv(np.asarray(A, dtype=np.float64))
-    e = np.asarray(b, dtype=np.float64) @ Ainv
+    cst, e = dirk_stage_coefficients(A, b)
     u = u0.clone()
     stats = []
     pc = None
@@ -126,8 +138,7 @@ def dirk_steps(model, u0, dt, nsteps, scheme="dirk33", restart=50, eta=1e-3, rto
             a0 = 1.0 / (A[i][i] * dt)
             r1 = un.clone()
             for l in range(i):
-                cil = sum(A[i][j] * Ainv[j][l] for j in range(l, i))
-                ldg.axpby(cil, Y[l], 1.0, r1)
+                ldg.axpby(float(cst[i, l]), Y[l], 1.0, r1)
             t = ldg.Time(a0=a0, r1=r1, c1=a0)
             if pc is None:
                 pc = ldg.BlockJacobi(model, u_lin=U, time=t, per_variable=per_variable, prec=bj_prec)
