@@ -221,3 +221,22 @@ def test_user_wave_model_matches_oracle(L):
                               newton_maxit=6)
     assert stats[0]["converged"]
     assert rel(ug.cpu().numpy(), u_ref) < 1e-8
+
+
+def test_user_model_argument_errors(L):
+    m = L.Mesh(I.box_mesh(2, 2), 2)
+    # a physics source needs kind MODEL_USER, and MODEL_USER needs a source
+    with pytest.raises(L.LDGError):
+        L.Model(m, L.MODEL_EULER, 4, [1.4], physics_source=U.EULER_2D, has_q=False)
+    with pytest.raises(L.LDGError):
+        L.Model(m, L.MODEL_USER, 4, [1.4])
+    # declared sizes that contradict the source, and a source that does not compile: the compiler's message
+    with pytest.raises(L.LDGError) as e:
+        L.Model(m, L.MODEL_USER, 5, [1.4], physics_source=U.EULER_2D, has_q=False)
+    assert "differs" in str(e.value)
+    with pytest.raises(L.LDGError) as e:
+        L.Model(m, L.MODEL_USER, 1, [1.0], physics_source=U.BROKEN, has_q=True)
+    assert "physics_source:6" in str(e.value)
+    # the library stays usable after the failures
+    md = L.Model(m, L.MODEL_USER, 4, [1.4], physics_source=U.EULER_2D, has_q=False)
+    assert md.N == 4 * 9 * 4
