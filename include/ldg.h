@@ -204,6 +204,27 @@ typedef struct {
   double c2;
 } ldg_time;
 
+/* The ODE that the paper couples to the PDE (Eq. 1c): alpha dw/dt + beta w =
+ * s_w(u), with w (nw components) at the element nodes, DEVICE [E][nw][nn].  A
+ * physics source defines it by
+ *
+ *     static constexpr int NW = ...;       in [1, 8]
+ *     __device__ static void ode_source(const double* mu, int naux, const double* u,
+ *                                       const double* a, double* sw);
+ *
+ * (u: the NCU state values at one node, a: its aux values, sw: [NW]; FP64).
+ * w does not enter the PDE, so the ODE is advanced after each implicit stage of
+ * the PDE, from that stage's state.  ldg_ode_size: nw, 0 when the model has no
+ * ODE (all built-in models).  ldg_ode_stage: one implicit stage with the time
+ * wrapper t, whose r1, r2 are here w-vectors [E][nw][nn] (or NULL):
+ *     w = (alpha (c1 r1 + c2 r2) + s_w(u)) / (alpha a0 + beta)   at every node,
+ * u the stage's PDE state [E][ncu][nn].  w may alias r1 or r2 (each node reads
+ * them before it writes); it must not alias u.  Errors: LDG_EINVAL (null
+ * arguments, t NULL, alpha a0 + beta = 0), LDG_EUNSUPPORTED (no ODE). */
+ldg_status ldg_ode_size(ldg_model model, int* nw);
+ldg_status ldg_ode_stage(ldg_model model, const ldg_time* t, double alpha, double beta, const double* u, double* w,
+                         void* stream);
+
 /* ------------------------------------------------------------- operator --- */
 /* G(u) (Eq. 1a-1b discretized, with the time wrapper) and optionally
  * q_out = q(u).  prec: LDG_FP64 or LDG_FP32 (others -> LDG_EINVAL). */

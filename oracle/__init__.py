@@ -423,13 +423,20 @@ def dirk_tableau(name):
     raise ValueError(name)
 
 
-def dirk_step(mesh, model, un, dt, A, b, rtol=1e-13, maxit=12):
-    """One DIRK step of M du/dt + R(u) = 0 from un; model is the steady model (its R).  Returns u_{n+1}."""
+def dirk_step(mesh, model, un, dt, A, b, rtol=1e-13, maxit=12, ode=None):
+    """One DIRK step of M du/dt + R(u) = 0 from un; model is the steady model (its R).  Returns u_{n+1}.
+
+    ode = (s_w, alpha, beta, w_n): the ODE coupled to the PDE (Eq. 1c), alpha dw/dt + beta w = s_w(u), with
+    s_w a function of the nodal state vector.  It runs through the same Butcher stages: W_i = w_n +
+    dt sum_j a_ij Wdot_j with alpha Wdot_i + beta W_i = s_w(U_i), so Wdot_i = (s_w(U_i) - beta (w_n +
+    dt sum_{j<i} a_ij Wdot_j)) / (alpha + beta dt a_ii); then w_{n+1} = w_n + dt sum_j b_j Wdot_j.
+    With ode the result is (u_{n+1}, w_{n+1})."""
     import scipy.sparse.linalg as spla
     ncu = model.ncu
     Mdiag = mesh.mass_apply(ncu, np.ones_like(un))
     s = len(b)
     R = []
+    Wdot = []
     U = un.copy()
     for i in range(s):
         rest = sum((A[i, j] * R[j] for j in range(i)), np.zeros_like(un))
@@ -445,8 +452,15 @@ def dirk_step(mesh, model, un, dt, A, b, rtol=1e-13, maxit=12):
 
         U, info = newton(F, solve, U, rtol=rtol, maxit=maxit)
         R.append(mesh.residual(model, U))
+        if ode is not None:
+            s_w, alpha, beta, wn = ode
+            base = wn + dt * sum((A[i, j] * Wdot[j] for j in range(i)), np.zeros_like(wn))
+            Wdot.append((s_w(U) - beta * base) / (alpha + beta * dt * A[i, i]))
     k = [-Rj / Mdiag for Rj in R]
-    return un + dt * sum(b[j] * k[j] for j in range(s))
+    u_next = un + dt * sum(b[j] * k[j] for j in range(s))
+    if ode is None:
+        return u_next
+    return u_next, ode[3] + dt * sum(b[j] * Wdot[j] for j in range(s))
 
 
 # ----------------------------------------------------------------------------

@@ -508,6 +508,26 @@ ldg_status ldg_user_physics_check(const char* physics_source, int nd, int p, int
   return jit_check(physics_source, nd, p + 1, ncu, has_q != 0);
 }
 
+ldg_status ldg_ode_size(ldg_model md, int* nw) {
+  LDG_ENTER();
+  CHECK_ARG(md && nw, "null argument");
+  *nw = jit_ode_size(*md);
+  return LDG_OK;
+}
+
+ldg_status ldg_ode_stage(ldg_model md, const ldg_time* t, double alpha, double beta, const double* u, double* w,
+                         void* stream) {
+  LDG_ENTER();
+  CHECK_ARG(md && t && u && w, "null argument");
+  CHECK_ARG((const double*)w != u, "w must not alias u");
+  CHECK_ARG(alpha * t->a0 + beta != 0.0, "alpha a0 + beta must not vanish");
+  if (jit_ode_size(*md) == 0) {
+    set_error("the model defines no ODE (a physics source with LdgUser::NW and ode_source)");
+    return LDG_EUNSUPPORTED;
+  }
+  return jit_ode(*md, make_time(t, true), alpha, beta, u, w, (hipStream_t)stream);
+}
+
 ldg_status ldg_model_destroy(ldg_model md) {
   LDG_ENTER();
   if (!md) return LDG_OK;

@@ -12,7 +12,8 @@
 
 namespace ldg {
 
-static_assert(BC_DIRICHLET == LDG_BC_DIRICHLET && BC_NEUMANN == LDG_BC_NEUMANN && BC_EXTRAP == LDG_BC_EXTRAP,
+static_assert((int)BC_DIRICHLET == (int)LDG_BC_DIRICHLET && (int)BC_NEUMANN == (int)LDG_BC_NEUMANN &&
+                  (int)BC_EXTRAP == (int)LDG_BC_EXTRAP,
               "device boundary kinds are the ABI's");
 
 // --------------------------------------------------------------------------
@@ -113,6 +114,9 @@ ldg_status jit_check(const char* user_source, int nd, int p1, int ncu, bool hasq
 ldg_status jit_grad(const Model& md, const double* u, void* q, bool fp32, bool with_data, hipStream_t s);
 ldg_status jit_resid(const Model& md, const TimeDev& t, const double* u, const void* q, const double* v,
                      const void* dq, double* out, bool fp32, bool tangent, hipStream_t s);
+int jit_ode_size(const Model& md);
+ldg_status jit_ode(const Model& md, const TimeDev& t, double alpha, double beta, const double* u, double* w,
+                   hipStream_t s);
 
 // shared host helpers (ldg_api.hip)
 TimeDev make_time(const ldg_time* t, bool with_rhs);

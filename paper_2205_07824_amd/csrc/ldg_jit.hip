@@ -23,6 +23,8 @@ struct JitOps {
   hipFunction_t resid[2][2] = {};  // [FP32][tangent]
   int epb_grad[2] = {0, 0};
   int epb_resid[2][2] = {{0, 0}, {0, 0}};
+  hipFunction_t ode = nullptr;     // one implicit stage of the coupled ODE (Eq. 1c)
+  int nw = 0;                      // its number of components (0: the source defines no ODE)
 };
 
 namespace {
@@ -32,7 +34,7 @@ std::string program_text(const char* user, int ncu, bool hasq) {
   p += "#define LDG_USER_PHYSICS 1\n#include \"ldg_device.hpp\"\nusing namespace ldg;\n";
   p += "#line 1 \"physics_source\"\n";
   p += user;
-  p += "\n#include \"ldg_operator_kernels.hpp\"\n";
+  p += "\n#include \"ldg_operator_kernels.hpp\"\n#include \"ldg_ode_kernel.hpp\"\n";
   p += "static_assert(LdgUser::NCU == " + std::to_string(ncu) + ", \"LdgUser::NCU differs from the model's ncu\");\n";
   p += std::string("static_assert(LdgUser::HASQ == ") + (hasq ? "true" : "false") +
        ", \"LdgUser::HASQ differs from has_q\");\n";
@@ -125,6 +127,19 @@ ldg_status jit_build(Model& md, const char* user) {
       return LDG_EDEVICE;
     }
   }
+  {
+    hipDeviceptr_t pnw = nullptr;
+    size_t bytes = 0;
+    if (hipModuleGetFunction(&J->ode, J->mod, "ldg_k_ode_stage") != hipSuccess ||
+        hipModuleGetGlobal(&pnw, &bytes, J->mod, "ldg_user_nw") != hipSuccess || bytes != sizeof(int) ||
+        hipMemcpyDtoH(&J->nw, pnw, sizeof(int)) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipModuleUnload(J->mod);
+      delete J;
+      set_error("compiled physics module lacks the ODE kernel");
+      return LDG_EDEVICE;
+    }
+  }
   for (int f = 0; f < 2; ++f) {
     const int rsz = f ? 4 : 8;
     J->epb_grad[f] = pick_epb_n(m.nn, grad_bytes(md.ncu, m.nd, m.p1, rsz));
@@ -184,6 +199,27 @@ ldg_status jit_resid(const Model& md, const TimeDev& t, const double* u, const v
   void* args[] = {&mdv,     fp32 ? (void*)&tabf : (void*)&tab, &mod, &td, (void*)&u, (void*)&q, (void*)&v,
                   (void*)&dq, (void*)&dterm, &out, &Fout};
   return launch(md.jit->resid[fp32][tangent], m.E, md.jit->epb_resid[fp32][tangent], m.nn, args, s);
+}
+
+int jit_ode_size(const Model& md) { return md.jit ? md.jit->nw : 0; }
+
+ldg_status jit_ode(const Model& md, const TimeDev& t, double alpha, double beta, const double* u, double* w,
+                   hipStream_t s) {
+  const Mesh& m = *md.mesh;
+  int64_t nodes = m.E * (int64_t)m.nn;
+  int nn = m.nn;
+  ModelDev mod = md.dev();
+  double a0 = t.a0, c1 = t.c1, c2 = t.c2;
+  const double* r1 = t.r1;
+  const double* r2 = t.r2;
+  void* args[] = {&nodes, &nn, &mod, &alpha, &beta, &a0, &c1, (void*)&r1, &c2, (void*)&r2, (void*)&u, &w};
+  const unsigned nblk = (unsigned)((nodes + 255) / 256);
+  if (nblk == 0) return LDG_OK;
+  if (hipModuleLaunchKernel(md.jit->ode, nblk, 1, 1, 256, 1, 1, 0, s, args, nullptr) != hipSuccess) {
+    set_error(std::string("launch of the ODE kernel failed: ") + hipGetErrorString(hipGetLastError()));
+    return LDG_EDEVICE;
+  }
+  return LDG_OK;
 }
 
 }  // namespace ldg

@@ -77,7 +77,7 @@ EXPORTED = ["ldg_last_error", "ldg_mesh_create", "ldg_mesh_info", "ldg_mesh_poin
             "ldg_precond_block_jacobi", "ldg_precond_apply", "ldg_precond_destroy", "ldg_gmres_solve",
             "ldg_newton_solve", "ldg_axpby", "ldg_norm2", "ldg_mlp_create", "ldg_mlp_destroy", "ldg_mlp_set_params",
             "ldg_mlp_get_params", "ldg_mlp_forward", "ldg_mlp_train_step", "ldg_mlp_gather_patches",
-            "ldg_precond_mlp", "ldg_model_create_user", "ldg_user_physics_check"]
+            "ldg_precond_mlp", "ldg_model_create_user", "ldg_user_physics_check", "ldg_ode_size", "ldg_ode_stage"]
 
 
 def lib():
@@ -118,6 +118,8 @@ def lib():
         "ldg_precond_mlp": [vp, vp, vp, C.c_int, C.POINTER(vp)],
         "ldg_model_create_user": [vp, C.POINTER(_ModelDesc), C.c_char_p, C.c_int, vp, C.POINTER(vp)],
         "ldg_user_physics_check": [C.c_char_p, C.c_int, C.c_int, C.c_int, C.c_int],
+        "ldg_ode_size": [vp, C.POINTER(C.c_int)],
+        "ldg_ode_stage": [vp, C.POINTER(_Time), C.c_double, C.c_double, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -229,6 +231,9 @@ class Model:
             _check(lib().ldg_model_create(mesh.h, C.byref(d), _stream(), C.byref(h)), "ldg_model_create")
         self.h = h
         self.N = mesh.size(ncu)
+        nw = C.c_int()
+        _check(lib().ldg_ode_size(h, C.byref(nw)), "ldg_ode_size")
+        self.nw = nw.value          # components of the coupled ODE (Eq. 1c); 0 without one
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -247,6 +252,16 @@ class Model:
     def jvp(self, u, v, time=None, prec=FP64, out=None):
         out = self.empty() if out is None else out
         _check(lib().ldg_jvp(self.h, _time(time), _ptr(u), _ptr(v), _ptr(out), prec, _stream()), "ldg_jvp")
+        return out
+
+    def ode_stage(self, u, time, alpha, beta, out=None):
+        """w of one implicit stage of alpha dw/dt + beta w = s_w(u) with the time wrapper `time` (its r1, r2 are
+        w-vectors), from the stage's PDE state u."""
+        out = torch.empty(self.mesh.E * self.nw * self.mesh.nn, dtype=torch.float64, device="cuda") \
+            if out is None else out
+        assert out.numel() == self.mesh.E * self.nw * self.mesh.nn
+        _check(lib().ldg_ode_stage(self.h, _time(time), C.c_double(alpha), C.c_double(beta), _ptr(u), _ptr(out),
+                                   _stream()), "ldg_ode_stage")
         return out
 
     def jacobian_blocks(self, u, time=None, per_variable=False):

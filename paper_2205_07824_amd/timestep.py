@@ -14,12 +14,16 @@ iterate.
   a0 = 1/(a_ii dt), r1 = u_n + sum_{l<i} c_il Y_l, c1 = a0, where
   c_il = sum_{l<=j<i} a_ij (A^-1)_jl; the step ends with
   u_{n+1} = u_n + sum_l (b^T A^-1)_l Y_l.  No inverse mass matrix is needed.
+* The ODE coupled to the PDE (Eq. 1c), alpha dw/dt + beta w = s_w(u): its
+  stages take the same form with the PDE's stage states, and each is one
+  pointwise library call (w enters neither the flux nor the source).
 
 Every numerical step is a library call; this module only sequences them and
 records the per-step statistics.
 """
 from __future__ import annotations
 
+import dataclasses
 import math
 import time
 
@@ -41,13 +45,24 @@ def euler_cfl_dt(U, nd, h, cfl, gamma=1.4):
     return cfl * h / float(speed.max())
 
 
+@dataclasses.dataclass
+class Ode:
+    """State of the ODE coupled to the PDE (Eq. 1c), alpha dw/dt + beta w = s_w(u): w is a device vector
+    [E][nw][nn] that the steppers advance in place."""
+    w: torch.Tensor
+    alpha: float = 1.0
+    beta: float = 0.0
+
+
 def bdf_steps(model, u0, dt, nsteps, restart=50, eta=1e-3, rtol=1e-8, jvp_prec=ldg.FP64, bj_prec=ldg.FP64,
               per_variable=False, newton_maxit=10, lin_maxit=5000, orth=ldg.ORTH_DCGS2, bj_refresh=1,
-              log=None, atol=0.0):
+              log=None, atol=0.0, ode=None):
     """Advance u0 by nsteps implicit steps; returns (u, per-step statistics).  bj_refresh: 1 rebuilds the
-    block-Jacobi preconditioner at every Newton iterate, 2 once per step (at its first iterate)."""
+    block-Jacobi preconditioner at every Newton iterate, 2 once per step (at its first iterate).  ode: the
+    coupled ODE of the model (Ode), advanced with the same BDF formula from each step's solution."""
     u = u0.clone()
     u_prev = None
+    w_prev = None
     stats = []
     pc = None
     for k in range(nsteps):
@@ -75,6 +90,11 @@ def bdf_steps(model, u0, dt, nsteps, restart=50, eta=1e-3, rtol=1e-8, jvp_prec=l
         u_prev = un
         if status != ldg.LDG_OK:
             break
+        if ode is not None:
+            wn = ode.w.clone()
+            tw = ldg.Time(a0=t.a0, r1=wn, c1=t.c1, r2=w_prev, c2=t.c2 if w_prev is not None else 0.0)
+            model.ode_stage(u, tw, ode.alpha, ode.beta, out=ode.w)
+            w_prev = wn
     return u, stats
 
 
@@ -119,9 +139,10 @@ def dirk_stage_coefficients(A, b):
 
 def dirk_steps(model, u0, dt, nsteps, scheme="dirk33", restart=50, eta=1e-3, rtol=1e-8, jvp_prec=ldg.FP64,
                bj_prec=ldg.FP64, per_variable=False, newton_maxit=10, lin_maxit=5000, orth=ldg.ORTH_DCGS2,
-               bj_refresh=1, log=None, atol=0.0):
+               bj_refresh=1, log=None, atol=0.0, ode=None):
     """Advance u0 by nsteps steps of a DIRK scheme (dirk_tableau); returns (u, per-step statistics).  Each
-    stage starts Newton from the previous stage value and stops at ||G|| <= max(rtol ||G_0||, atol)."""
+    stage starts Newton from the previous stage value and stops at ||G|| <= max(rtol ||G_0||, atol).  ode: the
+    coupled ODE of the model (Ode); its stages take the same stage form, each from its PDE stage's state."""
     A, b = dirk_tableau(scheme)
     s = len(b)
     cst, e = dirk_stage_coefficients(A, b)
@@ -131,6 +152,8 @@ def dirk_steps(model, u0, dt, nsteps, scheme="dirk33", restart=50, eta=1e-3, rto
     for k in range(nsteps):
         un = u.clone()
         Y = []
+        wn = ode.w.clone() if ode is not None else None
+        Yw = []
         rec = {"step": k + 1, "seconds": 0.0, "converged": True, "newton_iters": 0, "gmres_iters": 0,
                "t_jvp": 0.0, "t_pc": 0.0, "t_orth": 0.0}
         U = un.clone()
@@ -160,12 +183,21 @@ def dirk_steps(model, u0, dt, nsteps, scheme="dirk33", restart=50, eta=1e-3, rto
             Yi = U.clone()
             ldg.axpby(-1.0, un, 1.0, Yi)
             Y.append(Yi)
+            if ode is not None:
+                rw = wn.clone()
+                for l in range(i):
+                    ldg.axpby(float(cst[i, l]), Yw[l], 1.0, rw)
+                Wi = model.ode_stage(U, ldg.Time(a0=a0, r1=rw, c1=a0), ode.alpha, ode.beta, out=rw)
+                ldg.axpby(-1.0, wn, 1.0, Wi)
+                Yw.append(Wi)
         if rec["converged"]:
             t0 = time.perf_counter()
             u = un.clone()
             for l in range(s):
                 if e[l] != 0.0:
                     ldg.axpby(float(e[l]), Y[l], 1.0, u)
+                    if ode is not None:
+                        ldg.axpby(float(e[l]), Yw[l], 1.0, ode.w)
             torch.cuda.synchronize()
             rec["seconds"] += time.perf_counter() - t0
         stats.append(rec)

@@ -240,3 +240,89 @@ def test_user_model_argument_errors(L):
     # the library stays usable after the failures
     md = L.Model(m, L.MODEL_USER, 4, [1.4], physics_source=U.EULER_2D, has_q=False)
     assert md.N == 4 * 9 * 4
+
+
+def test_ode_stage_matches_its_definition(L):
+    """One implicit stage of the coupled ODE, alpha (a0 w - c1 r1 - c2 r2) + beta w = s_w(u), at every node,
+    against the stage equation solved in numpy with the source's s_w = (u, mu1 q1 q2)."""
+    import torch
+    m = L.Mesh(I.box_mesh(2, 3, periodic=(True, True), perturb=0.05, seed=4), 3)
+    md = L.Model(m, L.MODEL_USER, 3, [2.0, 0.5], bc_kind=(0,), physics_source=U.WAVE_2D_W, has_q=False)
+    assert md.nw == 2
+    E, nn = m.E, m.nn
+    rng = np.random.default_rng(8)
+    u = rng.uniform(-1, 1, (E, 3, nn))
+    r1, r2 = rng.uniform(-1, 1, (E, 2, nn)), rng.uniform(-1, 1, (E, 2, nn))
+    sw = np.stack([u[:, 0], 0.5 * u[:, 1] * u[:, 2]], axis=1)
+    for alpha, beta, a0, c1, c2, with_r2 in ((1.3, 0.4, 1.7, 0.9, -0.3, True), (1.0, 0.0, 25.0, 25.0, 0.0, False),
+                                             (0.0, 2.0, 5.0, 5.0, 0.0, False)):
+        t = L.Time(a0=a0, r1=dev(r1.reshape(-1)), c1=c1, r2=dev(r2.reshape(-1)) if with_r2 else None, c2=c2)
+        w = md.ode_stage(dev(u.reshape(-1)), t, alpha, beta).cpu().numpy().reshape(E, 2, nn)
+        # residual of the stage equation, relative to its terms
+        res = alpha * (a0 * w - c1 * r1 - (c2 * r2 if with_r2 else 0.0)) + beta * w - sw
+        scale = np.abs(alpha * a0 * w).max() + np.abs(beta * w).max() + np.abs(sw).max()
+        _say("ode stage", alpha, beta, np.abs(res).max() / scale)
+        assert np.abs(res).max() < 1e-14 * scale
+    # w may overwrite r1 in place
+    r1d = dev(r1.reshape(-1))
+    t = L.Time(a0=1.7, r1=r1d, c1=0.9)
+    ref = md.ode_stage(dev(u.reshape(-1)), t, 1.3, 0.4).cpu().numpy()
+    md.ode_stage(dev(u.reshape(-1)), t, 1.3, 0.4, out=r1d)
+    torch.cuda.synchronize()
+    assert np.array_equal(r1d.cpu().numpy(), ref)
+    # a singular stage and a model without an ODE are errors
+    with pytest.raises(L.LDGError):
+        md.ode_stage(dev(u.reshape(-1)), L.Time(a0=2.0, r1=r1d, c1=2.0), 1.0, -2.0)
+    md0 = L.Model(m, L.MODEL_USER, 3, [2.0], bc_kind=(0,), physics_source=U.WAVE_2D, has_q=False)
+    assert md0.nw == 0
+    with pytest.raises(L.LDGError):
+        md0.ode_stage(dev(u.reshape(-1)), t, 1.0, 0.0)
+
+
+def test_dirk_with_coupled_ode_matches_oracle(L):
+    """The wave model with its displacement ODE (and a nonlinear second component) through two DIRK(3,3)
+    steps against the oracle's DIRK step with the same ODE; and BDF1/BDF2 on a steady state, where the
+    displacement grows exactly linearly."""
+    import oracle as O
+    import torch
+    from paper_2205_07824_amd import timestep as TS
+    c2, n, p, dt = 2.0, 4, 3, 0.02
+    box = I.box_mesh(2, n, periodic=(True, True), perturb=0.05, seed=2)
+    om = O.Mesh(box, p)
+    k = 2 * np.pi * np.array([1.0, 2.0])
+    th = om.points()[0] @ k
+    U0 = np.stack([-np.cos(th), -k[0] * np.cos(th), -k[1] * np.cos(th)], axis=1).reshape(-1)
+    m = L.Mesh(box, p)
+    md = L.Model(m, L.MODEL_USER, 3, [c2, 0.5], bc_kind=(0,), physics_source=U.WAVE_2D_W, has_q=False)
+    E, nn = m.E, m.nn
+    w0 = np.random.default_rng(9).uniform(-1, 1, E * 2 * nn)
+
+    def sw(X):
+        X = X.reshape(E, 3, nn)
+        return np.stack([X[:, 0], 0.5 * X[:, 1] * X[:, 2]], axis=1).reshape(-1)
+
+    A, b = O.dirk_tableau("dirk33")
+    for alpha, beta in ((1.0, 0.0), (2.0, 0.5)):
+        u_ref, w_ref = U0.copy(), w0.copy()
+        for _ in range(2):
+            u_ref, w_ref = O.dirk_step(om, O.Model(O.MODEL_WAVE, 3, [c2]), u_ref, dt, A, b,
+                                       ode=(sw, alpha, beta, w_ref))
+        ode = TS.Ode(w=dev(w0.copy()), alpha=alpha, beta=beta)
+        ug, stats = TS.dirk_steps(md, dev(U0.copy()), dt, 2, scheme="dirk33", restart=50, eta=1e-10, rtol=1e-12,
+                                  newton_maxit=6, ode=ode)
+        assert all(s["converged"] for s in stats)
+        eu, ew = rel(ug.cpu().numpy(), u_ref), rel(ode.w.cpu().numpy(), w_ref)
+        _say("dirk33 + ode", alpha, beta, "u", eu, "w", ew)
+        assert eu < 1e-8 and ew < 1e-8
+    # steady state: BDF1 then BDF2 give w_n = w_0 + n dt u0 exactly for alpha w' = u0 (beta = 0)
+    us = np.broadcast_to(np.array([0.7, -0.3, 0.4])[None, :, None], (E, 3, nn)).reshape(-1).copy()
+    ode = TS.Ode(w=dev(w0.copy()), alpha=2.0, beta=0.0)
+    _, stats = TS.bdf_steps(md, dev(us), dt, 3, restart=20, eta=1e-10, rtol=1e-12, atol=1e-12, newton_maxit=4,
+                            ode=ode)
+    assert all(s["converged"] for s in stats)
+    torch.cuda.synchronize()
+    w = ode.w.cpu().numpy().reshape(E, 2, nn)
+    w_exact = w0.reshape(E, 2, nn) + 3 * dt * np.stack([np.full((E, nn), 0.7), np.full((E, nn), 0.5 * -0.3 * 0.4)],
+                                                      axis=1) / 2.0
+    _say("bdf + ode steady", np.abs(w - w_exact).max())
+    assert np.abs(w - w_exact).max() < 1e-12

@@ -597,3 +597,65 @@ def test_taylor_green_closed_forms():
     vel = U[..., 1:4] / rho[..., None]
     ek = np.mean(0.5 * rho * (vel ** 2).sum(-1))
     assert abs(ek - 0.125) < 2e-3
+
+
+# ---------------------------------------------------------------- the coupled ODE (Eq. 1c) in the DIRK step
+def _wave_plane(n, p):
+    # w = sin(k.x - |k| t) (c = 1): u = w_t, q = -grad w
+    m = O.Mesh(I.box_mesh(2, n, periodic=(True, True)), p)
+    k = 2 * np.pi * np.array([1.0, 1.0])
+    om = np.linalg.norm(k)
+    th = m.points()[0] @ k
+    U = np.stack([-om * np.cos(th), -k[0] * np.cos(th), -k[1] * np.cos(th)], axis=1).reshape(-1)
+    return m, th, om, U
+
+
+def _wave_ode_steps(m, U, w0, dt, nsteps, scheme, alpha=1.0, beta=0.0):
+    A, b = O.dirk_tableau(scheme)
+    md = O.Model(O.MODEL_WAVE, 3, [1.0])
+    sw = lambda X: X.reshape(m.E, 3, m.nn)[:, :1, :].reshape(-1).copy()   # s_w = u (the velocity)
+    u, w = U.copy(), w0.copy()
+    for _ in range(nsteps):
+        u, w = O.dirk_step(m, md, u, dt, A, b, ode=(sw, alpha, beta, w))
+    return u, w
+
+
+@pytest.mark.parametrize("scheme", ["be", "dirk22", "dirk33", "dirk34"])
+def test_ode_constant_forcing_follows_the_stability_function(scheme):
+    # a constant state is steady for the wave model, so s_w = u0 is constant and alpha w' + beta w = u0 is a
+    # scalar linear ODE per node: one step maps w - w* (w* = u0 / beta) by the scheme's stability function
+    # R(z) = det(I - z A + z 1 b^T) / det(I - z A) at z = -beta dt / alpha
+    m = O.Mesh(I.box_mesh(2, 3, periodic=(True, True), perturb=0.05, seed=4), 2)
+    u0 = np.broadcast_to(np.array([0.7, -0.3, 0.4])[None, :, None], (m.E, 3, m.nn)).reshape(-1).copy()
+    w0 = np.random.default_rng(3).uniform(-1, 1, m.E * m.nn)
+    A, b = O.dirk_tableau(scheme)
+    one = np.ones(len(b))
+    for alpha, beta, dt in ((1.0, 0.0, 0.1), (2.0, 3.0, 0.4), (0.5, -1.0, 0.05)):
+        _, w1 = _wave_ode_steps(m, u0, w0, dt, 1, scheme, alpha, beta)
+        if beta == 0.0:
+            expect = w0 + dt * 0.7 / alpha
+        else:
+            z = -beta * dt / alpha
+            I_ = np.eye(len(b))
+            Rz = np.linalg.det(I_ - z * A + z * np.outer(one, b)) / np.linalg.det(I_ - z * A)
+            ws = 0.7 / beta
+            expect = ws + Rz * (w0 - ws)
+        assert np.abs(w1 - expect).max() < 1e-13, (alpha, beta)
+
+
+def test_ode_displacement_of_a_plane_wave():
+    # w_t = u recovers the displacement w = sin(k.x - |k| t) of the plane wave (error: space and time)
+    m, th, om, U = _wave_plane(6, 3)
+    T = 0.05
+    _, w = _wave_ode_steps(m, U, np.sin(th).reshape(-1), T / 5, 5, "dirk33")
+    err = np.abs(w - np.sin(th - om * T).reshape(-1)).max()
+    assert err < 5e-4, err
+
+
+@pytest.mark.parametrize("scheme,order", [("be", 1), ("dirk22", 2), ("dirk33", 3)])
+def test_ode_coupled_temporal_order(scheme, order):
+    # the displacement inherits the scheme's order (each ODE stage takes its own PDE stage's state)
+    m, th, om, U = _wave_plane(4, 2)
+    ws = [_wave_ode_steps(m, U, np.sin(th).reshape(-1), 0.1 / ns, ns, scheme)[1] for ns in (4, 8, 16)]
+    rate = np.log2(np.abs(ws[0] - ws[1]).max() / np.abs(ws[1] - ws[2]).max())
+    assert abs(rate - order) < 0.15, rate

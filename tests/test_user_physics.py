@@ -12,7 +12,8 @@ def L():
 
 
 @pytest.mark.parametrize("src,nd,p,ncu,has_q", [(U.EULER_2D, 2, 4, 4, False), (U.NONLINEAR_DIFFUSION, 3, 2, 1, True),
-                                                (U.SHALLOW_WATER_2D, 2, 4, 3, False), (U.WAVE_2D, 2, 3, 3, False)])
+                                                (U.SHALLOW_WATER_2D, 2, 4, 3, False), (U.WAVE_2D, 2, 3, 3, False),
+                                                (U.WAVE_2D_W, 2, 3, 3, False)])
 def test_physics_sources_compile(L, src, nd, p, ncu, has_q):
     L.user_physics_check(src, nd, p, ncu, has_q)
 
@@ -33,3 +34,10 @@ def test_declared_sizes_must_match_the_source(L, ncu, has_q):
 def test_orders_without_kernels_rejected(L):
     with pytest.raises(L.LDGError):
         L.user_physics_check(U.EULER_2D, 3, 4, 4, False)
+
+
+def test_ode_size_out_of_range_rejected(L):
+    src = U.WAVE_2D_W.replace("static constexpr int NW = 2;", "static constexpr int NW = 9;")
+    with pytest.raises(L.LDGError) as e:
+        L.user_physics_check(src, 2, 3, 3, False)
+    assert "NW must be in [1, 8]" in str(e.value)

@@ -8,7 +8,8 @@ aux field), central flux plus an interior penalty mu1 mu0 {kappa(x)} (u- - u+);
 with mu2 = 0 it is the built-in Poisson operator without reaction.  SHALLOW_WATER_2D is the shallow-water system
 (h, h v) with the local Lax-Friedrichs flux (speed |v.n| + sqrt(g h)).  WAVE_2D
 is the paper's wave model written as a first-order system in (u, q) with the
-upwind (Lax-Friedrichs, speed c) flux.
+upwind (Lax-Friedrichs, speed c) flux; WAVE_2D_W adds the coupled ODE (Eq. 1c)
+for the displacement, w_t = u.
 """
 
 EULER_2D = r"""
@@ -150,6 +151,15 @@ struct LdgUser {
   }
 };
 """
+
+# the wave model with the paper's displacement ODE (w_t = u, first component) and a second, nonlinear
+# component s_w = mu[1] q1 q2, so that a sum of two fields and a product are both checked
+WAVE_2D_W = WAVE_2D.replace("static constexpr int NAUX = 0;", """static constexpr int NAUX = 0;
+  static constexpr int NW = 2;
+  __device__ static void ode_source(const double* mu, int, const double* u, const double*, double* sw) {
+    sw[0] = u[0];
+    sw[1] = mu[1] * u[1] * u[2];
+  }""", 1)
 
 BROKEN = r"""
 struct LdgUser {
