@@ -343,6 +343,63 @@ def bickley_jet_steps(ldg, I, log, nsteps=3):
     return res
 
 
+def wave_displacement_steps(ldg, I, log, nsteps=4):
+    """The paper's wave model with its displacement ODE (Eq. 1c, w_t = u, plus a nonlinear second component
+    mu1 q1 q2): the plane wave w = sin(k.x - |k| t), k = 2 pi (2, 1), c = 1, on 256^2 periodic quads of the unit
+    square, p=4, physics and ODE compiled at run time, DIRK(3,3) at CFL 5 (c dt / h), Newton-GMRES(50) +
+    block-Jacobi to 1e-10.  JVP throughput, the ODE stage kernel's time and bandwidth (56 B per node: u, r1, w),
+    seconds per step, and the displacement's error against the closed form."""
+    import torch
+    from paper_2205_07824_amd import timestep as TS
+    sys.path.insert(0, ROOT)
+    from tests import user_physics as UP
+    n, p = 256, 4
+    m = ldg.Mesh(I.box_mesh(2, n, periodic=(True, True)), p)
+    xn, _, _, _ = m.points()
+    k = 2 * np.pi * np.array([2.0, 1.0])
+    om = float(np.linalg.norm(k))
+    th = xn @ k                                            # [E][nn]
+    U0 = np.stack([-om * np.cos(th), -k[0] * np.cos(th), -k[1] * np.cos(th)], axis=1).reshape(-1)
+    dt = 5.0 / n
+    t0 = time.perf_counter()
+    md = ldg.Model(m, ldg.MODEL_USER, 3, [1.0, 0.5], physics_source=UP.WAVE_2D_W, has_q=False)
+    res = {"workload": "wave model + displacement ODE, p=4, 256^2 periodic quads, plane wave k = 2pi(2,1), "
+                       "DIRK(3,3) at CFL 5", "dof": md.N, "ode_components": md.nw, "dt": dt,
+           "physics_compile_s": round(time.perf_counter() - t0, 2)}
+    u0 = torch.as_tensor(U0, device="cuda")
+    v = torch.as_tensor(np.random.default_rng(3).uniform(-1, 1, md.N), device="cuda")
+    t = ldg.Time(a0=1.0 / dt)
+    Jv = md.empty()
+    for nm, pr in (("fp64", ldg.FP64), ("fp32", ldg.FP32)):
+        md.jvp(u0, v, time=t, out=Jv, prec=pr)
+        e = event_time(lambda: md.jvp(u0, v, time=t, out=Jv, prec=pr), 20)
+        res[f"jvp_{nm}_gdofs"] = round(md.N / e / 1e9, 3)
+    nodes = m.E * m.nn
+    w0 = np.stack([np.sin(th), np.zeros_like(th)], axis=1).reshape(-1)
+    wr = torch.as_tensor(w0, device="cuda")
+    wo = torch.empty_like(wr)
+    tw = ldg.Time(a0=1.0 / dt, r1=wr, c1=1.0 / dt)
+    md.ode_stage(u0, tw, 1.0, 0.0, out=wo)
+    e = event_time(lambda: md.ode_stage(u0, tw, 1.0, 0.0, out=wo), 50)
+    res["ode_stage_us"] = round(e * 1e6, 2)
+    res["ode_stage_gbs"] = round(56.0 * nodes / e / 1e9, 1)
+    ode = TS.Ode(w=torch.as_tensor(w0, device="cuda"), alpha=1.0, beta=0.0)
+    _, stats = TS.dirk_steps(md, u0.clone(), dt, nsteps, scheme="dirk33", restart=50, eta=1e-3, rtol=1e-10,
+                             atol=1e-10, jvp_prec=ldg.FP64, bj_prec=ldg.FP64, bj_refresh=2, log=log, ode=ode)
+    torch.cuda.synchronize()
+    later = stats[1:] if len(stats) > 1 else stats
+    w = ode.w.cpu().numpy().reshape(m.E, 2, m.nn)[:, 0]
+    res["dirk33_fp64"] = {"seconds_per_step_2_to_%d" % nsteps: round(float(np.mean([r["seconds"] for r in later])), 4),
+                          "all_converged": all(r["converged"] for r in stats) and len(stats) == nsteps,
+                          "newton_iters": [r["newton_iters"] for r in stats],
+                          "gmres_iters": [r["gmres_iters"] for r in stats]}
+    res["displacement_max_error"] = float(np.abs(w - np.sin(th - om * nsteps * dt)).max())
+    log("wave + ode", res)
+    del md, m, u0, v, Jv, wr, wo, ode
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -485,6 +542,7 @@ def main():
     if not args.no_implicit:
         out["implicit_steps"] = implicit_steps(ldg, I, log)
         out["bickley_jet"] = bickley_jet_steps(ldg, I, log)
+        out["wave_displacement"] = wave_displacement_steps(ldg, I, log)
 
     # oracle on a bounded sample of elements, host, one core
     if not args.no_cpu:

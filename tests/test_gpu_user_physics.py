@@ -10,6 +10,8 @@
   mu2 > 0 discrete conservation on a periodic mesh (the fluxes are
   conservative and the basis sums to one) and its JVP against central
   differences of its own residual.
+* The wave model with the coupled displacement ODE (Eq. 1c): one ODE stage
+  against its defining equation, and DIRK(3,3) steps against the oracle's.
 """
 import sys
 
