@@ -181,7 +181,16 @@ ldg_status ldg_model_destroy(ldg_model model);
  * vmax).  f is the physical flux [NCU][D] (R = -(f, grad phi) + <Fh, phi> -
  * (src, phi)), Fh the numerical flux along the unit normal n (interior faces,
  * Dirichlet faces with uR = g, qR = qL); Neumann and extrapolation tags behave
- * as for the built-in models.  desc->kind must be LDG_MODEL_USER; the source
+ * as for the built-in models.  A source with HASQ = false may also define the
+ * outside state of its Dirichlet-kind faces (e.g. a slip wall):
+ *
+ *     static constexpr bool BOU = true;
+ *     template <int D, class V, class R> __device__ static void
+ *       bou(const double* mu, int naux, int tag, const V* uL, const V (*qL)[D],
+ *           const R* aL, const R* n, V* ub);
+ *
+ * ub arrives holding the tag's data g (zero without boundary data) and leaves
+ * holding uR for numflux.  desc->kind must be LDG_MODEL_USER; the source
  * term is the data field desc->src.  The model is nonlinear: JVPs need u.
  * Errors: LDG_EINVAL with the compiler's log in ldg_last_error() when the
  * source does not compile; otherwise as ldg_model_create. */

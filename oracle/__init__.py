@@ -20,7 +20,7 @@ _SRC = os.path.join(_HERE, "ldg_oracle.cpp")
 _LIB = os.path.join(_HERE, "libldg_oracle.so")
 
 MODEL_POISSON, MODEL_CONVDIFF, MODEL_EULER, MODEL_NS, MODEL_SHALLOW_WATER, MODEL_WAVE = 0, 1, 2, 3, 4, 5
-BC_DIRICHLET, BC_NEUMANN, BC_EXTRAP = 0, 1, 2
+BC_DIRICHLET, BC_NEUMANN, BC_EXTRAP, BC_SLIP_WALL = 0, 1, 2, 3
 
 
 def build(force=True):

@@ -431,7 +431,7 @@ struct OModel {
   const double* aux;   // [E][naux][nn]
   const double* src;   // [E][ncu][nqv]
   const double* bdata; // [nbf][ncu][nqf]
-  std::vector<int> bc_kind;   // per tag: 0 Dirichlet, 1 Neumann (flux data), 2 extrapolation
+  std::vector<int> bc_kind;   // per tag: 0 Dirichlet, 1 Neumann (flux data), 2 extrapolation, 3 slip wall
   double a0;
   const double* r;     // [E][ncu][nn] or null
 };
@@ -787,6 +787,14 @@ static void element_residual(const OMesh& M, const OModel& md, const T* u, const
           num_flux(md, um, qm, am, ub, qm, am, n, Fh);
         } else if (kind == 1) {
           for (int c = 0; c < ncu; ++c) Fh[c] = T(md.bdata ? md.bdata[((size_t)fc.bidx * ncu + c) * M.nqf + f] : 0.0);
+        } else if (kind == 3) {
+          // slip wall (Euler, shallow water): the outside state is the inside one with its normal
+          // momentum reversed, so the wall passes no mass and no energy
+          T ub[5], mn = T(0.0);
+          for (int k = 0; k < nd; ++k) mn += um[1 + k] * n[k];
+          for (int c = 0; c < ncu; ++c) ub[c] = um[c];
+          for (int k = 0; k < nd; ++k) ub[1 + k] = um[1 + k] - 2.0 * mn * n[k];
+          num_flux(md, um, qm, am, ub, qm, am, n, Fh);
         } else {
           T fl[15];
           phys_flux(md, um, qm, am, fl);
@@ -873,6 +881,10 @@ static OModel to_model(const OMesh& M, const ldgo_model_desc* d) {
       ((md.kind == 4 || md.kind == 5) && md.ncu != M.nd + 1))
     throw std::runtime_error("ncu inconsistent with the model");
   if (md.kind == 1 && md.naux != 1 + M.nd) throw std::runtime_error("convection-diffusion needs aux = [kappa, b]");
+  for (int b : md.bc_kind) {
+    if (b < 0 || b > 3) throw std::runtime_error("unknown boundary kind");
+    if (b == 3 && md.kind != 2 && md.kind != 4) throw std::runtime_error("slip walls need Euler or shallow water");
+  }
   return md;
 }
 

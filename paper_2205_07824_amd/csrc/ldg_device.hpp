@@ -50,6 +50,10 @@ struct MeshDev {
 };
 
 // Device view of a model's parameters.
+// void for any well-formed type list (member detection in the run-time compiled physics)
+template <class... T>
+struct VoidOf { using type = void; };
+
 struct ModelDev {
   double mu[MAXMU];
   int naux;

@@ -14,9 +14,6 @@
 
 namespace ldg {
 
-template <class... T>
-struct VoidOf { using type = void; };
-
 template <class U, class = void>
 struct UserOde {
   static constexpr int NW = 0;

@@ -655,6 +655,9 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const doub
 #pragma unroll
           for (int c = 0; c < NCU; ++c)
             ub[c] = (MODE != 0 && md.bdata) ? T::mk(R(md.bdata[((int64_t)b * NCU + c) * NFP + ff])) : T::mk(R(0));
+#ifdef LDG_USER_PHYSICS
+          if constexpr (KIND == K_USER) boundary_state<KIND, D, V, R>(md.mu, md.naux, tag, um, qm, am, n, ub);
+#endif
           num_flux<KIND, D, V, R>(md.mu, md.naux, um, qm, am, ub, qm, am, n, Fh);
         } else if (kind == BC_NEUMANN) {
 #pragma unroll

@@ -118,6 +118,34 @@ __device__ inline V wave_speed(R gam, const V* u, const R* n) {
   return vabs(vn) + vsqrt(gam * pr * rinv);
 }
 
+#ifdef LDG_USER_PHYSICS
+template <class U, class = void>
+struct UserBou { static constexpr bool value = false; };
+template <class U>
+struct UserBou<U, typename VoidOf<decltype(U::BOU)>::type> { static constexpr bool value = U::BOU; };
+// dependent on U, so that sources without a boundary function never instantiate it
+template <class U, int D, class V, class R>
+__device__ inline void user_bou(const double* mu, int naux, int tag, const V* uL, const V (*qL)[D], const R* aL,
+                                const R* n, V* ub) {
+  static_assert(!U::HASQ, "boundary functions are for sources whose flux does not depend on q");
+  U::template bou<D, V, R>(mu, naux, tag, uL, qL, aL, n, ub);
+}
+#endif
+
+// outside state on a Dirichlet-kind boundary face: ub arrives holding the data g.
+// A model compiled at run time may define a boundary function (LdgUser::BOU and
+// bou<D>), which maps (tag, inside trace, n, g) to the outside state, e.g. a slip
+// wall that reverses the normal momentum; for every other model ub stays g.
+template <int KIND, int D, class V, class R>
+__device__ inline void boundary_state(const double* mu, int naux, int tag, const V* uL, const V (*qL)[D],
+                                      const R* aL, const R* n, V* ub) {
+#ifdef LDG_USER_PHYSICS
+  if constexpr (KIND == K_USER) {
+    if constexpr (UserBou<::LdgUser>::value) user_bou<::LdgUser, D, V, R>(mu, naux, tag, uL, qL, aL, n, ub);
+  }
+#endif
+}
+
 // interior numerical flux (also used at Dirichlet faces with u+ = g, q+ = q-, a+ = a-)
 template <int KIND, int D, class V, class R>
 __device__ inline void num_flux(const double* mu, int naux, const V* uL, const V (*qL)[D], const R* aL,

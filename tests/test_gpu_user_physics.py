@@ -10,6 +10,7 @@
   mu2 > 0 discrete conservation on a periodic mesh (the fluxes are
   conservative and the basis sums to one) and its JVP against central
   differences of its own residual.
+* A boundary function in the source (Euler slip walls) against the oracle's slip wall.
 * The wave model with the coupled displacement ODE (Eq. 1c): one ODE stage
   against its defining equation, and DIRK(3,3) steps against the oracle's.
 """
@@ -328,3 +329,38 @@ def test_dirk_with_coupled_ode_matches_oracle(L):
                                                       axis=1) / 2.0
     _say("bdf + ode steady", np.abs(w - w_exact).max())
     assert np.abs(w - w_exact).max() < 1e-12
+
+
+def test_user_slip_wall_matches_oracle(L):
+    """A boundary function in the physics source: Euler in a channel (periodic in x) whose walls (tags 2, 3)
+    reverse the normal momentum, against the oracle's slip-wall boundary kind: residual and JVP in FP64 and
+    FP32, with a time wrapper; and a uniform flow along the walls stays steady."""
+    import oracle as O
+    p = 3
+    box = I.box_mesh(2, 4, periodic=(True, False), perturb=0.05, seed=5)
+    om = O.Mesh(box, p)
+    m = L.Mesh(box, p)
+    md = L.Model(m, L.MODEL_USER, 4, [1.4], bc_kind=(0, 0, 0, 0), physics_source=U.EULER_2D_SLIP, has_q=False)
+    rng = np.random.default_rng(11)
+    E, nn = m.E, m.nn
+    u = np.empty((E, 4, nn))
+    u[:, 0] = 1.0 + 0.2 * rng.uniform(-1, 1, (E, nn))
+    u[:, 1:3] = 0.3 * rng.uniform(-1, 1, (E, 2, nn))
+    u[:, 3] = 2.5 + 0.2 * rng.uniform(-1, 1, (E, nn))
+    u = u.reshape(-1)
+    v = rng.uniform(-1, 1, u.size)
+    r1 = u + 0.01 * rng.uniform(-1, 1, u.size)
+    a0 = 4.0
+    omd = O.Model(O.MODEL_EULER, 4, [1.4], bc_kind=(0, 0, O.BC_SLIP_WALL, O.BC_SLIP_WALL), a0=a0, r=a0 * r1)
+    G_ref, Jv_ref = om.residual(omd, u), om.jvp(omd, u, v)
+    t = L.Time(a0=a0, r1=dev(r1), c1=a0)
+    for prec, tol in ((L.FP64, 1e-12), (L.FP32, 1e-5)):
+        G = md.residual(dev(u), time=t, prec=prec).cpu().numpy()
+        Jv = md.jvp(dev(u), dev(v), time=t, prec=prec).cpu().numpy()
+        _say("slip wall prec", prec, "residual", rel(G, G_ref), "jvp", rel(Jv, Jv_ref))
+        assert rel(G, G_ref) < tol and rel(Jv, Jv_ref) < tol
+    state = np.array([1.2, 0.6, 0.0, 1.0 / 0.4 + 0.5 * 1.2 * 0.25])
+    us = np.broadcast_to(state[None, :, None], (E, 4, nn)).reshape(-1).copy()
+    G = md.residual(dev(us)).cpu().numpy()
+    _say("slip wall channel flow residual", np.abs(G).max())
+    assert np.abs(G).max() < 1e-12

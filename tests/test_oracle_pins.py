@@ -659,3 +659,41 @@ def test_ode_coupled_temporal_order(scheme, order):
     ws = [_wave_ode_steps(m, U, np.sin(th).reshape(-1), 0.1 / ns, ns, scheme)[1] for ns in (4, 8, 16)]
     rate = np.log2(np.abs(ws[0] - ws[1]).max() / np.abs(ws[1] - ws[2]).max())
     assert abs(rate - order) < 0.15, rate
+
+
+# ---------------------------------------------------------------- slip walls (Euler)
+def _channel(n=4, seed=5):
+    # periodic in x, walls at y = 0 and y = 1 (tags 2 and 3), interior vertices perturbed
+    box = I.box_mesh(2, n, periodic=(True, False), perturb=0.05, seed=seed)
+    return box, O.Mesh(box, 3)
+
+
+def test_slip_wall_channel_flow_is_steady():
+    _, m = _channel()
+    md = O.Model(O.MODEL_EULER, 4, [1.4], bc_kind=(0, 0, O.BC_SLIP_WALL, O.BC_SLIP_WALL))
+    rho, vx, p = 1.2, 0.5, 1.0
+    state = np.array([rho, rho * vx, 0.0, p / 0.4 + 0.5 * rho * vx * vx])
+    u = np.broadcast_to(state[None, :, None], (m.E, 4, m.nn)).reshape(-1).copy()
+    assert np.abs(m.residual(md, u)).max() < 1e-12
+
+
+def test_slip_wall_passes_no_mass_energy_or_tangential_momentum():
+    # the reflected state makes the wall flux (0, 0, p n_y + dissipation, 0) on walls with n = (0, +-1): the
+    # residual summed over all nodes vanishes for mass, x-momentum and energy but not for y-momentum
+    _, m = _channel()
+    md = O.Model(O.MODEL_EULER, 4, [1.4], bc_kind=(0, 0, O.BC_SLIP_WALL, O.BC_SLIP_WALL))
+    rng = np.random.default_rng(7)
+    u = np.empty((m.E, 4, m.nn))
+    u[:, 0] = 1.0 + 0.2 * rng.uniform(-1, 1, (m.E, m.nn))
+    u[:, 1:3] = 0.3 * rng.uniform(-1, 1, (m.E, 2, m.nn))
+    u[:, 3] = 2.5 + 0.2 * rng.uniform(-1, 1, (m.E, m.nn))
+    R = m.residual(md, u.reshape(-1)).reshape(m.E, 4, m.nn)
+    tot = [abs(R[:, c].sum()) / np.abs(R[:, c]).sum() for c in range(4)]
+    assert tot[0] < 1e-13 and tot[1] < 1e-13 and tot[3] < 1e-13, tot
+    assert tot[2] > 1e-3, tot
+    # the wall's tangent agrees with central differences of the residual
+    v = rng.uniform(-1, 1, u.size)
+    Jv = m.jvp(md, u.reshape(-1), v)
+    h = 1e-6
+    fd = (m.residual(md, u.reshape(-1) + h * v) - m.residual(md, u.reshape(-1) - h * v)) / (2 * h)
+    assert np.linalg.norm(Jv - fd) < 1e-7 * np.linalg.norm(Jv)

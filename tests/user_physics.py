@@ -152,6 +152,20 @@ struct LdgUser {
 };
 """
 
+# Euler with slip walls on tags 2 and 3 (the outside state reverses the normal momentum) and the boundary
+# data elsewhere
+EULER_2D_SLIP = EULER_2D.replace("static constexpr int NAUX = 0;", """static constexpr int NAUX = 0;
+  static constexpr bool BOU = true;
+  template <int D, class V, class R>
+  __device__ static void bou(const double*, int, int tag, const V* uL, const V (*)[D], const R*, const R* n,
+                             V* ub) {
+    if (tag != 2 && tag != 3) return;
+    V mn = uL[1] * n[0];
+    for (int k = 1; k < D; ++k) mn += uL[1 + k] * n[k];
+    for (int c = 0; c < NCU; ++c) ub[c] = uL[c];
+    for (int k = 0; k < D; ++k) ub[1 + k] = uL[1 + k] - R(2) * mn * n[k];
+  }""", 1)
+
 # the wave model with the paper's displacement ODE (w_t = u, first component) and a second, nonlinear
 # component s_w = mu[1] q1 q2, so that a sum of two fields and a product are both checked
 WAVE_2D_W = WAVE_2D.replace("static constexpr int NAUX = 0;", """static constexpr int NAUX = 0;
