@@ -422,6 +422,8 @@ def main():
                     help="only one Newton-GMRES form on the Poisson workload (for a kernel trace)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 512 MiB buffer 10 times (scales the HBM byte counters)")
+    ap.add_argument("--profile-wave-only", action="store_true",
+                    help="only the wave model + displacement ODE leg (for a kernel trace)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
@@ -442,6 +444,9 @@ def main():
         return
     if args.profile_mfma_only:
         print(json.dumps(mfma_p4(ldg, I, log, steps=args.steps)))
+        return
+    if args.profile_wave_only:
+        print(json.dumps(wave_displacement_steps(ldg, I, log)))
         return
     box, m, md = build_workload(ldg, I, n=args.n)
     N = md.N

@@ -125,11 +125,26 @@ __global__ void __launch_bounds__(256) k_gj_invert(int nb, double* __restrict__ 
     for (int j = tid; j < nb; j += nt) A[k * nb + j] = (j == k ? 1.0 : A[k * nb + j]) * ipv;
     __syncthreads();
     // rank-1 update of the other rows: thread (r0, j) owns column j of rows r0, r0 + rpp, ...
+    // (four rows per round, all loads issued before the stores: every entry is
+    // read and written by its own thread only, so the reordering is exact)
     if (r0 < rpp) {
       const double akj = A[k * nb + jc];
-      for (int i = r0; i < nb; i += rpp) {
+      const bool kcol = jc == k;
+      int i = r0;
+      for (; i + 3 * rpp < nb; i += 4 * rpp) {
+        double a[4], f[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          a[t] = A[(i + t * rpp) * nb + jc];
+          f[t] = fcol[i + t * rpp];
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (i + t * rpp != k) A[(i + t * rpp) * nb + jc] = (kcol ? 0.0 : a[t]) - f[t] * akj;
+      }
+      for (; i < nb; i += rpp) {
         if (i == k) continue;
-        const double base = (jc == k) ? 0.0 : A[i * nb + jc];
+        const double base = kcol ? 0.0 : A[i * nb + jc];
         A[i * nb + jc] = base - fcol[i] * akj;
       }
     }
