@@ -81,7 +81,7 @@ __global__ void __launch_bounds__(256) k_gj_invert(int nb, double* __restrict__ 
   __shared__ int piv[128];
   __shared__ double fcol[128];
   __shared__ int pidx;
-  __shared__ double bestv;
+  __shared__ double bestv, pval;
   const int64_t b = blockIdx.x;
   double* G = blocks + b * (int64_t)nb * nb;
   double* A = use_lds ? lds : G;
@@ -106,30 +106,33 @@ __global__ void __launch_bounds__(256) k_gj_invert(int nb, double* __restrict__ 
         const int oi = __shfl_down(bi, off, 64);
         if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
       }
-      if (tid == 0) { pidx = bi; bestv = bv; piv[k] = bi; }
+      if (tid == 0) { pidx = bi; bestv = bv; piv[k] = bi; pval = A[bi * nb + k]; }
     }
     __syncthreads();
     const int p = pidx;
-    if (tid == 0 && !(bestv > 0.0)) atomicAdd(info, 1);
-    if (p != k)
-      for (int j = tid; j < nb; j += nt) {
-        const double t = A[k * nb + j];
-        A[k * nb + j] = A[p * nb + j];
-        A[p * nb + j] = t;
-      }
-    __syncthreads();
-    const double pv = A[k * nb + k];
+    const double pv = pval;
     const double ipv = pv != 0.0 ? 1.0 / pv : 0.0;
-    for (int i = tid; i < nb; i += nt) fcol[i] = (i == k) ? 0.0 : A[i * nb + k];
-    __syncthreads();
-    for (int j = tid; j < nb; j += nt) A[k * nb + j] = (j == k ? 1.0 : A[k * nb + j]) * ipv;
+    if (tid == 0 && !(bestv > 0.0)) atomicAdd(info, 1);
+    // interchange rows k and p and scale the new row k, in every column but k;
+    // fcol = the new column k off row k.  Column k itself is only read here: the
+    // update below writes all of it (the inverse's column k is -fcol / pv off
+    // the diagonal and 1 / pv on it)
+    for (int j = tid; j < nb; j += nt) {
+      if (j != k) {
+        const double akj = A[k * nb + j], apj = A[p * nb + j];
+        A[k * nb + j] = apj * ipv;
+        if (p != k) A[p * nb + j] = akj;
+      }
+      fcol[j] = (j == k) ? 0.0 : A[(j == p ? k : j) * nb + k];
+    }
     __syncthreads();
     // rank-1 update of the other rows: thread (r0, j) owns column j of rows r0, r0 + rpp, ...
     // (four rows per round, all loads issued before the stores: every entry is
     // read and written by its own thread only, so the reordering is exact)
+    if (tid == 0) A[k * nb + k] = ipv;
     if (r0 < rpp) {
-      const double akj = A[k * nb + jc];
       const bool kcol = jc == k;
+      const double akj = kcol ? ipv : A[k * nb + jc];
       int i = r0;
       for (; i + 3 * rpp < nb; i += 4 * rpp) {
         double a[4], f[4];
