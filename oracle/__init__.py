@@ -68,6 +68,8 @@ def lib():
         L.ldgo_l2_error.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, dp, dp, dp, dp, dp]
         L.ldgo_point_flux.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, dp]
         L.ldgo_point_numflux.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, dp, dp, dp, dp, dp]
+        L.ldgo_set_tie_break.restype = C.c_int
+        L.ldgo_set_tie_break.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -253,6 +255,23 @@ class Mesh:
         lib().ldgo_l2_error(self.h, m, ncu, c, _d(u), _d(q), _d(np.ascontiguousarray(uex, dtype=np.float64)),
                             _d(None if qex is None else np.ascontiguousarray(qex, dtype=np.float64)), _d(out))
         return out[0] / out[1], (out[2] / out[3] if q is not None else None)
+
+
+class tie_break:
+    """Context manager selecting the one-sided derivative the dual numbers take at an
+    exact kink: +1 is the default convention (sign(0) = +1, a max tie takes the first
+    argument's tangent), -1 the other side."""
+
+    def __init__(self, t):
+        self.t = t
+
+    def __enter__(self):
+        self.old = lib().ldgo_set_tie_break(int(self.t))
+        return self
+
+    def __exit__(self, *exc):
+        lib().ldgo_set_tie_break(self.old)
+        return False
 
 
 def gauss_legendre(m):

@@ -53,8 +53,20 @@ static inline Dual& operator+=(Dual& a, Dual b) { a = a + b; return a; }
 static inline Dual& operator-=(Dual& a, Dual b) { a = a - b; return a; }
 static inline Dual& operator*=(Dual& a, Dual b) { a = a * b; return a; }
 static inline Dual sqrt(Dual a) { double s = std::sqrt(a.v); return Dual(s, a.d / (2.0 * s)); }
-static inline Dual fabs(Dual a) { return a.v >= 0 ? a : -a; }
-static inline Dual dmax(Dual a, Dual b) { return a.v >= b.v ? a : b; }
+// Tie convention at the kinks: +1 (default) is the one above; -1 takes the other
+// one-sided derivative (sign(0) = -1, the tangent of b when a == b), so that a
+// test can form both one-sided directional derivatives at an exact tie.
+static int g_tie = 1;
+static inline Dual fabs(Dual a) {
+  if (a.v > 0) return a;
+  if (a.v < 0) return -a;
+  return g_tie > 0 ? a : -a;
+}
+static inline Dual dmax(Dual a, Dual b) {
+  if (a.v > b.v) return a;
+  if (a.v < b.v) return b;
+  return g_tie > 0 ? a : b;
+}
 static inline double dmax(double a, double b) { return a >= b ? a : b; }
 static inline double value(double a) { return a; }
 static inline double value(Dual a) { return a.v; }
@@ -893,6 +905,14 @@ static OModel to_model(const OMesh& M, const ldgo_model_desc* d) {
 extern "C" {
 
 const char* ldgo_last_error() { return g_err.c_str(); }
+
+// +1: sign(0) = +1 and max ties take the first argument's tangent (the default);
+// -1: the opposite one-sided choice.  Returns the previous setting.
+int ldgo_set_tie_break(int t) {
+  const int old = g_tie;
+  g_tie = t >= 0 ? 1 : -1;
+  return old;
+}
 
 int ldgo_gauss_legendre(int m, double* x, double* w) {
   GUARD({ std::vector<double> a, b; gauss_legendre(m, a, b); for (int i = 0; i < m; ++i) { x[i] = a[i]; w[i] = b[i]; } })

@@ -697,3 +697,110 @@ def test_slip_wall_passes_no_mass_energy_or_tangential_momentum():
     h = 1e-6
     fd = (m.residual(md, u.reshape(-1) + h * v) - m.residual(md, u.reshape(-1) - h * v)) / (2 * h)
     assert np.linalg.norm(Jv - fd) < 1e-7 * np.linalg.norm(Jv)
+
+
+# ---------------------------------------------------------------- NS heat conduction (mu gamma / Pr grad e)
+@pytest.mark.parametrize("nd", [2, 3])
+def test_ns_heat_conduction_closed_form(nd):
+    """Uniform velocity (no shear), linear density and internal energy: the viscous part of
+    the flux is pure conduction, energy flux -(mu gamma / Pr) de/dx_k with e = E/rho - |v|^2/2,
+    and the mass and momentum rows carry no viscous flux."""
+    gam, Re, Pr = 1.4, 25.0, 0.71
+    ncu = nd + 2
+    md = O.Model(O.MODEL_NS, ncu, [gam, Re, Pr, 1.0])
+    mdi = O.Model(O.MODEL_EULER, ncu, [gam])
+    rng = np.random.default_rng(21)
+    for _ in range(4):
+        rho, e = 0.8 + 0.4 * rng.random(), 2.0 + rng.random()
+        V = rng.normal(size=nd) * 0.3
+        grho = rng.normal(size=nd) * 0.2      # grad rho
+        ge = rng.normal(size=nd)              # grad e
+        k2 = 0.5 * V @ V
+        u = np.concatenate([[rho], rho * V, [rho * (e + k2)]])
+        grad = np.zeros((ncu, nd))
+        grad[0] = grho
+        for i in range(nd):
+            grad[1 + i] = V[i] * grho
+        grad[ncu - 1] = grho * (e + k2) + rho * ge
+        q = (-grad).reshape(-1)
+        visc = O.point_flux(mdi, nd, u, q, np.zeros(4)) - O.point_flux(md, nd, u, q, np.zeros(4))
+        cond = gam / (Pr * Re) * ge
+        assert np.abs(visc[ncu - 1] - cond).max() < 1e-13 * (1 + np.abs(cond).max())
+        assert np.abs(visc[:ncu - 1]).max() < 1e-13
+
+
+# ---------------------------------------------------------------- convection-diffusion flux and rates
+def test_convdiff_numerical_flux_upwind_closed_form():
+    """Interior numerical flux of -div(kappa grad u) + div(b u): upwind convective part
+    (b.n) u- for b.n > 0 and (b.n) u+ for b.n < 0, central diffusive part
+    1/2 kappa0 (kappa- q- + kappa+ q+).n and penalty tau kappa0 {kappa} (u- - u+)."""
+    nd = 2
+    rng = np.random.default_rng(22)
+    for tau in (0.0, 3.0):
+        md = O.Model(O.MODEL_CONVDIFF, 1, [1.7, tau], naux=3)
+        for _ in range(8):
+            b = rng.normal(size=nd)
+            kL, kR = 0.5 + rng.random(), 0.5 + rng.random()
+            aL = np.concatenate([[kL], b])
+            aR = np.concatenate([[kR], b])
+            n = rng.normal(size=nd)
+            n /= np.linalg.norm(n)
+            uL, uR = rng.normal(), rng.normal()
+            qL, qR = rng.normal(size=nd), rng.normal(size=nd)
+            F = O.point_numflux(md, nd, [uL], qL, aL, [uR], qR, aR, n)[0]
+            bn = b @ n
+            conv = bn * (uL if bn > 0 else uR)
+            diff = 0.5 * 1.7 * (kL * qL + kR * qR) @ n + tau * 1.7 * 0.5 * (kL + kR) * (uL - uR)
+            assert abs(F - (conv + diff)) < 1e-14 * (1 + abs(conv) + abs(diff))
+
+
+def _convdiff_mms_errors(n, p, b):
+    """-lap u + b.grad u = s on the unit square, u = sin(pi x) sin(pi y), kappa = 1, constant b."""
+    box = I.box_mesh(2, n)
+    m = O.Mesh(box, p)
+    xn, xq, xb, _ = m.points()
+    ue, ge, lap = I.mms_sin2d(xq)
+    s = lap + ge @ b
+    aux = np.concatenate([np.ones((m.E, 1, m.nn)), np.broadcast_to(b[None, :, None], (m.E, 2, m.nn))], axis=1)
+    md = O.Model(O.MODEL_CONVDIFF, 1, [1.0, penalty(p, 1.0 / n)], aux=aux, src=s.reshape(m.E, 1, m.nqv),
+                 bdata=np.zeros((m.nbf, 1, m.nqf)), bc_kind=[0])
+    N = m.size(1)
+    J = m.jacobian(md, np.zeros(N))
+    u = spla.spsolve(J.tocsc(), -m.residual(md, np.zeros(N)))
+    _, q = m.residual(md, u, want_q=True)
+    xe = m.error_points(p + 3)
+    ue, ge, _ = I.mms_sin2d(xe)
+    return m.l2_error(p + 3, 1, 0, u, q, ue, -ge)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_mms_rates_convdiff_2d(p):
+    """Manufactured solution of the convection-diffusion model: u converges at order p+1.
+    A downwind flux, a dropped convective term or a sign error in b.u breaks the rate or
+    the error level."""
+    b = np.array([2.0, -1.0])
+    errs = [_convdiff_mms_errors(n, p, b) for n in (4, 8, 16)]
+    ru = math.log2(errs[1][0] / errs[2][0])
+    assert abs(ru - (p + 1)) < 0.2, (p, ru)
+    assert errs[2][0] < 10.0 ** (-(p + 1)), errs
+
+
+# ---------------------------------------------------------------- Adam
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient g, the bias-corrected moments equal g and g^2 at every
+    step t (1 - b^t cancels exactly), so Adam moves each parameter by -lr g / (|g| + eps)
+    per step: p_t = p_0 - t lr g / (|g| + eps)."""
+    rng = np.random.default_rng(23)
+    shapes = [(5, 4), (5,), (3, 5)]
+    p0 = [rng.normal(size=s) for s in shapes]
+    g = [rng.normal(size=s) for s in shapes]
+    g[1][0] = 0.0
+    m = [np.zeros(s) for s in shapes]
+    v = [np.zeros(s) for s in shapes]
+    lr, eps = 3e-3, 1e-8
+    p = [a.copy() for a in p0]
+    for t in range(1, 6):
+        p = O.adam_step(p, g, m, v, t, lr, eps=eps)
+        for a, a0, gg in zip(p, p0, g):
+            expect = a0 - t * lr * gg / (np.abs(gg) + eps)
+            assert np.abs(a - expect).max() < 1e-12 * t * lr
