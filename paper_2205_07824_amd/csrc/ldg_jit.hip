@@ -38,6 +38,8 @@ std::string program_text(const char* user, int ncu, bool hasq) {
   p += "static_assert(LdgUser::NCU == " + std::to_string(ncu) + ", \"LdgUser::NCU differs from the model's ncu\");\n";
   p += std::string("static_assert(LdgUser::HASQ == ") + (hasq ? "true" : "false") +
        ", \"LdgUser::HASQ differs from has_q\");\n";
+  // the kernels stage max(NAUX, 1) aux values per point: the host reads the bound back
+  p += "extern \"C\" __device__ int ldg_user_naux = LdgUser::NAUX;\n";
   return p;
 }
 
@@ -128,16 +130,26 @@ ldg_status jit_build(Model& md, const char* user) {
     }
   }
   {
-    hipDeviceptr_t pnw = nullptr;
-    size_t bytes = 0;
+    hipDeviceptr_t pnw = nullptr, pna = nullptr;
+    size_t bytes = 0, bytes_a = 0;
+    int naux_max = 0;
     if (hipModuleGetFunction(&J->ode, J->mod, "ldg_k_ode_stage") != hipSuccess ||
         hipModuleGetGlobal(&pnw, &bytes, J->mod, "ldg_user_nw") != hipSuccess || bytes != sizeof(int) ||
-        hipMemcpyDtoH(&J->nw, pnw, sizeof(int)) != hipSuccess) {
+        hipMemcpyDtoH(&J->nw, pnw, sizeof(int)) != hipSuccess ||
+        hipModuleGetGlobal(&pna, &bytes_a, J->mod, "ldg_user_naux") != hipSuccess || bytes_a != sizeof(int) ||
+        hipMemcpyDtoH(&naux_max, pna, sizeof(int)) != hipSuccess) {
       (void)hipGetLastError();
       (void)hipModuleUnload(J->mod);
       delete J;
-      set_error("compiled physics module lacks the ODE kernel");
+      set_error("compiled physics module lacks the ODE kernel or its sizes");
       return LDG_EDEVICE;
+    }
+    if (md.naux > naux_max) {
+      (void)hipModuleUnload(J->mod);
+      delete J;
+      set_error("desc->naux = " + std::to_string(md.naux) + " exceeds LdgUser::NAUX = " + std::to_string(naux_max) +
+                " (the kernels hold NAUX aux values per point)");
+      return LDG_EINVAL;
     }
   }
   for (int f = 0; f < 2; ++f) {

@@ -327,13 +327,21 @@ static ldg_status mlp_backward(MlpNet& net, const float* X, const float* T, int6
 // neighbours contribute zeros.  Features: [r patch / s (5 nn) | log kappa patch
 // (5 nn) | b patch (5 x 2 nn)], s = ||r patch||_2 + 1e-300.  Target rows (when
 // e is given): e on K / s.
-__global__ void k_gather_patches(int64_t B, const int32_t* __restrict__ elems, int nn, const int32_t* __restrict__ nbr,
-                                 const double* __restrict__ r, const double* __restrict__ aux, int naux,
-                                 const double* __restrict__ e, float* __restrict__ X, float* __restrict__ Y,
-                                 double* __restrict__ S) {
+__global__ void k_gather_patches(int64_t B, int64_t E, const int32_t* __restrict__ elems, int nn,
+                                 const int32_t* __restrict__ nbr, const double* __restrict__ r,
+                                 const double* __restrict__ aux, int naux, const double* __restrict__ e,
+                                 float* __restrict__ X, float* __restrict__ Y, double* __restrict__ S) {
   const int64_t bidx = blockIdx.x;
   if (bidx >= B) return;
   const int64_t K = elems ? elems[bidx] : bidx;
+  if (K < 0 || K >= E) {
+    // an element index outside the mesh yields an all-zero sample (scale 0) instead of a stray read
+    for (int t = threadIdx.x; t < 20 * nn; t += blockDim.x) X[bidx * 20 * nn + t] = 0.f;
+    if (Y && e)
+      for (int j = threadIdx.x; j < nn; j += blockDim.x) Y[bidx * nn + j] = 0.f;
+    if (S && threadIdx.x == 0) S[bidx] = 0.0;
+    return;
+  }
   __shared__ double red[64];
   __shared__ int64_t pe[5];
   if (threadIdx.x < 5) {
@@ -497,7 +505,8 @@ ldg_status ldg_mlp_gather_patches(ldg_model md, const double* r, const double* e
   if (!md || !r || !X || B <= 0) { set_error("bad arguments"); return LDG_EINVAL; }
   if (md->mesh->nd != 2 || md->ncu != 1) { set_error("element patches are defined for 2D scalar models"); return LDG_EUNSUPPORTED; }
   if (md->naux != 0 && md->naux != 3) { set_error("patch features need aux = [kappa, b_x, b_y]"); return LDG_EUNSUPPORTED; }
-  hipLaunchKernelGGL(k_gather_patches, dim3((unsigned)B), dim3(64), 0, (hipStream_t)stream, B, elem_idx, md->mesh->nn,
+  hipLaunchKernelGGL(k_gather_patches, dim3((unsigned)B), dim3(64), 0, (hipStream_t)stream, B, md->mesh->E, elem_idx,
+                     md->mesh->nn,
                      md->mesh->d_nbr, r, md->aux, md->naux, e_target, X, Y, S);
   LDG_TRY(hipGetLastError());
   return LDG_OK;
@@ -531,7 +540,7 @@ ldg_status mlp_precond_apply(void* data, const double* r, double* z, hipStream_t
     st = precond_apply_impl(d->bj, r, z, s);
     if (st != LDG_OK) return st;
   }
-  hipLaunchKernelGGL(k_gather_patches, dim3((unsigned)E), dim3(64), 0, s, E, (const int32_t*)nullptr, nn,
+  hipLaunchKernelGGL(k_gather_patches, dim3((unsigned)E), dim3(64), 0, s, E, E, (const int32_t*)nullptr, nn,
                      md.mesh->d_nbr, r, md.aux, md.naux, (const double*)nullptr, d->X, (float*)nullptr, d->S);
   LDG_TRY(hipGetLastError());
   st = mlp_forward(*d->net, d->X, E, d->Yo, s);

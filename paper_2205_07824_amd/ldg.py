@@ -134,10 +134,22 @@ def _check(status, what=""):
         raise LDGError(status, f"{what}: {lib().ldg_last_error().decode()}")
 
 
-def _ptr(t):
+def _ptr(t, what="tensor", dtype=torch.float64, numel=None, optional=True):
+    """Device pointer of a tensor after checking what the C ABI assumes of it: a contiguous
+    HIP tensor of the given dtype and element count.  Any mismatch raises ValueError here,
+    before a wrong-sized or wrong-typed buffer can reach a kernel."""
     if t is None:
-        return None
-    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA/HIP tensors"
+        if optional:
+            return None
+        raise ValueError(f"{what}: required")
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{what}: must be a device (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{what}: dtype {t.dtype}, expected {dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what}: {t.numel()} elements, expected {numel}")
     return C.c_void_p(t.data_ptr())
 
 
@@ -196,14 +208,15 @@ class Time:
     r2: torch.Tensor = None
     c2: float = 0.0
 
-    def c(self):
-        self._c = _Time(self.a0, None if self.r1 is None else self.r1.data_ptr(), self.c1,
-                        None if self.r2 is None else self.r2.data_ptr(), self.c2)
+    def c(self, n):
+        """ABI struct; r1 and r2 must be FP64 device vectors of n entries."""
+        self._c = _Time(self.a0, _ptr(self.r1, "time.r1", numel=n), self.c1, _ptr(self.r2, "time.r2", numel=n),
+                        self.c2)
         return C.byref(self._c)
 
 
-def _time(t):
-    return None if t is None else t.c()
+def _time(t, n):
+    return None if t is None else t.c(n)
 
 
 class Model:
@@ -219,9 +232,12 @@ class Model:
         self.aux, self.src, self.bdata = to(aux), to(src), to(bdata)
         self._mu = _np(mu, np.float64)
         self._bc = _np(bc_kind, np.int32)
-        naux = 0 if self.aux is None else int(self.aux.shape[1])
+        naux = 0 if self.aux is None else int(self.aux.numel() // max(mesh.E * mesh.nn, 1))
+        E, nn = mesh.E, mesh.nn
         d = _ModelDesc(kind, ncu, len(self._mu), self._mu.ctypes.data_as(C.POINTER(C.c_double)), naux,
-                       _ptr(self.aux), _ptr(self.src), _ptr(self.bdata), len(self._bc),
+                       _ptr(self.aux, "aux [E][naux][nn]", numel=E * naux * nn),
+                       _ptr(self.src, "src [E][ncu][nqv]", numel=E * ncu * mesh.nqv),
+                       _ptr(self.bdata, "bdata [nbf][ncu][nqf]", numel=mesh.nbf * ncu * mesh.nqf), len(self._bc),
                        self._bc.ctypes.data_as(C.POINTER(C.c_int32)))
         h = C.c_void_p()
         if physics_source is not None:
@@ -245,22 +261,28 @@ class Model:
 
     def residual(self, u, time=None, prec=FP64, q_out=None, out=None):
         out = self.empty() if out is None else out
-        _check(lib().ldg_residual(self.h, _time(time), _ptr(u), _ptr(out), _ptr(q_out), prec, _stream()),
-               "ldg_residual")
+        N = self.N
+        _check(lib().ldg_residual(self.h, _time(time, N), _ptr(u, "u", numel=N, optional=False),
+                                  _ptr(out, "out", numel=N), _ptr(q_out, "q_out", numel=N * self.mesh.nd), prec,
+                                  _stream()), "ldg_residual")
         return out
 
     def jvp(self, u, v, time=None, prec=FP64, out=None):
         out = self.empty() if out is None else out
-        _check(lib().ldg_jvp(self.h, _time(time), _ptr(u), _ptr(v), _ptr(out), prec, _stream()), "ldg_jvp")
+        N = self.N
+        _check(lib().ldg_jvp(self.h, _time(time, N), _ptr(u, "u", numel=N), _ptr(v, "v", numel=N, optional=False),
+                             _ptr(out, "out", numel=N), prec, _stream()), "ldg_jvp")
         return out
 
     def ode_stage(self, u, time, alpha, beta, out=None):
         """w of one implicit stage of alpha dw/dt + beta w = s_w(u) with the time wrapper `time` (its r1, r2 are
         w-vectors), from the stage's PDE state u."""
-        out = torch.empty(self.mesh.E * self.nw * self.mesh.nn, dtype=torch.float64, device="cuda") \
-            if out is None else out
-        assert out.numel() == self.mesh.E * self.nw * self.mesh.nn
-        _check(lib().ldg_ode_stage(self.h, _time(time), C.c_double(alpha), C.c_double(beta), _ptr(u), _ptr(out),
+        nwv = self.mesh.E * self.nw * self.mesh.nn
+        out = torch.empty(nwv, dtype=torch.float64, device="cuda") if out is None else out
+        if time is None:
+            raise ValueError("ode_stage: a time wrapper is required")
+        _check(lib().ldg_ode_stage(self.h, _time(time, nwv), C.c_double(alpha), C.c_double(beta),
+                                   _ptr(u, "u", numel=self.N, optional=False), _ptr(out, "out", numel=nwv),
                                    _stream()), "ldg_ode_stage")
         return out
 
@@ -271,8 +293,8 @@ class Model:
         else:
             nb = self.ncu * nn
             out = torch.zeros((self.mesh.E, nb, nb), dtype=torch.float64, device="cuda")
-        _check(lib().ldg_jacobian_blocks(self.h, _time(time), _ptr(u), int(per_variable), _ptr(out), _stream()),
-               "ldg_jacobian_blocks")
+        _check(lib().ldg_jacobian_blocks(self.h, _time(time, self.N), _ptr(u, "u", numel=self.N), int(per_variable),
+                                         _ptr(out), _stream()), "ldg_jacobian_blocks")
         return out
 
 
@@ -280,13 +302,16 @@ class BlockJacobi:
     def __init__(self, model, u_lin=None, time=None, per_variable=False, prec=FP64):
         self.model = model
         h = C.c_void_p()
-        _check(lib().ldg_precond_block_jacobi(model.h, _time(time), _ptr(u_lin), int(per_variable), prec, _stream(),
-                                              C.byref(h)), "ldg_precond_block_jacobi")
+        _check(lib().ldg_precond_block_jacobi(model.h, _time(time, model.N), _ptr(u_lin, "u_lin", numel=model.N),
+                                              int(per_variable), prec, _stream(), C.byref(h)),
+               "ldg_precond_block_jacobi")
         self.h = h
 
     def apply(self, r, out=None):
         out = self.model.empty() if out is None else out
-        _check(lib().ldg_precond_apply(self.h, _ptr(r), _ptr(out), _stream()), "ldg_precond_apply")
+        N = self.model.N
+        _check(lib().ldg_precond_apply(self.h, _ptr(r, "r", numel=N, optional=False), _ptr(out, "out", numel=N),
+                                       _stream()), "ldg_precond_apply")
         return out
 
     def __del__(self):
@@ -329,13 +354,19 @@ class MLP:
     def forward(self, X, out=None):
         B = X.shape[0]
         out = torch.empty((B, self.dims[2]), dtype=torch.float32, device="cuda") if out is None else out
-        _check(lib().ldg_mlp_forward(self.h, _ptr(X), B, _ptr(out), _stream()), "ldg_mlp_forward")
+        f32 = torch.float32
+        _check(lib().ldg_mlp_forward(self.h, _ptr(X, "X [B][in]", f32, B * self.dims[0], optional=False), B,
+                                     _ptr(out, "out [B][out]", f32, B * self.dims[2], optional=False), _stream()),
+               "ldg_mlp_forward")
         return out
 
     def train_step(self, X, Y, lr):
         loss = C.c_float()
-        _check(lib().ldg_mlp_train_step(self.h, _ptr(X), _ptr(Y), X.shape[0], float(lr), C.byref(loss), _stream()),
-               "ldg_mlp_train_step")
+        B = X.shape[0]
+        f32 = torch.float32
+        _check(lib().ldg_mlp_train_step(self.h, _ptr(X, "X [B][in]", f32, B * self.dims[0], optional=False),
+                                        _ptr(Y, "Y [B][out]", f32, B * self.dims[2], optional=False), B, float(lr),
+                                        C.byref(loss), _stream()), "ldg_mlp_train_step")
         return float(loss.value)
 
     def __del__(self):
@@ -347,11 +378,18 @@ class MLP:
 def gather_patches(model, r, e=None, elems=None, want_scale=False):
     B = model.mesh.E if elems is None else elems.numel()
     nn = model.mesh.nn
+    if elems is not None and B > 0:
+        lo, hi = int(elems.min()), int(elems.max())
+        if lo < 0 or hi >= model.mesh.E:
+            raise ValueError(f"elems: indices must lie in [0, {model.mesh.E}), got [{lo}, {hi}]")
     X = torch.empty((B, 20 * nn), dtype=torch.float32, device="cuda")
     Y = torch.empty((B, nn), dtype=torch.float32, device="cuda") if e is not None else None
     S = torch.empty(B, dtype=torch.float64, device="cuda") if want_scale else None
-    _check(lib().ldg_mlp_gather_patches(model.h, _ptr(r), _ptr(e), _ptr(elems), B, _ptr(X), _ptr(Y), _ptr(S),
-                                        _stream()), "ldg_mlp_gather_patches")
+    N = model.N
+    _check(lib().ldg_mlp_gather_patches(model.h, _ptr(r, "r", numel=N, optional=False), _ptr(e, "e", numel=N),
+                                        _ptr(elems, "elems", torch.int32), B, _ptr(X, dtype=torch.float32),
+                                        _ptr(Y, dtype=torch.float32), _ptr(S), _stream()),
+           "ldg_mlp_gather_patches")
     return X, Y, S
 
 
@@ -365,7 +403,9 @@ class LearnedPrecond:
 
     def apply(self, r, out=None):
         out = self.model.empty() if out is None else out
-        _check(lib().ldg_precond_apply(self.h, _ptr(r), _ptr(out), _stream()), "ldg_precond_apply")
+        N = self.model.N
+        _check(lib().ldg_precond_apply(self.h, _ptr(r, "r", numel=N, optional=False), _ptr(out, "out", numel=N),
+                                       _stream()), "ldg_precond_apply")
         return out
 
     def __del__(self):
@@ -387,8 +427,10 @@ def gmres(model, b, x=None, u_lin=None, time=None, check=True, **kw):
     x = torch.zeros_like(b) if x is None else x
     o = gmres_opts(**kw)
     st = GmresStats()
-    status = lib().ldg_gmres_solve(model.h, _time(time), _ptr(u_lin), _ptr(b), _ptr(x), C.byref(o), C.byref(st),
-                                   _stream())
+    N = model.N
+    status = lib().ldg_gmres_solve(model.h, _time(time, N), _ptr(u_lin, "u_lin", numel=N),
+                                   _ptr(b, "b", numel=N, optional=False), _ptr(x, "x", numel=N, optional=False),
+                                   C.byref(o), C.byref(st), _stream())
     if check and status not in (LDG_OK,):
         _check(status, "ldg_gmres_solve")
     return x, st.as_dict(), status
@@ -399,7 +441,8 @@ def newton(model, u, time=None, maxit=20, rtol=1e-8, atol=0.0, eta=1e-3, bj_refr
     o = NewtonOpts(maxit, rtol, atol, eta, int(bj_refresh), int(bj_per_variable), bj_prec,
                    gmres_opts(maxit=lin_maxit, **lin))
     st = NewtonStats()
-    status = lib().ldg_newton_solve(model.h, _time(time), _ptr(u), C.byref(o), C.byref(st), _stream())
+    status = lib().ldg_newton_solve(model.h, _time(time, model.N), _ptr(u, "u", numel=model.N, optional=False),
+                                    C.byref(o), C.byref(st), _stream())
     if check and status != LDG_OK:
         _check(status, "ldg_newton_solve")
     return u, st.as_dict(), status
@@ -412,12 +455,13 @@ def user_physics_check(source, nd, p, ncu, has_q=True):
 
 def axpby(a, x, b, y):
     """y = a x + b y on the device (FP64 vectors of equal length)."""
-    assert x.numel() == y.numel()
-    _check(lib().ldg_axpby(x.numel(), C.c_double(a), _ptr(x), C.c_double(b), _ptr(y), _stream()), "ldg_axpby")
+    n = x.numel()
+    _check(lib().ldg_axpby(n, C.c_double(a), _ptr(x, "x", optional=False), C.c_double(b),
+                           _ptr(y, "y", numel=n, optional=False), _stream()), "ldg_axpby")
     return y
 
 
 def norm(x):
     out = C.c_double()
-    _check(lib().ldg_norm2(x.numel(), _ptr(x), C.byref(out), _stream()), "ldg_norm2")
+    _check(lib().ldg_norm2(x.numel(), _ptr(x, "x", optional=False), C.byref(out), _stream()), "ldg_norm2")
     return float(np.sqrt(out.value))

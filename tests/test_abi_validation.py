@@ -81,3 +81,16 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=300)
     assert r.returncode == 2
     assert "one GPU" in r.stdout
+
+
+def test_binding_rejects_host_and_missing_tensors():
+    """The binding checks every tensor before its pointer crosses the ABI (no device needed for these)."""
+    import torch
+    from paper_2205_07824_amd import ldg
+    with pytest.raises(ValueError, match="device"):
+        ldg._ptr(torch.zeros(4, dtype=torch.float64), "v")
+    with pytest.raises(ValueError, match="required"):
+        ldg._ptr(None, "v", optional=False)
+    assert ldg._ptr(None, "v") is None
+    with pytest.raises(ValueError, match="device"):
+        ldg.Time(a0=1.0, r1=torch.zeros(4, dtype=torch.float64)).c(4)

@@ -147,18 +147,37 @@ def test_jacobian_blocks_per_variable_ns(L):
     assert rel(B[:6], Bref) < 1e-12
 
 
-def test_block_jacobi_apply_inverts_blocks(L):
-    import torch
-    c = CS.c2_poisson3d()
-    _say("case c2 block-Jacobi apply")
+# Poisson blocks (nb = 64), Euler p=4 (nb = 100) and per-variable NS p=2 (nb = 27); the Euler
+# blocks need row interchanges in the partial-pivoting elimination (76 in the first 6 blocks)
+BJ_APPLY_CASES = [("c2", False, None, False), ("c3", False, 6, True), ("c4p2", True, 6, False)]
+
+
+@pytest.mark.parametrize("case,per_variable,ncheck,swaps", BJ_APPLY_CASES)
+def test_block_jacobi_apply_inverts_blocks(L, case, per_variable, ncheck, swaps):
+    c = {"c2": lambda: CS.c2_poisson3d(), "c3": lambda: CS.c3_euler2d(n=4),
+         "c4p2": lambda: CS.c4_ns3d(n=3, p=2)}[case]()
+    _say("case", case, "block-Jacobi apply")
     m, md, t, dev = build_gpu(L, c)
-    Bref = c.om.blocks(c.oracle_model(), c.u)
-    for prec, tol in ((L.FP64, 1e-12), (L.FP32, 1e-5)):
-        pc = L.BlockJacobi(md, u_lin=None, time=t, prec=prec)
-        r = np.random.default_rng(4).uniform(-1, 1, c.om.size(1))
-        z = pc.apply(dev(r)).cpu().numpy().reshape(c.om.E, -1)
+    elems = np.arange(ncheck) if ncheck else None
+    Bref = np.asarray(c.om.blocks(c.oracle_model(), c.u, elems=elems, per_variable=per_variable))
+    nb = c.om.nn if per_variable else c.ncu * c.om.nn
+    Bref = Bref.reshape(-1, nb, nb)
+    nblk = Bref.shape[0]
+    # row interchanges of the oracle's partial-pivoting LU on the same blocks
+    lu = CS.O.BlockLU(Bref)
+    nswap = int((lu.piv != np.arange(nb)[None, :]).sum())
+    _say("row interchanges in", nblk, "blocks:", nswap)
+    if swaps:
+        assert nswap > 0
+    u_lin = None if c.kind in (CS.O.MODEL_POISSON, CS.O.MODEL_CONVDIFF) else dev(c.u)
+    for prec, tol in ((L.FP64, 1e-10), (L.FP32, 1e-4)):
+        pc = L.BlockJacobi(md, u_lin=u_lin, time=t, per_variable=per_variable, prec=prec)
+        r = np.random.default_rng(4).uniform(-1, 1, c.om.size(c.ncu))
+        z = pc.apply(dev(r)).cpu().numpy().reshape(-1, nb)[:nblk]
         back = np.einsum("eij,ej->ei", Bref, z).reshape(-1)
-        assert rel(back, r) < tol * 100
+        e = rel(back, r.reshape(-1, nb)[:nblk].reshape(-1))
+        _say(case, "prec", prec, "|B z - r| / |r| =", e)
+        assert e < tol
 
 
 # block sizes 64 (16 groups of four columns), 100 (25), 16 (4), per-variable 27 (7, padded)

@@ -240,6 +240,11 @@ def test_user_model_argument_errors(L):
     with pytest.raises(L.LDGError) as e:
         L.Model(m, L.MODEL_USER, 1, [1.0], physics_source=U.BROKEN, has_q=True)
     assert "physics_source:6" in str(e.value)
+    # more aux fields than the source's NAUX bound (the kernels hold NAUX values per point)
+    aux = np.ones((m.E, 2, m.nn))
+    with pytest.raises(L.LDGError) as e:
+        L.Model(m, L.MODEL_USER, 4, [1.4], aux=aux, physics_source=U.EULER_2D, has_q=False)
+    assert "NAUX" in str(e.value)
     # the library stays usable after the failures
     md = L.Model(m, L.MODEL_USER, 4, [1.4], physics_source=U.EULER_2D, has_q=False)
     assert md.N == 4 * 9 * 4
