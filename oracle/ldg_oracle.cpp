@@ -169,30 +169,37 @@ static void unflat(int flat, int m, int nd, int* ix) {
 }
 
 // multilinear map and its Jacobian at a reference point
+// x(xi) = sum_v N_v(xi) X_v with N_v = prod_k (1 + s_k(v) xi_k) / 2.  Its
+// derivative along xi_j is written over the element's edges along j: the edge
+// vector (X_hi - X_lo) / 2 weighted by the other directions' shape factors, so
+// that a coordinate that does not change along an edge contributes exactly zero
+// (axis-aligned faces get exactly axis-aligned normals, which the tie convention
+// at |v.n| = 0 relies on).
 static void map_point(const OMesh& M, long K, const double* xi, double* x, double* J /*[nd][nd], J[i][j] = dx_i/dxi_j*/) {
   const int nd = M.nd;
   for (int i = 0; i < nd; ++i) { x[i] = 0; for (int j = 0; j < nd; ++j) J[i * nd + j] = 0; }
   for (int v = 0; v < M.nv; ++v) {
     double N = 1.0;
-    double dN[3];
     for (int k = 0; k < nd; ++k) {
       double s = ((v >> k) & 1) ? 1.0 : -1.0;
       N *= 0.5 * (1.0 + s * xi[k]);
     }
-    for (int j = 0; j < nd; ++j) {
-      double t = 1.0;
-      for (int k = 0; k < nd; ++k) {
-        double s = ((v >> k) & 1) ? 1.0 : -1.0;
-        t *= (k == j) ? 0.5 * s : 0.5 * (1.0 + s * xi[k]);
-      }
-      dN[j] = t;
-    }
     const double* Xv = &M.X[(K * M.nv + v) * nd];
-    for (int i = 0; i < nd; ++i) {
-      x[i] += N * Xv[i];
-      for (int j = 0; j < nd; ++j) J[i * nd + j] += dN[j] * Xv[i];
-    }
+    for (int i = 0; i < nd; ++i) x[i] += N * Xv[i];
   }
+  for (int j = 0; j < nd; ++j)
+    for (int v = 0; v < M.nv; ++v) {
+      if ((v >> j) & 1) continue;                 // edge from corner v to corner v + 2^j
+      double w = 0.5;
+      for (int k = 0; k < nd; ++k) {
+        if (k == j) continue;
+        double s = ((v >> k) & 1) ? 1.0 : -1.0;
+        w *= 0.5 * (1.0 + s * xi[k]);
+      }
+      const double* Xlo = &M.X[(K * M.nv + v) * nd];
+      const double* Xhi = &M.X[(K * M.nv + (v | (1 << j))) * nd];
+      for (int i = 0; i < nd; ++i) J[i * nd + j] += w * (Xhi[i] - Xlo[i]);
+    }
 }
 
 static double det_and_inverse(int nd, const double* J, double* Ji) {
