@@ -167,17 +167,24 @@ ldg_status ldg_mesh_create(int nd, int p, int nq1d, int64_t nvert, const double*
         X[v * nd + k] = c;
       }
     }
+    // C[mm] = (1/nv) sum_v (prod over the bits k of mm of +-1) X[v], as one
+    // half-sum / half-difference butterfly per direction: a coefficient whose
+    // corner values coincide (e.g. the xi_y term of x on an axis-aligned
+    // element) comes out exactly zero, so axis-aligned faces get exactly
+    // axis-aligned normals (a sequential signed sum left rounding residues of
+    // ~1e-17, which gave random signs to normal velocities that are exactly
+    // zero, e.g. w = 0 on z-faces, at the kink of |v.n|)
     double* C = &m->h_coef[(size_t)K * nv * nd];
-    for (int mm = 0; mm < nv; ++mm)
-      for (int i = 0; i < nd; ++i) {
-        double s = 0;
-        for (int v = 0; v < nv; ++v) {
-          double sg = 1;
-          for (int k = 0; k < nd; ++k)
-            if ((mm >> k) & 1) sg *= ((v >> k) & 1) ? 1.0 : -1.0;
-          s += sg * X[v * nd + i];
+    for (int t = 0; t < nv * nd; ++t) C[t] = X[t];
+    for (int k = 0; k < nd; ++k)
+      for (int v = 0; v < nv; ++v) {
+        if ((v >> k) & 1) continue;
+        const int w = v | (1 << k);
+        for (int i = 0; i < nd; ++i) {
+          const double lo = C[v * nd + i], hi = C[w * nd + i];
+          C[v * nd + i] = 0.5 * (lo + hi);
+          C[w * nd + i] = 0.5 * (hi - lo);
         }
-        C[mm * nd + i] = s / nv;
       }
     for (int mm = 0; mm < nv; ++mm)
       if (__builtin_popcount(mm) >= 2)

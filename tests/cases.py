@@ -111,10 +111,11 @@ def c3_euler2d(n=6, p=4, seed=1, dt=0.5):
                 u=u, v=np.random.default_rng(seed + 1).uniform(-1, 1, U.shape), om=om)
 
 
-def c4_ns3d(n=3, p=3, seed=1, dt=0.1):
-    """3D Navier-Stokes Taylor-Green vortex p=3 on a periodic n^3 mesh of (0,2pi)^3, BDF2 wrapper."""
+def c4_ns3d(n=3, p=3, seed=1, dt=0.1, shift=0.0):
+    """3D Navier-Stokes Taylor-Green vortex p=3 on a periodic n^3 mesh of (0,2pi)^3 (moved by shift along
+    every axis), BDF2 wrapper."""
     L = 2 * np.pi
-    box = I.box_mesh(3, n, lo=(0, 0, 0), hi=(L, L, L), periodic=(True,) * 3)
+    box = I.box_mesh(3, n, lo=(shift,) * 3, hi=(L + shift,) * 3, periodic=(True,) * 3)
     om = O.Mesh(box, p)
     xn, _, _, _ = om.points()
     U = I.taylor_green(xn, mach=0.1).transpose(0, 2, 1).reshape(-1)
