@@ -1,15 +1,19 @@
 """Benchmark: LDG Jacobian-vector product throughput and Newton-GMRES time-to-1e-8.
 
-Workload: 3D Poisson/heat, LDG p=3 on a 32^3 hex mesh of the unit cube with
-interior vertices perturbed by +-5% of h (seed 0), manufactured solution
-exp(x+y+z) sin(pi x y z), Dirichlet data; N = 32^3 * 64 = 2,097,152 DOF.
+Headline workload: 3D compressible Navier-Stokes, Taylor-Green vortex (Re 1600,
+Mach 0.1, Pr 0.71) on a periodic 64^3 hex mesh of (0, 2 pi)^3, LDG p=3, five
+conserved variables: N = 64^3 * 64 * 5 = 83,886,080 DOF, the largest of the
+configurations and the only one whose vectors exceed the last-level cache.
 
-Timed steps: K applications of the FP64 Jacobian-vector product J v (the
-gradient kernel + the residual/tangent kernel), inputs resident in HBM.
-value = N * K / (timed seconds) in GDOF/s.  After the timed region the same
-run reports: the JVP in FP32, the residual, per-kernel HIP-event timings,
-Newton-GMRES time-to-1e-8 for the plain FP64 block-Jacobi form and the mixed
-forms, and the oracle on a bounded sample of elements on the host (1 core).
+Timed steps: K applications of the FP64 Jacobian-vector product J(u) v with
+q(u) cached as inside GMRES (ldg_jvp_prepared: the gradient kernel for the
+tangent of q + the tangent residual kernel), at the BDF2 wrapper of a CFL-10
+step, inputs resident in HBM.  value = N * K / (timed seconds) in GDOF/s.  After
+the timed region the same run reports the FP32 product, the unprepared product,
+the residual, the 3D Poisson workload (32^3 perturbed hexes: JVPs in every
+precision mode and Newton-GMRES time-to-1e-8 for the plain FP64 block-Jacobi
+form and the mixed forms), the other workload shapes, implicit steps, and the
+oracle on a bounded sample of elements on the host (1 core).
 """
 import argparse
 import hashlib
@@ -30,25 +34,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-JVP_KERNEL_SOURCES = ("ldg_device.hpp", "ldg_physics.hpp", "ldg_operator_kernels.hpp", "ldg_operator_launch.hpp",
-                      "ldg_op_poisson.hip")
+OPERATOR_SOURCES = ("ldg_device.hpp", "ldg_physics.hpp", "ldg_operator_kernels.hpp", "ldg_operator_launch.hpp")
 
 
-def kernel_sources_sha256():
-    """Hash of the sources that define the Poisson JVP kernels (names and contents)."""
+def kernel_sources_sha256(kind_source):
+    """Hash of the sources that define one model kind's operator kernels (names and contents)."""
     h = hashlib.sha256()
-    for name in JVP_KERNEL_SOURCES:
+    for name in OPERATOR_SOURCES + (kind_source,):
         h.update(name.encode())
         with open(os.path.join(ROOT, "paper_2205_07824_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def recorded_traffic(n):
-    """HBM bytes per JVP launch from the committed TCC counter summary, or None
-    when the kernels changed since the counters were taken (or for another size)."""
-    path = os.path.join(ROOT, "profiles", "jvp_poisson3d_p3_32cube_hbm_counters.md")
-    if n != 32 or not os.path.exists(path):
+def recorded_traffic(profile, kind_source):
+    """HBM bytes per JVP launch from a committed TCC counter summary, or None when the kernels changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", profile)
+    if not os.path.exists(path):
         return None
     kv = {}
     with open(path) as f:
@@ -56,9 +59,23 @@ def recorded_traffic(n):
             if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "sources_sha256"):
                 k, v = line.split(":", 1)
                 kv[k] = v.strip()
-    if kv.get("sources_sha256") != kernel_sources_sha256() or "traffic_bytes_per_launch" not in kv:
+    if kv.get("sources_sha256") != kernel_sources_sha256(kind_source) or "traffic_bytes_per_launch" not in kv:
         return None
     return int(kv["traffic_bytes_per_launch"])
+
+
+def host_info():
+    """Host cores and CPU model of the machine the oracle runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
 
 
 def build_workload(ldg, I, n=32, p=3):
@@ -72,6 +89,28 @@ def build_workload(ldg, I, n=32, p=3):
     md = ldg.Model(m, ldg.MODEL_POISSON, 1, [1.0, tau, 0.0], src=f.reshape(m.E, 1, m.nqv),
                    bdata=ub.reshape(m.nbf, 1, m.nqf), bc_kind=(0,))
     return box, m, md
+
+
+def ns_workload(ldg, I, n=64, p=3):
+    """3D compressible Navier-Stokes Taylor-Green vortex (Re 1600, Mach 0.1, Pr 0.71) on a periodic n^3 hex mesh
+    of (0, 2 pi)^3, LDG p=3, BDF2 wrapper at dt = 10 h / max(|v| + c) (CFL 10); u = the initial state, v a seeded
+    U(-1, 1) direction."""
+    import torch
+    L = 2 * np.pi
+    box = I.box_mesh(3, n, lo=(0, 0, 0), hi=(L, L, L), periodic=(True,) * 3)
+    m = ldg.Mesh(box, p)
+    xn, _, _, _ = m.points()
+    Ut = I.taylor_green(xn)                                   # [E][nn][5]
+    del xn
+    rho = Ut[..., 0]
+    vel = np.sqrt((Ut[..., 1:4] ** 2).sum(-1)) / rho
+    pr = 0.4 * (Ut[..., 4] - 0.5 * rho * vel ** 2)
+    dt = 10.0 * (L / n) / float((vel + np.sqrt(1.4 * pr / rho)).max())
+    md = ldg.Model(m, ldg.MODEL_NS, 5, [1.4, 1600.0, 0.71, (p + 1) ** 2 * n / L])
+    u = torch.as_tensor(np.ascontiguousarray(Ut.transpose(0, 2, 1)).reshape(-1), device="cuda")
+    del Ut
+    v = torch.as_tensor(np.random.default_rng(2).uniform(-1, 1, md.N), device="cuda")
+    return box, m, md, u, v, ldg.Time(a0=1.5 / dt), dt
 
 
 def event_time(fn, reps):
@@ -106,8 +145,7 @@ def other_workloads(ldg, I, log):
         res[f"euler2d_p4_256sq_jvp_{nm}_gdofs"] = round(md.N / e / 1e9, 3)
     res["euler2d_p4_256sq_dof"] = md.N
     # the same physics as a run-time compiled model (user source, hipRTC at model creation)
-    sys.path.insert(0, ROOT)
-    from tests import user_physics as UP
+    from paper_2205_07824_amd import physics as UP
     t0 = time.perf_counter()
     mu_ = ldg.Model(m, ldg.MODEL_USER, 4, [1.4], physics_source=UP.EULER_2D, has_q=False)
     res["euler2d_p4_user_physics_compile_s"] = round(time.perf_counter() - t0, 2)
@@ -117,29 +155,6 @@ def other_workloads(ldg, I, log):
         res[f"euler2d_p4_256sq_user_physics_jvp_{nm}_gdofs"] = round(md.N / e / 1e9, 3)
     log("euler", res)
     del md, mu_, m, u, v, Jv
-    torch.cuda.empty_cache()
-    # 3D Navier-Stokes Taylor-Green vortex, p=3, periodic 64^3 on (0, 2 pi)^3, Re 1600, Mach 0.1, Pr 0.71
-    L = 2 * np.pi
-    n = 64
-    box = I.box_mesh(3, n, lo=(0, 0, 0), hi=(L, L, L), periodic=(True,) * 3)
-    m = ldg.Mesh(box, 3)
-    xn, _, _, _ = m.points()
-    U = I.taylor_green(xn).transpose(0, 2, 1).reshape(-1)
-    del xn
-    md = ldg.Model(m, ldg.MODEL_NS, 5, [1.4, 1600.0, 0.71, 16.0 * n / L])
-    u = torch.as_tensor(U, device="cuda")
-    del U
-    v = torch.as_tensor(np.random.default_rng(2).uniform(-1, 1, md.N), device="cuda")
-    t = ldg.Time(a0=1.5 / 0.01)
-    Jv = md.empty()
-    for nm, pr in (("fp64", ldg.FP64), ("fp32", ldg.FP32)):
-        md.jvp(u, v, time=t, out=Jv, prec=pr)
-        e = event_time(lambda: md.jvp(u, v, time=t, out=Jv, prec=pr), 5)
-        res[f"ns3d_tgv_p3_64cube_jvp_{nm}_gdofs"] = round(md.N / e / 1e9, 3)
-        res[f"ns3d_tgv_p3_64cube_jvp_{nm}_ms"] = round(e * 1e3, 3)
-    res["ns3d_tgv_p3_64cube_dof"] = md.N
-    log("ns", res)
-    del md, m, u, v, Jv
     torch.cuda.empty_cache()
     # the Poisson workload scaled to 96^3 (N = 56.6M, vectors larger than the 256 MB last-level cache)
     box, m, md = build_workload(ldg, I, n=96)
@@ -307,8 +322,7 @@ def bickley_jet_steps(ldg, I, log, nsteps=3):
     seconds per step (steps 2..nsteps) in the FP64 and the mixed form."""
     import torch
     from paper_2205_07824_amd import timestep as TS
-    sys.path.insert(0, ROOT)
-    from tests import user_physics as UP
+    from paper_2205_07824_amd import physics as UP
     L, n, g = 4.0 * np.pi, 128, 1.0e4
     box = I.box_mesh(2, n, lo=(-L / 2, -L / 2), hi=(L / 2, L / 2), periodic=(True, True))
     m = ldg.Mesh(box, 4)
@@ -351,8 +365,7 @@ def wave_displacement_steps(ldg, I, log, nsteps=4):
     seconds per step, and the displacement's error against the closed form."""
     import torch
     from paper_2205_07824_amd import timestep as TS
-    sys.path.insert(0, ROOT)
-    from tests import user_physics as UP
+    from paper_2205_07824_amd import physics as UP
     n, p = 256, 4
     m = ldg.Mesh(I.box_mesh(2, n, periodic=(True, True)), p)
     xn, _, _, _ = m.points()
@@ -405,23 +418,28 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--n", type=int, default=32)
+    ap.add_argument("--n", type=int, default=32, help="elements per direction of the 3D Poisson workload")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--orth", choices=("dcgs2", "cgs2"), default="dcgs2",
                     help="Gram-Schmidt variant of the Newton-GMRES legs")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra-workloads", action="store_true",
-                    help="skip the 2D Euler, 3D Navier-Stokes and 96^3 Poisson JVP throughput legs")
+                    help="skip the 2D Euler and 96^3 Poisson JVP throughput legs")
     ap.add_argument("--no-implicit", action="store_true",
                     help="skip the 2D Euler BDF2 Newton-GMRES steps")
     ap.add_argument("--profile-jvp-only", action="store_true",
-                    help="only the timed JVP steps (for counter collection)")
+                    help="only the timed headline JVP steps (for counter collection)")
+    ap.add_argument("--profile-poisson-only", action="store_true",
+                    help="only the FP64 JVP of the 3D Poisson workload (for counter collection)")
     ap.add_argument("--profile-mfma-only", action="store_true",
                     help="only the 2D Poisson p=4 MFMA JVP leg (for counter collection)")
     ap.add_argument("--profile-solve-only", choices=sorted(NEWTON_FORMS), default=None,
                     help="only one Newton-GMRES form on the Poisson workload (for a kernel trace)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 512 MiB buffer 10 times (scales the HBM byte counters)")
+    ap.add_argument("--profile-ns-only", action="store_true",
+                    help="only --steps FP64 Jacobian-vector products of the 64^3 Navier-Stokes workload with q(u) "
+                         "cached (for a kernel trace or counters)")
     ap.add_argument("--profile-wave-only", action="store_true",
                     help="only the wave model + displacement ODE leg (for a kernel trace)")
     args = ap.parse_args()
@@ -448,30 +466,54 @@ def main():
     if args.profile_wave_only:
         print(json.dumps(wave_displacement_steps(ldg, I, log)))
         return
-    box, m, md = build_workload(ldg, I, n=args.n)
-    N = md.N
+    if args.profile_ns_only:
+        _, m, md, u, v, t, _ = ns_workload(ldg, I)
+        Jv = md.empty()
+        for pr in (ldg.FP64,):
+            md.jvp_prepare(u, pr)
+            md.jvp_prepared(u, v, time=t, out=Jv, prec=pr)
+            e = event_time(lambda: md.jvp_prepared(u, v, time=t, out=Jv, prec=pr), args.steps)
+            log(f"ns 64^3 prepared JVP prec {pr}: {e * 1e3:.3f} ms")
+        print(json.dumps({"ns3d_tgv_p3_64cube_prepared_jvp_fp64_ms": round(e * 1e3, 4), "dof": md.N}))
+        return
     if args.profile_solve_only:
+        _, _, md = build_workload(ldg, I, n=args.n)
         orth = ldg.ORTH_DCGS2 if args.orth == "dcgs2" else ldg.ORTH_CGS2
         print(json.dumps(newton_form(ldg, md, args.profile_solve_only, orth, log)))
         return
-    log(f"workload: E={m.E} nn={m.nn} N={N} colours={m.ncolors}")
-    v = torch.as_tensor(np.random.default_rng(2).uniform(-1, 1, N), device="cuda")
-    u = torch.as_tensor(np.random.default_rng(1).uniform(-1, 1, N), device="cuda")
+    if args.profile_poisson_only:
+        _, m, md = build_workload(ldg, I, n=args.n)
+        v = torch.as_tensor(np.random.default_rng(2).uniform(-1, 1, md.N), device="cuda")
+        Jv = md.empty()
+        for _ in range(args.warmup):
+            md.jvp(None, v, out=Jv)
+        e = event_time(lambda: md.jvp(None, v, out=Jv), args.steps)
+        print(json.dumps({"poisson3d_p3_jvp_fp64_us": round(e * 1e6, 2), "n": args.n}))
+        return
+
+    # ---- headline: FP64 J(u) v of the 64^3 Navier-Stokes workload, q(u) cached
+    box_ns, m, md, u, v, t, dt = ns_workload(ldg, I)
+    N = md.N
+    log(f"workload: 64^3 Navier-Stokes TGV, E={m.E} nn={m.nn} N={N} colours={m.ncolors} dt={dt:.4g}")
+    md.jvp_prepare(u, ldg.FP64)
     Jv = md.empty()
 
+    def step():
+        md.jvp_prepared(u, v, time=t, out=Jv, prec=ldg.FP64)
+
     for _ in range(args.warmup):
-        md.jvp(None, v, out=Jv)
+        step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e_jvp = event_time(lambda: md.jvp(None, v, out=Jv), args.steps)
+    e_jvp = event_time(step, args.steps)
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
     value = N * args.steps / T / 1e9
-    log(f"FP64 JVP: {e_jvp * 1e6:.1f} us/launch (events), wall {T / args.steps * 1e6:.1f} us/step")
+    log(f"FP64 JVP (q cached): {e_jvp * 1e3:.3f} ms/launch (events), wall {T / args.steps * 1e3:.3f} ms/step")
 
-    # roofline of the JVP (gradient + tangent kernels): algorithmic bytes = read v,
-    # write Jv (8 B/DOF each) + element geometry (8 vertices x 3 coords x 8 B)
-    alg_bytes = 16.0 * N + 192.0 * m.E
+    # roofline of the product: algorithmic bytes = read u and v, write Jv (24 B/DOF; the uniform mesh needs no
+    # stored geometry)
+    alg_bytes = 24.0 * N
     achieved = alg_bytes / e_jvp / 1e9
     out = {
         "metric": "LDG JVP GDOF/s + Newton-GMRES time-to-1e-8, plain FP64 vs mixed/learned",
@@ -486,13 +528,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"3D Poisson LDG p=3, {args.n}^3 hexes, interior vertices perturbed +-5% h, "
-                               f"exp(x+y+z)sin(pi xyz) manufactured solution",
-                   "dof": N, "elements": m.E, "p": 3, "quadrature": "collocated Gauss-Legendre 4^3"},
-        "roofline": {"bound": "hbm", "kernel": "ldg_jvp (k_grad + k_resid, FP64)", "achieved": round(achieved, 2),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": recorded_traffic(args.n), "alg_bytes_per_launch": alg_bytes,
-                     "launch_us": round(e_jvp * 1e6, 3)},
+        "config": {"workload": "3D compressible Navier-Stokes Taylor-Green vortex (Re 1600, Mach 0.1, Pr 0.71), "
+                               "LDG p=3 on a periodic 64^3 hex mesh of (0, 2pi)^3; FP64 J(u)v with q(u) cached, "
+                               "BDF2 wrapper at CFL 10",
+                   "dof": N, "elements": m.E, "p": 3, "variables": 5, "quadrature": "collocated Gauss-Legendre 4^3"},
+        "roofline": {"bound": "hbm", "kernel": "ldg_jvp_prepared (k_grad: tangent of q; k_resid: tangent residual; "
+                                               "FP64)",
+                     "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": recorded_traffic("jvp_ns3d_tgv_p3_64cube_hbm_counters.md", "ldg_op_ns.hip"),
+                     "alg_bytes_per_launch": alg_bytes, "launch_us": round(e_jvp * 1e6, 3)},
     }
     if args.profile_jvp_only:
         print(json.dumps(out))
@@ -507,33 +552,36 @@ def main():
     copy_gbs = 2.0 * a_.numel() * 8 / e_copy / 1e9
     out["roofline"]["measured_copy_gbs"] = round(copy_gbs, 1)
     out["roofline"]["frac_of_measured_copy"] = round(achieved / copy_gbs, 4)
+    # the same product counting the read of the q(u) cache (3 x 8 B/DOF more)
+    out["roofline"]["achieved_with_q_cache_read"] = round(48.0 * N / e_jvp / 1e9, 2)
     del a_, c_
     torch.cuda.empty_cache()
 
-    # other precisions / operator evaluations (events, outside the timed steps)
-    extra = {}
-    e32 = event_time(lambda: md.jvp(None, v, out=Jv, prec=ldg.FP32), 50)
-    extra["jvp_fp32_gdofs"] = round(N / e32 / 1e9, 3)
-    Jref = md.jvp(None, v).clone()
-    for nm, pr in (("bf16_mfma", ldg.BF16_MFMA), ("fp16_mfma", ldg.FP16_MFMA), ("fp32", ldg.FP32)):
-        try:
-            eb = event_time(lambda: md.jvp(None, v, out=Jv, prec=pr), 50)
-            extra[f"jvp_{nm}_gdofs"] = round(N / eb / 1e9, 3)
-            extra[f"jvp_{nm}_rel_err_vs_fp64"] = float(((Jv - Jref).norm() / Jref.norm()).item())
-        except ldg.LDGError as ex:
-            extra[f"jvp_{nm}_gdofs"] = None
-            log(nm, "jvp:", ex)
+    extra = {"ns3d_tgv_p3_64cube_jvp_fp64_ms": round(e_jvp * 1e3, 4)}
+    md.jvp_prepare(u, ldg.FP32)
+    e32 = event_time(lambda: md.jvp_prepared(u, v, time=t, out=Jv, prec=ldg.FP32), 10)
+    extra["ns3d_tgv_p3_64cube_jvp_fp32_ms"] = round(e32 * 1e3, 4)
+    extra["ns3d_tgv_p3_64cube_jvp_fp32_gdofs"] = round(N / e32 / 1e9, 3)
+    Jref = md.jvp_prepared(u, v, time=t, prec=ldg.FP64).clone()
+    J32 = md.jvp_prepared(u, v, time=t, prec=ldg.FP32)
+    extra["ns3d_tgv_p3_64cube_jvp_fp32_rel_err_vs_fp64"] = float(((J32 - Jref).norm() / Jref.norm()).item())
+    del J32
+    eu = event_time(lambda: md.jvp(u, v, time=t, out=Jv, prec=ldg.FP64), 5)
+    extra["ns3d_tgv_p3_64cube_jvp_fp64_with_q_ms"] = round(eu * 1e3, 4)
     G = md.empty()
-    er = event_time(lambda: md.residual(u, out=G), 50)
-    extra["residual_fp64_gdofs"] = round(N / er / 1e9, 3)
-    extra["jvp_fp64_us"] = round(e_jvp * 1e6, 2)
-    extra["jvp_fp32_us"] = round(e32 * 1e6, 2)
-    log("extra:", extra)
+    er = event_time(lambda: md.residual(u, time=t, out=G), 5)
+    extra["ns3d_tgv_p3_64cube_residual_fp64_ms"] = round(er * 1e3, 4)
+    del G
+    log("ns extra:", extra)
 
-    # Newton-GMRES to ||G|| <= 1e-8 ||G(u0)||, u0 = 0, GMRES(30) + block Jacobi
-    if not args.no_solve:
-        orth = ldg.ORTH_DCGS2 if args.orth == "dcgs2" else ldg.ORTH_CGS2
-        out["newton_gmres"] = {name: newton_form(ldg, md, name, orth, log) for name in NEWTON_FORMS}
+    # oracle on a bounded sample of elements, host, one core
+    if not args.no_cpu:
+        out["cpu_baseline"] = ns_cpu_baseline(box_ns, md, u, v, t, Jref, log)
+    del md, m, u, v, Jv, Jref
+    torch.cuda.empty_cache()
+
+    # ---- the 3D Poisson workload (32^3 perturbed hexes): every precision mode, Newton-GMRES forms
+    out["poisson3d_p3_32cube"] = poisson_legs(ldg, I, args, log)
 
     # JVP throughput on the other workload shapes (FP64 and FP32, HIP events)
     if not args.no_extra_workloads:
@@ -548,38 +596,80 @@ def main():
         out["implicit_steps"] = implicit_steps(ldg, I, log)
         out["bickley_jet"] = bickley_jet_steps(ldg, I, log)
         out["wave_displacement"] = wave_displacement_steps(ldg, I, log)
-
-    # oracle on a bounded sample of elements, host, one core
-    if not args.no_cpu:
-        try:
-            import oracle as O
-            om = O.Mesh(box, 3)
-            xn, xq, xb, _ = om.points()
-            _, _, f = I.mms_expsin3d(xq)
-            ub, _, _ = I.mms_expsin3d(xb)
-            omd = O.Model(O.MODEL_POISSON, 1, [1.0, 16.0 * args.n, 0.0], src=f.reshape(om.E, 1, om.nqv),
-                          bdata=ub.reshape(om.nbf, 1, om.nqf), bc_kind=[0])
-            vv = v.cpu().numpy()
-            uu = np.zeros(N)
-            sel = np.arange(0, om.E, max(1, om.E // 12288), dtype=np.int64)[:12288]
-            t0 = time.process_time()
-            _, Jv_s = om.sample(omd, uu, vv, sel)
-            tc = time.process_time() - t0
-            # spot parity of the timed GPU kernels on the sample
-            Jg = md.jvp(None, v).cpu().numpy().reshape(om.E, -1)[sel]
-            err = float(np.linalg.norm(Jg - Jv_s) / np.linalg.norm(Jv_s))
-            dofs = len(sel) * om.nn
-            out["cpu_baseline"] = {"value": round(dofs / tc / 1e9, 6), "unit": "GDOF/s", "cores": 1,
-                                   "kind": "oracle",
-                                   "sample": f"FP64 oracle JVP on {len(sel)} of {om.E} elements (each with its q "
-                                             f"neighbourhood), {tc:.1f} s process time",
-                                   "gpu_vs_oracle_rel_err_on_sample": err}
-            log("cpu baseline", out["cpu_baseline"])
-        except Exception as ex:  # the oracle is optional on the measuring box
-            log("cpu baseline skipped:", ex)
-            out["cpu_baseline"] = None
     out["extra"] = extra
     print(json.dumps(out))
+
+
+def ns_cpu_baseline(box, md, u, v, t, Jgpu, log, budget_s=15.0):
+    """The oracle's FP64 J(u) v of the Navier-Stokes workload on a bounded sample of elements (each with the
+    neighbourhood its q needs), on one host core, and the GPU product compared on the same rows."""
+    try:
+        import oracle as O
+        om = O.Mesh(box, 3)
+        omd = O.Model(O.MODEL_NS, 5, list(md.mu), a0=t.a0)
+        uu, vv = u.cpu().numpy(), v.cpu().numpy()
+        probe = np.arange(0, om.E, om.E // 32, dtype=np.int64)[:32]
+        t0 = time.process_time()
+        om.sample(omd, uu, vv, probe)
+        per = (time.process_time() - t0) / len(probe)
+        count = int(min(om.E, max(64, budget_s / max(per, 1e-9))))
+        sel = np.unique(np.linspace(0, om.E - 1, count).astype(np.int64))
+        t0 = time.process_time()
+        _, Jv_s = om.sample(omd, uu, vv, sel)
+        tc = time.process_time() - t0
+        Jg = Jgpu.cpu().numpy().reshape(om.E, -1)[sel]
+        err = float(np.linalg.norm(Jg - Jv_s) / np.linalg.norm(Jv_s))
+        dofs = len(sel) * om.nn * 5
+        res = {"value": round(dofs / tc / 1e9, 7), "unit": "GDOF/s", "cores": 1, "kind": "oracle",
+               "sample": f"FP64 oracle J(u)v with q(u) formed on each element's neighbourhood, {len(sel)} of "
+                         f"{om.E} elements of the 64^3 Navier-Stokes workload, {tc:.1f} s process time",
+               "gpu_vs_oracle_rel_err_on_sample": err}
+        res.update(host_info())
+        log("cpu baseline", res)
+        return res
+    except Exception as ex:  # the oracle is optional on the measuring box
+        log("cpu baseline skipped:", ex)
+        return None
+
+
+def poisson_legs(ldg, I, args, log):
+    """3D Poisson p=3 on 32^3 perturbed hexes: the FP64 JVP (events), every other precision mode with its error,
+    the residual, and Newton-GMRES time-to-1e-8 in the six forms."""
+    import torch
+    box, m, md = build_workload(ldg, I, n=args.n)
+    N = md.N
+    v = torch.as_tensor(np.random.default_rng(2).uniform(-1, 1, N), device="cuda")
+    u = torch.as_tensor(np.random.default_rng(1).uniform(-1, 1, N), device="cuda")
+    Jv = md.empty()
+    for _ in range(5):
+        md.jvp(None, v, out=Jv)
+    e64 = event_time(lambda: md.jvp(None, v, out=Jv), 100)
+    res = {"workload": f"3D Poisson LDG p=3, {args.n}^3 hexes, interior vertices perturbed +-5% h", "dof": N,
+           "jvp_fp64_us": round(e64 * 1e6, 2), "jvp_fp64_gdofs": round(N / e64 / 1e9, 3)}
+    alg = 16.0 * N + 192.0 * m.E
+    res["jvp_fp64_roofline"] = {"alg_bytes": alg, "achieved_gbs": round(alg / e64 / 1e9, 1),
+                                "frac": round(alg / e64 / 1e9 / HBM_PEAK_GBS, 4),
+                                "traffic": recorded_traffic("jvp_poisson3d_p3_32cube_hbm_counters.md",
+                                                            "ldg_op_poisson.hip")}
+    Jref = md.jvp(None, v).clone()
+    for nm, pr in (("fp32", ldg.FP32), ("bf16_mfma", ldg.BF16_MFMA), ("fp16_mfma", ldg.FP16_MFMA)):
+        try:
+            eb = event_time(lambda: md.jvp(None, v, out=Jv, prec=pr), 50)
+            res[f"jvp_{nm}_gdofs"] = round(N / eb / 1e9, 3)
+            res[f"jvp_{nm}_rel_err_vs_fp64"] = float(((Jv - Jref).norm() / Jref.norm()).item())
+        except ldg.LDGError as ex:
+            res[f"jvp_{nm}_gdofs"] = None
+            log(nm, "jvp:", ex)
+    G = md.empty()
+    er = event_time(lambda: md.residual(u, out=G), 50)
+    res["residual_fp64_gdofs"] = round(N / er / 1e9, 3)
+    log("poisson:", res)
+    if not args.no_solve:
+        orth = ldg.ORTH_DCGS2 if args.orth == "dcgs2" else ldg.ORTH_CGS2
+        res["newton_gmres"] = {name: newton_form(ldg, md, name, orth, log) for name in NEWTON_FORMS}
+    del md, m, u, v, Jv, Jref, G
+    torch.cuda.empty_cache()
+    return res
 
 
 if __name__ == "__main__":

@@ -181,8 +181,16 @@ ldg_status ldg_model_destroy(ldg_model model);
  * vmax).  f is the physical flux [NCU][D] (R = -(f, grad phi) + <Fh, phi> -
  * (src, phi)), Fh the numerical flux along the unit normal n (interior faces,
  * Dirichlet faces with uR = g, qR = qL); Neumann and extrapolation tags behave
- * as for the built-in models.  A source with HASQ = false may also define the
- * outside state of its Dirichlet-kind faces (e.g. a slip wall):
+ * as for the built-in models.  A source may also define the state-dependent
+ * source s(u, q) of Eq. 1b, which enters the residual as -(s, phi) beside the
+ * data field desc->src:
+ *
+ *     static constexpr bool SOURCE = true;
+ *     template <int D, class V, class R> __device__ static void
+ *       source(const double* mu, int naux, const V* u, const V (*q)[D], const R* a, V* s);
+ *
+ * (s: [NCU] at one point), and the outside state of its Dirichlet-kind faces
+ * (e.g. a slip wall):
  *
  *     static constexpr bool BOU = true;
  *     template <int D, class V, class R> __device__ static void
@@ -190,8 +198,9 @@ ldg_status ldg_model_destroy(ldg_model model);
  *           const R* aL, const R* n, V* ub);
  *
  * ub arrives holding the tag's data g (zero without boundary data) and leaves
- * holding uR for numflux.  desc->kind must be LDG_MODEL_USER; the source
- * term is the data field desc->src.  The model is nonlinear: JVPs need u.
+ * holding uR for numflux; the outside gradient there is qR = qL, and the
+ * gradient equation's boundary trace stays uhat = g.  desc->kind must be
+ * LDG_MODEL_USER.  The model is nonlinear: JVPs need u.
  * Errors: LDG_EINVAL with the compiler's log in ldg_last_error() when the
  * source does not compile; otherwise as ldg_model_create. */
 ldg_status ldg_model_create_user(ldg_mesh mesh, const ldg_model_desc* desc, const char* physics_source, int has_q,
@@ -246,6 +255,20 @@ ldg_status ldg_residual(ldg_model model, const ldg_time* t, const double* u, dou
  * (may be NULL).  u, v, Jv: DEVICE [E][ncu][nn]; Jv must not alias u or v. */
 ldg_status ldg_jvp(ldg_model model, const ldg_time* t, const double* u, const double* v, double* Jv,
                    ldg_precision prec, void* stream);
+
+/* The same product with q(u) cached, as the solvers evaluate it (Section 3.3:
+ * inside Newton-GMRES every product of one linear solve shares the
+ * linearization point u, so q(u) = -grad u of Eq. 1a is formed once).
+ * ldg_jvp_prepare computes q(u) into the model's cache for prec (LDG_FP64 or
+ * LDG_FP32; a no-op for models without q); ldg_jvp_prepared then evaluates
+ * J(u) v like ldg_jvp without recomputing it.  The cache is keyed by the
+ * pointer u and the precision: the caller must not change u's contents in
+ * between, and ldg_jvp, ldg_gmres_solve, ldg_newton_solve and the block-Jacobi
+ * builds on the same model replace the cache.  Errors: LDG_EINVAL when q of
+ * this u is not cached in this precision. */
+ldg_status ldg_jvp_prepare(ldg_model model, const double* u, ldg_precision prec, void* stream);
+ldg_status ldg_jvp_prepared(ldg_model model, const ldg_time* t, const double* u, const double* v, double* Jv,
+                            ldg_precision prec, void* stream);
 
 /* ------------------------------------------------------- preconditioners --- */
 /* Exact diagonal blocks dG_K/du_K of the Jacobian at u_lin, by probing with the

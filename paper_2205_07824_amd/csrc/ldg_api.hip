@@ -288,6 +288,27 @@ ldg_status ldg_mesh_create(int nd, int p, int nq1d, int64_t nvert, const double*
     clist.insert(clist.end(), m->color_elems[c].begin(), m->color_elems[c].end());
   }
   m->color_off[m->ncolors] = (int64_t)clist.size();
+  // per colour, the elements whose q tangent a JVP seeded on that colour needs
+  // (the colour and its face neighbours)
+  std::vector<int32_t> nlist;
+  m->nbhd_off.assign(m->ncolors + 1, 0);
+  {
+    std::vector<int64_t> mark(nelem, -1);
+    for (int c = 0; c < m->ncolors; ++c) {
+      m->nbhd_off[c] = (int64_t)nlist.size();
+      std::vector<int32_t> sc;
+      for (int32_t K : m->color_elems[c]) {
+        if (mark[K] != c) { mark[K] = c; sc.push_back(K); }
+        for (int F = 0; F < nf; ++F) {
+          const int32_t nb = m->h_nbr[(size_t)K * nf + F];
+          if (nb >= 0 && mark[nb] != c) { mark[nb] = c; sc.push_back(nb); }
+        }
+      }
+      std::sort(sc.begin(), sc.end());
+      nlist.insert(nlist.end(), sc.begin(), sc.end());
+    }
+    m->nbhd_off[m->ncolors] = (int64_t)nlist.size();
+  }
 
   // operator visit order.  3D: elements sorted by the Morton code of their
   // centroid (the constant monomial coefficient), so that the work-groups in
@@ -335,11 +356,15 @@ ldg_status ldg_mesh_create(int nd, int p, int nq1d, int64_t nvert, const double*
     e = hipMemcpy(m->d_btag, m->h_btag.data(), m->h_btag.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc((void**)&m->d_color_list, clist.size() * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemcpy(m->d_color_list, clist.data(), clist.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->d_color_nbhd, std::max<size_t>(1, nlist.size()) * sizeof(int32_t));
+  if (e == hipSuccess && !nlist.empty())
+    e = hipMemcpy(m->d_color_nbhd, nlist.data(), nlist.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc((void**)&m->d_order, m->h_order.size() * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemcpy(m->d_order, m->h_order.data(), m->h_order.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     set_error(std::string("mesh upload: ") + hipGetErrorString(e));
-    hipFree(m->d_coef); hipFree(m->d_nbr); hipFree(m->d_btag); hipFree(m->d_color_list); hipFree(m->d_order);
+    hipFree(m->d_coef); hipFree(m->d_nbr); hipFree(m->d_btag); hipFree(m->d_color_list); hipFree(m->d_color_nbhd);
+    hipFree(m->d_order);
     delete m;
     return e == hipErrorOutOfMemory ? LDG_ENOMEM : LDG_EDEVICE;
   }
@@ -399,7 +424,8 @@ ldg_status ldg_mesh_points(ldg_mesh m, double* xnode, double* xquad, double* xbf
 ldg_status ldg_mesh_destroy(ldg_mesh m) {
   LDG_ENTER();
   if (!m) return LDG_OK;
-  hipFree(m->d_coef); hipFree(m->d_nbr); hipFree(m->d_btag); hipFree(m->d_color_list); hipFree(m->d_order);
+  hipFree(m->d_coef); hipFree(m->d_nbr); hipFree(m->d_btag); hipFree(m->d_color_list); hipFree(m->d_color_nbhd);
+    hipFree(m->d_order);
   delete m;
   return LDG_OK;
 }
@@ -482,6 +508,7 @@ static ldg_status model_create(ldg_mesh m, const ldg_model_desc* d, const char* 
   }
   if (md->linear) {
     ldg_status st = op_data_terms(*md, s);
+    if (st == LDG_OK) st = mfma_prepare(*md);
     if (st != LDG_OK) { ldg_model_destroy(md); return st; }
   } else {
     md->d_srcn = const_cast<double*>(d->src);   // collocated: quadrature points are the nodes
@@ -627,8 +654,10 @@ ldg_status jvp_impl(Model& md, const ldg_time* t, const double* u, const double*
   ldg_status st;
   void* qc = fp32 ? (void*)md.d_q32 : (void*)md.d_q;
   if (!prepared && md.hasq) {
+    md.q_of[fp32 ? 1 : 0] = nullptr;
     st = op_grad(md, u, qc, fp32, true, s);
     if (st != LDG_OK) return st;
+    md.q_of[fp32 ? 1 : 0] = u;
   }
   if (md.hasq) {
     st = op_grad(md, v, md.d_dq, fp32, false, s);
@@ -655,6 +684,36 @@ ldg_status ldg_jvp(ldg_model md, const ldg_time* t, const double* u, const doubl
   CHECK_ARG(md && v && Jv, "null argument");
   CHECK_ARG(Jv != v && Jv != u, "Jv must not alias u or v");
   return jvp_impl(*md, t, u, v, Jv, prec, false, (hipStream_t)stream);
+}
+
+ldg_status ldg_jvp_prepare(ldg_model md, const double* u, ldg_precision prec, void* stream) {
+  LDG_ENTER();
+  CHECK_ARG(md && u, "null argument");
+  CHECK_ARG(prec == LDG_FP64 || prec == LDG_FP32, "ldg_jvp_prepare: precision must be FP64 or FP32");
+  if (md->linear || !md->hasq) return LDG_OK;
+  const bool fp32 = prec == LDG_FP32;
+  md->q_of[fp32 ? 1 : 0] = nullptr;
+  ldg_status st = op_grad(*md, u, fp32 ? (void*)md->d_q32 : (void*)md->d_q, fp32, true, (hipStream_t)stream);
+  if (st != LDG_OK) return st;
+  md->q_of[fp32 ? 1 : 0] = u;
+  return LDG_OK;
+}
+
+ldg_status ldg_jvp_prepared(ldg_model md, const ldg_time* t, const double* u, const double* v, double* Jv,
+                            ldg_precision prec, void* stream) {
+  LDG_ENTER();
+  CHECK_ARG(md && v && Jv, "null argument");
+  CHECK_ARG(Jv != v && Jv != u, "Jv must not alias u or v");
+  if (prec != LDG_FP64 && prec != LDG_FP32) return jvp_impl(*md, t, u, v, Jv, prec, false, (hipStream_t)stream);
+  if (!md->linear && md->hasq) {
+    CHECK_ARG(u != nullptr, "nonlinear model needs u");
+    if (md->q_of[prec == LDG_FP32 ? 1 : 0] != u) {
+      set_error("ldg_jvp_prepared: q of this u is not cached in this precision (call ldg_jvp_prepare first; "
+                "solver and preconditioner calls on the model replace the cache)");
+      return LDG_EINVAL;
+    }
+  }
+  return jvp_impl(*md, t, u, v, Jv, prec, true, (hipStream_t)stream);
 }
 
 ldg_status ldg_axpby(int64_t n, double a, const double* x, double b, double* y, void* stream) {

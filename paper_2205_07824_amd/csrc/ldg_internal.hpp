@@ -41,10 +41,24 @@ struct Mesh {
   std::vector<int32_t> h_order;       // [E] Morton order of the element centroids
   int32_t* d_order = nullptr;
   std::vector<int64_t> color_off;     // [ncolors+1] offsets into d_color_list
+  int32_t* d_color_nbhd = nullptr;    // per colour: its elements and their face neighbours, sorted
+  std::vector<int64_t> nbhd_off;      // [ncolors+1] offsets into d_color_nbhd
+  // Element subsets of the operator launches ([0] gradient kernels, [1]
+  // residual / tangent kernels; nullptr = every element).  Block probing sets
+  // them: a JVP seeded on one colour needs its rows only on that colour, and
+  // the tangent of q only on the colour and its face neighbours.
+  const int32_t* sub_list[2] = {nullptr, nullptr};
+  int64_t sub_count[2] = {0, 0};
   MeshDev dev() const { return MeshDev{(int)E, (int)nbf, d_coef, d_nbr, d_btag, d_order}; }
+  MeshDev dev_op(int which) const {
+    if (!sub_list[which]) return dev();
+    return MeshDev{(int)sub_count[which], (int)nbf, d_coef, d_nbr, d_btag, sub_list[which]};
+  }
+  int64_t op_E(int which) const { return sub_list[which] ? sub_count[which] : E; }
 };
 
 struct JitOps;   // run-time compiled physics (ldg_jit.hip)
+struct MfmaWork; // operators of the MFMA product (ldg_mfma.hip)
 
 struct Model {
   Mesh* mesh;
@@ -58,6 +72,7 @@ struct Model {
   bool linear;
   bool hasq = true;           // the model's flux depends on q (all but Euler)
   JitOps* jit = nullptr;      // kernels of a model compiled at run time
+  MfmaWork* mfma = nullptr;   // operators of the MFMA product (linear models)
   double* d_qg = nullptr;     // linear models: q offset from boundary data  [E][ncu][nd][nn]
   double* d_dterm = nullptr;  // linear models: data terms of the residual   [E][ncu][nn]
   double* d_srcn = nullptr;   // nonlinear models: source at nodes          [E][ncu][nn]
@@ -69,6 +84,7 @@ struct Model {
   double* d_tmp = nullptr;    // vector-size scratch (FD JVP, linearization)
   double* d_tmp2 = nullptr;
   double* d_red = nullptr;    // reduction scratch (4096 doubles)
+  const double* q_of[2] = {nullptr, nullptr};   // state whose q sits in d_q / d_q32 (ldg_jvp_prepared checks it)
   size_t N() const { return (size_t)mesh->E * ncu * mesh->nn; }
   ModelDev dev() const {
     ModelDev d{};
@@ -105,7 +121,8 @@ ldg_status op_jvp_nonlinear(const Model& md, const TimeDev& t, const double* u, 
                             const void* dq, double* out, bool fp32, hipStream_t s);
 ldg_status op_data_terms(Model& md, hipStream_t s);
 ldg_status op_mfma_jvp(const Model& md, const TimeDev& t, const double* v, double* out, bool fp16, hipStream_t s);
-void mfma_release(const Model& md);
+ldg_status mfma_prepare(Model& md);
+void mfma_release(Model& md);
 
 // run-time compiled physics (ldg_jit.hip)
 ldg_status jit_build(Model& md, const char* user_source);

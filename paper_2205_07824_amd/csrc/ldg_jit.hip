@@ -176,6 +176,7 @@ ldg_status jit_check(const char* user, int nd, int p1, int ncu, bool hasq) {
 namespace {
 ldg_status launch(hipFunction_t f, int64_t E, int epb, int nn, void** args, hipStream_t s) {
   const unsigned nblk = (unsigned)((E + epb - 1) / epb);
+  if (nblk == 0) return LDG_OK;
   if (hipModuleLaunchKernel(f, nblk, 1, 1, (unsigned)(epb * nn), 1, 1, 0, s, args, nullptr) != hipSuccess) {
     set_error(std::string("launch of a compiled physics kernel failed: ") + hipGetErrorString(hipGetLastError()));
     return LDG_EDEVICE;
@@ -188,20 +189,20 @@ ldg_status launch(hipFunction_t f, int64_t E, int epb, int nn, void** args, hipS
 ldg_status jit_grad(const Model& md, const double* u, void* q, bool fp32, bool with_data, hipStream_t s) {
   if (!md.hasq) return LDG_OK;
   const Mesh& m = *md.mesh;
-  MeshDev mdv = m.dev();
+  MeshDev mdv = m.dev_op(0);
   ModelDev mod = md.dev();
   const double* qoff = nullptr;
   const float* dux = nullptr;
   BasisTab tab = m.tab;
   BasisTabF tabf = m.tabf;
   void* args[] = {&mdv, fp32 ? (void*)&tabf : (void*)&tab, &mod, (void*)&u, &q, (void*)&qoff, (void*)&dux};
-  return launch(md.jit->grad[fp32][with_data], m.E, md.jit->epb_grad[fp32], m.nn, args, s);
+  return launch(md.jit->grad[fp32][with_data], m.op_E(0), md.jit->epb_grad[fp32], m.nn, args, s);
 }
 
 ldg_status jit_resid(const Model& md, const TimeDev& t, const double* u, const void* q, const double* v,
                      const void* dq, double* out, bool fp32, bool tangent, hipStream_t s) {
   const Mesh& m = *md.mesh;
-  MeshDev mdv = m.dev();
+  MeshDev mdv = m.dev_op(1);
   ModelDev mod = md.dev();
   TimeDev td = t;
   BasisTab tab = m.tab;
@@ -210,7 +211,7 @@ ldg_status jit_resid(const Model& md, const TimeDev& t, const double* u, const v
   float* Fout = nullptr;
   void* args[] = {&mdv,     fp32 ? (void*)&tabf : (void*)&tab, &mod, &td, (void*)&u, (void*)&q, (void*)&v,
                   (void*)&dq, (void*)&dterm, &out, &Fout};
-  return launch(md.jit->resid[fp32][tangent], m.E, md.jit->epb_resid[fp32][tangent], m.nn, args, s);
+  return launch(md.jit->resid[fp32][tangent], m.op_E(1), md.jit->epb_resid[fp32][tangent], m.nn, args, s);
 }
 
 int jit_ode_size(const Model& md) { return md.jit ? md.jit->nw : 0; }

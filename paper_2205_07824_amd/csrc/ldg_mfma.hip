@@ -101,24 +101,18 @@ static ldg_status gemm_launch(bool f16, int M, int N, int K, const TA* A, const 
   return LDG_OK;
 }
 
+// Operators of the two GEMMs, built once at model creation (linear models).
+// The FP32 intermediates of a product use the model's workspace: dU and F
+// share the FP64 linearization cache d_q (linear models never fill it; 2 NQ
+// floats = NQ doubles), q goes to the tangent buffer d_dq.
 struct MfmaWork {
-  const Model* md = nullptr;
   float* G = nullptr;    // [(d nn)][nn] reference-gradient operator
   float* GT = nullptr;   // [nn][(d nn)] its transpose (for the first GEMM's B operand)
-  float* dU = nullptr;   // [E][d nn]
-  float* F = nullptr;    // [E][d nn]
-  float* q = nullptr;    // [E][d nn]
 };
 
-static thread_local std::vector<MfmaWork*> g_mfma;
-
-static MfmaWork* work_for(const Model& md) {
-  for (auto* w : g_mfma)
-    if (w->md == &md) return w;
+ldg_status mfma_prepare(Model& md) {
   const Mesh& m = *md.mesh;
   const int nn = m.nn, d = m.nd, P1 = m.p1;
-  auto* w = new MfmaWork();
-  w->md = &md;
   std::vector<float> G((size_t)d * nn * nn, 0.0f), GT((size_t)nn * d * nn, 0.0f);
   for (int j = 0; j < d; ++j)
     for (int i = 0; i < nn; ++i)
@@ -132,47 +126,43 @@ static MfmaWork* work_for(const Model& md) {
         G[((size_t)j * nn + i) * nn + mm] = val;
         GT[(size_t)mm * d * nn + (size_t)j * nn + i] = val;
       }
-  const size_t E = m.E;
-  if (hipMalloc((void**)&w->G, G.size() * 4) != hipSuccess || hipMalloc((void**)&w->GT, GT.size() * 4) != hipSuccess ||
-      hipMalloc((void**)&w->dU, E * d * nn * 4) != hipSuccess || hipMalloc((void**)&w->F, E * d * nn * 4) != hipSuccess ||
-      hipMalloc((void**)&w->q, E * d * nn * 4) != hipSuccess) {
-    delete w;
-    return nullptr;
-  }
-  (void)hipMemcpy(w->G, G.data(), G.size() * 4, hipMemcpyHostToDevice);
-  (void)hipMemcpy(w->GT, GT.data(), GT.size() * 4, hipMemcpyHostToDevice);
-  g_mfma.push_back(w);
-  return w;
+  auto* w = new MfmaWork();
+  md.mfma = w;   // released by mfma_release, also on the error paths below
+  LDG_TRY(hipMalloc((void**)&w->G, G.size() * 4));
+  LDG_TRY(hipMalloc((void**)&w->GT, GT.size() * 4));
+  LDG_TRY(hipMemcpy(w->G, G.data(), G.size() * 4, hipMemcpyHostToDevice));
+  LDG_TRY(hipMemcpy(w->GT, GT.data(), GT.size() * 4, hipMemcpyHostToDevice));
+  return LDG_OK;
 }
 
-void mfma_release(const Model& md) {
-  for (size_t i = 0; i < g_mfma.size(); ++i)
-    if (g_mfma[i]->md == &md) {
-      MfmaWork* w = g_mfma[i];
-      (void)hipFree(w->G); (void)hipFree(w->GT); (void)hipFree(w->dU); (void)hipFree(w->F); (void)hipFree(w->q);
-      delete w;
-      g_mfma.erase(g_mfma.begin() + i);
-      return;
-    }
+void mfma_release(Model& md) {
+  if (!md.mfma) return;
+  (void)hipFree(md.mfma->G);
+  (void)hipFree(md.mfma->GT);
+  delete md.mfma;
+  md.mfma = nullptr;
 }
 
 ldg_status op_mfma_jvp(const Model& md, const TimeDev& t, const double* v, double* out, bool fp16, hipStream_t s) {
-  MfmaWork* w = work_for(md);
-  if (!w) { set_error("MFMA JVP workspace allocation failed"); return LDG_ENOMEM; }
+  const MfmaWork* w = md.mfma;
+  if (!w) { set_error("MFMA JVP operators missing (linear models build them at creation)"); return LDG_EUNSUPPORTED; }
   const Mesh& m = *md.mesh;
   const int nn = m.nn, d = m.nd;
   const int E = (int)m.E;
+  float* dU = (float*)md.d_q;
+  float* F = dU + (size_t)E * d * nn;
+  float* q = (float*)md.d_dq;
   // reference gradient of v on MFMA: dU = V G^T  ([E][nn] x [nn][d nn])
-  ldg_status st = gemm_launch<double, float, false>(fp16, E, d * nn, nn, v, w->GT, w->dU, s);
+  ldg_status st = gemm_launch<double, float, false>(fp16, E, d * nn, nn, v, w->GT, dU, s);
   if (st != LDG_OK) return st;
   // q = metric transform + lifting (FP32)
-  st = op_grad_ext(md, v, w->dU, w->q, s);
+  st = op_grad_ext(md, v, dU, q, s);
   if (st != LDG_OK) return st;
   // fluxes, face terms, pointwise terms (FP32); contravariant flux to F
-  st = op_resid_ext(md, t, v, w->q, w->F, out, s);
+  st = op_resid_ext(md, t, v, q, F, out, s);
   if (st != LDG_OK) return st;
   // weak divergence on MFMA: out -= F G  ([E][d nn] x [d nn][nn])
-  return gemm_launch<float, double, true>(fp16, E, nn, d * nn, w->F, w->G, out, s);
+  return gemm_launch<float, double, true>(fp16, E, nn, d * nn, F, w->G, out, s);
 }
 
 }  // namespace ldg

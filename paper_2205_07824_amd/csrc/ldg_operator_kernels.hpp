@@ -68,8 +68,10 @@ __host__ __device__ constexpr int geo_tab_size(int d, int p1) {
 __host__ __device__ constexpr int grad_bytes(int ncu, int d, int p1, int rsz) {
   return rsz * (ncu * ipow(p1, d) + 2 * d * ncu * d * ipow(p1, d - 1) + geo_tab_size(d, p1)) + 8 * (1 << d) * d;
 }
+// (the tangent kernel, mode 2, reads q and its tangent from global memory and
+// stages only the dual state u in LDS)
 __host__ __device__ constexpr int resid_bytes(int ncu, bool hasq, int mode, int d, int p1, int rsz) {
-  return (mode == 2 ? 2 * rsz : rsz) * (ncu * ipow(p1, d) + (hasq ? ncu * d * ipow(p1, d) : 0)) +
+  return (mode == 2 ? 2 * rsz * ncu * ipow(p1, d) : rsz * (ncu * ipow(p1, d) + (hasq ? ncu * d * ipow(p1, d) : 0))) +
          rsz * (ncu * d * ipow(p1, d) + 2 * d * ncu * ipow(p1, d - 1) + geo_tab_size(d, p1)) + 8 * (1 << d) * d;
 }
 
@@ -314,12 +316,16 @@ struct ResidCfg {
   static constexpr int NCU = PH::NCU, NN = ipow(P1, D), NFP = ipow(P1, D - 1), NF = 2 * D, NV = 1 << D;
   static constexpr bool HASQ = PH::HASQ;
   static constexpr int NQ = HASQ ? NCU * D : 1;
-  static constexpr int BYTES = sizeof(V) * (NCU * NN + (HASQ ? NCU * D * NN : 0)) +
+  // q staged in LDS: the residual kernels (modes 0, 1); the tangent kernel reads q, dq from global memory
+  static constexpr bool QLDS = HASQ && MODE != 2;
+  static constexpr int BYTES = sizeof(V) * (NCU * NN + (QLDS ? NCU * D * NN : 0)) +
                                sizeof(R) * (NCU * D * NN + NF * NCU * NFP + GeoTab<D, P1>::SIZE) + 8 * NV * D;
   static_assert(BYTES == resid_bytes(NCU, HASQ, MODE, D, P1, sizeof(R)), "one formula for the host and the kernels");
   static constexpr int EPB = pick_epb<NN, BYTES>();
   // the linear 3D FP64 instance needs 98 VGPRs unconstrained (4 waves per SIMD);
   // capping it at 96 for a fifth wave measured 6 us faster on the 32^3 p=3 JVP
+  // (an occupancy hint of 3 or 4 waves on the dual Navier-Stokes tangent spilled
+  // registers to scratch and measured 1.4-1.8x slower than the unconstrained 2)
   static constexpr int MIN_WAVES =
       (Phys<KIND, D>::LINEAR && D == 3 && MODE == 0 && std::is_same<R, double>::value) ? 5 : 1;
 };
@@ -496,12 +502,12 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const doub
   using V = typename C::V;
   using T = VT<V>;
   constexpr int NCU = C::NCU, NN = C::NN, NFP = C::NFP, NF = C::NF, NV = C::NV, EPB = C::EPB, NQ = C::NQ;
-  constexpr bool HASQ = C::HASQ;
+  constexpr bool HASQ = C::HASQ, QLDS = C::QLDS;
   constexpr int NA = Phys<KIND, D>::NAUX > 0 ? Phys<KIND, D>::NAUX : 1;
   using L = TabLayout<P1>;
   __shared__ R s_tab[L::SIZE];
   __shared__ V s_u[EPB][NCU][NN];
-  __shared__ V s_q[EPB][NQ][HASQ ? NN : 1];
+  __shared__ V s_q[EPB][QLDS ? NQ : 1][QLDS ? NN : 1];
   __shared__ R s_F[EPB][NCU][D][NN];
   __shared__ R s_Fh[EPB][NF][NCU][NFP];
   __shared__ double s_c[EPB][NV * D];
@@ -523,12 +529,11 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const doub
       if constexpr (MODE == 2) s_u[el][c][i] = T::mk(R(u[o]), R(v[o]));
       else s_u[el][c][i] = R(u[o]);
     }
-    if constexpr (HASQ) {
+    if constexpr (QLDS) {
 #pragma unroll
       for (int c = 0; c < NQ; ++c) {
         const int64_t o = (K * NQ + c) * NN + i;
-        if constexpr (MODE == 2) s_q[el][c][i] = T::mk(q[o], dq[o]);
-        else s_q[el][c][i] = q[o];
+        s_q[el][c][i] = q[o];
       }
     }
     for (int t = i; t < NV * D; t += NN) s_c[el][t] = m.coef[K * NV * D + t];
@@ -568,9 +573,14 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const doub
 #pragma unroll
         for (int k = 0; k < D; ++k) {
           V t = T::mk(R(0));
-          if constexpr (HASQ) {
+          if constexpr (QLDS) {
 #pragma unroll
             for (int mm = 0; mm < P1; ++mm) t += l_own[mm] * s_q[e][c * D + k][base + mm * SD];
+          } else if constexpr (HASQ) {
+            // tangent kernel: the element's own q lines from global memory (cached)
+            const int64_t oq = ((Ke * NCU + c) * D + k) * NN + base;
+#pragma unroll
+            for (int mm = 0; mm < P1; ++mm) t += l_own[mm] * T::mk(q[oq + mm * SD], dq[oq + mm * SD]);
           }
           qm[c][k] = t;
         }
@@ -607,6 +617,8 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const doub
       V Fh[NCU];
       const int nb = m.nbr[Ke * NF + F];
       if (nb >= 0) {
+        // built-in models: this side's half of the flux first, then the neighbour's traces
+        if constexpr (KIND != K_USER) half_normal_flux<KIND, D, V, R>(md.mu, md.naux, um, qm, am, n, Fh, false);
         V up[NCU], qp[NCU][D];
         R ap2[NA];
 #pragma unroll
@@ -643,7 +655,12 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const doub
           }
           ap2[t] = sacc;
         }
-        num_flux<KIND, D, V, R>(md.mu, md.naux, um, qm, am, up, qp, ap2, n, Fh);
+        if constexpr (KIND != K_USER) {
+          half_normal_flux<KIND, D, V, R>(md.mu, md.naux, up, qp, ap2, n, Fh, true);
+          penalty_flux<KIND, D, V, R>(md.mu, um, am, up, ap2, md.naux, n, Fh);
+        } else {
+          num_flux<KIND, D, V, R>(md.mu, md.naux, um, qm, am, up, qp, ap2, n, Fh);
+        }
       } else {
         const int b = -(nb + 1);
         int tag = m.btag[b];
@@ -683,12 +700,19 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const doub
       }
     }
   };
-  for (int it = threadIdx.x; it < D * EPB * 2 * NFP; it += blockDim.x) {
-    const int dir = it / (EPB * 2 * NFP), loc = it % (EPB * 2 * NFP);
-    if (dir == 0) face_dir(std::integral_constant<int, 0>{}, loc);
-    else if (dir == 1) face_dir(std::integral_constant<int, 1>{}, loc);
-    else if constexpr (D == 3) face_dir(std::integral_constant<int, 2>{}, loc);
-  }
+  auto faces = [&]() {
+    for (int it = threadIdx.x; it < D * EPB * 2 * NFP; it += blockDim.x) {
+      const int dir = it / (EPB * 2 * NFP), loc = it % (EPB * 2 * NFP);
+      if (dir == 0) face_dir(std::integral_constant<int, 0>{}, loc);
+      else if (dir == 1) face_dir(std::integral_constant<int, 1>{}, loc);
+      else if constexpr (D == 3) face_dir(std::integral_constant<int, 2>{}, loc);
+    }
+  };
+  // the tangent kernel visits the nodes first, so that the element's own q
+  // lines, read again by its face points, are still in cache (64^3
+  // Navier-Stokes FP64 tangent 9.9 -> 7.8 ms)
+  constexpr bool VOLUME_FIRST = (MODE == 2);
+  if constexpr (!VOLUME_FIRST) faces();
 
   // ---- volume: flux at the node, contravariant components to LDS, pointwise terms
   R r[NCU];
@@ -710,8 +734,14 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const doub
       uu[c] = s_u[el][c][i];
 #pragma unroll
       for (int k = 0; k < D; ++k) {
-        if constexpr (HASQ) qq[c][k] = s_q[el][c * D + k][i];
-        else qq[c][k] = T::mk(R(0));
+        if constexpr (QLDS) {
+          qq[c][k] = s_q[el][c * D + k][i];
+        } else if constexpr (HASQ) {
+          const int64_t o = ((K * NCU + c) * D + k) * NN + i;
+          qq[c][k] = T::mk(q[o], dq[o]);
+        } else {
+          qq[c][k] = T::mk(R(0));
+        }
       }
     }
     R aa[NA];
@@ -719,6 +749,8 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const doub
     for (int t = 0; t < NA; ++t) aa[t] = (t < md.naux) ? R(md.aux[(K * md.naux + t) * NN + i]) : R(0);
     V f[NCU][D];
     phys_flux<KIND, D, V, R>(md.mu, md.naux, uu, qq, aa, f);
+    V sv[NCU];
+    if constexpr (has_point_source<KIND, D>()) point_source<KIND, D, V, R>(md.mu, md.naux, uu, qq, aa, sv);
 #pragma unroll
     for (int c = 0; c < NCU; ++c) {
 #pragma unroll
@@ -744,9 +776,14 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const doub
           if (md.src) rc -= wdet * R(md.src[o]);
         }
       }
+      if constexpr (has_point_source<KIND, D>()) {
+        if constexpr (MODE == 2) rc -= wdet * sv[c].d;
+        else rc -= wdet * sv[c];
+      }
       r[c] = rc;
     }
   }
+  if constexpr (VOLUME_FIRST) faces();
   __syncthreads();
   if (!active) return;
 

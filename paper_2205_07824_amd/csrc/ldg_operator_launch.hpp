@@ -16,23 +16,25 @@ static ldg_status launch_grad(const Model& md, const double* u, void* q, bool wi
   const double* qoff = (with_data && Phys<KIND, D>::LINEAR) ? md.d_qg : nullptr;
   constexpr int NN = GradCfg<KIND, D, P1, R>::NN, EPB = GradCfg<KIND, D, P1, R>::EPB;
   const Mesh& m = *md.mesh;
-  const int nblk = (int)((m.E + EPB - 1) / EPB);
+  const int nblk = (int)((m.op_E(0) + EPB - 1) / EPB);
+  if (nblk == 0) return LDG_OK;
+  const MeshDev mdv = m.dev_op(0);
   typename TabOf<R>::T tab;
   if constexpr (std::is_same<R, double>::value) tab = m.tab; else tab = m.tabf;
   const float* nodu = nullptr;
   if (in_kernel_data) {
     if (m.affine)
-      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, true, false, true>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), tab,
+      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, true, false, true>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
                          md.dev(), u, (R*)q, qoff, nodu);
     else
-      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, true, false, false>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), tab,
+      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, true, false, false>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
                          md.dev(), u, (R*)q, qoff, nodu);
   } else {
     if (m.affine)
-      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, false, false, true>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), tab,
+      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, false, false, true>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
                          md.dev(), u, (R*)q, qoff, nodu);
     else
-      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, false, false, false>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), tab,
+      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, false, false, false>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
                          md.dev(), u, (R*)q, qoff, nodu);
   }
   LDG_TRY(hipGetLastError());
@@ -44,15 +46,17 @@ static ldg_status launch_resid(const Model& md, const TimeDev& t, const double* 
                                const void* dq, const double* dterm, double* out, hipStream_t s) {
   constexpr int NN = ResidCfg<KIND, D, P1, R, MODE>::NN, EPB = ResidCfg<KIND, D, P1, R, MODE>::EPB;
   const Mesh& m = *md.mesh;
-  const int nblk = (int)((m.E + EPB - 1) / EPB);
+  const int nblk = (int)((m.op_E(1) + EPB - 1) / EPB);
+  if (nblk == 0) return LDG_OK;
+  const MeshDev mdv = m.dev_op(1);
   typename TabOf<R>::T tab;
   if constexpr (std::is_same<R, double>::value) tab = m.tab; else tab = m.tabf;
   float* noF = nullptr;
   if (m.affine)
-    hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, true>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), tab,
+    hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, true>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
                        md.dev(), t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
   else
-    hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, false>), dim3(nblk), dim3(EPB * NN), 0, s, m.dev(), tab,
+    hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, false>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
                        md.dev(), t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
   LDG_TRY(hipGetLastError());
   return LDG_OK;

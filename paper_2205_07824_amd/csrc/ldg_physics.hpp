@@ -127,15 +127,43 @@ struct UserBou<U, typename VoidOf<decltype(U::BOU)>::type> { static constexpr bo
 template <class U, int D, class V, class R>
 __device__ inline void user_bou(const double* mu, int naux, int tag, const V* uL, const V (*qL)[D], const R* aL,
                                 const R* n, V* ub) {
-  static_assert(!U::HASQ, "boundary functions are for sources whose flux does not depend on q");
   U::template bou<D, V, R>(mu, naux, tag, uL, qL, aL, n, ub);
 }
+template <class U, class = void>
+struct UserSrc { static constexpr bool value = false; };
+template <class U>
+struct UserSrc<U, typename VoidOf<decltype(U::SOURCE)>::type> { static constexpr bool value = U::SOURCE; };
+template <class U, int D, class V, class R>
+__device__ inline void user_source(const double* mu, int naux, const V* u, const V (*q)[D], const R* a, V* s) {
+  U::template source<D, V, R>(mu, naux, u, q, a, s);
+}
 #endif
+
+// state-dependent source s(u, q) of Eq. 1b at a point: a model compiled at run
+// time may define one (LdgUser::SOURCE and source<D>); it enters the residual
+// as -(s, phi) beside the data source.  false: the model has none.
+template <int KIND, int D>
+__host__ __device__ constexpr bool has_point_source() {
+#ifdef LDG_USER_PHYSICS
+  if constexpr (KIND == K_USER) return UserSrc<::LdgUser>::value;
+#endif
+  return false;
+}
+template <int KIND, int D, class V, class R>
+__device__ inline void point_source(const double* mu, int naux, const V* u, const V (*q)[D], const R* a, V* s) {
+#ifdef LDG_USER_PHYSICS
+  if constexpr (KIND == K_USER) {
+    if constexpr (UserSrc<::LdgUser>::value) user_source<::LdgUser, D, V, R>(mu, naux, u, q, a, s);
+  }
+#endif
+}
 
 // outside state on a Dirichlet-kind boundary face: ub arrives holding the data g.
 // A model compiled at run time may define a boundary function (LdgUser::BOU and
 // bou<D>), which maps (tag, inside trace, n, g) to the outside state, e.g. a slip
-// wall that reverses the normal momentum; for every other model ub stays g.
+// wall that reverses the normal momentum; for every other model ub stays g.  The
+// outside gradient of the numerical flux stays q+ = q-, and the gradient
+// equation's boundary trace stays uhat = g (the Dirichlet data).
 template <int KIND, int D, class V, class R>
 __device__ inline void boundary_state(const double* mu, int naux, int tag, const V* uL, const V (*qL)[D],
                                       const R* aL, const R* n, V* ub) {
@@ -146,27 +174,29 @@ __device__ inline void boundary_state(const double* mu, int naux, int tag, const
 #endif
 }
 
-// interior numerical flux (also used at Dirichlet faces with u+ = g, q+ = q-, a+ = a-)
+// The built-in numerical flux in three pieces, so that a face can finish one
+// side's flux before it reads the other side (one dual flux array live at a
+// time): Fh (+)= 1/2 f(u, q).n per side, then Fh += sigma (uL - uR).
 template <int KIND, int D, class V, class R>
-__device__ inline void num_flux(const double* mu, int naux, const V* uL, const V (*qL)[D], const R* aL,
-                                const V* uR, const V (*qR)[D], const R* aR, const R* n, V* Fh) {
-#ifdef LDG_USER_PHYSICS
-  if constexpr (KIND == K_USER) {
-    ::LdgUser::template numflux<D, V, R>(mu, naux, uL, qL, aL, uR, qR, aR, n, Fh);
-  } else
-#endif
-  {
+__device__ inline void half_normal_flux(const double* mu, int naux, const V* u, const V (*q)[D], const R* a,
+                                        const R* n, V* Fh, bool add) {
   constexpr int NCU = Phys<KIND, D>::NCU;
-  V fL[NCU][D], fR[NCU][D];
-  phys_flux<KIND, D, V, R>(mu, naux, uL, qL, aL, fL);
-  phys_flux<KIND, D, V, R>(mu, naux, uR, qR, aR, fR);
+  V f[NCU][D];
+  phys_flux<KIND, D, V, R>(mu, naux, u, q, a, f);
 #pragma unroll
   for (int c = 0; c < NCU; ++c) {
-    V s = R(0.5) * (fL[c][0] + fR[c][0]) * n[0];
+    V s = f[c][0] * n[0];
 #pragma unroll
-    for (int k = 1; k < D; ++k) s += R(0.5) * (fL[c][k] + fR[c][k]) * n[k];
-    Fh[c] = s;
+    for (int k = 1; k < D; ++k) s += f[c][k] * n[k];
+    if (add) Fh[c] += R(0.5) * s;
+    else Fh[c] = R(0.5) * s;
   }
+}
+
+template <int KIND, int D, class V, class R>
+__device__ inline void penalty_flux(const double* mu, const V* uL, const R* aL, const V* uR, const R* aR,
+                                    int naux, const R* n, V* Fh) {
+  constexpr int NCU = Phys<KIND, D>::NCU;
   if constexpr (KIND == K_POISSON) {
     R kL = naux >= 1 ? aL[0] : R(1), kR = naux >= 1 ? aR[0] : R(1);
     R sig = R(mu[1]) * R(mu[0]) * R(0.5) * (kL + kR);
@@ -186,6 +216,21 @@ __device__ inline void num_flux(const double* mu, int naux, const V* uL, const V
 #pragma unroll
     for (int c = 0; c < NCU; ++c) Fh[c] += sig * (uL[c] - uR[c]);
   }
+}
+
+// interior numerical flux (also used at Dirichlet faces with u+ = g, q+ = q-, a+ = a-)
+template <int KIND, int D, class V, class R>
+__device__ inline void num_flux(const double* mu, int naux, const V* uL, const V (*qL)[D], const R* aL,
+                                const V* uR, const V (*qR)[D], const R* aR, const R* n, V* Fh) {
+#ifdef LDG_USER_PHYSICS
+  if constexpr (KIND == K_USER) {
+    ::LdgUser::template numflux<D, V, R>(mu, naux, uL, qL, aL, uR, qR, aR, n, Fh);
+  } else
+#endif
+  {
+    half_normal_flux<KIND, D, V, R>(mu, naux, uL, qL, aL, n, Fh, false);
+    half_normal_flux<KIND, D, V, R>(mu, naux, uR, qR, aR, n, Fh, true);
+    penalty_flux<KIND, D, V, R>(mu, uL, aL, uR, aR, naux, n, Fh);
   }
 }
 

@@ -312,20 +312,34 @@ static ldg_status assemble_blocks(Model& md, const ldg_time* t, const double* u_
   const int64_t n = (int64_t)md.N();
   ldg_status st;
   if (!md.linear && md.hasq) {
+    md.q_of[0] = md.q_of[1] = nullptr;
     st = op_grad(md, u_lin, md.d_q, false, true, s);
     if (st != LDG_OK) return st;
+    md.q_of[0] = u_lin;
     if (probe == LDG_FP32) {
       st = op_grad(md, u_lin, md.d_q32, true, true, s);
       if (st != LDG_OK) return st;
+      md.q_of[1] = u_lin;
     }
   }
   double* v = md.d_tmp;
   double* Jv = md.d_tmp2;
   st = vec_fill(n, 0.0, v, s);
   if (st != LDG_OK) return st;
+  // the probing JVPs run on element subsets: rows on the seeded colour only,
+  // the q tangent on the colour and its face neighbours (the other entries of
+  // Jv and of the q tangent are left stale and never read)
+  struct SubsetReset {
+    Mesh& m;
+    ~SubsetReset() { m.sub_list[0] = m.sub_list[1] = nullptr; m.sub_count[0] = m.sub_count[1] = 0; }
+  } reset{m};
   for (int c = 0; c < m.ncolors; ++c) {
     const int cnt = (int)(m.color_off[c + 1] - m.color_off[c]);
     const int32_t* list = m.d_color_list + m.color_off[c];
+    m.sub_list[0] = m.d_color_nbhd + m.nbhd_off[c];
+    m.sub_count[0] = m.nbhd_off[c + 1] - m.nbhd_off[c];
+    m.sub_list[1] = list;
+    m.sub_count[1] = cnt;
     for (int j = 0; j < NB; ++j) {
       hipLaunchKernelGGL(k_probe_set, dim3((cnt + 255) / 256), dim3(256), 0, s, cnt, list, NB, j, 1.0, v);
       st = jvp_impl(md, t, u_lin, v, Jv, probe, true, s);

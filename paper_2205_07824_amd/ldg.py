@@ -73,7 +73,8 @@ class NewtonStats(C.Structure):
 _lib = None
 
 EXPORTED = ["ldg_last_error", "ldg_mesh_create", "ldg_mesh_info", "ldg_mesh_points", "ldg_mesh_destroy",
-            "ldg_model_create", "ldg_model_destroy", "ldg_residual", "ldg_jvp", "ldg_jacobian_blocks",
+            "ldg_model_create", "ldg_model_destroy", "ldg_residual", "ldg_jvp", "ldg_jvp_prepare", "ldg_jvp_prepared",
+            "ldg_jacobian_blocks",
             "ldg_precond_block_jacobi", "ldg_precond_apply", "ldg_precond_destroy", "ldg_gmres_solve",
             "ldg_newton_solve", "ldg_axpby", "ldg_norm2", "ldg_mlp_create", "ldg_mlp_destroy", "ldg_mlp_set_params",
             "ldg_mlp_get_params", "ldg_mlp_forward", "ldg_mlp_train_step", "ldg_mlp_gather_patches",
@@ -100,6 +101,8 @@ def lib():
         "ldg_model_destroy": [vp],
         "ldg_residual": [vp, C.POINTER(_Time), vp, vp, vp, C.c_int, vp],
         "ldg_jvp": [vp, C.POINTER(_Time), vp, vp, vp, C.c_int, vp],
+        "ldg_jvp_prepare": [vp, vp, C.c_int, vp],
+        "ldg_jvp_prepared": [vp, C.POINTER(_Time), vp, vp, vp, C.c_int, vp],
         "ldg_jacobian_blocks": [vp, C.POINTER(_Time), vp, C.c_int, vp, vp],
         "ldg_precond_block_jacobi": [vp, C.POINTER(_Time), vp, C.c_int, C.c_int, vp, C.POINTER(vp)],
         "ldg_precond_apply": [vp, vp, vp, vp],
@@ -209,7 +212,8 @@ class Time:
     c2: float = 0.0
 
     def c(self, n):
-        """ABI struct; r1 and r2 must be FP64 device vectors of n entries."""
+        """ABI struct; r1 and r2 must be FP64 device vectors of n entries (any length when n is None: the call
+        reads neither, e.g. an ODE stage of a model without an ODE, which the library rejects)."""
         self._c = _Time(self.a0, _ptr(self.r1, "time.r1", numel=n), self.c1, _ptr(self.r2, "time.r2", numel=n),
                         self.c2)
         return C.byref(self._c)
@@ -274,15 +278,31 @@ class Model:
                              _ptr(out, "out", numel=N), prec, _stream()), "ldg_jvp")
         return out
 
+    def jvp_prepare(self, u, prec=FP64):
+        """Cache q(u) in the model for jvp_prepared (the solvers' linearization point)."""
+        _check(lib().ldg_jvp_prepare(self.h, _ptr(u, "u", numel=self.N, optional=False), prec, _stream()),
+               "ldg_jvp_prepare")
+
+    def jvp_prepared(self, u, v, time=None, prec=FP64, out=None):
+        """J(u) v with q(u) from the last jvp_prepare(u, prec)."""
+        out = self.empty() if out is None else out
+        N = self.N
+        _check(lib().ldg_jvp_prepared(self.h, _time(time, N), _ptr(u, "u", numel=N),
+                                      _ptr(v, "v", numel=N, optional=False), _ptr(out, "out", numel=N), prec,
+                                      _stream()), "ldg_jvp_prepared")
+        return out
+
     def ode_stage(self, u, time, alpha, beta, out=None):
         """w of one implicit stage of alpha dw/dt + beta w = s_w(u) with the time wrapper `time` (its r1, r2 are
         w-vectors), from the stage's PDE state u."""
         nwv = self.mesh.E * self.nw * self.mesh.nn
-        out = torch.empty(nwv, dtype=torch.float64, device="cuda") if out is None else out
+        out = torch.empty(max(nwv, 1), dtype=torch.float64, device="cuda") if out is None else out
         if time is None:
             raise ValueError("ode_stage: a time wrapper is required")
-        _check(lib().ldg_ode_stage(self.h, _time(time, nwv), C.c_double(alpha), C.c_double(beta),
-                                   _ptr(u, "u", numel=self.N, optional=False), _ptr(out, "out", numel=nwv),
+        # without an ODE (nw = 0) the library returns LDG_EUNSUPPORTED before it reads any vector
+        nchk = nwv if self.nw > 0 else None
+        _check(lib().ldg_ode_stage(self.h, _time(time, nchk), C.c_double(alpha), C.c_double(beta),
+                                   _ptr(u, "u", numel=self.N, optional=False), _ptr(out, "out", numel=nchk),
                                    _stream()), "ldg_ode_stage")
         return out
 

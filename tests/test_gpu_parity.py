@@ -373,6 +373,36 @@ def test_newton_euler_bdf2_step_matches_oracle(L):
     assert rel(u.cpu().numpy(), u_ref) < 1e-8
 
 
+@pytest.mark.parametrize("jvp", ["fp64", "fp32"])
+def test_newton_ns_bdf2_step_matches_oracle(L, jvp):
+    """One BDF2 step of the Navier-Stokes Taylor-Green case (n = 3, p = 2, N = 3645): the library's Newton-GMRES
+    with per-variable block-Jacobi (FP64 JVP, or FP32 JVP with the FP64 residual) against the root of the
+    oracle's residual, found by Newton iterations on the oracle's assembled Jacobian (chord form: the Jacobian
+    of the starting state, factored once)."""
+    import scipy.sparse.linalg as spla
+    c = CS.c4_ns3d(n=3, p=2, shift=0.3)
+    _say("case c4 n=3 p=2 newton", jvp)
+    om = c.oracle_model()
+    lu = spla.splu(c.om.jacobian(om, c.u).tocsc())
+    u_ref = c.u.copy()
+    g0 = np.linalg.norm(c.om.residual(om, u_ref))
+    for _ in range(40):
+        g = c.om.residual(om, u_ref)
+        if np.linalg.norm(g) <= 1e-13 * g0:
+            break
+        u_ref -= lu.solve(g)
+    assert np.linalg.norm(c.om.residual(om, u_ref)) <= 1e-13 * g0
+    m, md, t, dev = build_gpu(L, c)
+    u = dev(c.u.copy())
+    P = L.FP64 if jvp == "fp64" else L.FP32
+    pc = L.BlockJacobi(md, u_lin=u, time=t, per_variable=True, prec=P)
+    u, st, status = L.newton(md, u, time=t, rtol=1e-12, eta=1e-10 if jvp == "fp64" else 1e-5, maxit=20,
+                             bj_refresh=True, pc=pc, restart=50, jvp_prec=P)
+    _say("newton ns stats", st)
+    assert status == L.LDG_OK
+    assert rel(u.cpu().numpy(), u_ref) < 1e-8
+
+
 def test_bdf_steps_match_oracle(L):
     """Three implicit steps (backward Euler, then BDF2) of the Euler vortex case against the oracle's Newton
     with sparse direct solves on the same step sequence."""

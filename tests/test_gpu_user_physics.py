@@ -369,3 +369,69 @@ def test_user_slip_wall_matches_oracle(L):
     G = md.residual(dev(us)).cpu().numpy()
     _say("slip wall channel flow residual", np.abs(G).max())
     assert np.abs(G).max() < 1e-12
+
+
+def test_user_reaction_source_matches_builtin_poisson_and_oracle(L):
+    """A state-dependent source s(u) = -lambda u (Eq. 1b) compiled at run time, with kappa(x), a data source and
+    Dirichlet data: against the oracle's Poisson model with reaction lambda (residual and JVP, FP64 and FP32)
+    and the built-in one."""
+    import oracle as O
+    from tests.util import penalty
+    n, p, lam = 4, 3, 0.7
+    box = I.box_mesh(2, n)
+    om = O.Mesh(box, p)
+    m = L.Mesh(box, p)
+    xn, xq, xb, _ = om.points()
+    _, _, f = I.mms_sin2d(xq)
+    ub, _, _ = I.mms_sin2d(xb)
+    kap = (1.0 + 0.5 * np.sin(3.0 * xn[..., 0]) * np.cos(2.0 * xn[..., 1]))[:, None, :]
+    tau = penalty(p, 1.0 / n)
+    data = dict(aux=kap, src=f.reshape(om.E, 1, om.nqv), bdata=ub.reshape(om.nbf, 1, om.nqf), bc_kind=(0,))
+    built = L.Model(m, L.MODEL_POISSON, 1, [1.3, tau, lam], **data)
+    user = L.Model(m, L.MODEL_USER, 1, [1.3, tau, 0.0, lam, 0.0], physics_source=U.REACTION_DIFFUSION, has_q=True,
+                   **data)
+    omd = O.Model(O.MODEL_POISSON, 1, [1.3, tau, lam], aux=kap, src=data["src"], bdata=data["bdata"], bc_kind=[0])
+    rng = np.random.default_rng(12)
+    u0, v0 = rng.uniform(-1, 1, user.N), rng.uniform(-1, 1, user.N)
+    G_ref, J_ref = om.residual(omd, u0), om.jvp(omd, u0, v0)
+    for prec, tol in ((L.FP64, 1e-12), (L.FP32, 1e-5)):
+        G = user.residual(dev(u0), prec=prec).cpu().numpy()
+        Jv = user.jvp(dev(u0), dev(v0), prec=prec).cpu().numpy()
+        Gb = built.residual(dev(u0), prec=prec).cpu().numpy()
+        _say("reaction source prec", prec, "vs oracle", rel(G, G_ref), rel(Jv, J_ref), "vs built-in", rel(G, Gb))
+        assert rel(G, G_ref) < tol and rel(Jv, J_ref) < tol and rel(G, Gb) < tol
+    # the source term alone: G(lambda) - G(0) = lambda M u, with M the oracle's mass matrix
+    plain = L.Model(m, L.MODEL_USER, 1, [1.3, tau, 0.0, 0.0, 0.0], physics_source=U.REACTION_DIFFUSION,
+                    has_q=True, **data)
+    dG = user.residual(dev(u0)).cpu().numpy() - plain.residual(dev(u0)).cpu().numpy()
+    Mu = lam * om.mass_apply(1, u0)
+    _say("source term vs lambda M u", rel(dG, Mu))
+    assert rel(dG, Mu) < 1e-11
+
+
+def test_user_nonlinear_source_and_boundary_function_tangent(L):
+    """A cubic source and a state-dependent boundary function on a q-dependent flux (outside state
+    g + mu5 uL^2 on the x+ side, q+ = q-): the JVP against central differences of the residual, and with
+    mu5 = 0 the boundary function reproduces the model without it."""
+    from tests.util import penalty
+    n, p = 4, 3
+    box = I.box_mesh(2, n, perturb=0.04, seed=5)
+    m = L.Mesh(box, p)
+    rng = np.random.default_rng(13)
+    data = dict(src=rng.uniform(-1, 1, (m.E, 1, m.nqv)), bdata=rng.uniform(-1, 1, (m.nbf, 1, m.nqf)),
+                bc_kind=(0, 0, 0, 0))
+    mu = [1.0, penalty(p, 1.0 / n), 0.3, 0.4, 0.5, 0.25]
+    md = L.Model(m, L.MODEL_USER, 1, mu, physics_source=U.REACTION_DIFFUSION_BOU, has_q=True, **data)
+    u0, v0 = rng.uniform(-1, 1, md.N), rng.uniform(-1, 1, md.N)
+    Jv = md.jvp(dev(u0), dev(v0)).cpu().numpy()
+    eps = 1e-5
+    fd = (md.residual(dev(u0 + eps * v0)).cpu().numpy() - md.residual(dev(u0 - eps * v0)).cpu().numpy()) / (2 * eps)
+    _say("source + boundary function: tangent vs central difference", rel(Jv, fd))
+    assert rel(Jv, fd) < 1e-7
+    mu0 = mu[:5] + [0.0]
+    a = L.Model(m, L.MODEL_USER, 1, mu0, physics_source=U.REACTION_DIFFUSION_BOU, has_q=True, **data)
+    b = L.Model(m, L.MODEL_USER, 1, mu0[:5], physics_source=U.REACTION_DIFFUSION, has_q=True, **data)
+    assert rel(a.residual(dev(u0)).cpu().numpy(), b.residual(dev(u0)).cpu().numpy()) < 1e-14
+    assert rel(a.jvp(dev(u0), dev(v0)).cpu().numpy(), b.jvp(dev(u0), dev(v0)).cpu().numpy()) < 1e-14
+    # and with mu5 != 0 it changes the residual
+    assert rel(md.residual(dev(u0)).cpu().numpy(), a.residual(dev(u0)).cpu().numpy()) > 1e-6

@@ -13,7 +13,9 @@ def L():
 
 @pytest.mark.parametrize("src,nd,p,ncu,has_q", [(U.EULER_2D, 2, 4, 4, False), (U.NONLINEAR_DIFFUSION, 3, 2, 1, True),
                                                 (U.SHALLOW_WATER_2D, 2, 4, 3, False), (U.WAVE_2D, 2, 3, 3, False),
-                                                (U.WAVE_2D_W, 2, 3, 3, False), (U.EULER_2D_SLIP, 2, 3, 4, False)])
+                                                (U.WAVE_2D_W, 2, 3, 3, False), (U.EULER_2D_SLIP, 2, 3, 4, False),
+                                                (U.REACTION_DIFFUSION, 2, 3, 1, True),
+                                                (U.REACTION_DIFFUSION_BOU, 3, 2, 1, True)])
 def test_physics_sources_compile(L, src, nd, p, ncu, has_q):
     L.user_physics_check(src, nd, p, ncu, has_q)
 
@@ -43,11 +45,8 @@ def test_ode_size_out_of_range_rejected(L):
     assert "NW must be in [1, 8]" in str(e.value)
 
 
-def test_boundary_function_needs_a_q_free_flux(L):
-    src = U.NONLINEAR_DIFFUSION.replace("static constexpr int NAUX", """static constexpr bool BOU = true;
-  template <int D, class V, class R>
-  __device__ static void bou(const double*, int, int, const V*, const V (*)[D], const R*, const R*, V*) {}
-  static constexpr int NAUX""", 1)
+def test_source_with_wrong_signature_is_a_compile_error(L):
+    src = U.REACTION_DIFFUSION.replace("const V (*)[D], const R*, V* s)", "V* s)", 1)
     with pytest.raises(L.LDGError) as e:
         L.user_physics_check(src, 2, 3, 1, True)
-    assert "boundary functions are for sources whose flux does not depend on q" in str(e.value)
+    assert "error" in str(e.value)
