@@ -305,6 +305,16 @@ ldg_status ldg_mlp_set_params(ldg_mlp net, const float* host_params);
 ldg_status ldg_mlp_get_params(ldg_mlp net, float* host_params, float* host_grads);
 /* Y[B][out] = net(X[B][in]); DEVICE float arrays. */
 ldg_status ldg_mlp_forward(ldg_mlp net, const float* X, int64_t B, float* Y, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): ldg_mlp_forward with
+ * the same kernels and the same result, but its hidden activations live in a
+ * fixed 32 MiB device array of the library (8,388,608 floats, one per GPU, held
+ * until the process ends) instead of the network's lazily grown work buffers.
+ * Needs 2 * B * width <= 8,388,608 (B <= 16384 at width 256), else LDG_EINVAL;
+ * calls no hipMalloc / hipFree.  Every call on one GPU shares that array, so
+ * calls that overlap on one GPU (other streams, other threads) race; calls
+ * queued on one stream are ordered.  X, Y: DEVICE float [B][in], [B][out]. */
+ldg_status ldg_mlp_forward_noalloc(ldg_mlp net, const float* X, int64_t B, float* Y, void* stream);
 /* One step on the mean squared error (1/(B out)) sum (net(X) - Y)^2: forward,
  * backward into the gradient buffer, then Adam (beta 0.9/0.999, eps 1e-8) with
  * learning rate lr when lr > 0.  The loss goes to HOST *loss_host (synchronizes). */

@@ -8,6 +8,8 @@
 // (round to nearest even) when it stages them into LDS.
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <string>
 
 #include "ldg_internal.hpp"
 
@@ -165,12 +167,14 @@ __global__ void k_splitk_reduce(int M, int N, int nz, const float* __restrict__ 
 
 static ldg_status gemm(MlpNet& net, int M, int N, int K, const float* A, int64_t sam, int64_t sak, const float* B,
                        int64_t sbk, int64_t sbn, float* C, int64_t scm, int64_t scn, const float* bias, int act,
-                       hipStream_t s) {
+                       hipStream_t s, bool allow_split = true) {
   if (!A || !B || !C || M <= 0 || N <= 0 || K <= 0) { set_error("GEMM operand missing or empty"); return LDG_EINVAL; }
   const int gx = (N + GT - 1) / GT, gy = (M + GT - 1) / GT;
   int nz = 1;
-  // split K when the output has few tiles and K is long (weight gradients)
-  while (gx * gy * nz < 256 && K / (nz * 2) >= 256) nz *= 2;
+  // split K when the output has few tiles and K is long (weight gradients); the
+  // split needs the partial buffer net.part, so callers that may not allocate
+  // pass allow_split = false
+  while (allow_split && gx * gy * nz < 256 && K / (nz * 2) >= 256) nz *= 2;
   int kchunk = (K + nz - 1) / nz;
   kchunk = (kchunk + GK - 1) / GK * GK;
   nz = (K + kchunk - 1) / kchunk;
@@ -282,16 +286,57 @@ static ldg_status ensure_cap(MlpNet& net, int64_t B, hipStream_t s) {
   return LDG_OK;
 }
 
+// the three layers with the hidden activations in H1, H2 ([B][width] each)
+static ldg_status mlp_layers(MlpNet& net, const float* X, int64_t B, float* H1, float* H2, float* Y, hipStream_t s,
+                             bool allow_split) {
+  if (!Y) { set_error("MLP forward without an output buffer"); return LDG_EINVAL; }
+  const int I = net.in_dim, W = net.width, O = net.out_dim;
+  const float* P = net.params;
+  ldg_status st;
+  if ((st = gemm(net, (int)B, W, I, X, I, 1, P + net.off[0], 1, I, H1, W, 1, P + net.off[1], 1, s, allow_split)) != LDG_OK)
+    return st;
+  if ((st = gemm(net, (int)B, W, W, H1, W, 1, P + net.off[2], 1, W, H2, W, 1, P + net.off[3], 1, s, allow_split)) != LDG_OK)
+    return st;
+  return gemm(net, (int)B, O, W, H2, W, 1, P + net.off[4], 1, W, Y, O, 1, P + net.off[5], 0, s, allow_split);
+}
+
 // forward into net.H1, net.H2, Y (Y may be net.Yo)
 static ldg_status mlp_forward(MlpNet& net, const float* X, int64_t B, float* Y, hipStream_t s) {
   ldg_status st = ensure_cap(net, B, s);
   if (st != LDG_OK) return st;
-  if (!Y) { set_error("MLP forward without an output buffer"); return LDG_EINVAL; }
-  const int I = net.in_dim, W = net.width, O = net.out_dim;
-  const float* P = net.params;
-  if ((st = gemm(net, (int)B, W, I, X, I, 1, P + net.off[0], 1, I, net.H1, W, 1, P + net.off[1], 1, s)) != LDG_OK) return st;
-  if ((st = gemm(net, (int)B, W, W, net.H1, W, 1, P + net.off[2], 1, W, net.H2, W, 1, P + net.off[3], 1, s)) != LDG_OK) return st;
-  return gemm(net, (int)B, O, W, net.H2, W, 1, P + net.off[4], 1, W, Y, O, 1, P + net.off[5], 0, s);
+  return mlp_layers(net, X, B, net.H1, net.H2, Y, s, true);
+}
+
+// ---- allocation-free forward --------------------------------------------
+// The hidden activations of ldg_mlp_forward_noalloc live in this fixed device
+// array (32 MiB; each GPU the library runs on holds its own copy until the
+// process ends).  Host code must not pass the array's name to a kernel: on the
+// host it is a stand-in, not a device address.  The device address is looked
+// up once per device and kept in g_scratch_dev.
+constexpr int64_t kScratchFloats = int64_t(1) << 23;
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static float* g_scratch_dev[kMaxDevices] = {};
+
+// device address of the scratch array on the current device
+static ldg_status scratch_address(float** out) {
+  int dev = -1;
+  LDG_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) { set_error("device index out of range"); return LDG_EDEVICE; }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      return LDG_EDEVICE;
+    }
+    g_scratch_dev[dev] = (float*)p;
+  }
+  *out = g_scratch_dev[dev];
+  return LDG_OK;
 }
 
 // gradients of the mean squared error into net.grads; loss into net.loss_dev
@@ -471,6 +516,23 @@ ldg_status ldg_mlp_forward(ldg_mlp n, const float* X, int64_t B, float* Y, void*
   LDG_ENTER();
   if (!n || !X || !Y || B <= 0 || B >= (1ll << 31)) { set_error("bad arguments"); return LDG_EINVAL; }
   return mlp_forward(*n, X, B, Y, (hipStream_t)stream);
+}
+
+ldg_status ldg_mlp_forward_noalloc(ldg_mlp n, const float* X, int64_t B, float* Y, void* stream) {
+  LDG_ENTER();
+  if (!n || !X || !Y || B <= 0 || B >= (1ll << 31)) { set_error("bad arguments"); return LDG_EINVAL; }
+  const int64_t need = 2 * B * (int64_t)n->width;
+  if (need > kScratchFloats) {
+    set_error("ldg_mlp_forward_noalloc: 2 * B * width = " + std::to_string(need) + " floats exceeds the fixed " +
+              std::to_string(kScratchFloats) + "-float scratch (B <= " + std::to_string(kScratchFloats / (2 * n->width)) +
+              " at this width); use ldg_mlp_forward");
+    return LDG_EINVAL;
+  }
+  float* sc = nullptr;
+  ldg_status st = scratch_address(&sc);
+  if (st != LDG_OK) return st;
+  // every entry of H1 and H2 that layer 2 and 3 read is written by layers 1 and 2 first
+  return mlp_layers(*n, X, B, sc, sc + B * (int64_t)n->width, Y, (hipStream_t)stream, false);
 }
 
 // forward + MSE + backward (+ Adam when lr > 0); loss to HOST *loss_host (synchronizes)

@@ -77,7 +77,7 @@ EXPORTED = ["ldg_last_error", "ldg_mesh_create", "ldg_mesh_info", "ldg_mesh_poin
             "ldg_jacobian_blocks",
             "ldg_precond_block_jacobi", "ldg_precond_apply", "ldg_precond_destroy", "ldg_gmres_solve",
             "ldg_newton_solve", "ldg_axpby", "ldg_norm2", "ldg_mlp_create", "ldg_mlp_destroy", "ldg_mlp_set_params",
-            "ldg_mlp_get_params", "ldg_mlp_forward", "ldg_mlp_train_step", "ldg_mlp_gather_patches",
+            "ldg_mlp_get_params", "ldg_mlp_forward", "ldg_mlp_forward_noalloc", "ldg_mlp_train_step", "ldg_mlp_gather_patches",
             "ldg_precond_mlp", "ldg_model_create_user", "ldg_user_physics_check", "ldg_ode_size", "ldg_ode_stage"]
 
 
@@ -116,6 +116,7 @@ def lib():
         "ldg_mlp_set_params": [vp, C.POINTER(C.c_float)],
         "ldg_mlp_get_params": [vp, C.POINTER(C.c_float), C.POINTER(C.c_float)],
         "ldg_mlp_forward": [vp, vp, C.c_int64, vp, vp],
+        "ldg_mlp_forward_noalloc": [vp, vp, C.c_int64, vp, vp],
         "ldg_mlp_train_step": [vp, vp, vp, C.c_int64, C.c_float, C.POINTER(C.c_float), vp],
         "ldg_mlp_gather_patches": [vp, vp, vp, vp, C.c_int64, vp, vp, vp, vp],
         "ldg_precond_mlp": [vp, vp, vp, C.c_int, C.POINTER(vp)],
@@ -378,6 +379,16 @@ class MLP:
         _check(lib().ldg_mlp_forward(self.h, _ptr(X, "X [B][in]", f32, B * self.dims[0], optional=False), B,
                                      _ptr(out, "out [B][out]", f32, B * self.dims[2], optional=False), _stream()),
                "ldg_mlp_forward")
+        return out
+
+    def forward_noalloc(self, X, out):
+        """ldg_mlp_forward_noalloc: the forward pass with the library's fixed scratch array (no device allocation
+        in the call); out [B][out] must be given."""
+        B = X.shape[0]
+        f32 = torch.float32
+        _check(lib().ldg_mlp_forward_noalloc(self.h, _ptr(X, "X [B][in]", f32, B * self.dims[0], optional=False), B,
+                                             _ptr(out, "out [B][out]", f32, B * self.dims[2], optional=False),
+                                             _stream()), "ldg_mlp_forward_noalloc")
         return out
 
     def train_step(self, X, Y, lr):
