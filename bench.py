@@ -283,11 +283,45 @@ def implicit_steps(ldg, I, log, nsteps=5):
     return res
 
 
+def ns_implicit_steps(ldg, I, log, nsteps=2, cfl=1.0):
+    """64^3 Navier-Stokes Taylor-Green vortex: a BDF1 step, then BDF2 steps, at acoustic CFL `cfl`
+    (dt = cfl h / max(|v| + c)), each solved by Newton-GMRES(40) + per-variable block-Jacobi (64 x 64 blocks,
+    rebuilt once per step) to ||G|| <= 1e-8 ||G_0||, eta = 1e-3.  Seconds per step over steps 2..nsteps, in
+    the plain FP64 form, the mixed form (FP32 JVP, FP16 factors; FP64 residual and Krylov vectors) and the
+    mixed form with FP32 state (the preconditioned vectors and the linearization point in FP32)."""
+    import torch
+    from paper_2205_07824_amd import timestep as TS
+    _, m, md, u0, _, _, dt10 = ns_workload(ldg, I)
+    dt = dt10 * cfl / 10.0
+    res = {"workload": "3D Navier-Stokes Taylor-Green vortex, p=3, periodic 64^3, BDF2 at acoustic CFL %g" % cfl,
+           "dof": md.N, "dt": dt, "steps": nsteps}
+    for name, jp, bp, s32 in (("fp64_jvp+fp64_bj", ldg.FP64, ldg.FP64, False),
+                              ("fp32_jvp+fp16_bj", ldg.FP32, ldg.FP16, False),
+                              ("fp32_state+fp16_bj", ldg.FP32, ldg.FP16, True)):
+        torch.cuda.synchronize()
+        _, stats = TS.bdf_steps(md, u0, dt, nsteps, restart=40, eta=1e-3, rtol=1e-8, jvp_prec=jp, bj_prec=bp,
+                                per_variable=True, bj_refresh=2, lin_maxit=3000, log=log, state32=s32)
+        later = stats[1:] if len(stats) > 1 else stats
+        res[name] = {"seconds_per_step_2_to_%d" % nsteps: round(float(np.mean([r["seconds"] for r in later])), 4),
+                     "all_converged": all(r["converged"] for r in stats) and len(stats) == nsteps,
+                     "newton_iters": [r["newton_iters"] for r in stats],
+                     "gmres_iters": [r["gmres_iters"] for r in stats],
+                     "t_jvp_s": round(sum(r["t_jvp"] for r in later), 4),
+                     "t_pc_s": round(sum(r["t_pc"] for r in later), 4),
+                     "t_orth_s": round(sum(r["t_orth"] for r in later), 4)}
+        log(name, res[name])
+        torch.cuda.empty_cache()
+    del md, m, u0
+    torch.cuda.empty_cache()
+    return res
+
+
 # Newton-GMRES forms on the Poisson workload: (JVP precision, block-Jacobi factor
 # storage, Newton forcing eta)
 NEWTON_FORMS = {"fp64_jvp+fp64_bj": ("FP64", "FP64", 1e-9), "fp64_jvp+fp32_bj": ("FP64", "FP32", 1e-9),
                 "fp64_jvp+fp16_bj": ("FP64", "FP16", 1e-9), "fp32_jvp+fp32_bj": ("FP32", "FP32", 1e-4),
-                "fp32_jvp+fp16_bj": ("FP32", "FP16", 1e-4), "fp32_jvp+bf16_bj": ("FP32", "BF16", 1e-4)}
+                "fp32_jvp+fp16_bj": ("FP32", "FP16", 1e-4), "fp32_jvp+bf16_bj": ("FP32", "BF16", 1e-4),
+                "fp32_state+fp16_bj": ("FP32", "FP16", 1e-4)}
 
 
 def newton_form(ldg, md, name, orth, log):
@@ -302,7 +336,7 @@ def newton_form(ldg, md, name, orth, log):
     t_bj = time.perf_counter() - t0
     x = torch.zeros(md.N, dtype=torch.float64, device="cuda")
     x, st, status = ldg.newton(md, x, rtol=1e-8, eta=eta, maxit=8, pc=pc, restart=30, lin_maxit=4000,
-                               jvp_prec=jp, orth=orth, check=False)
+                               jvp_prec=jp, orth=orth, state32=name.startswith("fp32_state"), check=False)
     torch.cuda.synchronize()
     t_all = time.perf_counter() - t0
     rec = {"time_to_1e-8_s": round(t_all, 4), "bj_build_s": round(t_bj, 4),
@@ -426,7 +460,7 @@ def main():
     ap.add_argument("--no-extra-workloads", action="store_true",
                     help="skip the 2D Euler and 96^3 Poisson JVP throughput legs")
     ap.add_argument("--no-implicit", action="store_true",
-                    help="skip the 2D Euler BDF2 Newton-GMRES steps")
+                    help="skip the implicit time steps (Navier-Stokes, Euler, shallow water, wave)")
     ap.add_argument("--profile-jvp-only", action="store_true",
                     help="only the timed headline JVP steps (for counter collection)")
     ap.add_argument("--profile-poisson-only", action="store_true",
@@ -591,8 +625,10 @@ def main():
     if not args.no_solve:
         out["other_solves"] = other_solves(ldg, I, log)
 
-    # implicit time steps on the 2D Euler workload (seconds per step averaged over steps 2..5)
+    # implicit time steps: the 64^3 Navier-Stokes workload, then the 2D Euler workload (seconds per step
+    # averaged over steps 2..5)
     if not args.no_implicit:
+        out["ns3d_tgv_implicit_steps"] = ns_implicit_steps(ldg, I, log)
         out["implicit_steps"] = implicit_steps(ldg, I, log)
         out["bickley_jet"] = bickley_jet_steps(ldg, I, log)
         out["wave_displacement"] = wave_displacement_steps(ldg, I, log)

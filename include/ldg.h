@@ -270,6 +270,14 @@ ldg_status ldg_jvp_prepare(ldg_model model, const double* u, ldg_precision prec,
 ldg_status ldg_jvp_prepared(ldg_model model, const ldg_time* t, const double* u, const double* v, double* Jv,
                             ldg_precision prec, void* stream);
 
+/* The same product with FP32 state: u and v in FP32 storage, FP32 arithmetic and
+ * intermediates (the LDG_FP32 mode), Jv in FP64 (it feeds FP64 orthogonalization).
+ * Halves the bytes of the input vectors; q(u) is formed from the FP32 state.  For
+ * the library's own models (run-time physics: LDG_EUNSUPPORTED).  u, v: DEVICE
+ * float [E][ncu][nn]; Jv: DEVICE double, must not alias u or v. */
+ldg_status ldg_jvp_state32(ldg_model model, const ldg_time* t, const float* u, const float* v, double* Jv,
+                           void* stream);
+
 /* ------------------------------------------------------- preconditioners --- */
 /* Exact diagonal blocks dG_K/du_K of the Jacobian at u_lin, by probing with the
  * distance-2 element colouring (one JVP per colour and local unknown), written
@@ -346,6 +354,10 @@ typedef struct {
   int inject_fault;       /* test hook: 1 = poison the preconditioner output with NaN */
   int orth;               /* 0 = CGS2 (three streaming sweeps over the basis), 1 = modified Gram-Schmidt,
                              2 = CGS2 with the re-orthogonalization delayed to the next step (two sweeps) */
+  int state32;            /* 1 = FP32 state: the preconditioned vectors z_j and the linearization point are
+                             stored in FP32 and the products read them in FP32 (as ldg_jvp_state32); the
+                             basis V, Gram-Schmidt, Givens and the true residual stay FP64.  Needs
+                             jvp_prec = LDG_FP32, orth = 2 and a block-Jacobi preconditioner or none */
 } ldg_gmres_opts;
 
 typedef struct {

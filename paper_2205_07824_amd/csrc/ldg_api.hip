@@ -608,6 +608,26 @@ ldg_status residual_impl(Model& md, const ldg_time* t, const double* u, double* 
   return LDG_OK;
 }
 
+// J(u) v with u, v in FP32 storage (FP32 arithmetic); for nonlinear models q
+// comes from md.d_q32 (prepared = true) or is formed here from the FP32 state.
+ldg_status jvp_state32(Model& md, const ldg_time* t, const float* u, const float* v, double* Jv,
+                              bool prepared, hipStream_t s) {
+  const TimeDev td = make_time(t, false);
+  ldg_status st = op_grad(md, v, md.d_dq, PM_FP32_STATE, false, s);
+  if (st != LDG_OK) return st;
+  if (md.linear) return op_resid(md, td, v, md.d_dq, Jv, PM_FP32_STATE, false, s);
+  if (!u) {
+    set_error("nonlinear model needs u");
+    return LDG_EINVAL;
+  }
+  if (!prepared && md.hasq) {
+    md.q_of[1] = nullptr;   // the cache now holds q of an FP32 state, which no FP64 pointer names
+    st = op_grad(md, u, md.d_q32, PM_FP32_STATE, true, s);
+    if (st != LDG_OK) return st;
+  }
+  return op_jvp_nonlinear(md, td, u, md.d_q32, v, md.d_dq, Jv, PM_FP32_STATE, s);
+}
+
 // J(u) v; for nonlinear models q(u) must already be in md.d_q (prepared = true)
 // or is computed here.
 ldg_status jvp_impl(Model& md, const ldg_time* t, const double* u, const double* v, double* Jv, ldg_precision prec,
@@ -684,6 +704,14 @@ ldg_status ldg_jvp(ldg_model md, const ldg_time* t, const double* u, const doubl
   CHECK_ARG(md && v && Jv, "null argument");
   CHECK_ARG(Jv != v && Jv != u, "Jv must not alias u or v");
   return jvp_impl(*md, t, u, v, Jv, prec, false, (hipStream_t)stream);
+}
+
+ldg_status ldg_jvp_state32(ldg_model md, const ldg_time* t, const float* u, const float* v, double* Jv,
+                           void* stream) {
+  LDG_ENTER();
+  CHECK_ARG(md && v && Jv, "null argument");
+  CHECK_ARG((const void*)Jv != (const void*)v && (const void*)Jv != (const void*)u, "Jv must not alias u or v");
+  return jvp_state32(*md, t, u, v, Jv, false, (hipStream_t)stream);
 }
 
 ldg_status ldg_jvp_prepare(ldg_model md, const double* u, ldg_precision prec, void* stream) {

@@ -113,12 +113,17 @@ void set_error(const std::string& msg);
     }                                                                              \
   } while (0)
 
-// operator entry points (ldg_operator.hip)
-ldg_status op_grad(const Model& md, const double* u, void* q, bool fp32, bool with_data, hipStream_t s);
-ldg_status op_resid(const Model& md, const TimeDev& t, const double* u, const void* q, double* out, bool fp32,
+// precision modes of the operator entry points: FP64; FP32 arithmetic and
+// intermediates with FP64 input vectors; FP32 arithmetic with FP32 input vectors
+// (u, v; the output stays FP64).  A bool argument converts to the first two.
+enum PrecMode { PM_FP64 = 0, PM_FP32 = 1, PM_FP32_STATE = 2 };
+
+// operator entry points (ldg_operator.hip); u and v are double, or float under PM_FP32_STATE
+ldg_status op_grad(const Model& md, const void* u, void* q, int pm, bool with_data, hipStream_t s);
+ldg_status op_resid(const Model& md, const TimeDev& t, const void* u, const void* q, double* out, int pm,
                     bool with_data, hipStream_t s);
-ldg_status op_jvp_nonlinear(const Model& md, const TimeDev& t, const double* u, const void* q, const double* v,
-                            const void* dq, double* out, bool fp32, hipStream_t s);
+ldg_status op_jvp_nonlinear(const Model& md, const TimeDev& t, const void* u, const void* q, const void* v,
+                            const void* dq, double* out, int pm, hipStream_t s);
 ldg_status op_data_terms(Model& md, hipStream_t s);
 ldg_status op_mfma_jvp(const Model& md, const TimeDev& t, const double* v, double* out, bool fp16, hipStream_t s);
 ldg_status mfma_prepare(Model& md);
@@ -139,6 +144,8 @@ ldg_status jit_ode(const Model& md, const TimeDev& t, double alpha, double beta,
 TimeDev make_time(const ldg_time* t, bool with_rhs);
 ldg_status residual_impl(Model& md, const ldg_time* t, const double* u, double* G, double* q_out, bool fp32,
                          hipStream_t s);
+ldg_status jvp_state32(Model& md, const ldg_time* t, const float* u, const float* v, double* Jv, bool prepared,
+                       hipStream_t s);
 ldg_status jvp_impl(Model& md, const ldg_time* t, const double* u, const double* v, double* Jv, ldg_precision prec,
                     bool prepared, hipStream_t s);
 

@@ -252,14 +252,16 @@ __global__ void k_reduce_rows(int nv, int nblk, const double* __restrict__ part,
 }
 
 // x += sum_i y_i Z_i
-__global__ void k_combine(int64_t n, int k, const double* __restrict__ Z, int64_t ldz, const double* __restrict__ y,
+// x += Z y (Z in FP64, or FP32 for the FP32-state solver)
+template <class ZT>
+__global__ void k_combine(int64_t n, int k, const ZT* __restrict__ Z, int64_t ldz, const double* __restrict__ y,
                           double* __restrict__ x) {
   __shared__ double ys[MAXM];
   for (int i = threadIdx.x; i < k; i += blockDim.x) ys[i] = y[i];
   __syncthreads();
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
     double acc = x[t];
-    for (int i = 0; i < k; ++i) acc += ys[i] * Z[(int64_t)i * ldz + t];
+    for (int i = 0; i < k; ++i) acc += ys[i] * (double)Z[(int64_t)i * ldz + t];
     x[t] = acc;
   }
 }
@@ -325,13 +327,18 @@ __global__ void k_arnoldi_start(ArnoldiState* st, int nblk, const double* __rest
 }
 
 // back substitution H(0:k,0:k) y = g(0:k)
+// y = R^-1 g on the rotated Hessenberg.  A zero diagonal (a breakdown column
+// whose direction the basis already spans; in flexible GMRES H may be singular)
+// drops that direction instead of dividing by zero; the true residual computed
+// after the update decides whether the cycle converged.
 __global__ void k_backsolve(ArnoldiState* st, int k) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const int ld = MAXM + 1;
   for (int i = k - 1; i >= 0; --i) {
     double s = st->g[i];
     for (int c = i + 1; c < k; ++c) s -= st->H[(int64_t)c * ld + i] * st->y[c];
-    st->y[i] = s / st->H[(int64_t)i * ld + i];
+    const double d = st->H[(int64_t)i * ld + i];
+    st->y[i] = d != 0.0 ? s / d : 0.0;
   }
 }
 
@@ -516,6 +523,11 @@ __global__ void __launch_bounds__(VB) k_dc_update(int64_t n, int j, const double
   }
 }
 
+__global__ void k_to_f32(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = (float)a[i];
+}
+
 // NaN injection for the failure-handling tests
 __global__ void k_poison(int64_t n, double* z) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -529,6 +541,7 @@ using namespace ldg;
 struct ldg_precond_s;
 namespace ldg {
 ldg_status precond_apply_impl(ldg_precond_s* pc, const double* r, double* z, hipStream_t s);
+ldg_status precond_apply_impl32(ldg_precond_s* pc, const double* r, float* z, hipStream_t s);
 ldg_status precond_rebuild(ldg_precond_s* pc, const ldg_time* t, const double* u_lin, hipStream_t s);
 int precond_kind(const ldg_precond_s* pc);
 ldg_precond_s* precond_fallback(ldg_precond_s* pc);
@@ -541,7 +554,10 @@ struct Workspace {
   int64_t n = 0;
   int m = 0;
   double* V = nullptr;     // [(m+1)][n]
-  double* Z = nullptr;     // [m][n]
+  double* Z = nullptr;     // [m][n] (FP64 solves)
+  float* Z32 = nullptr;    // [m][n] (FP32-state solves, instead of Z)
+  float* u32 = nullptr;    // [n] FP32 copy of the linearization point (FP32-state solves)
+  bool s32 = false;
   double* w = nullptr;
   double* r = nullptr;
   double* part = nullptr;  // [(2 MAXM + 3) * RED_BLOCKS] block partials
@@ -557,19 +573,26 @@ struct Workspace {
   bool ok = false;
   void release() {
     if (!ok) return;
-    hipFree(V); hipFree(Z); hipFree(w); hipFree(r); hipFree(part); hipFree(npart); hipFree(h1); hipFree(h2);
+    hipFree(V); hipFree(Z); hipFree(Z32); hipFree(u32); hipFree(w); hipFree(r); hipFree(part); hipFree(npart);
+    hipFree(h1); hipFree(h2);
+    Z = nullptr; Z32 = nullptr; u32 = nullptr;
     hipFree(U); hipFree(coef);
     hipFree(st); hipHostFree(pinned);
     for (auto& e : ev) hipEventDestroy(e);
     for (auto& e : evs) hipEventDestroy(e);
     ok = false;
   }
-  ldg_status ensure(int64_t nn, int mm) {
-    if (ok && nn == n && mm <= m) return LDG_OK;
+  ldg_status ensure(int64_t nn, int mm, bool state32) {
+    if (ok && nn == n && mm <= m && state32 == s32) return LDG_OK;
     release();
-    n = nn; m = mm;
+    n = nn; m = mm; s32 = state32;
     LDG_TRY(hipMalloc((void**)&V, sizeof(double) * (m + 1) * n));
-    LDG_TRY(hipMalloc((void**)&Z, sizeof(double) * m * n));
+    if (s32) {
+      LDG_TRY(hipMalloc((void**)&Z32, sizeof(float) * m * n));
+      LDG_TRY(hipMalloc((void**)&u32, sizeof(float) * n));
+    } else {
+      LDG_TRY(hipMalloc((void**)&Z, sizeof(double) * m * n));
+    }
     LDG_TRY(hipMalloc((void**)&w, sizeof(double) * n));
     LDG_TRY(hipMalloc((void**)&r, sizeof(double) * n));
     LDG_TRY(hipMalloc((void**)&part, sizeof(double) * (2 * MAXM + 3) * RED_BLOCKS));
@@ -747,12 +770,22 @@ static ldg_status dcgs2_cycle(Model& md, const ldg_time* t, const double* u_lin,
     return res <= tol || brk;
   };
   int queued = -1, done = 0;
+  const bool s32 = o.state32 != 0;
   for (int j = 0; j < m && its < o.maxit; ++j) {
     const int sl = j & 1;
-    double* zj = ws.Z + (int64_t)j * n;
+    double* zj = s32 ? nullptr : ws.Z + (int64_t)j * n;
+    float* zj32 = s32 ? ws.Z32 + (int64_t)j * n : nullptr;
     clk.begin(its, sl);
     clk.mark(ws, sl, 0, s);
-    if (use_pc) {
+    if (s32) {
+      // FP32 state: z_j stored in FP32, the product reads it and the FP32 copy of u_lin
+      if (use_pc) {
+        st = precond_apply_impl32(pc_cur, ws.U, zj32, s);
+        if (st != LDG_OK) return st;
+      } else {
+        hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(VB), 0, s, n, ws.U, zj32);
+      }
+    } else if (use_pc) {
       st = precond_apply_impl(pc_cur, ws.U, zj, s);
       if (st != LDG_OK) return st;
       if (o.inject_fault == 1) hipLaunchKernelGGL(k_poison, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, zj);
@@ -773,7 +806,7 @@ static ldg_status dcgs2_cycle(Model& md, const ldg_time* t, const double* u_lin,
       LDG_TRY(hipMemcpyAsync(zj, ws.U, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
     clk.mark(ws, sl, 1, s);
-    st = jvp_impl(md, t, u_lin, zj, ws.w, jp, true, s);
+    st = s32 ? jvp_state32(md, t, ws.u32, zj32, ws.w, true, s) : jvp_impl(md, t, u_lin, zj, ws.w, jp, true, s);
     if (st != LDG_OK) return st;
     clk.mark(ws, sl, 2, s);
     sweep1(j, ws.w);
@@ -827,9 +860,13 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
   const int m = o.restart;
   if (m < 1 || m > MAXM) { set_error("restart must be in [1, 128]"); return LDG_EINVAL; }
   if (o.orth < 0 || o.orth > 2) { set_error("orth must be 0 (CGS2), 1 (MGS) or 2 (delayed CGS2)"); return LDG_EINVAL; }
+  if (o.state32) {
+    if (o.jvp_prec != LDG_FP32) { set_error("state32 needs jvp_prec = LDG_FP32"); return LDG_EINVAL; }
+    if (o.orth != 2) { set_error("state32 is built for the delayed CGS2 orthogonalization (orth = 2)"); return LDG_EUNSUPPORTED; }
+  }
   if (!g_ws_ptr) g_ws_ptr = new Workspace();
   Workspace& ws = *g_ws_ptr;
-  ldg_status st = ws.ensure(n, m);
+  ldg_status st = ws.ensure(n, m, o.state32 != 0);
   if (st != LDG_OK) return st;
   const int nb = nblk_for(n);
   const int gV = nb;
@@ -845,6 +882,7 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
       md.q_of[1] = u_lin;
     }
   }
+  if (o.state32 && u_lin) hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(VB), 0, s, n, u_lin, ws.u32);
   const ldg_precision jp = o.jvp_prec;
   const bool use_pc = o.pc != nullptr;
   // learned preconditioner: watched for non-finite output and stagnation
@@ -960,8 +998,11 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
     // x += Z y
     if (k > 0 && result == LDG_OK) {
       hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, s, ws.st, k);
-      hipLaunchKernelGGL(k_combine, dim3(gV), dim3(VB), 0, s, n, k, (use_pc || o.orth == 2) ? ws.Z : ws.V, n,
-                         ws.st->y, x);
+      if (o.state32)
+        hipLaunchKernelGGL(k_combine<float>, dim3(gV), dim3(VB), 0, s, n, k, (const float*)ws.Z32, n, ws.st->y, x);
+      else
+        hipLaunchKernelGGL(k_combine<double>, dim3(gV), dim3(VB), 0, s, n, k,
+                           (const double*)((use_pc || o.orth == 2) ? ws.Z : ws.V), n, ws.st->y, x);
       LDG_TRY(hipGetLastError());
     }
     ++S.restarts;

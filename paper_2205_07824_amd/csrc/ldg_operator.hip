@@ -140,24 +140,37 @@ static ldg_status by_kind(int kind, F0 f0, F1 f1, F2 f2, F3 f3, Args&&... args) 
   return LDG_EINVAL;
 }
 
-ldg_status op_grad(const Model& md, const double* u, void* q, bool fp32, bool with_data, hipStream_t s) {
-  if (md.kind == LDG_MODEL_USER) return jit_grad(md, u, q, fp32, with_data, s);
-  return by_kind(md.kind, KindOps<0>::grad, KindOps<1>::grad, KindOps<2>::grad, KindOps<3>::grad, md, u, q, fp32,
+static ldg_status no_state32_for_user(const Model& md, int pm) {
+  if (md.kind == LDG_MODEL_USER && pm == PM_FP32_STATE) {
+    set_error("FP32-state products are built for the library's own models, not for run-time physics");
+    return LDG_EUNSUPPORTED;
+  }
+  return LDG_OK;
+}
+
+ldg_status op_grad(const Model& md, const void* u, void* q, int pm, bool with_data, hipStream_t s) {
+  if (ldg_status st = no_state32_for_user(md, pm)) return st;
+  if (md.kind == LDG_MODEL_USER) return jit_grad(md, (const double*)u, q, pm == PM_FP32, with_data, s);
+  return by_kind(md.kind, KindOps<0>::grad, KindOps<1>::grad, KindOps<2>::grad, KindOps<3>::grad, md, u, q, pm,
                  with_data, s);
 }
 
-ldg_status op_resid(const Model& md, const TimeDev& t, const double* u, const void* q, double* out, bool fp32,
+ldg_status op_resid(const Model& md, const TimeDev& t, const void* u, const void* q, double* out, int pm,
                     bool with_data, hipStream_t s) {
-  if (md.kind == LDG_MODEL_USER) return jit_resid(md, t, u, q, nullptr, nullptr, out, fp32, false, s);
+  if (ldg_status st = no_state32_for_user(md, pm)) return st;
+  if (md.kind == LDG_MODEL_USER)
+    return jit_resid(md, t, (const double*)u, q, nullptr, nullptr, out, pm == PM_FP32, false, s);
   return by_kind(md.kind, KindOps<0>::resid, KindOps<1>::resid, KindOps<2>::resid, KindOps<3>::resid, md, t, u, q,
-                 out, fp32, with_data, s);
+                 out, pm, with_data, s);
 }
 
-ldg_status op_jvp_nonlinear(const Model& md, const TimeDev& t, const double* u, const void* q, const double* v,
-                            const void* dq, double* out, bool fp32, hipStream_t s) {
-  if (md.kind == LDG_MODEL_USER) return jit_resid(md, t, u, q, v, dq, out, fp32, true, s);
+ldg_status op_jvp_nonlinear(const Model& md, const TimeDev& t, const void* u, const void* q, const void* v,
+                            const void* dq, double* out, int pm, hipStream_t s) {
+  if (ldg_status st = no_state32_for_user(md, pm)) return st;
+  if (md.kind == LDG_MODEL_USER)
+    return jit_resid(md, t, (const double*)u, q, (const double*)v, dq, out, pm == PM_FP32, true, s);
   return by_kind(md.kind, KindOps<0>::tangent, KindOps<1>::tangent, KindOps<2>::tangent, KindOps<3>::tangent, md, t,
-                 u, q, v, dq, out, fp32, s);
+                 u, q, v, dq, out, pm, s);
 }
 
 ldg_status op_grad_ext(const Model& md, const double* u, const float* du, float* q, hipStream_t s) {

@@ -337,9 +337,10 @@ struct ResidCfg {
 // DATA = true: Dirichlet uhat = g from bdata (nonlinear models); false:
 // homogeneous (tangents, and linear models whose data enter through qoff).
 // ============================================================================
-template <int KIND, int D, int P1, class R, bool DATA, bool EXT = false, bool AFF = false>
+// S: storage type of the state u (double; float for the FP32-state products)
+template <int KIND, int D, int P1, class R, bool DATA, bool EXT = false, bool AFF = false, class S = double>
 __global__ void __launch_bounds__(256)
-k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const double* __restrict__ u, R* __restrict__ q,
+k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const S* __restrict__ u, R* __restrict__ q,
        const double* __restrict__ qoff, const float* __restrict__ dux = nullptr) {
   using C = GradCfg<KIND, D, P1, R>;
   constexpr int NCU = C::NCU, NN = C::NN, NFP = C::NFP, NF = C::NF, NV = C::NV, EPB = C::EPB;
@@ -400,7 +401,7 @@ k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const double* __restric
       if (nb >= 0) {
 #pragma unroll
         for (int c = 0; c < NCU; ++c) {
-          const double* un = u + ((int64_t)nb * NCU + c) * NN + base;
+          const S* un = u + ((int64_t)nb * NCU + c) * NN + base;
           R sacc = R(0);
 #pragma unroll
           for (int mm = 0; mm < P1; ++mm) sacc += l_nbr[mm] * R(un[mm * SD]);
@@ -492,11 +493,13 @@ k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const double* __restric
 //   MODE 2: tangent of the nonlinear residual at (u, q) in direction (v, dq),
 //           dual-number arithmetic; + a0 M v
 // ============================================================================
-template <int KIND, int D, int P1, class R, int MODE, bool EXT = false, bool AFF = false>
+// S: storage type of the input vectors u, v (double; float for the FP32-state
+// products of modes 0 and 2)
+template <int KIND, int D, int P1, class R, int MODE, bool EXT = false, bool AFF = false, class S = double>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(ResidCfg<KIND, D, P1, R, MODE>::MIN_WAVES)))
-k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const double* __restrict__ u,
-        const R* __restrict__ q, const double* __restrict__ v, const R* __restrict__ dq,
+k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const S* __restrict__ u,
+        const R* __restrict__ q, const S* __restrict__ v, const R* __restrict__ dq,
         const double* __restrict__ dterm, double* __restrict__ out, float* __restrict__ Fout = nullptr) {
   using C = ResidCfg<KIND, D, P1, R, MODE>;
   using V = typename C::V;

@@ -9,8 +9,11 @@ namespace ldg {
 // ============================================================================
 // host dispatch
 // ============================================================================
-template <int KIND, int D, int P1, class R>
-static ldg_status launch_grad(const Model& md, const double* u, void* q, bool with_data, hipStream_t s) {
+// precision modes of the operator entry points: PM_FP64, PM_FP32 (FP32 arithmetic
+// and intermediates, FP64 vectors), PM_FP32_STATE (FP32 arithmetic, FP32 input vectors)
+template <int KIND, int D, int P1, class R, class S = double>
+static ldg_status launch_grad(const Model& md, const void* uv, void* q, bool with_data, hipStream_t s) {
+  const S* u = (const S*)uv;
   // linear models: homogeneous kernel + boundary-data offset; nonlinear: data in the kernel
   const bool in_kernel_data = with_data && !Phys<KIND, D>::LINEAR;
   const double* qoff = (with_data && Phys<KIND, D>::LINEAR) ? md.d_qg : nullptr;
@@ -24,26 +27,28 @@ static ldg_status launch_grad(const Model& md, const double* u, void* q, bool wi
   const float* nodu = nullptr;
   if (in_kernel_data) {
     if (m.affine)
-      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, true, false, true>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
+      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, true, false, true, S>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
                          md.dev(), u, (R*)q, qoff, nodu);
     else
-      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, true, false, false>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
+      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, true, false, false, S>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
                          md.dev(), u, (R*)q, qoff, nodu);
   } else {
     if (m.affine)
-      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, false, false, true>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
+      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, false, false, true, S>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
                          md.dev(), u, (R*)q, qoff, nodu);
     else
-      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, false, false, false>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
+      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, false, false, false, S>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
                          md.dev(), u, (R*)q, qoff, nodu);
   }
   LDG_TRY(hipGetLastError());
   return LDG_OK;
 }
 
-template <int KIND, int D, int P1, class R, int MODE>
-static ldg_status launch_resid(const Model& md, const TimeDev& t, const double* u, const void* q, const double* v,
+template <int KIND, int D, int P1, class R, int MODE, class S = double>
+static ldg_status launch_resid(const Model& md, const TimeDev& t, const void* uv, const void* q, const void* vv,
                                const void* dq, const double* dterm, double* out, hipStream_t s) {
+  const S* u = (const S*)uv;
+  const S* v = (const S*)vv;
   constexpr int NN = ResidCfg<KIND, D, P1, R, MODE>::NN, EPB = ResidCfg<KIND, D, P1, R, MODE>::EPB;
   const Mesh& m = *md.mesh;
   const int nblk = (int)((m.op_E(1) + EPB - 1) / EPB);
@@ -53,10 +58,10 @@ static ldg_status launch_resid(const Model& md, const TimeDev& t, const double* 
   if constexpr (std::is_same<R, double>::value) tab = m.tab; else tab = m.tabf;
   float* noF = nullptr;
   if (m.affine)
-    hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, true>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
+    hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, true, S>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
                        md.dev(), t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
   else
-    hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, false>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
+    hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, false, S>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
                        md.dev(), t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
   LDG_TRY(hipGetLastError());
   return LDG_OK;
@@ -98,11 +103,12 @@ static ldg_status dispatch_kind(int nd, int p1, Args&&... args) {
 
 template <int KI, int DD, int PP>
 struct GradOp {
-  static ldg_status run(const Model& md, const double* u, void* q, bool fp32, bool with_data, hipStream_t s) {
+  static ldg_status run(const Model& md, const void* u, void* q, int pm, bool with_data, hipStream_t s) {
     if constexpr (KI == K_EULER) {
       return LDG_OK;
     } else {
-      if (fp32) return launch_grad<KI, DD, PP, float>(md, u, q, with_data, s);
+      if (pm == PM_FP32_STATE) return launch_grad<KI, DD, PP, float, float>(md, u, q, with_data, s);
+      if (pm == PM_FP32) return launch_grad<KI, DD, PP, float>(md, u, q, with_data, s);
       return launch_grad<KI, DD, PP, double>(md, u, q, with_data, s);
     }
   }
@@ -110,14 +116,19 @@ struct GradOp {
 
 template <int KI, int DD, int PP>
 struct ResidOp {
-  static ldg_status run(const Model& md, const TimeDev& t, const double* u, const void* q, double* out, bool fp32,
+  static ldg_status run(const Model& md, const TimeDev& t, const void* u, const void* q, double* out, int pm,
                         bool with_data, hipStream_t s) {
     if constexpr (KI <= K_CONVDIFF) {
       const double* dt = with_data ? md.d_dterm : nullptr;
-      if (fp32) return launch_resid<KI, DD, PP, float, 0>(md, t, u, q, nullptr, nullptr, dt, out, s);
+      if (pm == PM_FP32_STATE) {
+        if (with_data) { set_error("the FP32-state operator is the linear part only"); return LDG_EINVAL; }
+        return launch_resid<KI, DD, PP, float, 0, float>(md, t, u, q, nullptr, nullptr, nullptr, out, s);
+      }
+      if (pm == PM_FP32) return launch_resid<KI, DD, PP, float, 0>(md, t, u, q, nullptr, nullptr, dt, out, s);
       return launch_resid<KI, DD, PP, double, 0>(md, t, u, q, nullptr, nullptr, dt, out, s);
     } else {
-      if (fp32) return launch_resid<KI, DD, PP, float, 1>(md, t, u, q, nullptr, nullptr, nullptr, out, s);
+      if (pm == PM_FP32_STATE) { set_error("the residual takes an FP64 state"); return LDG_EINVAL; }
+      if (pm == PM_FP32) return launch_resid<KI, DD, PP, float, 1>(md, t, u, q, nullptr, nullptr, nullptr, out, s);
       return launch_resid<KI, DD, PP, double, 1>(md, t, u, q, nullptr, nullptr, nullptr, out, s);
     }
   }
@@ -125,13 +136,14 @@ struct ResidOp {
 
 template <int KI, int DD, int PP>
 struct TangentOp {
-  static ldg_status run(const Model& md, const TimeDev& t, const double* u, const void* q, const double* v,
-                        const void* dq, double* out, bool fp32, hipStream_t s) {
+  static ldg_status run(const Model& md, const TimeDev& t, const void* u, const void* q, const void* v,
+                        const void* dq, double* out, int pm, hipStream_t s) {
     if constexpr (KI <= K_CONVDIFF) {
       set_error("tangent kernel requested for a linear model");
       return LDG_EINVAL;
     } else {
-      if (fp32) return launch_resid<KI, DD, PP, float, 2>(md, t, u, q, v, dq, nullptr, out, s);
+      if (pm == PM_FP32_STATE) return launch_resid<KI, DD, PP, float, 2, float>(md, t, u, q, v, dq, nullptr, out, s);
+      if (pm == PM_FP32) return launch_resid<KI, DD, PP, float, 2>(md, t, u, q, v, dq, nullptr, out, s);
       return launch_resid<KI, DD, PP, double, 2>(md, t, u, q, v, dq, nullptr, out, s);
     }
   }
@@ -155,29 +167,29 @@ struct ResidExtOp {
 
 // per-kind entry points, defined in ldg_op_<kind>.hip
 template <int KI> struct KindOps {
-  static ldg_status grad(const Model& md, const double* u, void* q, bool fp32, bool with_data, hipStream_t s);
-  static ldg_status resid(const Model& md, const TimeDev& t, const double* u, const void* q, double* out, bool fp32,
+  static ldg_status grad(const Model& md, const void* u, void* q, int pm, bool with_data, hipStream_t s);
+  static ldg_status resid(const Model& md, const TimeDev& t, const void* u, const void* q, double* out, int pm,
                           bool with_data, hipStream_t s);
-  static ldg_status tangent(const Model& md, const TimeDev& t, const double* u, const void* q, const double* v,
-                            const void* dq, double* out, bool fp32, hipStream_t s);
+  static ldg_status tangent(const Model& md, const TimeDev& t, const void* u, const void* q, const void* v,
+                            const void* dq, double* out, int pm, hipStream_t s);
   static ldg_status grad_ext(const Model& md, const double* u, const float* du, float* q, hipStream_t s);
   static ldg_status resid_ext(const Model& md, const TimeDev& t, const double* u, const float* q, float* F,
                               double* out, hipStream_t s);
 };
 
 #define LDG_DEFINE_KIND_OPS(KI)                                                                                  \
-  template <> ldg_status KindOps<KI>::grad(const Model& md, const double* u, void* q, bool fp32, bool with_data,  \
+  template <> ldg_status KindOps<KI>::grad(const Model& md, const void* u, void* q, int pm, bool with_data,      \
                                            hipStream_t s) {                                                      \
-    return dispatch_kind<KI, GradOp>(md.mesh->nd, md.mesh->p1, md, u, q, fp32, with_data, s);                    \
+    return dispatch_kind<KI, GradOp>(md.mesh->nd, md.mesh->p1, md, u, q, pm, with_data, s);                      \
   }                                                                                                              \
-  template <> ldg_status KindOps<KI>::resid(const Model& md, const TimeDev& t, const double* u, const void* q,   \
-                                            double* out, bool fp32, bool with_data, hipStream_t s) {             \
-    return dispatch_kind<KI, ResidOp>(md.mesh->nd, md.mesh->p1, md, t, u, q, out, fp32, with_data, s);           \
+  template <> ldg_status KindOps<KI>::resid(const Model& md, const TimeDev& t, const void* u, const void* q,     \
+                                            double* out, int pm, bool with_data, hipStream_t s) {                \
+    return dispatch_kind<KI, ResidOp>(md.mesh->nd, md.mesh->p1, md, t, u, q, out, pm, with_data, s);             \
   }                                                                                                              \
-  template <> ldg_status KindOps<KI>::tangent(const Model& md, const TimeDev& t, const double* u, const void* q, \
-                                              const double* v, const void* dq, double* out, bool fp32,           \
+  template <> ldg_status KindOps<KI>::tangent(const Model& md, const TimeDev& t, const void* u, const void* q,   \
+                                              const void* v, const void* dq, double* out, int pm,                \
                                               hipStream_t s) {                                                   \
-    return dispatch_kind<KI, TangentOp>(md.mesh->nd, md.mesh->p1, md, t, u, q, v, dq, out, fp32, s);             \
+    return dispatch_kind<KI, TangentOp>(md.mesh->nd, md.mesh->p1, md, t, u, q, v, dq, out, pm, s);               \
   }                                                                                                              \
   template <> ldg_status KindOps<KI>::grad_ext(const Model& md, const double* u, const float* du, float* q,      \
                                                hipStream_t s) {                                                  \

@@ -198,9 +198,10 @@ __global__ void __launch_bounds__(256) k_gj_invert(int nb, double* __restrict__ 
 // lines, which plain loads reuse (nontemporal ones measured slower there).
 // NB > 0: block size fixed at compile time (loop fully unrolled); NB = 0: any
 // block size.
-template <class S, int NB>
+// O: storage type of z (double; float for the FP32-state solvers)
+template <class S, int NB, class O = double>
 __global__ void __launch_bounds__(1024) k_bj_apply(int nb_rt, int64_t nblocks, int bpb, const S* __restrict__ inv,
-                                                  const double* __restrict__ r, double* __restrict__ z) {
+                                                  const double* __restrict__ r, O* __restrict__ z) {
   extern __shared__ double rs[];
   const int nb = NB > 0 ? NB : nb_rt;
   const int lb = threadIdx.x / nb, i = threadIdx.x % nb;
@@ -223,7 +224,7 @@ __global__ void __launch_bounds__(1024) k_bj_apply(int nb_rt, int64_t nblocks, i
     }
     for (; j < nb; ++j) acc[0] += (double)M[j * nb] * rb[j];
   }
-  z[b * nb + i] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  z[b * nb + i] = (O)((acc[0] + acc[1]) + (acc[2] + acc[3]));
 }
 
 // z_b = B_b^-1 r_b from the 16-bit grouped layout: one thread per row, one
@@ -238,10 +239,10 @@ __device__ inline void decode4(u32x2 w, double* e) {
   }
 }
 
-template <int H, int NG>
+template <int H, int NG, class O = double>
 __global__ void __launch_bounds__(1024) k_bj_apply16(int nb, int ng_rt, int64_t nblocks, int bpb,
                                                     const uint16_t* __restrict__ inv, const float* __restrict__ scale,
-                                                    const double* __restrict__ r, double* __restrict__ z) {
+                                                    const double* __restrict__ r, O* __restrict__ z) {
   extern __shared__ double rs[];
   const int ng = NG > 0 ? NG : ng_rt;
   const int lb = threadIdx.x / nb, i = threadIdx.x % nb;
@@ -298,7 +299,7 @@ __global__ void __launch_bounds__(1024) k_bj_apply16(int nb, int ng_rt, int64_t 
 #pragma unroll 4
     for (int g = 0; g < ng; ++g) group(g, __builtin_nontemporal_load(M + (int64_t)g * nb));
   }
-  z[b * nb + i] = (double)scale[b * nb + i] * ((acc[0] + acc[1]) + (acc[2] + acc[3]));
+  z[b * nb + i] = (O)((double)scale[b * nb + i] * ((acc[0] + acc[1]) + (acc[2] + acc[3])));
 }
 
 static bool is16(ldg_precision p) { return p == LDG_BF16 || p == LDG_FP16; }
@@ -416,8 +417,8 @@ ldg_status mlp_precond_apply(void* data, const double* r, double* z, hipStream_t
 void* mlp_precond_create(Model* md, struct MlpNet* net, ldg_precond_s* bj, int composite);
 void mlp_precond_destroy(void* data);
 
-ldg_status precond_apply_impl(ldg_precond_s* pc, const double* r, double* z, hipStream_t s) {
-  if (pc->kind == 1) return mlp_precond_apply(pc->mlp_data, r, z, s);
+template <class O>
+static ldg_status bj_apply(ldg_precond_s* pc, const double* r, O* z, hipStream_t s) {
   const int nb = pc->nb;
   int bpb = 256 / nb;
   if (bpb < 1) bpb = 1;
@@ -431,7 +432,7 @@ ldg_status precond_apply_impl(ldg_precond_s* pc, const double* r, double* z, hip
     // compile-time group counts for the common block sizes: 16 (nb 64), 25
     // (nb 100), 7 (nb 25, 27), 4 (nb 16)
 #define LDG_APPLY16(HH, NGC)                                                                                         \
-  hipLaunchKernelGGL((k_bj_apply16<HH, NGC>), dim3(grid), thr, sh16, s, nb, pc->ng, pc->nblocks, bpb, inv, pc->scale, \
+  hipLaunchKernelGGL((k_bj_apply16<HH, NGC, O>), dim3(grid), thr, sh16, s, nb, pc->ng, pc->nblocks, bpb, inv, pc->scale, \
                      r, z)
 #define LDG_APPLY16_ALL(HH)                     \
   switch (pc->ng) {                             \
@@ -450,17 +451,31 @@ ldg_status precond_apply_impl(ldg_precond_s* pc, const double* r, double* z, hip
 #undef LDG_APPLY16
   } else if (pc->prec == LDG_FP32) {
     if (nb == 64)
-      hipLaunchKernelGGL((k_bj_apply<float, 64>), dim3(grid), thr, sh, s, nb, pc->nblocks, bpb, (const float*)pc->inv, r, z);
+      hipLaunchKernelGGL((k_bj_apply<float, 64, O>), dim3(grid), thr, sh, s, nb, pc->nblocks, bpb, (const float*)pc->inv, r, z);
     else
-      hipLaunchKernelGGL((k_bj_apply<float, 0>), dim3(grid), thr, sh, s, nb, pc->nblocks, bpb, (const float*)pc->inv, r, z);
+      hipLaunchKernelGGL((k_bj_apply<float, 0, O>), dim3(grid), thr, sh, s, nb, pc->nblocks, bpb, (const float*)pc->inv, r, z);
   } else {
     if (nb == 64)
-      hipLaunchKernelGGL((k_bj_apply<double, 64>), dim3(grid), thr, sh, s, nb, pc->nblocks, bpb, (const double*)pc->inv, r, z);
+      hipLaunchKernelGGL((k_bj_apply<double, 64, O>), dim3(grid), thr, sh, s, nb, pc->nblocks, bpb, (const double*)pc->inv, r, z);
     else
-      hipLaunchKernelGGL((k_bj_apply<double, 0>), dim3(grid), thr, sh, s, nb, pc->nblocks, bpb, (const double*)pc->inv, r, z);
+      hipLaunchKernelGGL((k_bj_apply<double, 0, O>), dim3(grid), thr, sh, s, nb, pc->nblocks, bpb, (const double*)pc->inv, r, z);
   }
   LDG_TRY(hipGetLastError());
   return LDG_OK;
+}
+
+ldg_status precond_apply_impl(ldg_precond_s* pc, const double* r, double* z, hipStream_t s) {
+  if (pc->kind == 1) return mlp_precond_apply(pc->mlp_data, r, z, s);
+  return bj_apply<double>(pc, r, z, s);
+}
+
+// the block-Jacobi apply with z in FP32 storage (FP32-state solvers)
+ldg_status precond_apply_impl32(ldg_precond_s* pc, const double* r, float* z, hipStream_t s) {
+  if (pc->kind == 1) {
+    set_error("the FP32-state solver takes the block-Jacobi preconditioner, not the learned one");
+    return LDG_EUNSUPPORTED;
+  }
+  return bj_apply<float>(pc, r, z, s);
 }
 
 int precond_kind(const ldg_precond_s* pc) { return pc ? pc->kind : -1; }

@@ -44,7 +44,7 @@ class _ModelDesc(C.Structure):
 class GmresOpts(C.Structure):
     _fields_ = [("restart", C.c_int), ("maxit", C.c_int), ("flexible", C.c_int), ("rtol", C.c_double),
                 ("atol", C.c_double), ("jvp_prec", C.c_int), ("pc", C.c_void_p), ("inject_fault", C.c_int),
-                ("orth", C.c_int)]
+                ("orth", C.c_int), ("state32", C.c_int)]
 
 
 class GmresStats(C.Structure):
@@ -74,6 +74,7 @@ _lib = None
 
 EXPORTED = ["ldg_last_error", "ldg_mesh_create", "ldg_mesh_info", "ldg_mesh_points", "ldg_mesh_destroy",
             "ldg_model_create", "ldg_model_destroy", "ldg_residual", "ldg_jvp", "ldg_jvp_prepare", "ldg_jvp_prepared",
+            "ldg_jvp_state32",
             "ldg_jacobian_blocks",
             "ldg_precond_block_jacobi", "ldg_precond_apply", "ldg_precond_destroy", "ldg_gmres_solve",
             "ldg_newton_solve", "ldg_axpby", "ldg_norm2", "ldg_mlp_create", "ldg_mlp_destroy", "ldg_mlp_set_params",
@@ -102,6 +103,7 @@ def lib():
         "ldg_residual": [vp, C.POINTER(_Time), vp, vp, vp, C.c_int, vp],
         "ldg_jvp": [vp, C.POINTER(_Time), vp, vp, vp, C.c_int, vp],
         "ldg_jvp_prepare": [vp, vp, C.c_int, vp],
+        "ldg_jvp_state32": [vp, C.POINTER(_Time), vp, vp, vp, vp],
         "ldg_jvp_prepared": [vp, C.POINTER(_Time), vp, vp, vp, C.c_int, vp],
         "ldg_jacobian_blocks": [vp, C.POINTER(_Time), vp, C.c_int, vp, vp],
         "ldg_precond_block_jacobi": [vp, C.POINTER(_Time), vp, C.c_int, C.c_int, vp, C.POINTER(vp)],
@@ -293,6 +295,16 @@ class Model:
                                       _stream()), "ldg_jvp_prepared")
         return out
 
+    def jvp_state32(self, u, v, time=None, out=None):
+        """J(u) v with u and v in FP32 storage (FP32 arithmetic), Jv in FP64."""
+        out = self.empty() if out is None else out
+        N = self.N
+        f32 = torch.float32
+        _check(lib().ldg_jvp_state32(self.h, _time(time, N), _ptr(u, "u [FP32]", f32, N),
+                                     _ptr(v, "v [FP32]", f32, N, optional=False), _ptr(out, "out", numel=N),
+                                     _stream()), "ldg_jvp_state32")
+        return out
+
     def ode_stage(self, u, time, alpha, beta, out=None):
         """w of one implicit stage of alpha dw/dt + beta w = s_w(u) with the time wrapper `time` (its r1, r2 are
         w-vectors), from the stage's PDE state u."""
@@ -449,9 +461,9 @@ ORTH_CGS2, ORTH_MGS, ORTH_DCGS2 = 0, 1, 2
 
 
 def gmres_opts(restart=30, maxit=1000, rtol=1e-8, atol=0.0, jvp_prec=FP64, pc=None, flexible=True, inject_fault=0,
-               orth=ORTH_DCGS2):
+               orth=ORTH_DCGS2, state32=False):
     return GmresOpts(restart, maxit, int(flexible), rtol, atol, jvp_prec, None if pc is None else pc.h, inject_fault,
-                     orth)
+                     orth, int(state32))
 
 
 def gmres(model, b, x=None, u_lin=None, time=None, check=True, **kw):

@@ -56,10 +56,12 @@ class Ode:
 
 def bdf_steps(model, u0, dt, nsteps, restart=50, eta=1e-3, rtol=1e-8, jvp_prec=ldg.FP64, bj_prec=ldg.FP64,
               per_variable=False, newton_maxit=10, lin_maxit=5000, orth=ldg.ORTH_DCGS2, bj_refresh=1,
-              log=None, atol=0.0, ode=None):
+              log=None, atol=0.0, ode=None, state32=False):
     """Advance u0 by nsteps implicit steps; returns (u, per-step statistics).  bj_refresh: 1 rebuilds the
     block-Jacobi preconditioner at every Newton iterate, 2 once per step (at its first iterate).  ode: the
-    coupled ODE of the model (Ode), advanced with the same BDF formula from each step's solution."""
+    coupled ODE of the model (Ode), advanced with the same BDF formula from each step's solution.  state32:
+    FP32 storage of the preconditioned Krylov vectors and of the linearization point in the products
+    (jvp_prec must be FP32)."""
     u = u0.clone()
     u_prev = None
     w_prev = None
@@ -78,7 +80,8 @@ def bdf_steps(model, u0, dt, nsteps, restart=50, eta=1e-3, rtol=1e-8, jvp_prec=l
         u, st, status = ldg.newton(model, u, time=t, rtol=rtol, atol=atol, eta=eta, maxit=newton_maxit,
                                    bj_refresh=bj_refresh,
                                    bj_per_variable=per_variable, bj_prec=bj_prec, pc=pc, restart=restart,
-                                   lin_maxit=lin_maxit, jvp_prec=jvp_prec, orth=orth, check=False)
+                                   lin_maxit=lin_maxit, jvp_prec=jvp_prec, orth=orth, state32=state32,
+                                   check=False)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         rec = {"step": k + 1, "seconds": el, "converged": status == ldg.LDG_OK, "newton_iters": st["iters"],
