@@ -642,9 +642,10 @@ def ns_cpu_baseline(box, md, u, v, t, Jgpu, log, budget_s=15.0):
     try:
         import oracle as O
         om = O.Mesh(box, 3)
-        omd = O.Model(O.MODEL_NS, 5, list(md.mu), a0=t.a0)
+        omd = O.Model(O.MODEL_NS, 5, [float(x) for x in md._mu], a0=t.a0)
         uu, vv = u.cpu().numpy(), v.cpu().numpy()
-        probe = np.arange(0, om.E, om.E // 32, dtype=np.int64)[:32]
+        probe = np.arange(0, om.E, om.E // 64, dtype=np.int64)[:64]
+        om.sample(omd, uu, vv, probe[:8])                       # first call: the oracle's one-off set-up
         t0 = time.process_time()
         om.sample(omd, uu, vv, probe)
         per = (time.process_time() - t0) / len(probe)
