@@ -200,10 +200,8 @@ def mfma_p4(ldg, I, log, steps=20):
 
 def other_solves(ldg, I, log):
     """Newton-GMRES time-to-tolerance on the 2D Poisson p=2 8x8 workload (Newton 1 step, GMRES(30) + block-Jacobi
-    to 1e-10) and one held-out 2D convection-diffusion instance at 128^2 p=3 (FGMRES(30) + block-Jacobi to 1e-8,
-    FP64 and FP32 factors)."""
+    to 1e-10)."""
     import torch
-    from paper_2205_07824_amd import learned as LP
     res = {}
     box = I.box_mesh(2, 8)
     m = ldg.Mesh(box, 2, 5)
@@ -224,19 +222,45 @@ def other_solves(ldg, I, log):
     res["poisson2d_p2_8x8"] = {"time_to_1e-10_s": round(el, 5), "converged": status == ldg.LDG_OK,
                                "gmres_iters": st["gmres_iters"], "dof": md.N}
     log("poisson 8x8", res["poisson2d_p2_8x8"])
-    inst = LP.c5_instance(100000, n=128, p=3)
-    cd = {"dof": inst["model"].N, "A": round(inst["A"], 3)}
-    for name, bp in (("fp64_bj", ldg.FP64), ("fp32_bj", ldg.FP32)):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        pc = ldg.BlockJacobi(inst["model"], prec=bp)
-        x, st, status = ldg.gmres(inst["model"], inst["b"], pc=pc, restart=30, rtol=1e-8, maxit=6000, check=False)
-        torch.cuda.synchronize()
-        cd[name] = {"time_to_1e-8_s": round(time.perf_counter() - t0, 4), "converged": status == ldg.LDG_OK,
-                    "iters": st["iters"], "res_ratio": st["res_true"] / max(st["res0"], 1e-300)}
-    res["convdiff2d_p3_128sq_seed100000"] = cd
-    log("convdiff 128^2", cd)
     return res
+
+
+LEARNED_NET = os.path.join(ROOT, "paper_2205_07824_amd", "data", "convdiff2d_p3_128sq_linear_mlp.npz")
+
+
+def learned_leg(ldg, I, log, held_out=4, restart=512):
+    """2D convection-diffusion p=3 on 128^2 quads (N = 262,144), held-out seeds 100000...: FGMRES(restart) to
+    1e-8 from x = 0 with FP64 block-Jacobi alone and with the learned linear form (the network shipped with the
+    package, trained by learned.py on seeds 0.. of the same workload); each time includes building its
+    preconditioner."""
+    import torch
+    from paper_2205_07824_amd import learned as LP
+    if not os.path.exists(LEARNED_NET):
+        log("learned leg skipped: no trained network at", LEARNED_NET)
+        return None
+    net, info = LP.load_network(LEARNED_NET)
+    rows = []
+    for i, sd in enumerate(range(100000, 100000 + held_out)):
+        inst = LP.c5_instance(sd, n=128, p=3)
+        if i == 0:   # the first solve of this basis size allocates the solver workspace: not timed
+            bj = ldg.BlockJacobi(inst["model"])
+            ldg.gmres(inst["model"], inst["b"], pc=bj, restart=restart, maxit=2, check=False)
+            del bj
+        r = LP.evaluate(inst, net, restart=restart, rtol=1e-8, maxit=20000)
+        r["seed"], r["A"] = sd, round(inst["A"], 3)
+        rows.append(r)
+        log("learned", sd, {k: (v["iters"], v["ok"], v["seconds"]) for k, v in r.items() if isinstance(v, dict)})
+        del inst
+    torch.cuda.empty_cache()
+    return {"workload": "2D convection-diffusion, LDG p=3, 128^2 quads, log-normal kappa, divergence-free b "
+                        "(|b| <= A, A ~ LogUniform[1, 100]), f = 1", "dof": 128 * 128 * 16,
+            "solver": f"FGMRES({restart}) from x = 0 to 1e-8, FP64", "held_out_seeds": [r["seed"] for r in rows],
+            "network": {k: info.get(k) for k in ("instances", "samples", "epochs", "dims", "n", "p")},
+            "rows": [{"seed": r["seed"], "A": r["A"],
+                      "block_jacobi": {k: r["block_jacobi"][k] for k in ("iters", "ok", "seconds")},
+                      "learned": {k: r["learned"][k] for k in ("iters", "ok", "seconds", "fell_back")}}
+                     for r in rows],
+            "summary": LP.summarize(rows)}
 
 
 def implicit_steps(ldg, I, log, nsteps=5):
@@ -429,7 +453,8 @@ def wave_displacement_steps(ldg, I, log, nsteps=4):
     md.ode_stage(u0, tw, 1.0, 0.0, out=wo)
     e = event_time(lambda: md.ode_stage(u0, tw, 1.0, 0.0, out=wo), 50)
     res["ode_stage_us"] = round(e * 1e6, 2)
-    res["ode_stage_gbs"] = round(56.0 * nodes / e / 1e9, 1)
+    # 92 MB of state, timed on the same buffers: the rate is the last-level cache's, not HBM's
+    res["ode_stage_cache_gbs"] = round(56.0 * nodes / e / 1e9, 1)
     ode = TS.Ode(w=torch.as_tensor(w0, device="cuda"), alpha=1.0, beta=0.0)
     _, stats = TS.dirk_steps(md, u0.clone(), dt, nsteps, scheme="dirk33", restart=50, eta=1e-3, rtol=1e-10,
                              atol=1e-10, jvp_prec=ldg.FP64, bj_prec=ldg.FP64, bj_refresh=2, log=log, ode=ode)
@@ -624,6 +649,7 @@ def main():
 
     if not args.no_solve:
         out["other_solves"] = other_solves(ldg, I, log)
+        out["learned"] = learned_leg(ldg, I, log)
 
     # implicit time steps: the 64^3 Navier-Stokes workload, then the 2D Euler workload (seconds per step
     # averaged over steps 2..5)
@@ -645,11 +671,18 @@ def ns_cpu_baseline(box, md, u, v, t, Jgpu, log, budget_s=15.0):
         omd = O.Model(O.MODEL_NS, 5, [float(x) for x in md._mu], a0=t.a0)
         uu, vv = u.cpu().numpy(), v.cpu().numpy()
         probe = np.arange(0, om.E, om.E // 64, dtype=np.int64)[:64]
-        om.sample(omd, uu, vv, probe[:8])                       # first call: the oracle's one-off set-up
+        # each call has a fixed cost that does not depend on the sample size: two probe sizes separate it
+        # from the cost per element, so that the sample fills the time budget
+        om.sample(omd, uu, vv, probe[:8])
+        t0 = time.process_time()
+        om.sample(omd, uu, vv, probe[:8])
+        t8 = time.process_time() - t0
         t0 = time.process_time()
         om.sample(omd, uu, vv, probe)
-        per = (time.process_time() - t0) / len(probe)
-        count = int(min(om.E, max(64, budget_s / max(per, 1e-9))))
+        t64 = time.process_time() - t0
+        per = max((t64 - t8) / 56, 1e-9)
+        fixed = max(t8 - 8 * per, 0.0)
+        count = int(min(om.E, max(64, (budget_s - fixed) / per)))
         sel = np.unique(np.linspace(0, om.E - 1, count).astype(np.int64))
         t0 = time.process_time()
         _, Jv_s = om.sample(omd, uu, vv, sel)

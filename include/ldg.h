@@ -328,6 +328,16 @@ ldg_status ldg_mlp_forward_noalloc(ldg_mlp net, const float* X, int64_t B, float
  * learning rate lr when lr > 0.  The loss goes to HOST *loss_host (synchronizes). */
 ldg_status ldg_mlp_train_step(ldg_mlp net, const float* X, const float* Y, int64_t B, float lr, float* loss_host,
                               void* stream);
+/* Training step of the linear form (ldg_precond_mlp with composite = 2): the
+ * network reads the coefficient features X[b][5 nn : 20 nn] of each sample (the
+ * layout of ldg_mlp_gather_patches; in_dim = 15 nn) and its output, viewed as
+ * the row-major matrix A_b [nn][5 nn] (out_dim = 5 nn^2), multiplies the
+ * residual patch X[b][0 : 5 nn]: loss (1/(B nn)) sum (A_b X[b][0:5nn] - Y[b])^2,
+ * gradients by the chain rule through the bilinear product, then Adam as
+ * ldg_mlp_train_step.  X, Y DEVICE float; loss to HOST *loss_host (synchronizes).
+ * EINVAL when the network's sizes are not (15 nn, width, 5 nn^2). */
+ldg_status ldg_mlp_train_step_bilinear(ldg_mlp net, const float* X, const float* Y, int64_t B, float lr,
+                                       float* loss_host, void* stream);
 /* Patch features of the listed elements (elem_idx DEVICE int32 [B], or NULL =
  * all elements in order) of a 2D scalar model: the element and its four face
  * neighbours (-x, +x, -y, +y; zeros outside the domain) give
@@ -336,11 +346,23 @@ ldg_status ldg_mlp_train_step(ldg_mlp net, const float* X, const float* Y, int64
  * e_target is given Y[B][nn] = e on the element / s. */
 ldg_status ldg_mlp_gather_patches(ldg_model model, const double* r, const double* e_target, const int32_t* elem_idx,
                                   int64_t B, float* X, float* Y, double* S, void* stream);
-/* Learned right preconditioner z = B^-1 r + s N(patches(r)) (composite = 1, needs
- * the block-Jacobi fallback_bj) or z = s N(patches(r)) (composite = 0).
- * Inside ldg_gmres_solve it is replaced by fallback_bj for the rest of the
- * solve when its output is non-finite or the residual drops by less than 1%
- * over 10 iterations (stats.fell_back = 1).  The handles must outlive it. */
+/* Learned right preconditioner (the learned-preconditioner pattern of the
+ * Newton-Krylov solver, Section 3.3, with block-Jacobi as its base), in one of
+ * three forms:
+ *  composite = 0: z = s N(patches(r) / s)              (net: 20 nn -> nn)
+ *  composite = 1: z = B^-1 r + s N(patches(r) / s)     (net: 20 nn -> nn)
+ *  composite = 2: z = B^-1 (r + A_K patch(r)_K), the linear form: the network
+ *                 maps the coefficient features of element K's patch (15 nn,
+ *                 the layout of ldg_mlp_gather_patches after its residual part)
+ *                 to the matrix A_K [nn][5 nn] (5 nn^2 outputs), evaluated for
+ *                 every element here, once (on the null stream, synchronized);
+ *                 later changes of the network's parameters need a new
+ *                 preconditioner.  Needs aux = [kappa, b_x, b_y].
+ * Forms 1 and 2 need the block-Jacobi fallback_bj.  EINVAL when the network's
+ * sizes do not match the form.  Inside ldg_gmres_solve it is replaced by
+ * fallback_bj for the rest of the solve when its output is non-finite or the
+ * residual drops by less than 1% over opts.watch_window iterations
+ * (stats.fell_back = 1).  The handles must outlive it. */
 ldg_status ldg_precond_mlp(ldg_model model, ldg_mlp net, ldg_precond fallback_bj, int composite, ldg_precond* out);
 
 /* ---------------------------------------------------------------- solvers - */
@@ -358,6 +380,18 @@ typedef struct {
                              stored in FP32 and the products read them in FP32 (as ldg_jvp_state32); the
                              basis V, Gram-Schmidt, Givens and the true residual stay FP64.  Needs
                              jvp_prec = LDG_FP32, orth = 2 and a block-Jacobi preconditioner or none */
+  int watch_window;       /* learned preconditioner (ldg_precond_mlp): it is replaced by its block-Jacobi
+                             fallback when the residual estimate falls by less than 1% over this many
+                             consecutive iterations; 0 = one restart cycle (restart iterations), < 0 = no
+                             stagnation watch (a non-finite output still falls back) */
+  double* record_v;       /* training-data hook, NULL = off: DEVICE [record_max][n] each; step i (counted over
+                             restarts) stores the vector v_i it hands to the preconditioner in record_v[i]
+                             and the product J z_i of the preconditioner's output z_i in record_jz[i], for
+                             i < record_max.  With block-Jacobi (z_i = B^-1 v_i) the residual J z_i has the
+                             exact correction z_i, with B z_i = v_i.  Not with state32; ldg_newton_solve
+                             ignores it in its inner solves */
+  double* record_jz;
+  int record_max;
 } ldg_gmres_opts;
 
 typedef struct {

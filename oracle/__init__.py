@@ -498,12 +498,49 @@ def mlp_forward(params, X):
 
 def mlp_loss_and_grad(params, X, Y):
     """Mean squared error 1/(B*out) sum (y - Y)^2 and its gradient w.r.t. the parameters."""
-    W1, b1, W2, b2, W3, b3 = params
-    y, (X, z1, h1, z2, h2) = mlp_forward(params, X)
+    y, cache = mlp_forward(params, X)
     B, nout = Y.shape
     diff = y - Y
     loss = np.sum(diff * diff) / (B * nout)
-    dy = 2.0 * diff / (B * nout)
+    return loss, _mlp_backward(params, cache, 2.0 * diff / (B * nout))
+
+
+def mlp_bilinear_loss_and_grad(params, X, Y, nn):
+    """The linear form's loss.  Row b of X holds the residual patch r_b = X[b, :5 nn]
+    and the coefficient features c_b = X[b, 5 nn:]; the network maps c_b to the
+    row-major matrix A_b [nn][5 nn] and predicts A_b r_b.  Loss 1/(B nn) sum
+    (A_b r_b - Y_b)^2; by the chain rule its gradient with respect to A_b is
+    dy_b r_b^T, which the network's backward pass takes from there."""
+    R, Cf = X[:, :5 * nn], X[:, 5 * nn:]
+    out, cache = mlp_forward(params, Cf)
+    B = X.shape[0]
+    A = out.reshape(B, nn, 5 * nn)
+    y = np.einsum("bij,bj->bi", A, R)
+    diff = y - Y
+    loss = np.sum(diff * diff) / (B * nn)
+    dy = 2.0 * diff / (B * nn)
+    dout = (dy[:, :, None] * R[:, None, :]).reshape(B, nn * 5 * nn)
+    return loss, _mlp_backward(params, cache, dout)
+
+
+def linear_patch_precond(Binv, A, nbrs, r):
+    """The linear form of the learned preconditioner, z = B^-1 (r + A_K patch(r)_K)
+    per element K: Binv [E][nn][nn] the inverse diagonal blocks, A [E][nn][5 nn],
+    nbrs [E][4] the face neighbours (-x, +x, -y, +y; -1 outside, where the patch
+    holds zeros)."""
+    E, nn = Binv.shape[0], Binv.shape[1]
+    R = r.reshape(E, nn)
+    z = np.zeros((E, nn))
+    for K in range(E):
+        patch = np.concatenate([R[k] if k >= 0 else np.zeros(nn) for k in [K] + [int(x) for x in nbrs[K]]])
+        z[K] = Binv[K] @ (R[K] + A[K] @ patch)
+    return z.reshape(-1)
+
+
+def _mlp_backward(params, cache, dy):
+    """Parameter gradients of the network from the gradient dy of the loss with respect to its output."""
+    W1, b1, W2, b2, W3, b3 = params
+    X, z1, h1, z2, h2 = cache
     gW3 = dy.T @ h2
     gb3 = dy.sum(0)
     dh2 = dy @ W3
@@ -514,7 +551,7 @@ def mlp_loss_and_grad(params, X, Y):
     dz1 = dh1 * (z1 > 0)
     gW1 = dz1.T @ X
     gb1 = dz1.sum(0)
-    return loss, [gW1, gb1, gW2, gb2, gW3, gb3]
+    return [gW1, gb1, gW2, gb2, gW3, gb3]
 
 
 def adam_step(params, grads, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):

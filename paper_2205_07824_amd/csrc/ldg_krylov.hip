@@ -116,7 +116,7 @@ ldg_status vec_norm2(int64_t n, const double* x, double* part, double* host_out,
 // basis values and G dot accumulators in registers, so all loads of one element
 // index are independent.  Block partials go to part[i * nblk + b] and are reduced
 // by k_reduce_rows (deterministic, no atomics).
-constexpr int MAXM = 128;
+constexpr int MAXM = 512;   // largest restart length (Krylov basis size)
 
 __device__ inline void chunk_of(int64_t n, int64_t* lo, int64_t* hi) {
   const int nblk = gridDim.x;
@@ -282,35 +282,45 @@ struct ArnoldiState {
 static_assert(offsetof(ArnoldiState, breakdown) == offsetof(ArnoldiState, resid) + sizeof(double),
               "resid and breakdown are copied to the host together");
 
-// h1[j + 1] holds ||w||^2 before the orthogonalization
+// h1[j + 1] holds ||w||^2 before the orthogonalization.  The column and the
+// previous rotations are staged in LDS, so that the sequential rotation chain
+// of thread 0 reads no global memory.
 __global__ void k_givens(ArnoldiState* st, int j, int nblk, const double* __restrict__ h1, const double* __restrict__ h2,
                          const double* __restrict__ npart) {
   __shared__ double sh[16];
+  __shared__ double colL[MAXM + 1], csL[MAXM], snL[MAXM];
   double s = 0.0;
   for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += npart[b];
   s = block_sum(s, sh);
-  if (threadIdx.x != 0) return;
-  st->wnorm0 = sqrt(h1[j + 1]);
-  const int ld = MAXM + 1;
-  double* col = st->H + (int64_t)j * ld;
-  for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
-  const double hn = sqrt(s);
-  col[j + 1] = hn;
-  st->breakdown = (hn <= 1e-14 * st->wnorm0) ? 1 : 0;
-  st->inv_hnext = hn > 0 ? 1.0 / hn : 0.0;
-  for (int i = 0; i < j; ++i) {
-    const double t = st->cs[i] * col[i] + st->sn[i] * col[i + 1];
-    col[i + 1] = -st->sn[i] * col[i] + st->cs[i] * col[i + 1];
-    col[i] = t;
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) colL[i] = h1[i] + h2[i];
+  for (int i = threadIdx.x; i < j; i += blockDim.x) {
+    csL[i] = st->cs[i];
+    snL[i] = st->sn[i];
   }
-  const double d = hypot(col[j], col[j + 1]);
-  st->cs[j] = d > 0 ? col[j] / d : 1.0;
-  st->sn[j] = d > 0 ? col[j + 1] / d : 0.0;
-  col[j] = d;
-  col[j + 1] = 0.0;
-  st->g[j + 1] = -st->sn[j] * st->g[j];
-  st->g[j] = st->cs[j] * st->g[j];
-  st->resid = fabs(st->g[j + 1]);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    st->wnorm0 = sqrt(h1[j + 1]);
+    const double hn = sqrt(s);
+    colL[j + 1] = hn;
+    st->breakdown = (hn <= 1e-14 * st->wnorm0) ? 1 : 0;
+    st->inv_hnext = hn > 0 ? 1.0 / hn : 0.0;
+    for (int i = 0; i < j; ++i) {
+      const double t = csL[i] * colL[i] + snL[i] * colL[i + 1];
+      colL[i + 1] = -snL[i] * colL[i] + csL[i] * colL[i + 1];
+      colL[i] = t;
+    }
+    const double d = hypot(colL[j], colL[j + 1]);
+    st->cs[j] = d > 0 ? colL[j] / d : 1.0;
+    st->sn[j] = d > 0 ? colL[j + 1] / d : 0.0;
+    colL[j] = d;
+    colL[j + 1] = 0.0;
+    st->g[j + 1] = -st->sn[j] * st->g[j];
+    st->g[j] = st->cs[j] * st->g[j];
+    st->resid = fabs(st->g[j + 1]);
+  }
+  __syncthreads();
+  double* col = st->H + (int64_t)j * (MAXM + 1);
+  for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) col[i] = colL[i];
 }
 
 __global__ void k_arnoldi_start(ArnoldiState* st, int nblk, const double* __restrict__ npart) {
@@ -331,14 +341,21 @@ __global__ void k_arnoldi_start(ArnoldiState* st, int nblk, const double* __rest
 // whose direction the basis already spans; in flexible GMRES H may be singular)
 // drops that direction instead of dividing by zero; the true residual computed
 // after the update decides whether the cycle converged.
+// Column-oriented, one work-group: y_i = g_i / R_ii, then g_c -= R_ci y_i for
+// c < i by all threads (column i of R is contiguous).
 __global__ void k_backsolve(ArnoldiState* st, int k) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (blockIdx.x != 0) return;
+  __shared__ double gs[MAXM];
   const int ld = MAXM + 1;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) gs[i] = st->g[i];
+  __syncthreads();
   for (int i = k - 1; i >= 0; --i) {
-    double s = st->g[i];
-    for (int c = i + 1; c < k; ++c) s -= st->H[(int64_t)c * ld + i] * st->y[c];
-    const double d = st->H[(int64_t)i * ld + i];
-    st->y[i] = d != 0.0 ? s / d : 0.0;
+    const double* col = st->H + (int64_t)i * ld;
+    const double d = col[i];
+    const double yi = d != 0.0 ? gs[i] / d : 0.0;
+    for (int c = threadIdx.x; c < i; c += blockDim.x) gs[c] -= col[c] * yi;
+    if (threadIdx.x == 0) st->y[i] = yi;
+    __syncthreads();
   }
 }
 
@@ -415,6 +432,8 @@ __global__ void __launch_bounds__(DC_SCALAR_THREADS) k_dc_scalar(ArnoldiState* s
                                                   const double* __restrict__ part, int nblk,
                                                   double* __restrict__ h1p, double* __restrict__ coef) {
   __shared__ double dots[2 * MAXM + 3];
+  __shared__ double colL[MAXM + 1], csL[MAXM], snL[MAXM];
+  __shared__ double red[2][DC_SCALAR_THREADS / 64];
   __shared__ double bc[3];   // 1/alpha, c/alpha, c
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int row = wid; row < 2 * j + 3; row += nw) {
@@ -428,50 +447,77 @@ __global__ void __launch_bounds__(DC_SCALAR_THREADS) k_dc_scalar(ArnoldiState* s
   __syncthreads();
   const double* a = dots;
   const double* b = dots + j;
+  // a.a and a.b over the work-group; the new Hessenberg column and the previous
+  // rotations staged in LDS for the sequential rotation chain of thread 0
+  {
+    double pa = 0.0, pb = 0.0;
+    for (int i = threadIdx.x; i < j; i += blockDim.x) {
+      pa += a[i] * a[i];
+      pb += a[i] * b[i];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      pa += __shfl_down(pa, off, 64);
+      pb += __shfl_down(pb, off, 64);
+    }
+    if (lane == 0) {
+      red[0][wid] = pa;
+      red[1][wid] = pb;
+    }
+  }
+  for (int i = threadIdx.x; i < j; i += blockDim.x) colL[i] = h1p[i] + a[i];
+  for (int i = threadIdx.x; i + 1 < j; i += blockDim.x) {
+    csL[i] = st->cs[i];
+    snL[i] = st->sn[i];
+  }
+  if (j == 0)
+    for (int i = threadIdx.x; i <= MAXM; i += blockDim.x) st->g[i] = 0.0;
+  __syncthreads();
   if (threadIdx.x == 0) {
     const double uu = dots[2 * j], uw = dots[2 * j + 1], ww = dots[2 * j + 2];
-    double ss = 0.0;
-    for (int i = 0; i < j; ++i) ss += a[i] * a[i];
+    double ss = 0.0, sb = 0.0;
+    for (int w = 0; w < nw; ++w) {
+      ss += red[0][w];
+      sb += red[1][w];
+    }
     double al2 = uu - ss;
     const double al = al2 > 0.0 ? sqrt(al2) : 0.0;
     int brk = 0;
     if (j == 0) {
-      for (int i = 0; i <= MAXM; ++i) st->g[i] = 0.0;
       st->g[0] = al;
       st->resid = al;
     } else {
-      const int ld = MAXM + 1;
       const int c = j - 1;
-      double* col = st->H + (int64_t)c * ld;
-      for (int i = 0; i < j; ++i) col[i] = h1p[i] + a[i];
-      col[j] = al;
+      colL[j] = al;
       brk = (al <= 1e-14 * st->wnorm0) ? 1 : 0;
       for (int i = 0; i < c; ++i) {
-        const double t = st->cs[i] * col[i] + st->sn[i] * col[i + 1];
-        col[i + 1] = -st->sn[i] * col[i] + st->cs[i] * col[i + 1];
-        col[i] = t;
+        const double t = csL[i] * colL[i] + snL[i] * colL[i + 1];
+        colL[i + 1] = -snL[i] * colL[i] + csL[i] * colL[i + 1];
+        colL[i] = t;
       }
-      const double d = hypot(col[c], col[c + 1]);
-      st->cs[c] = d > 0 ? col[c] / d : 1.0;
-      st->sn[c] = d > 0 ? col[c + 1] / d : 0.0;
-      col[c] = d;
-      col[c + 1] = 0.0;
+      const double d = hypot(colL[c], colL[c + 1]);
+      st->cs[c] = d > 0 ? colL[c] / d : 1.0;
+      st->sn[c] = d > 0 ? colL[c + 1] / d : 0.0;
+      colL[c] = d;
+      colL[c + 1] = 0.0;
       st->g[c + 1] = -st->sn[c] * st->g[c];
       st->g[c] = st->cs[c] * st->g[c];
       st->resid = fabs(st->g[c + 1]);
     }
     st->breakdown = brk;
     const double inva = (al > 0.0 && !brk) ? 1.0 / al : 0.0;
-    double sb = 0.0;
-    for (int i = 0; i < j; ++i) sb += a[i] * b[i];
     const double cc = (uw - sb) * inva;
     bc[0] = inva;
     bc[1] = cc * inva;
     bc[2] = cc;
     if (!closing) st->wnorm0 = sqrt(ww);
   }
-  if (closing) return;
   __syncthreads();
+  if (j > 0) {
+    double* col = st->H + (int64_t)(j - 1) * (MAXM + 1);
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) col[i] = colL[i];
+  }
+  if (closing) return;
   const double dl = bc[1];
   for (int i = threadIdx.x; i < j; i += blockDim.x) {
     coef[i] = a[i];
@@ -728,8 +774,18 @@ static ldg_status true_residual(Model& md, const ldg_time* t, const double* u, c
 // One restart cycle of FGMRES with the delayed re-orthogonalization (orth = 2):
 // k returns the number of final columns of H, stop whether the cycle ended on
 // convergence or breakdown.  ws.r holds the cycle's residual on entry.
+// Training-data hook (ldg_gmres_opts.record_*): the preconditioner's input v
+// of global step `its` and the product J z of its output, copied for the caller.
+static ldg_status record_pair(const ldg_gmres_opts& o, int its, int64_t n, const double* vj, const double* jz,
+                              hipStream_t s) {
+  if (!o.record_v || its >= o.record_max) return LDG_OK;
+  LDG_TRY(hipMemcpyAsync(o.record_v + (int64_t)its * n, vj, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  LDG_TRY(hipMemcpyAsync(o.record_jz + (int64_t)its * n, jz, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return LDG_OK;
+}
+
 static ldg_status dcgs2_cycle(Model& md, const ldg_time* t, const double* u_lin, ldg_precision jp,
-                              const ldg_gmres_opts& o, Workspace& ws, ldg_precond_s*& pc_cur, bool watch,
+                              const ldg_gmres_opts& o, Workspace& ws, ldg_precond_s*& pc_cur, bool watch, int watch_win,
                               double& watch_ref, int& watch_it, double tol, int& its, int& k, bool& stop,
                               ldg_status& result, ldg_gmres_stats& S, PhaseClock& clk, hipStream_t s) {
   const int64_t n = ws.n;
@@ -759,9 +815,9 @@ static ldg_status dcgs2_cycle(Model& md, const ldg_time* t, const double* u_lin,
     std::memcpy(&brk, ws.pinned + 2 * sl + 1, sizeof(int));
     S.res_est = res;
     if (!std::isfinite(res)) { result = LDG_EBREAKDOWN; return true; }
-    if (watch && pc_cur == o.pc) {
+    if (watch && watch_win > 0 && pc_cur == o.pc) {
       if (watch_ref < 0) { watch_ref = res; watch_it = 0; }
-      if (++watch_it >= 10) {
+      if (++watch_it >= watch_win) {
         if (res > 0.99 * watch_ref && precond_fallback(o.pc)) { pc_cur = precond_fallback(o.pc); S.fell_back = 1; }
         watch_ref = res;
         watch_it = 0;
@@ -808,6 +864,7 @@ static ldg_status dcgs2_cycle(Model& md, const ldg_time* t, const double* u_lin,
     clk.mark(ws, sl, 1, s);
     st = s32 ? jvp_state32(md, t, ws.u32, zj32, ws.w, true, s) : jvp_impl(md, t, u_lin, zj, ws.w, jp, true, s);
     if (st != LDG_OK) return st;
+    if (!s32 && (st = record_pair(o, its, n, ws.U, ws.w, s)) != LDG_OK) return st;
     clk.mark(ws, sl, 2, s);
     sweep1(j, ws.w);
     hipLaunchKernelGGL(k_dc_scalar, dim3(1), dim3(DC_SCALAR_THREADS), 0, s, ws.st, j, 0, ws.part, nbc, ws.h1, ws.coef);
@@ -858,12 +915,17 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
   ldg_gmres_stats S{};
   const int64_t n = (int64_t)md.N();
   const int m = o.restart;
-  if (m < 1 || m > MAXM) { set_error("restart must be in [1, 128]"); return LDG_EINVAL; }
+  if (m < 1 || m > MAXM) { set_error("restart must be in [1, " + std::to_string(MAXM) + "]"); return LDG_EINVAL; }
   if (o.orth < 0 || o.orth > 2) { set_error("orth must be 0 (CGS2), 1 (MGS) or 2 (delayed CGS2)"); return LDG_EINVAL; }
   if (o.state32) {
     if (o.jvp_prec != LDG_FP32) { set_error("state32 needs jvp_prec = LDG_FP32"); return LDG_EINVAL; }
     if (o.orth != 2) { set_error("state32 is built for the delayed CGS2 orthogonalization (orth = 2)"); return LDG_EUNSUPPORTED; }
   }
+  if ((o.record_v != nullptr) != (o.record_jz != nullptr) || o.record_max < 0) {
+    set_error("record_v and record_jz are given together, with record_max >= 0");
+    return LDG_EINVAL;
+  }
+  if (o.record_v && o.state32) { set_error("recording is not built for the FP32 state"); return LDG_EUNSUPPORTED; }
   if (!g_ws_ptr) g_ws_ptr = new Workspace();
   Workspace& ws = *g_ws_ptr;
   ldg_status st = ws.ensure(n, m, o.state32 != 0);
@@ -886,9 +948,11 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
   const ldg_precision jp = o.jvp_prec;
   const bool use_pc = o.pc != nullptr;
   // learned preconditioner: watched for non-finite output and stagnation
-  // (residual reduced by less than 1% over 10 iterations); then block-Jacobi
+  // (residual estimate reduced by less than 1% over watch_win iterations: one
+  // restart cycle unless the caller sets it; none when negative); then block-Jacobi
   ldg_precond_s* pc_cur = o.pc;
   const bool watch = use_pc && precond_kind(o.pc) == 1;
+  const int watch_win = o.watch_window > 0 ? o.watch_window : (o.watch_window == 0 ? m : 0);
   double watch_ref = -1.0;
   int watch_it = 0;
   double r0 = 0.0;
@@ -905,7 +969,7 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
     int k = 0;
     bool stop = false;
     if (o.orth == 2) {
-      st = dcgs2_cycle(md, t, u_lin, jp, o, ws, pc_cur, watch, watch_ref, watch_it, tol, its, k, stop, result, S, clk, s);
+      st = dcgs2_cycle(md, t, u_lin, jp, o, ws, pc_cur, watch, watch_win, watch_ref, watch_it, tol, its, k, stop, result, S, clk, s);
       if (st != LDG_OK) return st;
       if (result == LDG_EDEVICE) return result;
     } else {
@@ -930,9 +994,9 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
         std::memcpy(&brk, ws.pinned + 2 * sl + 1, sizeof(int));
         S.res_est = res;
         if (!std::isfinite(res)) { result = LDG_EBREAKDOWN; return true; }
-        if (watch && pc_cur == o.pc) {
+        if (watch && watch_win > 0 && pc_cur == o.pc) {
           if (watch_ref < 0) { watch_ref = res; watch_it = 0; }
-          if (++watch_it >= 10) {
+          if (++watch_it >= watch_win) {
             if (res > 0.99 * watch_ref && precond_fallback(o.pc)) { pc_cur = precond_fallback(o.pc); S.fell_back = 1; }
             watch_ref = res;
             watch_it = 0;
@@ -967,6 +1031,7 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
         clk.mark(ws, sl, 1, s);
         st = jvp_impl(md, t, u_lin, zj, ws.w, jp, true, s);
         if (st != LDG_OK) return st;
+        if ((st = record_pair(o, its, n, vj, ws.w, s)) != LDG_OK) return st;
         clk.mark(ws, sl, 2, s);
         // CGS2: h1 = V^T w (+ ||w||^2), w -= V h1, h2 = V^T w, w -= V h2 (+ ||w||^2); or MGS
         st = o.orth == 1 ? mgs(n, j + 1, ws, s) : cgs2(n, j + 1, ws, s);
@@ -997,7 +1062,7 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
     }
     // x += Z y
     if (k > 0 && result == LDG_OK) {
-      hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(64), 0, s, ws.st, k);
+      hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(256), 0, s, ws.st, k);
       if (o.state32)
         hipLaunchKernelGGL(k_combine<float>, dim3(gV), dim3(VB), 0, s, n, k, (const float*)ws.Z32, n, ws.st->y, x);
       else
@@ -1060,6 +1125,8 @@ ldg_status ldg_newton_solve(ldg_model md, const ldg_time* t, double* u, const ld
   S.res0 = g0;
   ldg_status result = LDG_OK;
   ldg_gmres_opts lin = opts->lin;
+  lin.record_v = lin.record_jz = nullptr;   // recording is a hook of single linear solves
+  lin.record_max = 0;
   lin.rtol = opts->eta;
   while (gn > std::max(opts->rtol * g0, opts->atol)) {
     if (S.iters >= opts->maxit) { result = LDG_ENOCONV; set_error("Newton did not converge"); break; }

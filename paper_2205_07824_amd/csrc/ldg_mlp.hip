@@ -1,7 +1,13 @@
 // Element-patch MLP preconditioner: patch gather, GEMMs on MFMA (bf16 operands,
-// fp32 accumulation) or FP32 VALU, forward / backward / Adam, and the
-// composite right preconditioner z = B^-1 r + s N(patch(r) / s) for flexible
-// GMRES, with block-Jacobi as the fallback.
+// fp32 accumulation) or FP32 VALU, forward / backward / Adam, and two right
+// preconditioners for flexible GMRES, with block-Jacobi as the fallback:
+//  * residual form: z = B^-1 r + s N(patch(r) / s), the network evaluated on
+//    every preconditioner input;
+//  * linear form: z = B^-1 (r + A_K patch(r)), where the network maps the
+//    coefficient patch of element K to its patch-to-element matrix A_K once,
+//    when the preconditioner is created (a fixed linear operator, as Krylov
+//    methods assume), trained with the bilinear loss of
+//    ldg_mlp_train_step_bilinear.
 //
 // Network: y = W3 relu(W2 relu(W1 x + b1) + b2) + b3, weights row-major
 // W_l[out][in], FP32 master copies; the GEMM kernel converts operands to bf16
@@ -287,13 +293,15 @@ static ldg_status ensure_cap(MlpNet& net, int64_t B, hipStream_t s) {
 }
 
 // the three layers with the hidden activations in H1, H2 ([B][width] each)
+// (X rows ldx floats apart: the network reads the first in_dim of each)
 static ldg_status mlp_layers(MlpNet& net, const float* X, int64_t B, float* H1, float* H2, float* Y, hipStream_t s,
-                             bool allow_split) {
+                             bool allow_split, int64_t ldx = -1) {
   if (!Y) { set_error("MLP forward without an output buffer"); return LDG_EINVAL; }
   const int I = net.in_dim, W = net.width, O = net.out_dim;
+  if (ldx < 0) ldx = I;
   const float* P = net.params;
   ldg_status st;
-  if ((st = gemm(net, (int)B, W, I, X, I, 1, P + net.off[0], 1, I, H1, W, 1, P + net.off[1], 1, s, allow_split)) != LDG_OK)
+  if ((st = gemm(net, (int)B, W, I, X, ldx, 1, P + net.off[0], 1, I, H1, W, 1, P + net.off[1], 1, s, allow_split)) != LDG_OK)
     return st;
   if ((st = gemm(net, (int)B, W, W, H1, W, 1, P + net.off[2], 1, W, H2, W, 1, P + net.off[3], 1, s, allow_split)) != LDG_OK)
     return st;
@@ -301,10 +309,10 @@ static ldg_status mlp_layers(MlpNet& net, const float* X, int64_t B, float* H1, 
 }
 
 // forward into net.H1, net.H2, Y (Y may be net.Yo)
-static ldg_status mlp_forward(MlpNet& net, const float* X, int64_t B, float* Y, hipStream_t s) {
+static ldg_status mlp_forward(MlpNet& net, const float* X, int64_t B, float* Y, hipStream_t s, int64_t ldx = -1) {
   ldg_status st = ensure_cap(net, B, s);
   if (st != LDG_OK) return st;
-  return mlp_layers(net, X, B, net.H1, net.H2, Y, s, true);
+  return mlp_layers(net, X, B, net.H1, net.H2, Y, s, true, ldx);
 }
 
 // ---- allocation-free forward --------------------------------------------
@@ -339,16 +347,13 @@ static ldg_status scratch_address(float** out) {
   return LDG_OK;
 }
 
-// gradients of the mean squared error into net.grads; loss into net.loss_dev
-static ldg_status mlp_backward(MlpNet& net, const float* X, const float* T, int64_t B, hipStream_t s) {
+// gradients of the loss into net.grads from its gradient dY with respect to the
+// network output (net.dY [B][out]); X rows ldx floats apart
+static ldg_status mlp_backward_dy(MlpNet& net, const float* X, int64_t ldx, int64_t B, hipStream_t s) {
   const int I = net.in_dim, W = net.width, O = net.out_dim;
   const float* P = net.params;
   float* G = net.grads;
   ldg_status st;
-  hipLaunchKernelGGL(k_zero_f, dim3(1), dim3(64), 0, s, (int64_t)1, net.loss_dev);
-  const int64_t ny = B * O;
-  hipLaunchKernelGGL(k_mse, dim3((unsigned)std::min<int64_t>((ny + 255) / 256, 1024)), dim3(256), 0, s, ny,
-                     1.0f / (float)ny, net.Yo, T, net.dY, net.loss_dev);
   // layer 3: gW3 = dY^T H2, gb3 = colsum dY, dH2 = dY W3
   if ((st = gemm(net, O, W, (int)B, net.dY, 1, O, net.H2, W, 1, G + net.off[4], W, 1, nullptr, 0, s)) != LDG_OK) return st;
   hipLaunchKernelGGL(k_colsum, dim3(O), dim3(256), 0, s, B, O, net.dY, G + net.off[5]);
@@ -360,13 +365,108 @@ static ldg_status mlp_backward(MlpNet& net, const float* X, const float* T, int6
   if ((st = gemm(net, (int)B, W, W, net.dH2, W, 1, P + net.off[2], W, 1, net.dH1, W, 1, nullptr, 0, s)) != LDG_OK) return st;
   hipLaunchKernelGGL(k_relu_mask, dim3((unsigned)((B * W + 255) / 256)), dim3(256), 0, s, B * W, net.H1, net.dH1);
   // layer 1
-  if ((st = gemm(net, W, I, (int)B, net.dH1, 1, W, X, I, 1, G + net.off[0], I, 1, nullptr, 0, s)) != LDG_OK) return st;
+  if ((st = gemm(net, W, I, (int)B, net.dH1, 1, W, X, ldx, 1, G + net.off[0], I, 1, nullptr, 0, s)) != LDG_OK) return st;
   hipLaunchKernelGGL(k_colsum, dim3(W), dim3(256), 0, s, B, W, net.dH1, G + net.off[1]);
   LDG_TRY(hipGetLastError());
   return LDG_OK;
 }
 
+// gradients of the mean squared error into net.grads; loss into net.loss_dev
+static ldg_status mlp_backward(MlpNet& net, const float* X, const float* T, int64_t B, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_f, dim3(1), dim3(64), 0, s, (int64_t)1, net.loss_dev);
+  const int64_t ny = B * net.out_dim;
+  hipLaunchKernelGGL(k_mse, dim3((unsigned)std::min<int64_t>((ny + 255) / 256, 1024)), dim3(256), 0, s, ny,
+                     1.0f / (float)ny, net.Yo, T, net.dY, net.loss_dev);
+  return mlp_backward_dy(net, X, net.in_dim, B, s);
+}
+
+// Bilinear head of the linear form: per sample b the network output Yo[b] is the
+// matrix A_b [nn][5 nn] (row-major) and the prediction is y_b = A_b r_b with
+// r_b = X[b][0 : 5 nn] (the residual patch / s).  Loss (1 / (B nn)) sum (y - T)^2
+// into *loss; its gradient with respect to Yo, dYo[b][i][j] = 2 (y_bi - T_bi) r_bj / (B nn).
+// One 64-thread block per sample.
+__global__ void k_bilinear_loss(int64_t B, int nn, const float* __restrict__ X, int64_t ldx,
+                                const float* __restrict__ Yo, const float* __restrict__ T, float scale,
+                                float* __restrict__ dYo, float* __restrict__ loss) {
+  const int64_t b = blockIdx.x;
+  if (b >= B) return;
+  const int nc = 5 * nn;
+  extern __shared__ float sh_bl[];   // r [nc], dy [nn]
+  float* rb = sh_bl;
+  float* dy = sh_bl + nc;
+  for (int j = threadIdx.x; j < nc; j += blockDim.x) rb[j] = X[b * ldx + j];
+  __syncthreads();
+  float part = 0.0f;
+  for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+    const float* a = Yo + (b * nn + i) * (int64_t)nc;
+    float y = 0.0f;
+    for (int j = 0; j < nc; ++j) y = fmaf(a[j], rb[j], y);
+    const float d = y - T[b * nn + i];
+    dy[i] = 2.0f * d * scale;
+    part += d * d;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nn * nc; t += blockDim.x) dYo[b * nn * (int64_t)nc + t] = dy[t / nc] * rb[t % nc];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
+  if (threadIdx.x == 0) atomicAdd(loss, part * scale);
+}
+
 // ------------------------------------------------------------- patches -----
+// Coefficient features of patch slot t / nn, node t % nn (element el, -1 outside
+// the domain: zeros), written into the row C = [log kappa (5 nn) | per slot
+// b_x / 100 (nn), b_y / 100 (nn)] (velocity scaled by the workload's |b| <= 100).
+__device__ inline void patch_coefs(float* C, int t, int64_t el, int nn, const double* __restrict__ aux, int naux) {
+  const int npatch = 5 * nn, j = t % nn;
+  float lk = 0.f, bx = 0.f, by = 0.f;
+  if (el >= 0 && naux >= 3) {
+    lk = (float)log(aux[(el * naux + 0) * nn + j]);
+    bx = (float)(0.01 * aux[(el * naux + 1) * nn + j]);
+    by = (float)(0.01 * aux[(el * naux + 2) * nn + j]);
+  }
+  C[t] = lk;
+  C[npatch + (t / nn) * 2 * nn + j] = bx;
+  C[npatch + (t / nn) * 2 * nn + nn + j] = by;
+}
+
+// the coefficient features of every element (rows of 15 nn floats)
+__global__ void k_coef_patches(int64_t E, int nn, const int32_t* __restrict__ nbr, const double* __restrict__ aux,
+                               int naux, float* __restrict__ C) {
+  const int64_t K = blockIdx.x;
+  if (K >= E) return;
+  for (int t = threadIdx.x; t < 5 * nn; t += blockDim.x) {
+    const int slot = t / nn;
+    const int64_t el = slot == 0 ? K : (int64_t)nbr[K * 4 + (slot - 1)];
+    patch_coefs(C + K * 15 * nn, t, el >= 0 ? el : -1, nn, aux, naux);
+  }
+}
+
+// y_K = r_K + A_K patch(r)_K: A [E][nn][5 nn] FP32, patch slots (K, -x, +x, -y, +y),
+// zeros outside the domain.  One 64-thread block per element; P = 2^k threads
+// per row (P nn <= 64) share its dot product.
+__global__ void k_patch_matvec(int64_t E, int nn, const int32_t* __restrict__ nbr, const float* __restrict__ A,
+                               const double* __restrict__ r, double* __restrict__ y) {
+  const int64_t K = blockIdx.x;
+  if (K >= E) return;
+  const int nc = 5 * nn;
+  __shared__ double rp[320];
+  for (int t = threadIdx.x; t < nc; t += blockDim.x) {
+    const int slot = t / nn;
+    const int64_t el = slot == 0 ? K : (int64_t)nbr[K * 4 + (slot - 1)];
+    rp[t] = el >= 0 ? r[el * nn + (t % nn)] : 0.0;
+  }
+  __syncthreads();
+  int P = 1;
+  while (2 * P * nn <= 64) P *= 2;
+  const int i = threadIdx.x / P, q = threadIdx.x % P;
+  double acc = 0.0;
+  if (i < nn) {
+    const float* a = A + (K * nn + i) * (int64_t)nc;
+    for (int j = q; j < nc; j += P) acc += (double)a[j] * rp[j];
+  }
+  for (int off = 1; off < P; off <<= 1) acc += __shfl_xor(acc, off, 64);
+  if (i < nn && q == 0) y[K * nn + i] = r[K * nn + i] + acc;
+}
 // For each listed element K (2D quadrilaterals, one variable): the patch is K
 // and its four face neighbours in local-face order (-x, +x, -y, +y); missing
 // neighbours contribute zeros.  Features: [r patch / s (5 nn) | log kappa patch
@@ -419,21 +519,8 @@ __global__ void k_gather_patches(int64_t B, int64_t E, const int32_t* __restrict
   float* Xr = X + bidx * in_dim;
   for (int t = threadIdx.x; t < npatch; t += blockDim.x) {
     const int64_t el = pe[t / nn];
-    const int j = t % nn;
-    float rv = 0.f, lk = 0.f, bx = 0.f, by = 0.f;
-    if (el >= 0) {
-      rv = (float)(r[el * nn + j] / sc);
-      if (naux >= 3) {
-        // velocity features scaled by 1/100 (the workload's |b| <= 100)
-        lk = (float)log(aux[(el * naux + 0) * nn + j]);
-        bx = (float)(0.01 * aux[(el * naux + 1) * nn + j]);
-        by = (float)(0.01 * aux[(el * naux + 2) * nn + j]);
-      }
-    }
-    Xr[t] = rv;
-    Xr[npatch + t] = lk;
-    Xr[2 * npatch + (t / nn) * 2 * nn + j] = bx;
-    Xr[2 * npatch + (t / nn) * 2 * nn + nn + j] = by;
+    Xr[t] = el >= 0 ? (float)(r[el * nn + (t % nn)] / sc) : 0.f;
+    patch_coefs(Xr + npatch, t, el, nn, aux, naux);
   }
   if (Y && e)
     for (int j = threadIdx.x; j < nn; j += blockDim.x) Y[bidx * nn + j] = (float)(e[K * nn + j] / sc);
@@ -452,6 +539,24 @@ __global__ void k_add_scaled_output(int64_t E, int nn, const float* __restrict__
 __global__ void k_count_nonfinite(int64_t n, const double* __restrict__ z, int* __restrict__ cnt) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n && !isfinite(z[i])) atomicAdd(cnt, 1);
+}
+
+// Adam step (when lr > 0) and the loss to the host (synchronizes)
+static ldg_status adam_and_loss(MlpNet& net, float lr, float* loss_host, hipStream_t s) {
+  MlpNet* n = &net;
+  if (lr > 0.0f) {
+    n->t += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - powf(b1, (float)n->t), c2 = 1.0f - powf(b2, (float)n->t);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n->nparams + 255) / 256)), dim3(256), 0, s, n->nparams, lr, b1, b2,
+                       1e-8f, c1, c2, n->params, n->grads, n->m1, n->m2);
+    LDG_TRY(hipGetLastError());
+  }
+  if (loss_host) {
+    LDG_TRY(hipMemcpyAsync(loss_host, n->loss_dev, sizeof(float), hipMemcpyDeviceToHost, s));
+    LDG_TRY(hipStreamSynchronize(s));
+  }
+  return LDG_OK;
 }
 
 }  // namespace ldg
@@ -546,20 +651,34 @@ ldg_status ldg_mlp_train_step(ldg_mlp n, const float* X, const float* Y, int64_t
   if (st == LDG_OK) st = mlp_forward(*n, X, B, n->Yo, s);
   if (st == LDG_OK) st = mlp_backward(*n, X, Y, B, s);
   if (st != LDG_OK) return st;
-  if (lr > 0.0f) {
-    n->t += 1;
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float c1 = 1.0f - powf(b1, (float)n->t), c2 = 1.0f - powf(b2, (float)n->t);
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n->nparams + 255) / 256)), dim3(256), 0, s, n->nparams, lr, b1, b2,
-                       1e-8f, c1, c2, n->params, n->grads, n->m1, n->m2);
-    LDG_TRY(hipGetLastError());
-  }
-  if (loss_host) {
-    LDG_TRY(hipMemcpyAsync(loss_host, n->loss_dev, sizeof(float), hipMemcpyDeviceToHost, s));
-    LDG_TRY(hipStreamSynchronize(s));
-  }
-  return LDG_OK;
+  return adam_and_loss(*n, lr, loss_host, s);
 }
+
+// the linear form's training step: the network reads the coefficient features
+// X[b][5 nn : 20 nn] and its output, viewed as A_b [nn][5 nn], multiplies the
+// residual patch X[b][0 : 5 nn]; mean squared error of A_b r_b against Y[b]
+ldg_status ldg_mlp_train_step_bilinear(ldg_mlp n, const float* X, const float* Y, int64_t B, float lr,
+                                       float* loss_host, void* stream) {
+  LDG_ENTER();
+  if (!n || !X || !Y || B <= 0 || B >= (1ll << 31)) { set_error("bad arguments"); return LDG_EINVAL; }
+  const int nn = n->in_dim / 15;
+  if (n->in_dim % 15 != 0 || nn < 1 || nn > 64 || n->out_dim != 5 * nn * nn) {
+    set_error("the linear form needs in_dim = 15 nn (coefficient patch) and out_dim = 5 nn^2 (an nn x 5 nn map)");
+    return LDG_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t ldx = 20 * (int64_t)nn;
+  ldg_status st = ensure_cap(*n, B, s);
+  if (st == LDG_OK) st = mlp_forward(*n, X + 5 * nn, B, n->Yo, s, ldx);
+  if (st != LDG_OK) return st;
+  hipLaunchKernelGGL(k_zero_f, dim3(1), dim3(64), 0, s, (int64_t)1, n->loss_dev);
+  hipLaunchKernelGGL(k_bilinear_loss, dim3((unsigned)B), dim3(64), sizeof(float) * 6 * nn, s, B, nn, X, ldx, n->Yo, Y,
+                     1.0f / (float)(B * nn), n->dY, n->loss_dev);
+  LDG_TRY(hipGetLastError());
+  if ((st = mlp_backward_dy(*n, X + 5 * nn, ldx, B, s)) != LDG_OK) return st;
+  return adam_and_loss(*n, lr, loss_host, s);
+}
+
 
 ldg_status ldg_mlp_gather_patches(ldg_model md, const double* r, const double* e_target, const int32_t* elem_idx,
                                   int64_t B, float* X, float* Y, double* S, void* stream) {
@@ -583,11 +702,13 @@ struct MlpPrecondData {
   Model* md;
   MlpNet* net;
   ldg_precond_s* bj;
-  int composite;
+  int composite;             // 0: s N(...), 1: B^-1 r + s N(...), 2: linear form B^-1 (r + A patch(r))
   float* X = nullptr;
   double* S = nullptr;
   float* Yo = nullptr;
   int* cnt = nullptr;
+  float* Amap = nullptr;     // linear form: A [E][nn][5 nn]
+  double* ybuf = nullptr;    // linear form: r + A patch(r)
 };
 
 ldg_status precond_apply_impl(ldg_precond_s* pc, const double* r, double* z, hipStream_t s);
@@ -598,6 +719,11 @@ ldg_status mlp_precond_apply(void* data, const double* r, double* z, hipStream_t
   const int64_t E = md.mesh->E;
   const int nn = md.mesh->nn;
   ldg_status st;
+  if (d->composite == 2) {
+    hipLaunchKernelGGL(k_patch_matvec, dim3((unsigned)E), dim3(64), 0, s, E, nn, md.mesh->d_nbr, d->Amap, r, d->ybuf);
+    LDG_TRY(hipGetLastError());
+    return precond_apply_impl(d->bj, d->ybuf, z, s);
+  }
   if (d->composite && d->bj) {
     st = precond_apply_impl(d->bj, r, z, s);
     if (st != LDG_OK) return st;
@@ -623,18 +749,56 @@ ldg_status mlp_precond_count_nonfinite(void* data, const double* z, int64_t n, i
   return LDG_OK;
 }
 
-void* mlp_precond_create(Model* md, MlpNet* net, ldg_precond_s* bj, int composite) {
+void mlp_precond_destroy(void* data);
+
+// The linear form: the coefficient features of every element, the network's
+// output A_K for each (on the null stream, which this call synchronizes).
+static ldg_status linear_form_setup(MlpPrecondData* d) {
+  Model& md = *d->md;
+  const int64_t E = md.mesh->E;
+  const int nn = md.mesh->nn;
+  float* C = nullptr;
+  LDG_TRY(hipMalloc((void**)&d->Amap, sizeof(float) * E * 5 * nn * nn));
+  LDG_TRY(hipMalloc((void**)&d->ybuf, sizeof(double) * E * nn));
+  LDG_TRY(hipMalloc((void**)&C, sizeof(float) * E * 15 * nn));
+  hipLaunchKernelGGL(k_coef_patches, dim3((unsigned)E), dim3(64), 0, nullptr, E, nn, md.mesh->d_nbr, md.aux, md.naux, C);
+  ldg_status st = LDG_OK;
+  if (hipGetLastError() != hipSuccess) { set_error("coefficient patch launch failed"); st = LDG_EDEVICE; }
+  if (st == LDG_OK) st = mlp_forward(*d->net, C, E, d->Amap, nullptr);
+  const hipError_t e = hipStreamSynchronize(nullptr);
+  (void)hipFree(C);
+  if (st == LDG_OK && e != hipSuccess) { set_error(std::string("linear form set-up: ") + hipGetErrorString(e)); st = LDG_EDEVICE; }
+  return st;
+}
+
+void* mlp_precond_create(Model* md, MlpNet* net, ldg_precond_s* bj, int composite, ldg_status* status) {
   auto* d = new MlpPrecondData();
   d->md = md; d->net = net; d->bj = bj; d->composite = composite;
   const int64_t E = md->mesh->E;
   const int nn = md->mesh->nn;
+  *status = LDG_OK;
+  if (composite == 2) {
+    *status = linear_form_setup(d);
+    if (*status == LDG_OK && hipMalloc((void**)&d->cnt, sizeof(int)) != hipSuccess) {
+      set_error("allocation failed");
+      *status = LDG_ENOMEM;
+    }
+    if (*status != LDG_OK) {
+      mlp_precond_destroy(d);
+      return nullptr;
+    }
+    return d;
+  }
+  *status = LDG_ENOMEM;
   if (hipMalloc((void**)&d->X, sizeof(float) * E * net->in_dim) != hipSuccess ||
       hipMalloc((void**)&d->S, sizeof(double) * E) != hipSuccess ||
       hipMalloc((void**)&d->Yo, sizeof(float) * E * nn) != hipSuccess ||
       hipMalloc((void**)&d->cnt, sizeof(int)) != hipSuccess) {
-    delete d;
+    set_error("allocation failed");
+    mlp_precond_destroy(d);
     return nullptr;
   }
+  *status = LDG_OK;
   return d;
 }
 
@@ -642,9 +806,15 @@ void mlp_precond_destroy(void* data) {
   auto* d = (MlpPrecondData*)data;
   if (!d) return;
   (void)hipFree(d->X); (void)hipFree(d->S); (void)hipFree(d->Yo); (void)hipFree(d->cnt);
+  (void)hipFree(d->Amap); (void)hipFree(d->ybuf);
   delete d;
 }
 
 ldg_precond_s* mlp_precond_fallback(void* data) { return ((MlpPrecondData*)data)->bj; }
+
+void mlp_dims(const MlpNet* net, int* in_dim, int* out_dim) {
+  *in_dim = net->in_dim;
+  *out_dim = net->out_dim;
+}
 
 }  // namespace ldg

@@ -414,7 +414,8 @@ ldg_status precond_rebuild(ldg_precond_s* pc, const ldg_time* t, const double* u
 }
 
 ldg_status mlp_precond_apply(void* data, const double* r, double* z, hipStream_t s);
-void* mlp_precond_create(Model* md, struct MlpNet* net, ldg_precond_s* bj, int composite);
+void* mlp_precond_create(Model* md, struct MlpNet* net, ldg_precond_s* bj, int composite, ldg_status* status);
+void mlp_dims(const struct MlpNet* net, int* in_dim, int* out_dim);
 void mlp_precond_destroy(void* data);
 
 template <class O>
@@ -559,14 +560,29 @@ ldg_status ldg_precond_mlp(ldg_model md, ldg_mlp net, ldg_precond fallback_bj, i
   if (!md || !net || !out) { set_error("null argument"); return LDG_EINVAL; }
   if (md->mesh->nd != 2 || md->ncu != 1) { set_error("element patches are defined for 2D scalar models"); return LDG_EUNSUPPORTED; }
   if (fallback_bj && fallback_bj->kind != 0) { set_error("fallback must be a block-Jacobi preconditioner"); return LDG_EINVAL; }
-  if (composite && !fallback_bj) { set_error("composite form needs the block-Jacobi part"); return LDG_EINVAL; }
+  if (composite < 0 || composite > 2) { set_error("composite must be 0, 1 or 2"); return LDG_EINVAL; }
+  if (composite && !fallback_bj) { set_error("composite forms need the block-Jacobi part"); return LDG_EINVAL; }
+  {
+    int in_dim = 0, out_dim = 0;
+    mlp_dims((const MlpNet*)net, &in_dim, &out_dim);
+    const int nn = md->mesh->nn;
+    const bool ok = composite == 2 ? (in_dim == 15 * nn && out_dim == 5 * nn * nn && nn <= 64)
+                                   : (in_dim == 20 * nn && out_dim == nn);
+    if (!ok) {
+      set_error(composite == 2 ? "linear form: the network maps 15 nn coefficient features to 5 nn^2 outputs"
+                               : "the network maps 20 nn patch features to nn outputs");
+      return LDG_EINVAL;
+    }
+  }
+  if (composite == 2 && md->naux != 3) { set_error("the linear form needs aux = [kappa, b_x, b_y]"); return LDG_EUNSUPPORTED; }
   auto* pc = new ldg_precond_s();
   pc->kind = 1;
   pc->md = md;
   pc->nb = 0;
   pc->nblocks = 0;
-  pc->mlp_data = mlp_precond_create(md, (MlpNet*)net, fallback_bj, composite);
-  if (!pc->mlp_data) { delete pc; set_error("allocation failed"); return LDG_ENOMEM; }
+  ldg_status st = LDG_OK;
+  pc->mlp_data = mlp_precond_create(md, (MlpNet*)net, fallback_bj, composite, &st);
+  if (!pc->mlp_data) { delete pc; return st == LDG_OK ? LDG_ENOMEM : st; }
   *out = pc;
   return LDG_OK;
 }

@@ -271,6 +271,20 @@ class GRF:
         arg = x.reshape(-1, x.shape[-1]) @ self.omega.T + self.phase[None, :]
         return (math.sqrt(2.0 / M) * np.cos(arg).sum(axis=1)).reshape(x.shape[:-1])
 
+    def log_kappa_on(self, x, device, chunk=65536):
+        """The same sum evaluated with torch in FP64 on a device (a torch tensor of
+        shape x.shape[:-1]); it agrees with log_kappa to rounding and serves sweeps
+        over many instances, where the host evaluation would dominate."""
+        import torch
+        M = self.phase.shape[0]
+        pts = torch.as_tensor(np.ascontiguousarray(x.reshape(-1, x.shape[-1])), dtype=torch.float64, device=device)
+        om = torch.as_tensor(self.omega, dtype=torch.float64, device=device)
+        ph = torch.as_tensor(self.phase, dtype=torch.float64, device=device)
+        out = torch.empty(pts.shape[0], dtype=torch.float64, device=device)
+        for s in range(0, pts.shape[0], chunk):
+            out[s:s + chunk] = torch.cos(pts[s:s + chunk] @ om.T + ph).sum(dim=1)
+        return (out * math.sqrt(2.0 / M)).reshape(x.shape[:-1])
+
 
 @dataclass
 class DivFreeVelocity:

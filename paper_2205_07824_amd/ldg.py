@@ -44,7 +44,8 @@ class _ModelDesc(C.Structure):
 class GmresOpts(C.Structure):
     _fields_ = [("restart", C.c_int), ("maxit", C.c_int), ("flexible", C.c_int), ("rtol", C.c_double),
                 ("atol", C.c_double), ("jvp_prec", C.c_int), ("pc", C.c_void_p), ("inject_fault", C.c_int),
-                ("orth", C.c_int), ("state32", C.c_int)]
+                ("orth", C.c_int), ("state32", C.c_int), ("watch_window", C.c_int),
+                ("record_v", C.c_void_p), ("record_jz", C.c_void_p), ("record_max", C.c_int)]
 
 
 class GmresStats(C.Structure):
@@ -78,7 +79,8 @@ EXPORTED = ["ldg_last_error", "ldg_mesh_create", "ldg_mesh_info", "ldg_mesh_poin
             "ldg_jacobian_blocks",
             "ldg_precond_block_jacobi", "ldg_precond_apply", "ldg_precond_destroy", "ldg_gmres_solve",
             "ldg_newton_solve", "ldg_axpby", "ldg_norm2", "ldg_mlp_create", "ldg_mlp_destroy", "ldg_mlp_set_params",
-            "ldg_mlp_get_params", "ldg_mlp_forward", "ldg_mlp_forward_noalloc", "ldg_mlp_train_step", "ldg_mlp_gather_patches",
+            "ldg_mlp_get_params", "ldg_mlp_forward", "ldg_mlp_forward_noalloc", "ldg_mlp_train_step",
+            "ldg_mlp_train_step_bilinear", "ldg_mlp_gather_patches",
             "ldg_precond_mlp", "ldg_model_create_user", "ldg_user_physics_check", "ldg_ode_size", "ldg_ode_stage"]
 
 
@@ -120,6 +122,7 @@ def lib():
         "ldg_mlp_forward": [vp, vp, C.c_int64, vp, vp],
         "ldg_mlp_forward_noalloc": [vp, vp, C.c_int64, vp, vp],
         "ldg_mlp_train_step": [vp, vp, vp, C.c_int64, C.c_float, C.POINTER(C.c_float), vp],
+        "ldg_mlp_train_step_bilinear": [vp, vp, vp, C.c_int64, C.c_float, C.POINTER(C.c_float), vp],
         "ldg_mlp_gather_patches": [vp, vp, vp, vp, C.c_int64, vp, vp, vp, vp],
         "ldg_precond_mlp": [vp, vp, vp, C.c_int, C.POINTER(vp)],
         "ldg_model_create_user": [vp, C.POINTER(_ModelDesc), C.c_char_p, C.c_int, vp, C.POINTER(vp)],
@@ -234,7 +237,12 @@ class Model:
                  has_q=True):
         self.mesh, self.kind, self.ncu = mesh, kind, ncu
         dev = torch.device("cuda")
-        to = lambda a: None if a is None else torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64).to(dev).contiguous()
+        def to(a):
+            if a is None:
+                return None
+            if isinstance(a, torch.Tensor):
+                return a.to(device=dev, dtype=torch.float64).contiguous()
+            return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64).to(dev).contiguous()
         # keep the device copies alive for the lifetime of the model
         self.aux, self.src, self.bdata = to(aux), to(src), to(bdata)
         self._mu = _np(mu, np.float64)
@@ -412,6 +420,18 @@ class MLP:
                                         C.byref(loss), _stream()), "ldg_mlp_train_step")
         return float(loss.value)
 
+    def train_step_bilinear(self, X, Y, lr):
+        """ldg_mlp_train_step_bilinear: X [B][20 nn] patch features (residual patch, then the coefficient
+        features the network reads), Y [B][nn] targets of A_b r_b."""
+        loss = C.c_float()
+        B = X.shape[0]
+        f32 = torch.float32
+        nn = self.dims[0] // 15
+        _check(lib().ldg_mlp_train_step_bilinear(self.h, _ptr(X, "X [B][20 nn]", f32, B * 20 * nn, optional=False),
+                                                 _ptr(Y, "Y [B][nn]", f32, B * nn, optional=False), B, float(lr),
+                                                 C.byref(loss), _stream()), "ldg_mlp_train_step_bilinear")
+        return float(loss.value)
+
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
             _lib.ldg_mlp_destroy(self.h)
@@ -437,10 +457,14 @@ def gather_patches(model, r, e=None, elems=None, want_scale=False):
 
 
 class LearnedPrecond:
+    """ldg_precond_mlp.  composite: False / 0 (network alone), True / 1 (block-Jacobi + network correction of
+    the residual form) or "linear" / 2 (z = B^-1 (r + A_K patch(r)), A_K from the coefficient patch)."""
+
     def __init__(self, model, net, bj, composite=True):
         self.model, self.net, self.bj = model, net, bj
+        form = 2 if composite == "linear" else int(composite)
         h = C.c_void_p()
-        _check(lib().ldg_precond_mlp(model.h, net.h, None if bj is None else bj.h, int(composite), C.byref(h)),
+        _check(lib().ldg_precond_mlp(model.h, net.h, None if bj is None else bj.h, form, C.byref(h)),
                "ldg_precond_mlp")
         self.h = h
 
@@ -461,16 +485,29 @@ ORTH_CGS2, ORTH_MGS, ORTH_DCGS2 = 0, 1, 2
 
 
 def gmres_opts(restart=30, maxit=1000, rtol=1e-8, atol=0.0, jvp_prec=FP64, pc=None, flexible=True, inject_fault=0,
-               orth=ORTH_DCGS2, state32=False):
+               orth=ORTH_DCGS2, state32=False, watch_window=0, record=None):
+    """record = (V, JZ): two contiguous FP64 device tensors [k][N] that receive, for the first k steps of the
+    solve, the preconditioner's input v_i and the product J z_i of its output (ldg_gmres_opts.record_*)."""
+    rz = rj = None
+    rmax = 0
+    if record is not None:
+        V, JZ = record
+        if V.shape != JZ.shape or V.dim() != 2:
+            raise ValueError("record: two tensors of equal shape [k][N]")
+        rz, rj = _ptr(V, "record V", optional=False), _ptr(JZ, "record JZ", optional=False)
+        rmax = V.shape[0]
     return GmresOpts(restart, maxit, int(flexible), rtol, atol, jvp_prec, None if pc is None else pc.h, inject_fault,
-                     orth, int(state32))
+                     orth, int(state32), int(watch_window), rz, rj, rmax)
 
 
 def gmres(model, b, x=None, u_lin=None, time=None, check=True, **kw):
     x = torch.zeros_like(b) if x is None else x
+    N = model.N
+    rec = kw.get("record")
+    if rec is not None and any(t.dim() != 2 or t.shape[1] != N for t in rec):
+        raise ValueError(f"record: tensors [k][{N}] expected")
     o = gmres_opts(**kw)
     st = GmresStats()
-    N = model.N
     status = lib().ldg_gmres_solve(model.h, _time(time, N), _ptr(u_lin, "u_lin", numel=N),
                                    _ptr(b, "b", numel=N, optional=False), _ptr(x, "x", numel=N, optional=False),
                                    C.byref(o), C.byref(st), _stream())

@@ -1,12 +1,18 @@
-"""Learned preconditioner, end to end at a reduced size (needs an MI355X).
+"""Learned preconditioner (linear form), end to end (needs an MI355X).
 
-Train the element-patch MLP on solver-generated pairs from seeded
-convection-diffusion instances, then solve held-out instances with FGMRES(30)
-and record the iteration and time ratios against block-Jacobi alone.  What
-must hold is asserted (training reduces the loss; every solve that reports
-convergence passes the FP64 true-residual check); the gain is recorded.
+1. At a reduced size: train the patch network on solver-generated pairs of
+   seeded 32^2 convection-diffusion instances (p = 3), then solve held-out
+   instances with FGMRES(128) from x = 0, with block-Jacobi alone and with the
+   learned linear form z = B^-1 (r + A_K patch(r)).
+2. The network shipped with the package (trained on 2000 instances of the
+   128^2 workload) on held-out 128^2 instances, FGMRES(512).
+
+Asserted: every solve converges and passes the FP64 true-residual check, and
+the learned form needs fewer iterations (and, at 128^2, less time including its
+set-up) than block-Jacobi on every held-out instance.
 """
 import json
+import os
 import sys
 
 import numpy as np
@@ -14,50 +20,57 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
+NET = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2205_07824_amd", "data",
+                   "convdiff2d_p3_128sq_linear_mlp.npz")
+
 
 def _say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
 
 
-def test_learned_preconditioner_gain_on_held_out():
+def _check_solves(res):
+    for k in ("block_jacobi", "learned"):
+        assert res[k]["ok"], (k, res[k])
+        assert res[k]["res_true"] <= 1.01e-8 * res[k]["res0"], (k, res[k])
+
+
+def test_learned_linear_form_gain_on_held_out_32sq():
+    from paper_2205_07824_amd import learned as LP
+    n, p = 32, 3
+    net, info = LP.fit_network(range(0, 24), n=n, p=p, nvec=2, per_vec=1024, solver_steps=256, solver_take=8,
+                               solver_per_vec=1024, epochs=30, log=None)
+    hist = info["loss"]
+    _say("samples", info["samples"], "loss", hist[0], "->", hist[-1])
+    assert np.isfinite(hist).all() and hist[-1] < hist[0]
+    ratios = []
+    for sd in range(100000, 100004):
+        inst = LP.c5_instance(sd, n=n, p=p)
+        res = LP.evaluate(inst, net, restart=128, rtol=1e-8, maxit=6000)
+        _say("held-out", sd, "A", round(inst["A"], 2), json.dumps({k: (v["iters"], v["seconds"], v["fell_back"])
+                                                                   for k, v in res.items()}))
+        _check_solves(res)
+        ratios.append(res["learned"]["iters"] / res["block_jacobi"]["iters"])
+    _say("iteration ratios learned / block-Jacobi", ratios)
+    assert max(ratios) < 0.9 and float(np.median(ratios)) < 0.8
+
+
+@pytest.mark.skipif(not os.path.exists(NET), reason="no trained network shipped")
+def test_shipped_network_gain_at_128sq():
     import torch
     from paper_2205_07824_amd import ldg, learned as LP
-    n, p = 32, 3
-    train_seeds, test_seeds = range(0, 8), range(100000, 100004)
-    rng = np.random.default_rng(0)
-    Xs, Ys = [], []
-    for sd in train_seeds:
-        inst = LP.c5_instance(sd, n=n, p=p)
-        bj = ldg.BlockJacobi(inst["model"])
-        xs, xstar = LP.solve_recording(inst, bj, restart=30, rtol=1e-10)
-        _say("instance", sd, "A", round(inst["A"], 2), "cycles", len(xs), "reference", xstar is not None)
-        if xstar is None:
-            continue
-        X, Y = LP.make_samples(inst, bj, xs, xstar, per_pair=512, rng=rng)
-        Xs += X
-        Ys += Y
-    X = torch.cat(Xs)
-    Y = torch.cat(Ys)
-    _say("samples", X.shape[0])
-    net = ldg.MLP(X.shape[1], 256, Y.shape[1], bf16=True)
-    net.set_params(LP.init_params((X.shape[1], 256, Y.shape[1]), seed=1))
-    hist = LP.train(net, X, Y, epochs=30, batch=min(8192, X.shape[0] // 4), lr=1e-3, log=_say)
-    assert np.isfinite(hist).all() and hist[-1] < hist[0]
-    rows = []
-    for sd in test_seeds:
-        inst = LP.c5_instance(sd, n=n, p=p)
-        bj = ldg.BlockJacobi(inst["model"])
-        pc = ldg.LearnedPrecond(inst["model"], net, bj, composite=True)
-        res = LP.evaluate(inst, bj, pc, restart=30, rtol=1e-8, maxit=6000)
-        res["A"] = inst["A"]
-        _say("held-out", sd, json.dumps(res))
-        for k in ("block_jacobi", "learned"):
-            if res[k]["ok"]:
-                assert res[k]["res_true"] <= 1.01e-8 * res[k]["res0"]
-        rows.append(res)
-    both = [r for r in rows if r["block_jacobi"]["ok"] and r["learned"]["ok"]]
-    ratios = [r["learned"]["iters"] / r["block_jacobi"]["iters"] for r in both]
-    _say("converged with both:", len(both), "of", len(rows), "iteration ratios learned/BJ:", ratios,
-         "learned-only converged:", sum(1 for r in rows if r["learned"]["ok"] and not r["block_jacobi"]["ok"]))
-    _say("learned summary", json.dumps({"n": n, "p": p, "loss": hist, "held_out": rows}))
+    net, info = LP.load_network(NET)
+    _say("network", {k: info.get(k) for k in ("instances", "samples", "epochs", "dims")})
+    for i, sd in enumerate((100002, 100003)):
+        inst = LP.c5_instance(sd, n=128, p=3)
+        if i == 0:   # allocate the solver workspace of this basis size outside the timed solves
+            bj = ldg.BlockJacobi(inst["model"])
+            ldg.gmres(inst["model"], inst["b"], pc=bj, restart=512, maxit=2, check=False)
+            del bj
+            torch.cuda.synchronize()
+        res = LP.evaluate(inst, net, restart=512, rtol=1e-8, maxit=20000)
+        _say("held-out", sd, "A", round(inst["A"], 2), json.dumps({k: (v["iters"], v["seconds"], v["fell_back"])
+                                                                   for k, v in res.items()}))
+        _check_solves(res)
+        assert res["learned"]["iters"] < 0.5 * res["block_jacobi"]["iters"]
+        assert res["learned"]["seconds"] < 0.7 * res["block_jacobi"]["seconds"]

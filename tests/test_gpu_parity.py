@@ -9,6 +9,7 @@ import sys
 import numpy as np
 import pytest
 
+import oracle as O
 from tests import cases as CS
 
 pytestmark = pytest.mark.gpu
@@ -296,7 +297,7 @@ def test_gmres_orthogonalization_variants_match_cgs2(L, orth, use_pc, restart):
 @pytest.mark.parametrize("orth", ["cgs2", "mgs", "dcgs2"])
 @pytest.mark.parametrize("restart", [1, 2, 128])
 def test_gmres_restart_extremes(L, orth, restart):
-    """Restart lengths 1, 2 and the maximum 128 with every orthogonalization: the true FP64 residual meets the
+    """Restart lengths 1, 2 and 128 with every orthogonalization: the true FP64 residual meets the
     tolerance (or, for GMRES(1)/(2), decreases monotonically over the cycles)."""
     import torch
     c = CS.c1_poisson2d()
@@ -319,6 +320,36 @@ def test_gmres_restart_extremes(L, orth, restart):
             r = L.norm(b - md.jvp(None, x))
             assert r <= prev * (1 + 1e-12)
             prev = r
+
+
+@pytest.mark.parametrize("orth", ["cgs2", "mgs", "dcgs2"])
+def test_gmres_long_restart_matches_oracle(L, orth):
+    """A basis longer than 128 vectors: on the 12^2 convection-diffusion system (block-Jacobi), FGMRES(512)
+    converges within one cycle in about 255 iterations, as the oracle's FGMRES(512) does, to the same solution;
+    with restart 128 both need about 460."""
+    import torch
+    c = CS.c5_convdiff2d(n=12, p=3, seed=5)
+    m = L.Mesh(c.box, c.p)
+    md = L.Model(m, c.kind, c.ncu, c.mu, aux=c.aux, src=c.src, bdata=c.bdata, bc_kind=c.bc_kind)
+    om = c.oracle_model()
+    N = c.om.size(1)
+    J = c.om.jacobian(om, np.zeros(N))
+    bref = -c.om.residual(om, np.zeros(N))
+    Bref = O.BlockLU(c.om.blocks(om, np.zeros(N)))
+    b = torch.as_tensor(bref, device="cuda")
+    o = {"cgs2": L.ORTH_CGS2, "mgs": L.ORTH_MGS, "dcgs2": L.ORTH_DCGS2}[orth]
+    pc = L.BlockJacobi(md)
+    for restart in (512, 128):
+        x, st, status = L.gmres(md, b, pc=pc, restart=restart, rtol=1e-10, maxit=3000, orth=o)
+        xref, info = O.fgmres(lambda v: J @ v, bref, M=Bref.solve, restart=restart, maxit=3000, rtol=1e-10)
+        _say("restart", restart, orth, "iters", st["iters"], "oracle", info["iters"], "restarts", st["restarts"])
+        assert status == L.LDG_OK and info["converged"]
+        assert st["res_true"] <= 1.01e-10 * st["res0"]
+        assert abs(st["iters"] - info["iters"]) <= 3
+        if restart == 512:
+            assert st["iters"] > 128 and st["restarts"] <= 1
+        xg = x.cpu().numpy()
+        assert np.linalg.norm(xg - xref) <= 1e-7 * np.linalg.norm(xref)
 
 
 def test_gmres_dcgs2_c1_matches_oracle_solution(L):

@@ -575,12 +575,81 @@ def test_mlp_backward_vs_central_difference():
             assert abs(fd - grads[pi].reshape(-1)[idx]) < 1e-7 * (1 + abs(fd))
 
 
+def test_mlp_bilinear_backward_vs_central_difference():
+    """The linear form's loss: every parameter gradient against central differences."""
+    rng = np.random.default_rng(17)
+    nn = 2
+    dims = [(6, 15 * nn), (6,), (4, 6), (4,), (5 * nn * nn, 4), (5 * nn * nn,)]
+    params = [rng.normal(size=s) * 0.5 for s in dims]
+    X, Y = rng.normal(size=(7, 20 * nn)), rng.normal(size=(7, nn))
+    loss, grads = O.mlp_bilinear_loss_and_grad(params, X, Y, nn)
+    for pi in range(len(params)):
+        flat = params[pi].reshape(-1)
+        for idx in range(min(flat.size, 8)):
+            h = 1e-6
+            old = flat[idx]
+            flat[idx] = old + h
+            lp, _ = O.mlp_bilinear_loss_and_grad(params, X, Y, nn)
+            flat[idx] = old - h
+            lm, _ = O.mlp_bilinear_loss_and_grad(params, X, Y, nn)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - grads[pi].reshape(-1)[idx]) < 1e-7 * (1 + abs(fd))
+
+
+def test_mlp_bilinear_constant_map_closed_form():
+    """With W3 = 0 the network outputs b3 for every sample: the prediction is M r with M = b3 read row-major as
+    [nn][5 nn] (not square, so a transposed reading fails), the loss is the plain least-squares residual of M
+    and its b3 gradient is (2 / (B nn)) (R M^T - Y)^T R."""
+    rng = np.random.default_rng(19)
+    nn, B = 3, 11
+    M = rng.normal(size=(nn, 5 * nn))
+    params = [rng.normal(size=(5, 15 * nn)), rng.normal(size=5), rng.normal(size=(4, 5)), rng.normal(size=4),
+              np.zeros((5 * nn * nn, 4)), M.reshape(-1).copy()]
+    X, Y = rng.normal(size=(B, 20 * nn)), rng.normal(size=(B, nn))
+    R = X[:, :5 * nn]
+    loss, grads = O.mlp_bilinear_loss_and_grad(params, X, Y, nn)
+    res = R @ M.T - Y
+    assert abs(loss - np.sum(res ** 2) / (B * nn)) < 1e-13 * (1 + loss)
+    assert np.abs(grads[5].reshape(nn, 5 * nn) - 2.0 / (B * nn) * res.T @ R).max() < 1e-13
+
+
+def test_linear_patch_precond_special_cases():
+    """z = B^-1 (r + A patch(r)): A = 0 is block-Jacobi, a centre block A = -I gives z = 0, and z_K depends on
+    r only through the patch of K (K and its face neighbours)."""
+    import scipy.linalg as sl
+    box = I.box_mesh(2, 3)
+    om = O.Mesh(box, 1)
+    E, nn = om.E, om.nn
+    nb = om.neighbours()
+    rng = np.random.default_rng(23)
+    Binv = np.stack([sl.inv(rng.normal(size=(nn, nn)) + 4 * np.eye(nn)) for _ in range(E)])
+    r = rng.normal(size=E * nn)
+    z0 = O.linear_patch_precond(Binv, np.zeros((E, nn, 5 * nn)), nb, r)
+    assert np.abs(z0 - np.einsum("eij,ej->ei", Binv, r.reshape(E, nn)).reshape(-1)).max() < 1e-14
+    Aneg = np.zeros((E, nn, 5 * nn))
+    Aneg[:, :, :nn] = -np.eye(nn)
+    assert np.abs(O.linear_patch_precond(Binv, Aneg, nb, r)).max() < 1e-14
+    A = rng.normal(size=(E, nn, 5 * nn))
+    z = O.linear_patch_precond(Binv, A, nb, r).reshape(E, nn)
+    K = 4                                          # the centre element of the 3x3 mesh
+    patch = {K} | {int(k) for k in nb[K] if k >= 0}
+    for L in range(E):
+        r2 = r.copy().reshape(E, nn)
+        r2[L] += 1.0
+        z2 = O.linear_patch_precond(Binv, A, nb, r2.reshape(-1)).reshape(E, nn)
+        changed = np.abs(z2[K] - z[K]).max() > 1e-12
+        assert changed == (L in patch), L
+
+
 # ---------------------------------------------------------------- P17 / P18 inputs
 def test_grf_statistics_and_divergence_free_velocity():
     grf = I.GRF.sample(4, ell=0.1)
     x = np.random.default_rng(5).uniform(0, 1, (20000, 2))
     lk = grf.log_kappa(x)
     assert abs(lk.var() - 1.0) < 0.1
+    # the torch evaluation used for instance sweeps is the same sum
+    assert np.abs(grf.log_kappa_on(x, "cpu", chunk=7000).numpy() - lk).max() < 1e-12
     b = I.DivFreeVelocity.sample(4)
     h = 1e-6
     pts = np.random.default_rng(6).uniform(0, 1, (50, 2))
