@@ -567,7 +567,7 @@ ldg_status ldg_model_destroy(ldg_model md) {
   if (!md) return LDG_OK;
   mfma_release(*md);
   jit_release(*md);
-  hipFree(md->d_q); hipFree(md->d_q32); hipFree(md->d_qres); hipFree(md->d_dq); hipFree(md->d_tmp); hipFree(md->d_tmp2); hipFree(md->d_red);
+  hipFree(md->d_q); hipFree(md->d_tr); hipFree(md->d_q32); hipFree(md->d_qres); hipFree(md->d_dq); hipFree(md->d_tmp); hipFree(md->d_tmp2); hipFree(md->d_red);
   hipFree(md->d_qg); hipFree(md->d_dterm);
   delete md;
   return LDG_OK;
@@ -674,10 +674,14 @@ ldg_status jvp_impl(Model& md, const ldg_time* t, const double* u, const double*
   ldg_status st;
   void* qc = fp32 ? (void*)md.d_q32 : (void*)md.d_q;
   if (!prepared && md.hasq) {
-    md.q_of[fp32 ? 1 : 0] = nullptr;
-    st = op_grad(md, u, qc, fp32, true, s);
-    if (st != LDG_OK) return st;
-    md.q_of[fp32 ? 1 : 0] = u;
+    if (fp32) {
+      md.q_of[1] = nullptr;
+      st = op_grad(md, u, qc, fp32, true, s);
+      if (st != LDG_OK) return st;
+      md.q_of[1] = u;
+    } else if ((st = form_q_cache64(md, u, s)) != LDG_OK) {
+      return st;
+    }
   }
   if (md.hasq) {
     st = op_grad(md, v, md.d_dq, fp32, false, s);
@@ -720,10 +724,11 @@ ldg_status ldg_jvp_prepare(ldg_model md, const double* u, ldg_precision prec, vo
   CHECK_ARG(prec == LDG_FP64 || prec == LDG_FP32, "ldg_jvp_prepare: precision must be FP64 or FP32");
   if (md->linear || !md->hasq) return LDG_OK;
   const bool fp32 = prec == LDG_FP32;
-  md->q_of[fp32 ? 1 : 0] = nullptr;
-  ldg_status st = op_grad(*md, u, fp32 ? (void*)md->d_q32 : (void*)md->d_q, fp32, true, (hipStream_t)stream);
+  if (!fp32) return form_q_cache64(*md, u, (hipStream_t)stream);
+  md->q_of[1] = nullptr;
+  ldg_status st = op_grad(*md, u, md->d_q32, true, true, (hipStream_t)stream);
   if (st != LDG_OK) return st;
-  md->q_of[fp32 ? 1 : 0] = u;
+  md->q_of[1] = u;
   return LDG_OK;
 }
 

@@ -62,6 +62,9 @@ struct ModelDev {
   const double* bdata;   // nonlinear models: [nbf][ncu][nfp]
   int bc_kind[MAXTAG];
   int nbc;
+  // face traces of the linearization point (u, q(u)) for the FP64 tangent kernels,
+  // [E][2 nd][(p+1)^(nd-1)][ncu (1 + nd)] (u, then q in [c][k] order); nullptr = none
+  const double* tr;
 };
 
 // time wrapper coefficients

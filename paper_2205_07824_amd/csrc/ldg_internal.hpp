@@ -85,6 +85,8 @@ struct Model {
   double* d_tmp2 = nullptr;
   double* d_red = nullptr;    // reduction scratch (4096 doubles)
   const double* q_of[2] = {nullptr, nullptr};   // state whose q sits in d_q / d_q32 (ldg_jvp_prepared checks it)
+  double* d_tr = nullptr;       // face traces of (u, q(u)) of the FP64 linearization point (Navier-Stokes)
+  const double* tr_of = nullptr;  // the state whose traces sit in d_tr
   size_t N() const { return (size_t)mesh->E * ncu * mesh->nn; }
   ModelDev dev() const {
     ModelDev d{};
@@ -125,6 +127,10 @@ ldg_status op_resid(const Model& md, const TimeDev& t, const void* u, const void
 ldg_status op_jvp_nonlinear(const Model& md, const TimeDev& t, const void* u, const void* q, const void* v,
                             const void* dq, double* out, int pm, hipStream_t s);
 ldg_status op_data_terms(Model& md, hipStream_t s);
+// q(u) of an FP64 linearization point into md.d_q (and, for the models whose
+// tangent kernels read them, the face traces of u and q(u) into md.d_tr);
+// sets md.q_of[0] (and md.tr_of) to u
+ldg_status form_q_cache64(Model& md, const double* u, hipStream_t s);
 ldg_status op_mfma_jvp(const Model& md, const TimeDev& t, const double* v, double* out, bool fp16, hipStream_t s);
 ldg_status mfma_prepare(Model& md);
 void mfma_release(Model& md);

@@ -934,10 +934,9 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
   const int gV = nb;
   // linearization point: q(u_lin) for the nonlinear models, once per solve
   if (!md.linear && md.hasq) {
-    md.q_of[0] = md.q_of[1] = nullptr;
-    st = op_grad(md, u_lin, md.d_q, false, true, s);
+    md.q_of[1] = nullptr;
+    st = form_q_cache64(md, u_lin, s);
     if (st != LDG_OK) return st;
-    md.q_of[0] = u_lin;
     if (o.jvp_prec == LDG_FP32) {
       st = op_grad(md, u_lin, md.d_q32, true, true, s);
       if (st != LDG_OK) return st;

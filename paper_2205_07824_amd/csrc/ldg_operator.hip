@@ -184,6 +184,46 @@ ldg_status op_resid_ext(const Model& md, const TimeDev& t, const double* u, cons
                  md, t, u, q, F, out, s);
 }
 
+// face traces of (u, q(u)) for the Navier-Stokes tangent (nd + 2 conserved variables)
+static ldg_status launch_face_traces(const Model& md, const double* u, hipStream_t s) {
+  const Mesh& m = *md.mesh;
+  const int64_t items = m.E * 2 * m.nd * (m.nd == 3 ? m.p1 * m.p1 : m.p1);
+  const unsigned nblk = (unsigned)((items + 255) / 256);
+  if (nblk == 0) return LDG_OK;
+#define LDG_TR(DD, PP)                                                                                             \
+  if (m.nd == DD && m.p1 == PP) {                                                                                  \
+    hipLaunchKernelGGL((k_face_traces<DD, PP, DD + 2>), dim3(nblk), dim3(256), 0, s, m.E, m.tab, u, md.d_q, md.d_tr); \
+    LDG_TRY(hipGetLastError());                                                                                    \
+    return LDG_OK;                                                                                                 \
+  }
+  LDG_TR(2, 2) LDG_TR(2, 3) LDG_TR(2, 4) LDG_TR(2, 5) LDG_TR(3, 2) LDG_TR(3, 3) LDG_TR(3, 4)
+#undef LDG_TR
+  set_error("no face-trace kernel for this (nd, p)");
+  return LDG_EUNSUPPORTED;
+}
+
+ldg_status form_q_cache64(Model& md, const double* u, hipStream_t s) {
+  md.q_of[0] = nullptr;
+  md.tr_of = nullptr;
+  ldg_status st = op_grad(md, u, md.d_q, PM_FP64, true, s);
+  if (st != LDG_OK) return st;
+  md.q_of[0] = u;
+  if (md.kind != K_NS) return LDG_OK;   // the models whose FP64 tangent kernel reads the traces
+  const Mesh& m = *md.mesh;
+  if (!md.d_tr) {
+    const int64_t n = m.E * 2 * m.nd * (m.nd == 3 ? m.p1 * m.p1 : m.p1) * (int64_t)md.ncu * (1 + m.nd);
+    if (hipMalloc((void**)&md.d_tr, sizeof(double) * n) != hipSuccess) {
+      (void)hipGetLastError();
+      md.d_tr = nullptr;
+      return LDG_OK;   // without the traces the tangent kernel reads the neighbours' lines
+    }
+  }
+  st = launch_face_traces(md, u, s);
+  if (st != LDG_OK) return st;
+  md.tr_of = u;
+  return LDG_OK;
+}
+
 // data terms of the linear models (qg, dterm), then fold qg into the stored
 // offset used by the gradient kernel
 ldg_status op_data_terms(Model& md, hipStream_t s) {

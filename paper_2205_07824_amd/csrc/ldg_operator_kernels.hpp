@@ -309,6 +309,49 @@ struct GradCfg {
   static constexpr int EPB = pick_epb<NN, BYTES>();
 };
 
+// Face traces of a linearization point for the FP64 tangent kernels: for every
+// element, face F = 2 DIR + side and face point ff (the numbering of k_resid's
+// faces), u and q(u) extrapolated to the face along the lines normal to it, in
+// the same order of operations as k_resid's own extrapolation, stored
+// [E][NF][NCU (1 + D)][NFP] (u, then q in [c][k] order).  Formed once per
+// linearization point; the tangent kernel then reads a neighbour's NCU (1 + D)
+// trace values at a face point instead of its P1-node lines of u and q.
+template <int D, int P1, int NCU>
+__global__ void __launch_bounds__(256) k_face_traces(int64_t E, BasisTab tab, const double* __restrict__ u,
+                                                     const double* __restrict__ q, double* __restrict__ tr) {
+  constexpr int NN = ipow(P1, D), NF = 2 * D, NFP = ipow(P1, D - 1), NVT = NCU * (1 + D);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= E * NF * NFP) return;
+  const int ff = (int)(t % NFP);
+  const int F = (int)((t / NFP) % NF);
+  const int64_t K = t / (NF * NFP);
+  const int dir = F >> 1, side = F & 1;
+  const int T0 = dir == 0 ? 1 : 0;
+  const int T1 = D == 3 ? (dir == 2 ? 1 : 2) : 0;
+  const int t0 = ff % P1, t1 = D == 3 ? ff / P1 : 0;
+  int base = t0 * stride_c(P1, T0);
+  if (D == 3) base += t1 * stride_c(P1, T1);
+  const int SD = stride_c(P1, dir);
+  const double* l = tab.lf[side];
+  double* o = tr + (K * NF + F) * NVT * NFP + ff;
+#pragma unroll
+  for (int c = 0; c < NCU; ++c) {
+    const double* up = u + (K * NCU + c) * NN + base;
+    double a = 0.0;
+#pragma unroll
+    for (int mm = 0; mm < P1; ++mm) a += l[mm] * up[mm * SD];
+    o[c * NFP] = a;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const double* qp = q + ((K * NCU + c) * D + k) * NN + base;
+      double b = 0.0;
+#pragma unroll
+      for (int mm = 0; mm < P1; ++mm) b += l[mm] * qp[mm * SD];
+      o[(NCU + c * D + k) * NFP] = b;
+    }
+  }
+}
+
 template <int KIND, int D, int P1, class R, int MODE>
 struct ResidCfg {
   using PH = Phys<KIND, D>;
@@ -495,9 +538,10 @@ k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const S* __restrict__ u
 // ============================================================================
 // S: storage type of the input vectors u, v (double; float for the FP32-state
 // products of modes 0 and 2)
-template <int KIND, int D, int P1, class R, int MODE, bool EXT = false, bool AFF = false, class S = double>
+template <int KIND, int D, int P1, class R, int MODE, bool EXT = false, bool AFF = false, class S = double,
+          bool TRC = false>
 __global__ void __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(ResidCfg<KIND, D, P1, R, MODE>::MIN_WAVES)))
+__attribute__((amdgpu_waves_per_eu(TRC ? 2 : ResidCfg<KIND, D, P1, R, MODE>::MIN_WAVES)))
 k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const S* __restrict__ u,
         const R* __restrict__ q, const S* __restrict__ v, const R* __restrict__ dq,
         const double* __restrict__ dterm, double* __restrict__ out, float* __restrict__ Fout = nullptr) {
@@ -580,10 +624,19 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const S* _
 #pragma unroll
             for (int mm = 0; mm < P1; ++mm) t += l_own[mm] * s_q[e][c * D + k][base + mm * SD];
           } else if constexpr (HASQ) {
-            // tangent kernel: the element's own q lines from global memory (cached)
+            // tangent kernel: the element's own q lines from global memory (cached);
+            // with the traces of the linearization point formed (TRC), q(u) at the
+            // face point in one read and only the lines of its tangent
             const int64_t oq = ((Ke * NCU + c) * D + k) * NN + base;
+            if constexpr (TRC) {
+              R td = R(0);
 #pragma unroll
-            for (int mm = 0; mm < P1; ++mm) t += l_own[mm] * T::mk(q[oq + mm * SD], dq[oq + mm * SD]);
+              for (int mm = 0; mm < P1; ++mm) td += l_own[mm] * dq[oq + mm * SD];
+              t = T::mk(R(md.tr[((Ke * NF + 2 * DIR + side) * (NCU * (1 + D)) + NCU + c * D + k) * NFP + ff]), td);
+            } else {
+#pragma unroll
+              for (int mm = 0; mm < P1; ++mm) t += l_own[mm] * T::mk(q[oq + mm * SD], dq[oq + mm * SD]);
+            }
           }
           qm[c][k] = t;
         }
@@ -624,14 +677,28 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const S* _
         if constexpr (KIND != K_USER) half_normal_flux<KIND, D, V, R>(md.mu, md.naux, um, qm, am, n, Fh, false);
         V up[NCU], qp[NCU][D];
         R ap2[NA];
+        // FP64 tangent with the traces of the linearization point formed (TRC): the
+        // neighbour's u and q(u) at this face point (its face F ^ 1), one read per
+        // value, consecutive face points adjacent ([E][NF][NCU (1 + D)][NFP])
+        const double* tp = nullptr;
+        if constexpr (TRC) tp = md.tr + ((int64_t)nb * NF + (F ^ 1)) * (NCU * (1 + D)) * NFP + ff;
 #pragma unroll
         for (int c = 0; c < NCU; ++c) {
           const int64_t o = ((int64_t)nb * NCU + c) * NN + base;
           V sacc = T::mk(R(0));
+          if constexpr (MODE == 2) {
+            if constexpr (TRC) {
+              R tv = R(0);
 #pragma unroll
-          for (int mm = 0; mm < P1; ++mm) {
-            if constexpr (MODE == 2) sacc += l_nbr[mm] * T::mk(R(u[o + mm * SD]), R(v[o + mm * SD]));
-            else sacc += l_nbr[mm] * R(u[o + mm * SD]);
+              for (int mm = 0; mm < P1; ++mm) tv += l_nbr[mm] * R(v[o + mm * SD]);
+              sacc = T::mk(R(tp[c * NFP]), tv);
+            } else {
+#pragma unroll
+              for (int mm = 0; mm < P1; ++mm) sacc += l_nbr[mm] * T::mk(R(u[o + mm * SD]), R(v[o + mm * SD]));
+            }
+          } else {
+#pragma unroll
+            for (int mm = 0; mm < P1; ++mm) sacc += l_nbr[mm] * R(u[o + mm * SD]);
           }
           up[c] = sacc;
 #pragma unroll
@@ -639,10 +706,19 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const S* _
             V t = T::mk(R(0));
             if constexpr (HASQ) {
               const int64_t oq = (((int64_t)nb * NCU + c) * D + k) * NN + base;
+              if constexpr (MODE == 2) {
+                if constexpr (TRC) {
+                  R td = R(0);
 #pragma unroll
-              for (int mm = 0; mm < P1; ++mm) {
-                if constexpr (MODE == 2) t += l_nbr[mm] * T::mk(q[oq + mm * SD], dq[oq + mm * SD]);
-                else t += l_nbr[mm] * q[oq + mm * SD];
+                  for (int mm = 0; mm < P1; ++mm) td += l_nbr[mm] * dq[oq + mm * SD];
+                  t = T::mk(R(tp[(NCU + c * D + k) * NFP]), td);
+                } else {
+#pragma unroll
+                  for (int mm = 0; mm < P1; ++mm) t += l_nbr[mm] * T::mk(q[oq + mm * SD], dq[oq + mm * SD]);
+                }
+              } else {
+#pragma unroll
+                for (int mm = 0; mm < P1; ++mm) t += l_nbr[mm] * q[oq + mm * SD];
               }
             }
             qp[c][k] = t;

@@ -57,12 +57,27 @@ static ldg_status launch_resid(const Model& md, const TimeDev& t, const void* uv
   typename TabOf<R>::T tab;
   if constexpr (std::is_same<R, double>::value) tab = m.tab; else tab = m.tabf;
   float* noF = nullptr;
+  ModelDev mod = md.dev();
+  // the FP64 tangent reads the neighbours' face traces of the linearization point when they are formed for u
+  if constexpr (MODE == 2 && std::is_same<R, double>::value && std::is_same<S, double>::value) {
+    if (md.d_tr && md.tr_of && md.tr_of == (const double*)uv && md.q_of[0] == (const double*)uv && q == md.d_q) {
+      mod.tr = md.d_tr;
+      if (m.affine)
+        hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, true, S, true>), dim3(nblk), dim3(EPB * NN), 0, s,
+                           mdv, tab, mod, t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
+      else
+        hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, false, S, true>), dim3(nblk), dim3(EPB * NN), 0, s,
+                           mdv, tab, mod, t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
+      LDG_TRY(hipGetLastError());
+      return LDG_OK;
+    }
+  }
   if (m.affine)
     hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, true, S>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
-                       md.dev(), t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
+                       mod, t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
   else
     hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, false, S>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
-                       md.dev(), t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
+                       mod, t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
   LDG_TRY(hipGetLastError());
   return LDG_OK;
 }

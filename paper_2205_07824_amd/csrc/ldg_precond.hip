@@ -313,10 +313,9 @@ static ldg_status assemble_blocks(Model& md, const ldg_time* t, const double* u_
   const int64_t n = (int64_t)md.N();
   ldg_status st;
   if (!md.linear && md.hasq) {
-    md.q_of[0] = md.q_of[1] = nullptr;
-    st = op_grad(md, u_lin, md.d_q, false, true, s);
+    md.q_of[1] = nullptr;
+    st = form_q_cache64(md, u_lin, s);
     if (st != LDG_OK) return st;
-    md.q_of[0] = u_lin;
     if (probe == LDG_FP32) {
       st = op_grad(md, u_lin, md.d_q32, true, true, s);
       if (st != LDG_OK) return st;
