@@ -567,7 +567,7 @@ ldg_status ldg_model_destroy(ldg_model md) {
   if (!md) return LDG_OK;
   mfma_release(*md);
   jit_release(*md);
-  hipFree(md->d_q); hipFree(md->d_tr); hipFree(md->d_q32); hipFree(md->d_qres); hipFree(md->d_dq); hipFree(md->d_tmp); hipFree(md->d_tmp2); hipFree(md->d_red);
+  hipFree(md->d_q); hipFree(md->d_tr); hipFree(md->d_tr32); hipFree(md->d_q32); hipFree(md->d_qres); hipFree(md->d_dq); hipFree(md->d_tmp); hipFree(md->d_tmp2); hipFree(md->d_red);
   hipFree(md->d_qg); hipFree(md->d_dterm);
   delete md;
   return LDG_OK;
@@ -621,8 +621,8 @@ ldg_status jvp_state32(Model& md, const ldg_time* t, const float* u, const float
     return LDG_EINVAL;
   }
   if (!prepared && md.hasq) {
-    md.q_of[1] = nullptr;   // the cache now holds q of an FP32 state, which no FP64 pointer names
-    st = op_grad(md, u, md.d_q32, PM_FP32_STATE, true, s);
+    // the cache now holds q of an FP32 state, which no FP64 pointer names
+    st = form_q_cache32(md, u, PM_FP32_STATE, s);
     if (st != LDG_OK) return st;
   }
   return op_jvp_nonlinear(md, td, u, md.d_q32, v, md.d_dq, Jv, PM_FP32_STATE, s);
@@ -675,10 +675,7 @@ ldg_status jvp_impl(Model& md, const ldg_time* t, const double* u, const double*
   void* qc = fp32 ? (void*)md.d_q32 : (void*)md.d_q;
   if (!prepared && md.hasq) {
     if (fp32) {
-      md.q_of[1] = nullptr;
-      st = op_grad(md, u, qc, fp32, true, s);
-      if (st != LDG_OK) return st;
-      md.q_of[1] = u;
+      if ((st = form_q_cache32(md, u, PM_FP32, s)) != LDG_OK) return st;
     } else if ((st = form_q_cache64(md, u, s)) != LDG_OK) {
       return st;
     }
@@ -725,11 +722,7 @@ ldg_status ldg_jvp_prepare(ldg_model md, const double* u, ldg_precision prec, vo
   if (md->linear || !md->hasq) return LDG_OK;
   const bool fp32 = prec == LDG_FP32;
   if (!fp32) return form_q_cache64(*md, u, (hipStream_t)stream);
-  md->q_of[1] = nullptr;
-  ldg_status st = op_grad(*md, u, md->d_q32, true, true, (hipStream_t)stream);
-  if (st != LDG_OK) return st;
-  md->q_of[1] = u;
-  return LDG_OK;
+  return form_q_cache32(*md, u, PM_FP32, (hipStream_t)stream);
 }
 
 ldg_status ldg_jvp_prepared(ldg_model md, const ldg_time* t, const double* u, const double* v, double* Jv,

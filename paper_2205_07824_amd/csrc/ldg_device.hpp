@@ -65,6 +65,7 @@ struct ModelDev {
   // face traces of the linearization point (u, q(u)) for the FP64 tangent kernels,
   // [E][2 nd][(p+1)^(nd-1)][ncu (1 + nd)] (u, then q in [c][k] order); nullptr = none
   const double* tr;
+  const float* tr32;   // the same for the FP32 tangent kernels (FP32 linearization point cache)
 };
 
 // time wrapper coefficients

@@ -87,6 +87,8 @@ struct Model {
   const double* q_of[2] = {nullptr, nullptr};   // state whose q sits in d_q / d_q32 (ldg_jvp_prepared checks it)
   double* d_tr = nullptr;       // face traces of (u, q(u)) of the FP64 linearization point (Navier-Stokes)
   const double* tr_of = nullptr;  // the state whose traces sit in d_tr
+  float* d_tr32 = nullptr;        // the same in FP32, formed with d_q32
+  bool tr32_valid = false;        // d_tr32 holds the traces of the state whose q sits in d_q32
   size_t N() const { return (size_t)mesh->E * ncu * mesh->nn; }
   ModelDev dev() const {
     ModelDev d{};
@@ -131,6 +133,10 @@ ldg_status op_data_terms(Model& md, hipStream_t s);
 // tangent kernels read them, the face traces of u and q(u) into md.d_tr);
 // sets md.q_of[0] (and md.tr_of) to u
 ldg_status form_q_cache64(Model& md, const double* u, hipStream_t s);
+// q(u) in FP32 into md.d_q32 and, for the Navier-Stokes tangent, its face traces
+// into md.d_tr32; u is double (pm = PM_FP32) or float (pm = PM_FP32_STATE);
+// md.q_of[1] becomes u for a double u, nullptr for a float one
+ldg_status form_q_cache32(Model& md, const void* u, int pm, hipStream_t s);
 ldg_status op_mfma_jvp(const Model& md, const TimeDev& t, const double* v, double* out, bool fp16, hipStream_t s);
 ldg_status mfma_prepare(Model& md);
 void mfma_release(Model& md);

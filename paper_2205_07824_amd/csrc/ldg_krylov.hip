@@ -938,9 +938,8 @@ ldg_status gmres_impl(Model& md, const ldg_time* t, const double* u_lin, const d
     st = form_q_cache64(md, u_lin, s);
     if (st != LDG_OK) return st;
     if (o.jvp_prec == LDG_FP32) {
-      st = op_grad(md, u_lin, md.d_q32, true, true, s);
+      st = form_q_cache32(md, u_lin, PM_FP32, s);
       if (st != LDG_OK) return st;
-      md.q_of[1] = u_lin;
     }
   }
   if (o.state32 && u_lin) hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(VB), 0, s, n, u_lin, ws.u32);

@@ -184,22 +184,31 @@ ldg_status op_resid_ext(const Model& md, const TimeDev& t, const double* u, cons
                  md, t, u, q, F, out, s);
 }
 
-// face traces of (u, q(u)) for the Navier-Stokes tangent (nd + 2 conserved variables)
-static ldg_status launch_face_traces(const Model& md, const double* u, hipStream_t s) {
+// face traces of (u, q(u)) for the Navier-Stokes tangent (nd + 2 conserved variables):
+// FP64 from md.d_q into md.d_tr, or FP32 from md.d_q32 into md.d_tr32 (u double or float)
+template <class R, class S>
+static ldg_status launch_face_traces(const Model& md, const S* u, const R* q, R* tr, hipStream_t s) {
   const Mesh& m = *md.mesh;
   const int64_t items = m.E * 2 * m.nd * (m.nd == 3 ? m.p1 * m.p1 : m.p1);
   const unsigned nblk = (unsigned)((items + 255) / 256);
   if (nblk == 0) return LDG_OK;
-#define LDG_TR(DD, PP)                                                                                             \
-  if (m.nd == DD && m.p1 == PP) {                                                                                  \
-    hipLaunchKernelGGL((k_face_traces<DD, PP, DD + 2>), dim3(nblk), dim3(256), 0, s, m.E, m.tab, u, md.d_q, md.d_tr); \
-    LDG_TRY(hipGetLastError());                                                                                    \
-    return LDG_OK;                                                                                                 \
+  typename TabOf<R>::T tab;
+  if constexpr (std::is_same<R, double>::value) tab = m.tab; else tab = m.tabf;
+#define LDG_TR(DD, PP)                                                                                           \
+  if (m.nd == DD && m.p1 == PP) {                                                                                \
+    hipLaunchKernelGGL((k_face_traces<DD, PP, DD + 2, R, S>), dim3(nblk), dim3(256), 0, s, m.E, tab, u, q, tr); \
+    LDG_TRY(hipGetLastError());                                                                                  \
+    return LDG_OK;                                                                                               \
   }
   LDG_TR(2, 2) LDG_TR(2, 3) LDG_TR(2, 4) LDG_TR(2, 5) LDG_TR(3, 2) LDG_TR(3, 3) LDG_TR(3, 4)
 #undef LDG_TR
   set_error("no face-trace kernel for this (nd, p)");
   return LDG_EUNSUPPORTED;
+}
+
+static int64_t trace_count(const Model& md) {
+  const Mesh& m = *md.mesh;
+  return m.E * 2 * m.nd * (m.nd == 3 ? m.p1 * m.p1 : m.p1) * (int64_t)md.ncu * (1 + m.nd);
 }
 
 ldg_status form_q_cache64(Model& md, const double* u, hipStream_t s) {
@@ -209,18 +218,33 @@ ldg_status form_q_cache64(Model& md, const double* u, hipStream_t s) {
   if (st != LDG_OK) return st;
   md.q_of[0] = u;
   if (md.kind != K_NS) return LDG_OK;   // the models whose FP64 tangent kernel reads the traces
-  const Mesh& m = *md.mesh;
-  if (!md.d_tr) {
-    const int64_t n = m.E * 2 * m.nd * (m.nd == 3 ? m.p1 * m.p1 : m.p1) * (int64_t)md.ncu * (1 + m.nd);
-    if (hipMalloc((void**)&md.d_tr, sizeof(double) * n) != hipSuccess) {
-      (void)hipGetLastError();
-      md.d_tr = nullptr;
-      return LDG_OK;   // without the traces the tangent kernel reads the neighbours' lines
-    }
+  if (!md.d_tr && hipMalloc((void**)&md.d_tr, sizeof(double) * trace_count(md)) != hipSuccess) {
+    (void)hipGetLastError();
+    md.d_tr = nullptr;
+    return LDG_OK;   // without the traces the tangent kernel reads the neighbours' lines
   }
-  st = launch_face_traces(md, u, s);
+  st = launch_face_traces<double, double>(md, u, md.d_q, md.d_tr, s);
   if (st != LDG_OK) return st;
   md.tr_of = u;
+  return LDG_OK;
+}
+
+ldg_status form_q_cache32(Model& md, const void* u, int pm, hipStream_t s) {
+  md.q_of[1] = nullptr;
+  md.tr32_valid = false;
+  ldg_status st = op_grad(md, u, md.d_q32, pm, true, s);
+  if (st != LDG_OK) return st;
+  if (pm == PM_FP32) md.q_of[1] = (const double*)u;
+  if (md.kind != K_NS) return LDG_OK;
+  if (!md.d_tr32 && hipMalloc((void**)&md.d_tr32, sizeof(float) * trace_count(md)) != hipSuccess) {
+    (void)hipGetLastError();
+    md.d_tr32 = nullptr;
+    return LDG_OK;
+  }
+  st = pm == PM_FP32_STATE ? launch_face_traces<float, float>(md, (const float*)u, md.d_q32, md.d_tr32, s)
+                           : launch_face_traces<float, double>(md, (const double*)u, md.d_q32, md.d_tr32, s);
+  if (st != LDG_OK) return st;
+  md.tr32_valid = true;
   return LDG_OK;
 }
 

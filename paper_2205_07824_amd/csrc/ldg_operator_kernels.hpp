@@ -316,9 +316,9 @@ struct GradCfg {
 // [E][NF][NCU (1 + D)][NFP] (u, then q in [c][k] order).  Formed once per
 // linearization point; the tangent kernel then reads a neighbour's NCU (1 + D)
 // trace values at a face point instead of its P1-node lines of u and q.
-template <int D, int P1, int NCU>
-__global__ void __launch_bounds__(256) k_face_traces(int64_t E, BasisTab tab, const double* __restrict__ u,
-                                                     const double* __restrict__ q, double* __restrict__ tr) {
+template <int D, int P1, int NCU, class R = double, class S = double>
+__global__ void __launch_bounds__(256) k_face_traces(int64_t E, typename TabOf<R>::T tab, const S* __restrict__ u,
+                                                     const R* __restrict__ q, R* __restrict__ tr) {
   constexpr int NN = ipow(P1, D), NF = 2 * D, NFP = ipow(P1, D - 1), NVT = NCU * (1 + D);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= E * NF * NFP) return;
@@ -332,19 +332,19 @@ __global__ void __launch_bounds__(256) k_face_traces(int64_t E, BasisTab tab, co
   int base = t0 * stride_c(P1, T0);
   if (D == 3) base += t1 * stride_c(P1, T1);
   const int SD = stride_c(P1, dir);
-  const double* l = tab.lf[side];
-  double* o = tr + (K * NF + F) * NVT * NFP + ff;
+  const R* l = tab.lf[side];
+  R* o = tr + (K * NF + F) * NVT * NFP + ff;
 #pragma unroll
   for (int c = 0; c < NCU; ++c) {
-    const double* up = u + (K * NCU + c) * NN + base;
-    double a = 0.0;
+    const S* up = u + (K * NCU + c) * NN + base;
+    R a = R(0);
 #pragma unroll
-    for (int mm = 0; mm < P1; ++mm) a += l[mm] * up[mm * SD];
+    for (int mm = 0; mm < P1; ++mm) a += l[mm] * R(up[mm * SD]);
     o[c * NFP] = a;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      const double* qp = q + ((K * NCU + c) * D + k) * NN + base;
-      double b = 0.0;
+      const R* qp = q + ((K * NCU + c) * D + k) * NN + base;
+      R b = R(0);
 #pragma unroll
       for (int mm = 0; mm < P1; ++mm) b += l[mm] * qp[mm * SD];
       o[(NCU + c * D + k) * NFP] = b;
@@ -632,7 +632,9 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const S* _
               R td = R(0);
 #pragma unroll
               for (int mm = 0; mm < P1; ++mm) td += l_own[mm] * dq[oq + mm * SD];
-              t = T::mk(R(md.tr[((Ke * NF + 2 * DIR + side) * (NCU * (1 + D)) + NCU + c * D + k) * NFP + ff]), td);
+              const R* trb;
+              if constexpr (std::is_same<R, double>::value) trb = md.tr; else trb = md.tr32;
+              t = T::mk(trb[((Ke * NF + 2 * DIR + side) * (NCU * (1 + D)) + NCU + c * D + k) * NFP + ff], td);
             } else {
 #pragma unroll
               for (int mm = 0; mm < P1; ++mm) t += l_own[mm] * T::mk(q[oq + mm * SD], dq[oq + mm * SD]);
@@ -680,8 +682,12 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const S* _
         // FP64 tangent with the traces of the linearization point formed (TRC): the
         // neighbour's u and q(u) at this face point (its face F ^ 1), one read per
         // value, consecutive face points adjacent ([E][NF][NCU (1 + D)][NFP])
-        const double* tp = nullptr;
-        if constexpr (TRC) tp = md.tr + ((int64_t)nb * NF + (F ^ 1)) * (NCU * (1 + D)) * NFP + ff;
+        const R* tp = nullptr;
+        if constexpr (TRC) {
+          const R* trb;
+          if constexpr (std::is_same<R, double>::value) trb = md.tr; else trb = md.tr32;
+          tp = trb + ((int64_t)nb * NF + (F ^ 1)) * (NCU * (1 + D)) * NFP + ff;
+        }
 #pragma unroll
         for (int c = 0; c < NCU; ++c) {
           const int64_t o = ((int64_t)nb * NCU + c) * NN + base;

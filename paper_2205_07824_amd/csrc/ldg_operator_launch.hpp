@@ -58,10 +58,18 @@ static ldg_status launch_resid(const Model& md, const TimeDev& t, const void* uv
   if constexpr (std::is_same<R, double>::value) tab = m.tab; else tab = m.tabf;
   float* noF = nullptr;
   ModelDev mod = md.dev();
-  // the FP64 tangent reads the neighbours' face traces of the linearization point when they are formed for u
-  if constexpr (MODE == 2 && std::is_same<R, double>::value && std::is_same<S, double>::value) {
-    if (md.d_tr && md.tr_of && md.tr_of == (const double*)uv && md.q_of[0] == (const double*)uv && q == md.d_q) {
+  // the tangent reads the face traces of the linearization point when they are formed for u
+  // (FP64: for this u; FP32: together with the FP32 q cache it reads)
+  if constexpr (MODE == 2 && KIND == K_NS) {
+    bool use = false;
+    if constexpr (std::is_same<R, double>::value && std::is_same<S, double>::value) {
+      use = md.d_tr && md.tr_of && md.tr_of == (const double*)uv && md.q_of[0] == (const double*)uv && q == md.d_q;
       mod.tr = md.d_tr;
+    } else if constexpr (std::is_same<R, float>::value) {
+      use = md.d_tr32 && md.tr32_valid && q == md.d_q32;
+      mod.tr32 = md.d_tr32;
+    }
+    if (use) {
       if (m.affine)
         hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, true, S, true>), dim3(nblk), dim3(EPB * NN), 0, s,
                            mdv, tab, mod, t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);

@@ -317,9 +317,8 @@ static ldg_status assemble_blocks(Model& md, const ldg_time* t, const double* u_
     st = form_q_cache64(md, u_lin, s);
     if (st != LDG_OK) return st;
     if (probe == LDG_FP32) {
-      st = op_grad(md, u_lin, md.d_q32, true, true, s);
+      st = form_q_cache32(md, u_lin, PM_FP32, s);
       if (st != LDG_OK) return st;
-      md.q_of[1] = u_lin;
     }
   }
   double* v = md.d_tmp;
