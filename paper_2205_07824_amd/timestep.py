@@ -56,12 +56,14 @@ class Ode:
 
 def bdf_steps(model, u0, dt, nsteps, restart=50, eta=1e-3, rtol=1e-8, jvp_prec=ldg.FP64, bj_prec=ldg.FP64,
               per_variable=False, newton_maxit=10, lin_maxit=5000, orth=ldg.ORTH_DCGS2, bj_refresh=1,
-              log=None, atol=0.0, ode=None, state32=False):
+              log=None, atol=0.0, ode=None, state32=False, bj_every=1):
     """Advance u0 by nsteps implicit steps; returns (u, per-step statistics).  bj_refresh: 1 rebuilds the
-    block-Jacobi preconditioner at every Newton iterate, 2 once per step (at its first iterate).  ode: the
-    coupled ODE of the model (Ode), advanced with the same BDF formula from each step's solution.  state32:
-    FP32 storage of the preconditioned Krylov vectors and of the linearization point in the products
-    (jvp_prec must be FP32)."""
+    block-Jacobi preconditioner at every Newton iterate, 2 once per step (at its first iterate).  bj_every:
+    steps between rebuilds; in between, a step keeps the blocks of the last rebuild (the first two steps, the
+    BDF1 start and the first BDF2 step, whose time wrappers differ, always rebuild).  ode: the coupled ODE of
+    the model (Ode), advanced with the same BDF formula from each step's solution.  state32: FP32 storage of
+    the preconditioned Krylov vectors and of the linearization point in the products (jvp_prec must be
+    FP32)."""
     u = u0.clone()
     u_prev = None
     w_prev = None
@@ -77,14 +79,16 @@ def bdf_steps(model, u0, dt, nsteps, restart=50, eta=1e-3, rtol=1e-8, jvp_prec=l
             pc = ldg.BlockJacobi(model, u_lin=u, time=t, per_variable=per_variable, prec=bj_prec)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        refresh = bj_refresh if (k <= 1 or (k - 1) % bj_every == 0) else 0
         u, st, status = ldg.newton(model, u, time=t, rtol=rtol, atol=atol, eta=eta, maxit=newton_maxit,
-                                   bj_refresh=bj_refresh,
+                                   bj_refresh=refresh,
                                    bj_per_variable=per_variable, bj_prec=bj_prec, pc=pc, restart=restart,
                                    lin_maxit=lin_maxit, jvp_prec=jvp_prec, orth=orth, state32=state32,
                                    check=False)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         rec = {"step": k + 1, "seconds": el, "converged": status == ldg.LDG_OK, "newton_iters": st["iters"],
+               "blocks_rebuilt": refresh != 0,
                "gmres_iters": st["gmres_iters"], "res_ratio": st["res_final"] / max(st["res0"], 1e-300),
                "t_jvp": st["t_jvp"], "t_pc": st["t_pc"], "t_orth": st["t_orth"]}
         stats.append(rec)
