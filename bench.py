@@ -354,8 +354,8 @@ NEWTON_FORMS = {"fp64_jvp+fp64_bj": ("FP64", "FP64", 1e-9), "fp64_jvp+fp32_bj": 
                 "fp32_state+fp16_bj": ("FP32", "FP16", 1e-4)}
 
 
-def newton_form(ldg, md, name, orth, log):
-    """Block-Jacobi build + Newton-GMRES(30) from u = 0 to ||G|| <= 1e-8 ||G(0)||, timed end to end."""
+def newton_form(ldg, md, name, orth, log, restart=30):
+    """Block-Jacobi build + Newton-GMRES(restart) from u = 0 to ||G|| <= 1e-8 ||G(0)||, timed end to end."""
     import torch
     jp, bp, eta = NEWTON_FORMS[name]
     jp, bp = getattr(ldg, jp), getattr(ldg, bp)
@@ -365,7 +365,7 @@ def newton_form(ldg, md, name, orth, log):
     torch.cuda.synchronize()
     t_bj = time.perf_counter() - t0
     x = torch.zeros(md.N, dtype=torch.float64, device="cuda")
-    x, st, status = ldg.newton(md, x, rtol=1e-8, eta=eta, maxit=8, pc=pc, restart=30, lin_maxit=4000,
+    x, st, status = ldg.newton(md, x, rtol=1e-8, eta=eta, maxit=8, pc=pc, restart=restart, lin_maxit=4000,
                                jvp_prec=jp, orth=orth, state32=name.startswith("fp32_state"), check=False)
     torch.cuda.synchronize()
     t_all = time.perf_counter() - t0
