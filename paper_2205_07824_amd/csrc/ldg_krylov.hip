@@ -278,6 +278,7 @@ struct ArnoldiState {
   int breakdown;                 // directly after resid: one 16-byte copy reads both
   int pad_;
   double wnorm0;                 // ||w|| before orthogonalization
+  double sigma;                  // delayed variant: the factor the pending vector U was divided by
 };
 static_assert(offsetof(ArnoldiState, breakdown) == offsetof(ArnoldiState, resid) + sizeof(double),
               "resid and breakdown are copied to the host together");
@@ -465,7 +466,10 @@ __global__ void __launch_bounds__(DC_SCALAR_THREADS) k_dc_scalar(ArnoldiState* s
       red[1][wid] = pb;
     }
   }
-  for (int i = threadIdx.x; i < j; i += blockDim.x) colL[i] = h1p[i] + a[i];
+  // U holds the pending vector divided by sigma (the previous step's alpha), which keeps
+  // its magnitude from compounding over the cycle; the column takes the factor back
+  const double sg = j > 0 ? st->sigma : 1.0;
+  for (int i = threadIdx.x; i < j; i += blockDim.x) colL[i] = h1p[i] + sg * a[i];
   for (int i = threadIdx.x; i + 1 < j; i += blockDim.x) {
     csL[i] = st->cs[i];
     snL[i] = st->sn[i];
@@ -488,8 +492,8 @@ __global__ void __launch_bounds__(DC_SCALAR_THREADS) k_dc_scalar(ArnoldiState* s
       st->resid = al;
     } else {
       const int c = j - 1;
-      colL[j] = al;
-      brk = (al <= 1e-14 * st->wnorm0) ? 1 : 0;
+      colL[j] = sg * al;
+      brk = (sg * al <= 1e-14 * st->wnorm0) ? 1 : 0;
       for (int i = 0; i < c; ++i) {
         const double t = csL[i] * colL[i] + snL[i] * colL[i + 1];
         colL[i + 1] = -snL[i] * colL[i] + csL[i] * colL[i + 1];
@@ -511,6 +515,7 @@ __global__ void __launch_bounds__(DC_SCALAR_THREADS) k_dc_scalar(ArnoldiState* s
     bc[1] = cc * inva;
     bc[2] = cc;
     if (!closing) st->wnorm0 = sqrt(ww);
+    st->sigma = al;   // the next pending vector is divided by this alpha (k_dc_update)
   }
   __syncthreads();
   if (j > 0) {
@@ -531,7 +536,9 @@ __global__ void __launch_bounds__(DC_SCALAR_THREADS) k_dc_scalar(ArnoldiState* s
   }
 }
 
-// v_j = (U - V s)/alpha -> Vj ; U <- W - (c/alpha) U - V gamma
+// v_j = (U - V s)/alpha -> Vj ; U <- (W - (c/alpha) U - V gamma) / alpha
+// (the division keeps the pending vector's magnitude from growing by |J M| per
+// step over a long cycle; k_dc_scalar multiplies the next column back)
 template <int G>
 __global__ void __launch_bounds__(VB) k_dc_update(int64_t n, int j, const double* __restrict__ V, int64_t ldv,
                                                   const double* __restrict__ coef, double* __restrict__ U,
@@ -565,7 +572,7 @@ __global__ void __launch_bounds__(VB) k_dc_update(int64_t n, int j, const double
       }
     }
     Vj[t] = va * inva;
-    U[t] = ua;
+    U[t] = ua * inva;
   }
 }
 

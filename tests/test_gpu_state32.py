@@ -92,3 +92,37 @@ def test_newton_ns_state32_matches_oracle(L):
     _say("newton ns state32 stats", st)
     assert status == L.LDG_OK
     assert rel(u.cpu().numpy(), u_ref) < 1e-8
+
+
+@pytest.mark.parametrize("state32", [False, True])
+def test_long_cycles_keep_converging(L, state32):
+    """Long restart cycles of the delayed Gram-Schmidt variant, FP32 products: the pending vector is rescaled
+    every step, so its magnitude does not grow by |J M| per step over the cycle (unscaled, the FP32-state
+    Newton solve of the 32^3 Poisson workload with FP16 blocks diverged at restart 256).  Every cycle length
+    converges to the FP64 true residual, and a longer cycle never needs more iterations."""
+    import torch
+    from paper_2205_07824_amd import inputs as I
+    box = I.box_mesh(3, 32, perturb=0.05, seed=0)
+    m = L.Mesh(box, 3)
+    xn, xq, xb, _ = m.points()
+    _, _, f = I.mms_expsin3d(xq)
+    ub, _, _ = I.mms_expsin3d(xb)
+    md = L.Model(m, L.MODEL_POISSON, 1, [1.0, 16.0 * 32, 0.0], src=f.reshape(m.E, 1, m.nqv),
+                 bdata=ub.reshape(m.nbf, 1, m.nqf), bc_kind=(0,))
+    b = torch.as_tensor(np.random.default_rng(3).uniform(-1, 1, md.N), device="cuda")
+    pc = L.BlockJacobi(md, prec=L.FP16)
+    its = []
+    for rs in (128, 256, 512):
+        x, st, status = L.gmres(md, b, pc=pc, restart=rs, rtol=1e-8, maxit=4000, jvp_prec=L.FP32, state32=state32,
+                                check=False)
+        _say("restart", rs, "state32", state32, "iters", st["iters"], "res", st["res_true"] / st["res0"])
+        assert status == L.LDG_OK
+        r = b - md.jvp(None, x)
+        assert L.norm(r) <= 1.01e-8 * st["res0"]
+        its.append(st["iters"])
+    assert its[1] <= its[0] and its[2] <= its[1]
+    u = torch.zeros(md.N, dtype=torch.float64, device="cuda")
+    u, st, status = L.newton(md, u, rtol=1e-8, eta=1e-4, maxit=8, pc=pc, restart=256, lin_maxit=4000,
+                             jvp_prec=L.FP32, state32=state32, check=False)
+    _say("newton restart 256", st)
+    assert status == L.LDG_OK and st["res_final"] <= 1.01e-8 * st["res0"]
