@@ -66,6 +66,7 @@ struct ModelDev {
   // [E][2 nd][(p+1)^(nd-1)][ncu (1 + nd)] (u, then q in [c][k] order); nullptr = none
   const double* tr;
   const float* tr32;   // the same for the FP32 tangent kernels (FP32 linearization point cache)
+  double* trt;         // face traces of the product's direction (v, tangent of q), FP64
 };
 
 // time wrapper coefficients

@@ -88,6 +88,9 @@ struct Model {
   double* d_tr = nullptr;       // face traces of (u, q(u)) of the FP64 linearization point (Navier-Stokes)
   const double* tr_of = nullptr;  // the state whose traces sit in d_tr
   float* d_tr32 = nullptr;        // the same in FP32, formed with d_q32
+  double* d_trt = nullptr;        // FP64 traces of the last product's direction
+  mutable const double* trt_of = nullptr;
+  mutable const int32_t* trt_sub = nullptr;
   bool tr32_valid = false;        // d_tr32 holds the traces of the state whose q sits in d_q32
   size_t N() const { return (size_t)mesh->E * ncu * mesh->nn; }
   ModelDev dev() const {

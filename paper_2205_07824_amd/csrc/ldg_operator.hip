@@ -218,9 +218,11 @@ ldg_status form_q_cache64(Model& md, const double* u, hipStream_t s) {
   if (st != LDG_OK) return st;
   md.q_of[0] = u;
   if (md.kind != K_NS) return LDG_OK;   // the models whose FP64 tangent kernel reads the traces
-  if (!md.d_tr && hipMalloc((void**)&md.d_tr, sizeof(double) * trace_count(md)) != hipSuccess) {
+  if (!md.d_tr && (hipMalloc((void**)&md.d_tr, sizeof(double) * trace_count(md)) != hipSuccess ||
+                   hipMalloc((void**)&md.d_trt, sizeof(double) * trace_count(md)) != hipSuccess)) {
     (void)hipGetLastError();
     md.d_tr = nullptr;
+    md.d_trt = nullptr;
     return LDG_OK;   // without the traces the tangent kernel reads the neighbours' lines
   }
   st = launch_face_traces<double, double>(md, u, md.d_q, md.d_tr, s);

@@ -309,13 +309,15 @@ struct GradCfg {
   static constexpr int EPB = pick_epb<NN, BYTES>();
 };
 
-// Face traces of a linearization point for the FP64 tangent kernels: for every
+// Face traces of a linearization point for the tangent kernels: for every
 // element, face F = 2 DIR + side and face point ff (the numbering of k_resid's
 // faces), u and q(u) extrapolated to the face along the lines normal to it, in
 // the same order of operations as k_resid's own extrapolation, stored
 // [E][NF][NCU (1 + D)][NFP] (u, then q in [c][k] order).  Formed once per
 // linearization point; the tangent kernel then reads a neighbour's NCU (1 + D)
-// trace values at a face point instead of its P1-node lines of u and q.
+// trace values at a face point instead of its P1-node lines of u and q.  The
+// FP64 tangent also reads the same traces of the product's direction (v and the
+// tangent of q), written by k_grad<..., TRT> as it forms the tangent of q.
 template <int D, int P1, int NCU, class R = double, class S = double>
 __global__ void __launch_bounds__(256) k_face_traces(int64_t E, typename TabOf<R>::T tab, const S* __restrict__ u,
                                                      const R* __restrict__ q, R* __restrict__ tr) {
@@ -381,7 +383,11 @@ struct ResidCfg {
 // homogeneous (tangents, and linear models whose data enter through qoff).
 // ============================================================================
 // S: storage type of the state u (double; float for the FP32-state products)
-template <int KIND, int D, int P1, class R, bool DATA, bool EXT = false, bool AFF = false, class S = double>
+// TRT: also write the face traces of u (here the product's direction) and of
+// the q it forms to md.trt ([E][NF][NCU (1 + D)][NFP], as k_face_traces), the
+// former from the face pass, the latter after staging q in the lifting buffer
+template <int KIND, int D, int P1, class R, bool DATA, bool EXT = false, bool AFF = false, class S = double,
+          bool TRT = false>
 __global__ void __launch_bounds__(256)
 k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const S* __restrict__ u, R* __restrict__ q,
        const double* __restrict__ qoff, const float* __restrict__ dux = nullptr) {
@@ -469,6 +475,11 @@ k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const S* __restrict__ u
       for (int c = 0; c < NCU; ++c)
 #pragma unroll
         for (int k = 0; k < D; ++k) s_L[e][F][c][k][f] = (um[c] - uh[c]) * N[k];
+      if constexpr (TRT) {
+        double* o = md.trt + (Ke * NF + F) * (NCU * (1 + D)) * NFP + f;
+#pragma unroll
+        for (int c = 0; c < NCU; ++c) o[c * NFP] = um[c];
+      }
     }
   };
   // face items flattened over the directions (direction-major), so that the
@@ -480,7 +491,9 @@ k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const S* __restrict__ u
     else if constexpr (D == 3) face_dir(std::integral_constant<int, 2>{}, loc);
   }
   __syncthreads();
-  if (!active) return;
+  if (!TRT && !active) return;
+  R qreg[TRT ? NCU : 1][TRT ? D : 1];
+  if (active) {
 
   int a[D];
   node_index<D, P1>(i, a);
@@ -523,6 +536,45 @@ k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const S* __restrict__ u
       const int64_t o = ((K * NCU + c) * D + k) * NN + i;
       if (qoff) qv += R(qoff[o]);
       q[o] = qv;
+      if constexpr (TRT) qreg[c][k] = qv;
+    }
+  }
+  }  // active
+  if constexpr (TRT) {
+    // the element's q, staged in the lifting buffer (read completely above), extrapolated to its faces
+    static_assert(NF * NFP >= NN, "the lifting buffer holds the element's q");
+    __syncthreads();
+    R* sq = &s_L[0][0][0][0][0];   // [EPB][NCU D][NN]
+    if (active) {
+#pragma unroll
+      for (int c = 0; c < NCU; ++c)
+#pragma unroll
+        for (int k = 0; k < D; ++k) sq[(el * NCU * D + c * D + k) * NN + i] = qreg[c][k];
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < EPB * NF * NFP; it += blockDim.x) {
+      const int e = it / (NF * NFP), F = (it / NFP) % NF, f = it % NFP;
+      const int64_t Ke = s_K[e];
+      if (Ke < 0) continue;
+      const int dir = F >> 1, side = F & 1;
+      const int T0 = dir == 0 ? 1 : 0;
+      const int T1 = D == 3 ? (dir == 2 ? 1 : 2) : 0;
+      const int t0 = f % P1, t1 = D == 3 ? f / P1 : 0;
+      int base = t0 * stride_c(P1, T0);
+      if (D == 3) base += t1 * stride_c(P1, T1);
+      const int SD = stride_c(P1, dir);
+      const R* l = tl + side * P1;
+      double* o = md.trt + (Ke * NF + F) * (NCU * (1 + D)) * NFP + f;
+#pragma unroll
+      for (int c = 0; c < NCU; ++c)
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          const R* qp = sq + (e * NCU * D + c * D + k) * NN + base;
+          R b = R(0);
+#pragma unroll
+          for (int mm = 0; mm < P1; ++mm) b += l[mm] * qp[mm * SD];
+          o[(NCU + c * D + k) * NFP] = b;
+        }
     }
   }
 }
@@ -625,10 +677,14 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const S* _
             for (int mm = 0; mm < P1; ++mm) t += l_own[mm] * s_q[e][c * D + k][base + mm * SD];
           } else if constexpr (HASQ) {
             // tangent kernel: the element's own q lines from global memory (cached);
-            // with the traces of the linearization point formed (TRC), q(u) at the
-            // face point in one read and only the lines of its tangent
+            // with the traces formed (TRC), q(u) at the face point in one read, and
+            // its tangent in one more (FP64: from the direction's traces) or from
+            // the lines of the tangent (FP32)
             const int64_t oq = ((Ke * NCU + c) * D + k) * NN + base;
-            if constexpr (TRC) {
+            if constexpr (TRC && std::is_same<R, double>::value) {
+              const int64_t ot = ((Ke * NF + 2 * DIR + side) * (NCU * (1 + D)) + NCU + c * D + k) * NFP + ff;
+              t = T::mk(R(md.tr[ot]), R(md.trt[ot]));
+            } else if constexpr (TRC) {
               R td = R(0);
 #pragma unroll
               for (int mm = 0; mm < P1; ++mm) td += l_own[mm] * dq[oq + mm * SD];
@@ -679,21 +735,27 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const S* _
         if constexpr (KIND != K_USER) half_normal_flux<KIND, D, V, R>(md.mu, md.naux, um, qm, am, n, Fh, false);
         V up[NCU], qp[NCU][D];
         R ap2[NA];
-        // FP64 tangent with the traces of the linearization point formed (TRC): the
+        // tangent with the traces of the linearization point formed (TRC): the
         // neighbour's u and q(u) at this face point (its face F ^ 1), one read per
-        // value, consecutive face points adjacent ([E][NF][NCU (1 + D)][NFP])
+        // value, consecutive face points adjacent ([E][NF][NCU (1 + D)][NFP]); FP64
+        // also reads v and the tangent of q there from the direction's traces
         const R* tp = nullptr;
+        const double* tpt = nullptr;
         if constexpr (TRC) {
           const R* trb;
           if constexpr (std::is_same<R, double>::value) trb = md.tr; else trb = md.tr32;
           tp = trb + ((int64_t)nb * NF + (F ^ 1)) * (NCU * (1 + D)) * NFP + ff;
+          if constexpr (std::is_same<R, double>::value)
+            tpt = md.trt + ((int64_t)nb * NF + (F ^ 1)) * (NCU * (1 + D)) * NFP + ff;
         }
 #pragma unroll
         for (int c = 0; c < NCU; ++c) {
           const int64_t o = ((int64_t)nb * NCU + c) * NN + base;
           V sacc = T::mk(R(0));
           if constexpr (MODE == 2) {
-            if constexpr (TRC) {
+            if constexpr (TRC && std::is_same<R, double>::value) {
+              sacc = T::mk(R(tp[c * NFP]), R(tpt[c * NFP]));
+            } else if constexpr (TRC) {
               R tv = R(0);
 #pragma unroll
               for (int mm = 0; mm < P1; ++mm) tv += l_nbr[mm] * R(v[o + mm * SD]);
@@ -713,7 +775,9 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const S* _
             if constexpr (HASQ) {
               const int64_t oq = (((int64_t)nb * NCU + c) * D + k) * NN + base;
               if constexpr (MODE == 2) {
-                if constexpr (TRC) {
+                if constexpr (TRC && std::is_same<R, double>::value) {
+                  t = T::mk(R(tp[(NCU + c * D + k) * NFP]), R(tpt[(NCU + c * D + k) * NFP]));
+                } else if constexpr (TRC) {
                   R td = R(0);
 #pragma unroll
                   for (int mm = 0; mm < P1; ++mm) td += l_nbr[mm] * dq[oq + mm * SD];

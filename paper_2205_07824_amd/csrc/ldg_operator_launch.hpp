@@ -19,12 +19,37 @@ static ldg_status launch_grad(const Model& md, const void* uv, void* q, bool wit
   const double* qoff = (with_data && Phys<KIND, D>::LINEAR) ? md.d_qg : nullptr;
   constexpr int NN = GradCfg<KIND, D, P1, R>::NN, EPB = GradCfg<KIND, D, P1, R>::EPB;
   const Mesh& m = *md.mesh;
+  if (q == md.d_dq) {
+    md.trt_of = nullptr;
+    md.trt_sub = nullptr;
+  }
   const int nblk = (int)((m.op_E(0) + EPB - 1) / EPB);
   if (nblk == 0) return LDG_OK;
   const MeshDev mdv = m.dev_op(0);
   typename TabOf<R>::T tab;
   if constexpr (std::is_same<R, double>::value) tab = m.tab; else tab = m.tabf;
   const float* nodu = nullptr;
+  constexpr int NFPc = GradCfg<KIND, D, P1, R>::NFP, NFc = GradCfg<KIND, D, P1, R>::NF;
+  // FP64 Navier-Stokes tangent of q: with the traces of the linearization point
+  // formed, also the direction's traces, which the tangent kernel then reads
+  // (valid for this direction and element subset until the next tangent of q)
+  if constexpr (KIND == K_NS && std::is_same<R, double>::value && std::is_same<S, double>::value &&
+                NFc * NFPc >= NN) {
+    if (!with_data && md.d_trt && q == md.d_dq) {
+      ModelDev mod = md.dev();
+      mod.trt = md.d_trt;
+      if (m.affine)
+        hipLaunchKernelGGL((k_grad<KIND, D, P1, R, false, false, true, S, true>), dim3(nblk), dim3(EPB * NN), 0, s,
+                           mdv, tab, mod, u, (R*)q, qoff, nodu);
+      else
+        hipLaunchKernelGGL((k_grad<KIND, D, P1, R, false, false, false, S, true>), dim3(nblk), dim3(EPB * NN), 0, s,
+                           mdv, tab, mod, u, (R*)q, qoff, nodu);
+      LDG_TRY(hipGetLastError());
+      md.trt_of = (const double*)uv;
+      md.trt_sub = m.sub_list[0];
+      return LDG_OK;
+    }
+  }
   if (in_kernel_data) {
     if (m.affine)
       hipLaunchKernelGGL((k_grad<KIND, D, P1, R, true, false, true, S>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
@@ -63,8 +88,10 @@ static ldg_status launch_resid(const Model& md, const TimeDev& t, const void* uv
   if constexpr (MODE == 2 && KIND == K_NS) {
     bool use = false;
     if constexpr (std::is_same<R, double>::value && std::is_same<S, double>::value) {
-      use = md.d_tr && md.tr_of && md.tr_of == (const double*)uv && md.q_of[0] == (const double*)uv && q == md.d_q;
+      use = md.d_tr && md.tr_of && md.tr_of == (const double*)uv && md.q_of[0] == (const double*)uv && q == md.d_q &&
+            md.d_trt && md.trt_of == (const double*)vv && dq == md.d_dq && md.trt_sub == m.sub_list[0];
       mod.tr = md.d_tr;
+      mod.trt = md.d_trt;
     } else if constexpr (std::is_same<R, float>::value) {
       use = md.d_tr32 && md.tr32_valid && q == md.d_q32;
       mod.tr32 = md.d_tr32;
