@@ -567,7 +567,7 @@ ldg_status ldg_model_destroy(ldg_model md) {
   if (!md) return LDG_OK;
   mfma_release(*md);
   jit_release(*md);
-  hipFree(md->d_q); hipFree(md->d_tr); hipFree(md->d_trt); hipFree(md->d_tr32); hipFree(md->d_q32); hipFree(md->d_qres); hipFree(md->d_dq); hipFree(md->d_tmp); hipFree(md->d_tmp2); hipFree(md->d_red);
+  hipFree(md->d_q); hipFree(md->d_tr); hipFree(md->d_trt); hipFree(md->d_probe); hipFree(md->d_tr32); hipFree(md->d_q32); hipFree(md->d_qres); hipFree(md->d_dq); hipFree(md->d_tmp); hipFree(md->d_tmp2); hipFree(md->d_red);
   hipFree(md->d_qg); hipFree(md->d_dterm);
   delete md;
   return LDG_OK;

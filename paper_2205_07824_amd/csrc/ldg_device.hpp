@@ -47,6 +47,10 @@ struct MeshDev {
   const int32_t* nbr;    // [E][2nd] >= 0 neighbour element; < 0: -(1 + boundary face index)
   const int32_t* btag;   // [nbf] boundary tag
   const int32_t* order;  // [E] element visit order of the operator kernels (a permutation of 0..E-1)
+  // batched products (block probing): work-group row blockIdx.y works on the
+  // y-th of gridDim.y products, whose per-product vectors (direction, tangent of
+  // q, result) lie bsn and bsq elements apart; 0 for a single product
+  int64_t bsn = 0, bsq = 0;
 };
 
 // Device view of a model's parameters.

@@ -50,9 +50,14 @@ struct Mesh {
   const int32_t* sub_list[2] = {nullptr, nullptr};
   int64_t sub_count[2] = {0, 0};
   MeshDev dev() const { return MeshDev{(int)E, (int)nbf, d_coef, d_nbr, d_btag, d_order}; }
+  // products batched over blockIdx.y (set with the subsets by the block probing)
+  int batch = 1;
+  int64_t bsn = 0, bsq = 0;
   MeshDev dev_op(int which) const {
-    if (!sub_list[which]) return dev();
-    return MeshDev{(int)sub_count[which], (int)nbf, d_coef, d_nbr, d_btag, sub_list[which]};
+    MeshDev r = sub_list[which] ? MeshDev{(int)sub_count[which], (int)nbf, d_coef, d_nbr, d_btag, sub_list[which]}
+                                : dev();
+    if (batch > 1) { r.bsn = bsn; r.bsq = bsq; }
+    return r;
   }
   int64_t op_E(int which) const { return sub_list[which] ? sub_count[which] : E; }
 };
@@ -92,6 +97,8 @@ struct Model {
   mutable const double* trt_of = nullptr;
   mutable const int32_t* trt_sub = nullptr;
   bool tr32_valid = false;        // d_tr32 holds the traces of the state whose q sits in d_q32
+  double* d_probe = nullptr;      // batched probing vectors (direction, result, tangent of q), per batch entry
+  int probe_batch = 0;            // batch entries d_probe holds
   size_t N() const { return (size_t)mesh->E * ncu * mesh->nn; }
   ModelDev dev() const {
     ModelDev d{};

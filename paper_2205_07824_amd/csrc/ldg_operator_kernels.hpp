@@ -391,6 +391,8 @@ template <int KIND, int D, int P1, class R, bool DATA, bool EXT = false, bool AF
 __global__ void __launch_bounds__(256)
 k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const S* __restrict__ u, R* __restrict__ q,
        const double* __restrict__ qoff, const float* __restrict__ dux = nullptr) {
+  u += (int64_t)blockIdx.y * m.bsn;   // batched products (zero strides otherwise)
+  q += (int64_t)blockIdx.y * m.bsq;
   using C = GradCfg<KIND, D, P1, R>;
   constexpr int NCU = C::NCU, NN = C::NN, NFP = C::NFP, NF = C::NF, NV = C::NV, EPB = C::EPB;
   using L = TabLayout<P1>;
@@ -597,6 +599,17 @@ __attribute__((amdgpu_waves_per_eu(TRC ? 2 : ResidCfg<KIND, D, P1, R, MODE>::MIN
 k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const S* __restrict__ u,
         const R* __restrict__ q, const S* __restrict__ v, const R* __restrict__ dq,
         const double* __restrict__ dterm, double* __restrict__ out, float* __restrict__ Fout = nullptr) {
+  if (m.bsn) {   // batched products: the direction (tangent) or the argument (linear residual) and the result
+    const int64_t by = blockIdx.y;
+    if constexpr (MODE == 2) {
+      v += by * m.bsn;
+      if (dq) dq += by * m.bsq;
+    } else {
+      u += by * m.bsn;
+      if (q) q += by * m.bsq;
+    }
+    out += by * m.bsn;
+  }
   using C = ResidCfg<KIND, D, P1, R, MODE>;
   using V = typename C::V;
   using T = VT<V>;

@@ -35,14 +35,14 @@ static ldg_status launch_grad(const Model& md, const void* uv, void* q, bool wit
   // (valid for this direction and element subset until the next tangent of q)
   if constexpr (KIND == K_NS && std::is_same<R, double>::value && std::is_same<S, double>::value &&
                 NFc * NFPc >= NN) {
-    if (!with_data && md.d_trt && q == md.d_dq) {
+    if (!with_data && md.d_trt && q == md.d_dq && m.batch == 1) {
       ModelDev mod = md.dev();
       mod.trt = md.d_trt;
       if (m.affine)
-        hipLaunchKernelGGL((k_grad<KIND, D, P1, R, false, false, true, S, true>), dim3(nblk), dim3(EPB * NN), 0, s,
+        hipLaunchKernelGGL((k_grad<KIND, D, P1, R, false, false, true, S, true>), dim3(nblk, m.batch), dim3(EPB * NN), 0, s,
                            mdv, tab, mod, u, (R*)q, qoff, nodu);
       else
-        hipLaunchKernelGGL((k_grad<KIND, D, P1, R, false, false, false, S, true>), dim3(nblk), dim3(EPB * NN), 0, s,
+        hipLaunchKernelGGL((k_grad<KIND, D, P1, R, false, false, false, S, true>), dim3(nblk, m.batch), dim3(EPB * NN), 0, s,
                            mdv, tab, mod, u, (R*)q, qoff, nodu);
       LDG_TRY(hipGetLastError());
       md.trt_of = (const double*)uv;
@@ -52,17 +52,17 @@ static ldg_status launch_grad(const Model& md, const void* uv, void* q, bool wit
   }
   if (in_kernel_data) {
     if (m.affine)
-      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, true, false, true, S>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
+      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, true, false, true, S>), dim3(nblk, m.batch), dim3(EPB * NN), 0, s, mdv, tab,
                          md.dev(), u, (R*)q, qoff, nodu);
     else
-      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, true, false, false, S>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
+      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, true, false, false, S>), dim3(nblk, m.batch), dim3(EPB * NN), 0, s, mdv, tab,
                          md.dev(), u, (R*)q, qoff, nodu);
   } else {
     if (m.affine)
-      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, false, false, true, S>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
+      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, false, false, true, S>), dim3(nblk, m.batch), dim3(EPB * NN), 0, s, mdv, tab,
                          md.dev(), u, (R*)q, qoff, nodu);
     else
-      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, false, false, false, S>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
+      hipLaunchKernelGGL((k_grad<KIND, D, P1, R, false, false, false, S>), dim3(nblk, m.batch), dim3(EPB * NN), 0, s, mdv, tab,
                          md.dev(), u, (R*)q, qoff, nodu);
   }
   LDG_TRY(hipGetLastError());
@@ -98,20 +98,20 @@ static ldg_status launch_resid(const Model& md, const TimeDev& t, const void* uv
     }
     if (use) {
       if (m.affine)
-        hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, true, S, true>), dim3(nblk), dim3(EPB * NN), 0, s,
+        hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, true, S, true>), dim3(nblk, m.batch), dim3(EPB * NN), 0, s,
                            mdv, tab, mod, t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
       else
-        hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, false, S, true>), dim3(nblk), dim3(EPB * NN), 0, s,
+        hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, false, S, true>), dim3(nblk, m.batch), dim3(EPB * NN), 0, s,
                            mdv, tab, mod, t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
       LDG_TRY(hipGetLastError());
       return LDG_OK;
     }
   }
   if (m.affine)
-    hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, true, S>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
+    hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, true, S>), dim3(nblk, m.batch), dim3(EPB * NN), 0, s, mdv, tab,
                        mod, t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
   else
-    hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, false, S>), dim3(nblk), dim3(EPB * NN), 0, s, mdv, tab,
+    hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, false, S>), dim3(nblk, m.batch), dim3(EPB * NN), 0, s, mdv, tab,
                        mod, t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
   LDG_TRY(hipGetLastError());
   return LDG_OK;

@@ -4,6 +4,7 @@
 // Gauss-Jordan inversion with partial pivoting, and a batched block-matrix
 // vector product as the apply (FP64, FP32, or 16-bit storage: bf16 or fp16 with
 // a power-of-two scale per row and FP64 accumulation).
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -35,10 +36,38 @@ __global__ void k_probe_set(int n, const int32_t* __restrict__ list, int NB, int
   if (t < n) v[(int64_t)list[t] * NB + j] = val;
 }
 
+// batched seeds: seed column j0 + y of every listed element in the y-th vector
+__global__ void k_probe_set_b(int n, const int32_t* __restrict__ list, int NB, int j0, int64_t stride, double val,
+                              double* __restrict__ v) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) v[blockIdx.y * stride + (int64_t)list[t] * NB + j0 + blockIdx.y] = val;
+}
+
 // column j of every listed element's block from Jv
 __global__ void k_probe_gather(int n, const int32_t* __restrict__ list, int NB, int nn, int j, int per_variable,
                                const double* __restrict__ Jv, double* __restrict__ blocks) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (per_variable) {
+    if (t >= (int64_t)n * nn) return;
+    const int64_t K = list[t / nn];
+    const int i = t % nn;
+    const int cv = j / nn, jn = j % nn;
+    const int ncu = NB / nn;
+    blocks[(((K * ncu + cv) * nn) + i) * nn + jn] = Jv[K * NB + cv * nn + i];
+  } else {
+    if (t >= (int64_t)n * NB) return;
+    const int64_t K = list[t / NB];
+    const int i = t % NB;
+    blocks[(K * NB + i) * NB + j] = Jv[K * NB + i];
+  }
+}
+
+// batched gather: column j0 + y from the y-th result vector
+__global__ void k_probe_gather_b(int n, const int32_t* __restrict__ list, int NB, int nn, int j0, int64_t stride,
+                                 int per_variable, const double* __restrict__ Jv, double* __restrict__ blocks) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = j0 + blockIdx.y;
+  Jv += blockIdx.y * stride;
   if (per_variable) {
     if (t >= (int64_t)n * nn) return;
     const int64_t K = list[t / nn];
@@ -321,17 +350,81 @@ static ldg_status assemble_blocks(Model& md, const ldg_time* t, const double* u_
       if (st != LDG_OK) return st;
     }
   }
-  double* v = md.d_tmp;
-  double* Jv = md.d_tmp2;
-  st = vec_fill(n, 0.0, v, s);
-  if (st != LDG_OK) return st;
   // the probing JVPs run on element subsets: rows on the seeded colour only,
   // the q tangent on the colour and its face neighbours (the other entries of
   // Jv and of the q tangent are left stale and never read)
   struct SubsetReset {
     Mesh& m;
-    ~SubsetReset() { m.sub_list[0] = m.sub_list[1] = nullptr; m.sub_count[0] = m.sub_count[1] = 0; }
+    ~SubsetReset() {
+      m.sub_list[0] = m.sub_list[1] = nullptr;
+      m.sub_count[0] = m.sub_count[1] = 0;
+      m.batch = 1;
+      m.bsn = m.bsq = 0;
+    }
   } reset{m};
+  if (md.kind != LDG_MODEL_USER) {
+    // B seed columns per launch (blockIdx.y), so that one colour's products fill
+    // the GPU: about 4096 elements per launch, at most 16 products, and at most
+    // 1 GiB of probing vectors (direction, result, tangent of q per product)
+    int64_t maxcnt = 1;
+    for (int c = 0; c < m.ncolors; ++c) maxcnt = std::max<int64_t>(maxcnt, m.nbhd_off[c + 1] - m.nbhd_off[c]);
+    const int64_t nq = md.hasq ? (int64_t)m.E * md.ncu * m.nd * m.nn : 0;
+    const int64_t per = 2 * n + nq;   // doubles per product (the FP32 tangent of q uses half of its share)
+    int B = (int)std::min<int64_t>(16, std::max<int64_t>(1, 4096 / maxcnt));
+    B = (int)std::min<int64_t>(B, std::max<int64_t>(1, (int64_t(1) << 27) / per));
+    B = std::min(B, NB);
+    if (md.probe_batch < B) {
+      hipFree(md.d_probe);
+      md.d_probe = nullptr;
+      md.probe_batch = 0;
+      if (hipMalloc((void**)&md.d_probe, sizeof(double) * per * B) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("block probing: out of device memory for the batched probing vectors");
+        return LDG_ENOMEM;
+      }
+      md.probe_batch = B;
+    }
+    double* vb = md.d_probe;
+    double* Jvb = vb + n * B;
+    void* dqb = Jvb + n * B;
+    const bool fp32 = probe == LDG_FP32;
+    const TimeDev td = make_time(t, false);
+    void* qc = fp32 ? (void*)md.d_q32 : (void*)md.d_q;
+    if ((st = vec_fill(n * B, 0.0, vb, s)) != LDG_OK) return st;
+    m.bsn = n;
+    m.bsq = nq;
+    for (int c = 0; c < m.ncolors; ++c) {
+      const int cnt = (int)(m.color_off[c + 1] - m.color_off[c]);
+      const int32_t* list = m.d_color_list + m.color_off[c];
+      m.sub_list[0] = m.d_color_nbhd + m.nbhd_off[c];
+      m.sub_count[0] = m.nbhd_off[c + 1] - m.nbhd_off[c];
+      m.sub_list[1] = list;
+      m.sub_count[1] = cnt;
+      for (int j0 = 0; j0 < NB; j0 += B) {
+        const int b = std::min(B, NB - j0);
+        m.batch = b;
+        hipLaunchKernelGGL(k_probe_set_b, dim3((cnt + 255) / 256, b), dim3(256), 0, s, cnt, list, NB, j0, n, 1.0, vb);
+        if (md.linear) {
+          if ((st = op_grad(md, vb, dqb, fp32, false, s)) != LDG_OK) return st;
+          if ((st = op_resid(md, td, vb, dqb, Jvb, fp32, false, s)) != LDG_OK) return st;
+        } else {
+          if (md.hasq && (st = op_grad(md, vb, dqb, fp32, false, s)) != LDG_OK) return st;
+          if ((st = op_jvp_nonlinear(md, td, u_lin, qc, vb, dqb, Jvb, fp32, s)) != LDG_OK)
+            return st;
+        }
+        const int64_t tot = per_variable ? (int64_t)cnt * m.nn : (int64_t)cnt * NB;
+        hipLaunchKernelGGL(k_probe_gather_b, dim3((unsigned)((tot + 255) / 256), b), dim3(256), 0, s, cnt, list, NB,
+                           m.nn, j0, n, per_variable, Jvb, blocks);
+        hipLaunchKernelGGL(k_probe_set_b, dim3((cnt + 255) / 256, b), dim3(256), 0, s, cnt, list, NB, j0, n, 0.0, vb);
+      }
+    }
+    LDG_TRY(hipGetLastError());
+    return LDG_OK;
+  }
+  double* v = md.d_tmp;
+  double* Jv = md.d_tmp2;
+  st = vec_fill(n, 0.0, v, s);
+  if (st != LDG_OK) return st;
   for (int c = 0; c < m.ncolors; ++c) {
     const int cnt = (int)(m.color_off[c + 1] - m.color_off[c]);
     const int32_t* list = m.d_color_list + m.color_off[c];
