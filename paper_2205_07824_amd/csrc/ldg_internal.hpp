@@ -94,7 +94,8 @@ struct Model {
   const double* tr_of = nullptr;  // the state whose traces sit in d_tr
   float* d_tr32 = nullptr;        // the same in FP32, formed with d_q32
   double* d_trt = nullptr;        // FP64 traces of the last product's direction
-  mutable const double* trt_of = nullptr;
+  // the direction and element subset whose traces were last written
+  mutable const void* trt_of = nullptr;
   mutable const int32_t* trt_sub = nullptr;
   bool tr32_valid = false;        // d_tr32 holds the traces of the state whose q sits in d_q32
   double* d_probe = nullptr;      // batched probing vectors (direction, result, tangent of q), per batch entry

@@ -211,6 +211,19 @@ static int64_t trace_count(const Model& md) {
   return m.E * 2 * m.nd * (m.nd == 3 ? m.p1 * m.p1 : m.p1) * (int64_t)md.ncu * (1 + m.nd);
 }
 
+// the FP64 traces of the linearization point and of the direction, both or neither
+static bool alloc_trace_pair(const Model& md, double** tr, double** trt) {
+  const size_t bytes = sizeof(double) * trace_count(md);
+  if (hipMalloc((void**)tr, bytes) == hipSuccess) {
+    if (hipMalloc((void**)trt, bytes) == hipSuccess) return true;
+    (void)hipFree(*tr);
+  }
+  (void)hipGetLastError();
+  *tr = nullptr;
+  *trt = nullptr;
+  return false;
+}
+
 ldg_status form_q_cache64(Model& md, const double* u, hipStream_t s) {
   md.q_of[0] = nullptr;
   md.tr_of = nullptr;
@@ -218,13 +231,8 @@ ldg_status form_q_cache64(Model& md, const double* u, hipStream_t s) {
   if (st != LDG_OK) return st;
   md.q_of[0] = u;
   if (md.kind != K_NS) return LDG_OK;   // the models whose FP64 tangent kernel reads the traces
-  if (!md.d_tr && (hipMalloc((void**)&md.d_tr, sizeof(double) * trace_count(md)) != hipSuccess ||
-                   hipMalloc((void**)&md.d_trt, sizeof(double) * trace_count(md)) != hipSuccess)) {
-    (void)hipGetLastError();
-    md.d_tr = nullptr;
-    md.d_trt = nullptr;
+  if (!md.d_tr && !alloc_trace_pair(md, &md.d_tr, &md.d_trt))
     return LDG_OK;   // without the traces the tangent kernel reads the neighbours' lines
-  }
   st = launch_face_traces<double, double>(md, u, md.d_q, md.d_tr, s);
   if (st != LDG_OK) return st;
   md.tr_of = u;

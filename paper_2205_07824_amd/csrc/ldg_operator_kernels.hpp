@@ -309,6 +309,15 @@ struct GradCfg {
   static constexpr int EPB = pick_epb<NN, BYTES>();
 };
 
+// the trace arrays of a precision (FP64 or FP32)
+template <class R> __device__ inline const R* lin_traces(const ModelDev& md) {
+  if constexpr (std::is_same<R, double>::value) return md.tr; else return md.tr32;
+}
+template <class R> __device__ inline R* dir_traces(const ModelDev& md) {
+  static_assert(std::is_same<R, double>::value, "direction traces are FP64");
+  return md.trt;
+}
+
 // Face traces of a linearization point for the tangent kernels: for every
 // element, face F = 2 DIR + side and face point ff (the numbering of k_resid's
 // faces), u and q(u) extrapolated to the face along the lines normal to it, in
@@ -316,8 +325,8 @@ struct GradCfg {
 // [E][NF][NCU (1 + D)][NFP] (u, then q in [c][k] order).  Formed once per
 // linearization point; the tangent kernel then reads a neighbour's NCU (1 + D)
 // trace values at a face point instead of its P1-node lines of u and q.  The
-// FP64 tangent also reads the same traces of the product's direction (v and the
-// tangent of q), written by k_grad<..., TRT> as it forms the tangent of q.
+// FP64 tangent can also read the same traces of the product's direction (v and
+// the tangent of q), written by k_grad<..., TRT> as it forms the tangent of q.
 template <int D, int P1, int NCU, class R = double, class S = double>
 __global__ void __launch_bounds__(256) k_face_traces(int64_t E, typename TabOf<R>::T tab, const S* __restrict__ u,
                                                      const R* __restrict__ q, R* __restrict__ tr) {
@@ -478,7 +487,7 @@ k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const S* __restrict__ u
 #pragma unroll
         for (int k = 0; k < D; ++k) s_L[e][F][c][k][f] = (um[c] - uh[c]) * N[k];
       if constexpr (TRT) {
-        double* o = md.trt + (Ke * NF + F) * (NCU * (1 + D)) * NFP + f;
+        R* o = dir_traces<R>(md) + (Ke * NF + F) * (NCU * (1 + D)) * NFP + f;
 #pragma unroll
         for (int c = 0; c < NCU; ++c) o[c * NFP] = um[c];
       }
@@ -566,7 +575,7 @@ k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const S* __restrict__ u
       if (D == 3) base += t1 * stride_c(P1, T1);
       const int SD = stride_c(P1, dir);
       const R* l = tl + side * P1;
-      double* o = md.trt + (Ke * NF + F) * (NCU * (1 + D)) * NFP + f;
+      R* o = dir_traces<R>(md) + (Ke * NF + F) * (NCU * (1 + D)) * NFP + f;
 #pragma unroll
       for (int c = 0; c < NCU; ++c)
 #pragma unroll
@@ -592,8 +601,10 @@ k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const S* __restrict__ u
 // ============================================================================
 // S: storage type of the input vectors u, v (double; float for the FP32-state
 // products of modes 0 and 2)
+// TRC: read the face traces of the linearization point (u, q(u)); TRT (with
+// TRC): also those of the direction (v, tangent of q) instead of its lines
 template <int KIND, int D, int P1, class R, int MODE, bool EXT = false, bool AFF = false, class S = double,
-          bool TRC = false>
+          bool TRC = false, bool TRT = false>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(TRC ? 2 : ResidCfg<KIND, D, P1, R, MODE>::MIN_WAVES)))
 k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const S* __restrict__ u,
@@ -691,19 +702,18 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const S* _
           } else if constexpr (HASQ) {
             // tangent kernel: the element's own q lines from global memory (cached);
             // with the traces formed (TRC), q(u) at the face point in one read, and
-            // its tangent in one more (FP64: from the direction's traces) or from
-            // the lines of the tangent (FP32)
+            // its tangent in one more (TRT: from the direction's traces) or from
+            // the lines of the tangent
             const int64_t oq = ((Ke * NCU + c) * D + k) * NN + base;
-            if constexpr (TRC && std::is_same<R, double>::value) {
+            if constexpr (TRT) {
               const int64_t ot = ((Ke * NF + 2 * DIR + side) * (NCU * (1 + D)) + NCU + c * D + k) * NFP + ff;
-              t = T::mk(R(md.tr[ot]), R(md.trt[ot]));
+              t = T::mk(lin_traces<R>(md)[ot], dir_traces<R>(md)[ot]);
             } else if constexpr (TRC) {
               R td = R(0);
 #pragma unroll
               for (int mm = 0; mm < P1; ++mm) td += l_own[mm] * dq[oq + mm * SD];
-              const R* trb;
-              if constexpr (std::is_same<R, double>::value) trb = md.tr; else trb = md.tr32;
-              t = T::mk(trb[((Ke * NF + 2 * DIR + side) * (NCU * (1 + D)) + NCU + c * D + k) * NFP + ff], td);
+              t = T::mk(lin_traces<R>(md)[((Ke * NF + 2 * DIR + side) * (NCU * (1 + D)) + NCU + c * D + k) * NFP + ff],
+                        td);
             } else {
 #pragma unroll
               for (int mm = 0; mm < P1; ++mm) t += l_own[mm] * T::mk(q[oq + mm * SD], dq[oq + mm * SD]);
@@ -750,24 +760,19 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const S* _
         R ap2[NA];
         // tangent with the traces of the linearization point formed (TRC): the
         // neighbour's u and q(u) at this face point (its face F ^ 1), one read per
-        // value, consecutive face points adjacent ([E][NF][NCU (1 + D)][NFP]); FP64
+        // value, consecutive face points adjacent ([E][NF][NCU (1 + D)][NFP]); TRT
         // also reads v and the tangent of q there from the direction's traces
         const R* tp = nullptr;
-        const double* tpt = nullptr;
-        if constexpr (TRC) {
-          const R* trb;
-          if constexpr (std::is_same<R, double>::value) trb = md.tr; else trb = md.tr32;
-          tp = trb + ((int64_t)nb * NF + (F ^ 1)) * (NCU * (1 + D)) * NFP + ff;
-          if constexpr (std::is_same<R, double>::value)
-            tpt = md.trt + ((int64_t)nb * NF + (F ^ 1)) * (NCU * (1 + D)) * NFP + ff;
-        }
+        const R* tpt = nullptr;
+        if constexpr (TRC) tp = lin_traces<R>(md) + ((int64_t)nb * NF + (F ^ 1)) * (NCU * (1 + D)) * NFP + ff;
+        if constexpr (TRT) tpt = dir_traces<R>(md) + ((int64_t)nb * NF + (F ^ 1)) * (NCU * (1 + D)) * NFP + ff;
 #pragma unroll
         for (int c = 0; c < NCU; ++c) {
           const int64_t o = ((int64_t)nb * NCU + c) * NN + base;
           V sacc = T::mk(R(0));
           if constexpr (MODE == 2) {
-            if constexpr (TRC && std::is_same<R, double>::value) {
-              sacc = T::mk(R(tp[c * NFP]), R(tpt[c * NFP]));
+            if constexpr (TRT) {
+              sacc = T::mk(tp[c * NFP], tpt[c * NFP]);
             } else if constexpr (TRC) {
               R tv = R(0);
 #pragma unroll
@@ -788,8 +793,8 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const S* _
             if constexpr (HASQ) {
               const int64_t oq = (((int64_t)nb * NCU + c) * D + k) * NN + base;
               if constexpr (MODE == 2) {
-                if constexpr (TRC && std::is_same<R, double>::value) {
-                  t = T::mk(R(tp[(NCU + c * D + k) * NFP]), R(tpt[(NCU + c * D + k) * NFP]));
+                if constexpr (TRT) {
+                  t = T::mk(tp[(NCU + c * D + k) * NFP], tpt[(NCU + c * D + k) * NFP]);
                 } else if constexpr (TRC) {
                   R td = R(0);
 #pragma unroll

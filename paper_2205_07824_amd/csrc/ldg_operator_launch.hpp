@@ -30,9 +30,11 @@ static ldg_status launch_grad(const Model& md, const void* uv, void* q, bool wit
   if constexpr (std::is_same<R, double>::value) tab = m.tab; else tab = m.tabf;
   const float* nodu = nullptr;
   constexpr int NFPc = GradCfg<KIND, D, P1, R>::NFP, NFc = GradCfg<KIND, D, P1, R>::NF;
-  // FP64 Navier-Stokes tangent of q: with the traces of the linearization point
-  // formed, also the direction's traces, which the tangent kernel then reads
-  // (valid for this direction and element subset until the next tangent of q)
+  // FP64 Navier-Stokes tangent of q: with trace storage allocated, also the
+  // direction's face traces, which the tangent kernel then reads (tied to this
+  // direction and element subset until the next tangent of q).  (The same for
+  // the FP32 tangent measured slower: its extra trace writes cost more than the
+  // line reads they replace.)
   if constexpr (KIND == K_NS && std::is_same<R, double>::value && std::is_same<S, double>::value &&
                 NFc * NFPc >= NN) {
     if (!with_data && md.d_trt && q == md.d_dq && m.batch == 1) {
@@ -45,7 +47,7 @@ static ldg_status launch_grad(const Model& md, const void* uv, void* q, bool wit
         hipLaunchKernelGGL((k_grad<KIND, D, P1, R, false, false, false, S, true>), dim3(nblk, m.batch), dim3(EPB * NN), 0, s,
                            mdv, tab, mod, u, (R*)q, qoff, nodu);
       LDG_TRY(hipGetLastError());
-      md.trt_of = (const double*)uv;
+      md.trt_of = uv;
       md.trt_sub = m.sub_list[0];
       return LDG_OK;
     }
@@ -83,26 +85,41 @@ static ldg_status launch_resid(const Model& md, const TimeDev& t, const void* uv
   if constexpr (std::is_same<R, double>::value) tab = m.tab; else tab = m.tabf;
   float* noF = nullptr;
   ModelDev mod = md.dev();
-  // the tangent reads the face traces of the linearization point when they are formed for u
-  // (FP64: for this u; FP32: together with the FP32 q cache it reads)
+  // the tangent reads the face traces of the linearization point when they are
+  // formed for u (FP64: for this u; FP32: together with the FP32 q cache it
+  // reads), and (FP64) those of the direction when the last tangent of q wrote
+  // them for this direction and element subset
   if constexpr (MODE == 2 && KIND == K_NS) {
-    bool use = false;
+    bool trc = false, dir = false;
     if constexpr (std::is_same<R, double>::value && std::is_same<S, double>::value) {
-      use = md.d_tr && md.tr_of && md.tr_of == (const double*)uv && md.q_of[0] == (const double*)uv && q == md.d_q &&
-            md.d_trt && md.trt_of == (const double*)vv && dq == md.d_dq && md.trt_sub == m.sub_list[0];
+      trc = md.d_tr && md.tr_of && md.tr_of == (const double*)uv && md.q_of[0] == (const double*)uv && q == md.d_q;
+      dir = trc && md.d_trt && md.trt_of == vv && dq == md.d_dq && md.trt_sub == m.sub_list[0] && m.batch == 1;
       mod.tr = md.d_tr;
       mod.trt = md.d_trt;
     } else if constexpr (std::is_same<R, float>::value) {
-      use = md.d_tr32 && md.tr32_valid && q == md.d_q32;
+      trc = md.d_tr32 && md.tr32_valid && q == md.d_q32;
       mod.tr32 = md.d_tr32;
     }
-    if (use) {
+    (void)dir;
+    if constexpr (std::is_same<R, double>::value && std::is_same<S, double>::value) {
+      if (dir) {
+        if (m.affine)
+          hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, true, S, true, true>), dim3(nblk, m.batch),
+                             dim3(EPB * NN), 0, s, mdv, tab, mod, t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
+        else
+          hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, false, S, true, true>), dim3(nblk, m.batch),
+                             dim3(EPB * NN), 0, s, mdv, tab, mod, t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
+        LDG_TRY(hipGetLastError());
+        return LDG_OK;
+      }
+    }
+    if (trc) {
       if (m.affine)
-        hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, true, S, true>), dim3(nblk, m.batch), dim3(EPB * NN), 0, s,
-                           mdv, tab, mod, t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
+        hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, true, S, true>), dim3(nblk, m.batch), dim3(EPB * NN),
+                           0, s, mdv, tab, mod, t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
       else
-        hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, false, S, true>), dim3(nblk, m.batch), dim3(EPB * NN), 0, s,
-                           mdv, tab, mod, t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
+        hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, false, S, true>), dim3(nblk, m.batch), dim3(EPB * NN),
+                           0, s, mdv, tab, mod, t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
       LDG_TRY(hipGetLastError());
       return LDG_OK;
     }
