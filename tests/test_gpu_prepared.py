@@ -59,3 +59,40 @@ def test_prepared_jvp_needs_its_cache(L):
     with pytest.raises(L.LDGError):
         md.jvp_prepared(u, v, time=t)
     md.jvp_prepared(u2, v, time=t)
+
+
+def test_direction_traces_follow_the_direction(L):
+    """The FP64 Navier-Stokes tangent reads face traces of the direction written by the gradient pass of the
+    same product.  They are tied to the direction's buffer only until the next tangent of q: a product after
+    the buffer's contents changed, after a product in another direction, and after a block-Jacobi build (whose
+    probing products run on element subsets and in batches) must still be the oracle's J(u) v."""
+    import torch
+    c = CS.c4_ns3d(n=3, p=2, shift=0.3)
+    _say("direction traces: c4 n=3 p=2")
+    m, md, t, dev = build_gpu(L, c)
+    om = c.oracle_model()
+    u = dev(c.u)
+    rng = np.random.default_rng(11)
+    v1 = dev(rng.uniform(-1, 1, md.N))
+    v2 = dev(rng.uniform(-1, 1, md.N))
+    md.jvp_prepare(u, L.FP64)
+
+    def check(v, what):
+        J = md.jvp_prepared(u, v, time=t, prec=L.FP64)
+        torch.cuda.synchronize()
+        e = rel(J.cpu().numpy(), c.om.jvp(om, c.u, v.cpu().numpy()))
+        _say(what, e)
+        assert e < 1e-12
+
+    check(v1, "v1")
+    check(v2, "v2")
+    v1.copy_(dev(rng.uniform(-1, 1, md.N)))          # same buffer, new contents
+    check(v1, "v1 refilled")
+    pc = L.BlockJacobi(md, u_lin=u, time=t, per_variable=True, prec=L.FP64)
+    torch.cuda.synchronize()
+    del pc
+    md.jvp_prepare(u, L.FP64)
+    check(v1, "v1 after a block build")
+    J = md.jvp(u, v2, time=t, prec=L.FP64)            # forms the cache itself, same kernels
+    torch.cuda.synchronize()
+    assert rel(J.cpu().numpy(), c.om.jvp(om, c.u, v2.cpu().numpy())) < 1e-12
