@@ -255,6 +255,15 @@ ldg_status ldg_mesh_create(int nd, int p, int nq1d, int64_t nvert, const double*
         ++m->nbf;
       }
 
+  m->nbr_distinct = true;
+  for (int64_t K = 0; K < nelem && m->nbr_distinct; ++K)
+    for (int F = 0; F < nf; ++F) {
+      const int32_t a = m->h_nbr[(size_t)K * nf + F];
+      if (a < 0) continue;
+      if (a == K) m->nbr_distinct = false;
+      for (int F2 = F + 1; F2 < nf; ++F2)
+        if (m->h_nbr[(size_t)K * nf + F2] == a) m->nbr_distinct = false;
+    }
   // greedy distance-2 colouring of the element face graph
   m->h_color.assign(nelem, -1);
   m->ncolors = 0;

@@ -53,6 +53,15 @@ struct Mesh {
   // products batched over blockIdx.y (set with the subsets by the block probing)
   int batch = 1;
   int64_t bsn = 0, bsq = 0;
+  // every element's face neighbours are distinct elements other than itself
+  // (no element touches another across two faces, as on 1- or 2-element-wide
+  // periodic meshes); the probing's closed-form neighbour traces need it
+  bool nbr_distinct = false;
+  // block probing on such an affine mesh, with the linearization point's traces
+  // formed: the tangent kernel forms the neighbours' tangent-of-q traces in
+  // closed form from its own direction trace, and the gradient pass runs on
+  // the seeded colour alone
+  bool probe_nbr = false;
   MeshDev dev_op(int which) const {
     MeshDev r = sub_list[which] ? MeshDev{(int)sub_count[which], (int)nbf, d_coef, d_nbr, d_btag, sub_list[which]}
                                 : dev();

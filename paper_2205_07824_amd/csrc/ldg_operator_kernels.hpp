@@ -602,9 +602,11 @@ k_grad(MeshDev m, typename TabOf<R>::T tab, ModelDev md, const S* __restrict__ u
 // S: storage type of the input vectors u, v (double; float for the FP32-state
 // products of modes 0 and 2)
 // TRC: read the face traces of the linearization point (u, q(u)); TRT (with
-// TRC): also those of the direction (v, tangent of q) instead of its lines
+// TRC): also those of the direction (v, tangent of q) instead of its lines;
+// PRB (with TRC, affine meshes): block probing, the neighbours' tangent-of-q
+// traces in closed form (Mesh::probe_nbr)
 template <int KIND, int D, int P1, class R, int MODE, bool EXT = false, bool AFF = false, class S = double,
-          bool TRC = false, bool TRT = false>
+          bool TRC = false, bool TRT = false, bool PRB = false>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(TRC ? 2 : ResidCfg<KIND, D, P1, R, MODE>::MIN_WAVES)))
 k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const S* __restrict__ u,
@@ -762,6 +764,30 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const S* _
         // neighbour's u and q(u) at this face point (its face F ^ 1), one read per
         // value, consecutive face points adjacent ([E][NF][NCU (1 + D)][NFP]); TRT
         // also reads v and the tangent of q there from the direction's traces
+        // block probing (PRB, affine meshes): the direction vanishes on the
+        // neighbour and on its other neighbours (distance-2 colouring, distinct
+        // neighbours), so the neighbour's tangent of q is the lifting of its jump
+        // 0 - (0 + v)/2 on this face alone; its trace here is pfac v Nn, with Nn the
+        // neighbour's face normal and pfac = -(1/2) sum_m l_m^2 / (w_m det)
+        R pfac = R(0), Nn[D];
+        if constexpr (MODE == 2 && HASQ && AFF && TRC && PRB) {
+          {
+            const double* cN = m.coef + (int64_t)nb * NV * D;
+            R xi0[D], Jn[D][D], adjn[D][D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) xi0[k] = R(0);
+            face_normal<D, DIR, R, true>(cN, xi0, 1 - side, Nn);
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+              for (int j = 0; j < D; ++j) Jn[i][j] = R(cN[(1 << j) * D + i]);
+            const R detn = adjugate<D, R>(Jn, adjn);
+            R sl = R(0);
+#pragma unroll
+            for (int mm = 0; mm < P1; ++mm) sl += l_nbr[mm] * l_nbr[mm] / tw[mm];
+            pfac = -R(0.5) * sl / detn;
+          }
+        }
         const R* tp = nullptr;
         const R* tpt = nullptr;
         if constexpr (TRC) tp = lin_traces<R>(md) + ((int64_t)nb * NF + (F ^ 1)) * (NCU * (1 + D)) * NFP + ff;
@@ -797,8 +823,12 @@ k_resid(MeshDev m, typename TabOf<R>::T tab, ModelDev md, TimeDev tm, const S* _
                   t = T::mk(tp[(NCU + c * D + k) * NFP], tpt[(NCU + c * D + k) * NFP]);
                 } else if constexpr (TRC) {
                   R td = R(0);
+                  if constexpr (PRB) {
+                    td = pfac * T::tan(um[c]) * Nn[k];
+                  } else {
 #pragma unroll
-                  for (int mm = 0; mm < P1; ++mm) td += l_nbr[mm] * dq[oq + mm * SD];
+                    for (int mm = 0; mm < P1; ++mm) td += l_nbr[mm] * dq[oq + mm * SD];
+                  }
                   t = T::mk(R(tp[(NCU + c * D + k) * NFP]), td);
                 } else {
 #pragma unroll

@@ -113,6 +113,16 @@ static ldg_status launch_resid(const Model& md, const TimeDev& t, const void* uv
         return LDG_OK;
       }
     }
+    if (trc && m.affine && m.probe_nbr) {
+      hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, true, S, true, false, true>), dim3(nblk, m.batch),
+                         dim3(EPB * NN), 0, s, mdv, tab, mod, t, u, (const R*)q, v, (const R*)dq, dterm, out, noF);
+      LDG_TRY(hipGetLastError());
+      return LDG_OK;
+    }
+    if (m.probe_nbr) {   // the neighbours' tangent of q was not formed: only the closed form has it
+      set_error("block probing with closed-form neighbour traces needs the linearization point's traces");
+      return LDG_EINVAL;
+    }
     if (trc) {
       if (m.affine)
         hipLaunchKernelGGL((k_resid<KIND, D, P1, R, MODE, false, true, S, true>), dim3(nblk, m.batch), dim3(EPB * NN),

@@ -360,6 +360,7 @@ static ldg_status assemble_blocks(Model& md, const ldg_time* t, const double* u_
       m.sub_count[0] = m.sub_count[1] = 0;
       m.batch = 1;
       m.bsn = m.bsq = 0;
+      m.probe_nbr = false;
     }
   } reset{m};
   if (md.kind != LDG_MODEL_USER) {
@@ -393,11 +394,17 @@ static ldg_status assemble_blocks(Model& md, const ldg_time* t, const double* u_
     if ((st = vec_fill(n * B, 0.0, vb, s)) != LDG_OK) return st;
     m.bsn = n;
     m.bsq = nq;
+    // Navier-Stokes on an affine mesh with distinct face neighbours and the
+    // linearization point's traces formed: the tangent kernel forms the
+    // neighbours' tangent-of-q traces in closed form, so the tangent of q is
+    // needed on the seeded colour only
+    m.probe_nbr = md.kind == LDG_MODEL_NS && m.affine && m.nbr_distinct &&
+                  (fp32 ? (md.d_tr32 && md.tr32_valid) : (md.d_tr && md.tr_of == u_lin));
     for (int c = 0; c < m.ncolors; ++c) {
       const int cnt = (int)(m.color_off[c + 1] - m.color_off[c]);
       const int32_t* list = m.d_color_list + m.color_off[c];
-      m.sub_list[0] = m.d_color_nbhd + m.nbhd_off[c];
-      m.sub_count[0] = m.nbhd_off[c + 1] - m.nbhd_off[c];
+      m.sub_list[0] = m.probe_nbr ? list : m.d_color_nbhd + m.nbhd_off[c];
+      m.sub_count[0] = m.probe_nbr ? cnt : m.nbhd_off[c + 1] - m.nbhd_off[c];
       m.sub_list[1] = list;
       m.sub_count[1] = cnt;
       for (int j0 = 0; j0 < NB; j0 += B) {
