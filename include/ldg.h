@@ -282,7 +282,11 @@ ldg_status ldg_jvp_state32(ldg_model model, const ldg_time* t, const float* u, c
 /* Exact diagonal blocks dG_K/du_K of the Jacobian at u_lin, by probing with the
  * distance-2 element colouring (one JVP per colour and local unknown), written
  * to blocks: DEVICE [E][nb][nb] row-major, nb = ncu*nn (per_variable = 0) or
- * [E][ncu][nn][nn] (per_variable = 1: the variable-diagonal sub-blocks). */
+ * [E][ncu][nn][nn] (per_variable = 1: the variable-diagonal sub-blocks).  For
+ * the library's own models the probing products of one colour run up to 16 seed
+ * columns per launch; their vectors (at most 1 GiB) are allocated by the model
+ * at its first block build and kept until it is destroyed (LDG_ENOMEM when that
+ * allocation fails). */
 ldg_status ldg_jacobian_blocks(ldg_model model, const ldg_time* t, const double* u_lin, int per_variable,
                                double* blocks, void* stream);
 
