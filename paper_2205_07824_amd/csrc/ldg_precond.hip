@@ -218,6 +218,105 @@ __global__ void __launch_bounds__(256) k_gj_invert(int nb, double* __restrict__ 
   }
 }
 
+// one double from a lane given by a wave-uniform index
+__device__ inline double lane_bcast(double v, int lane) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffu), lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Gauss-Jordan inversion of 64 x 64 blocks, one wave per block, lane r holding
+// row r in registers.  Row pivoting without interchanges: the pivot of column k
+// is the unused row of largest magnitude (lowest row on ties), broadcast to the
+// wave through LDS.  The in-place update leaves X with inverse[k][l] =
+// X[piv[k]][m] where piv[m] = l, so lane r, the pivot of step k_r, writes its row
+// as row k_r of the inverse, entry m to column piv[m].  Output layouts and the
+// singular-block count as k_gj_invert.
+template <class S, int H>
+__global__ void __launch_bounds__(64) k_gj_invert64(const double* __restrict__ blocks, S* __restrict__ inv,
+                                                    float* __restrict__ scale, int* __restrict__ info) {
+  constexpr int NB = 64;
+  __shared__ int piv[NB];
+  __shared__ double rowp[NB];   // the pivot row, broadcast through LDS
+  const int r = threadIdx.x;
+  const int64_t b = blockIdx.x;
+  const double* g = blocks + b * (NB * NB) + (int64_t)r * NB;
+  double x[NB];
+#pragma unroll
+  for (int j = 0; j < NB; j += 2) {
+    const double2 t = *reinterpret_cast<const double2*>(g + j);
+    x[j] = t.x;
+    x[j + 1] = t.y;
+  }
+  bool used = false, singular = false;
+  int myk = 0;
+  // the pivot loop runs at run time; the entries stay in registers because every
+  // access to x is in a fully unrolled column loop (column k picked by selects)
+  for (int k = 0; k < NB; ++k) {
+    double xk = 0.0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) xk = (j == k) ? x[j] : xk;
+    double bv = used ? -1.0 : fabs(xk);
+    int bi = r;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(bv, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    const int p = __builtin_amdgcn_readfirstlane(bi);
+    const double pv = lane_bcast(xk, p);
+    if (!(bv > 0.0)) singular = true;
+    const double ipv = pv != 0.0 ? 1.0 / pv : 0.0;
+    const bool me = r == p;
+    if (me) {
+      used = true;
+      myk = k;
+    }
+    if (r == 0) piv[k] = p;
+    const double f = me ? 0.0 : xk;
+    const double nk = me ? ipv : -f * ipv;
+    if (me) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) rowp[j] = x[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const double pj = rowp[j] * ipv;
+      const double nv = me ? pj : x[j] - f * pj;
+      x[j] = (j == k) ? nk : nv;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (r == 0 && singular) atomicAdd(info, 1);
+  if constexpr (H == 0) {
+    S* out = inv + b * (NB * NB);
+#pragma unroll
+    for (int m = 0; m < NB; ++m) out[piv[m] * NB + myk] = (S)x[m];   // out[j][i] = inverse[i][j]
+  } else {
+    double mx = 0.0;
+#pragma unroll
+    for (int m = 0; m < NB; ++m) mx = fmax(mx, fabs(x[m]));
+    int e = 0;
+    if (mx > 0.0) (void)frexp(mx, &e);
+    const double sc = ldexp(1.0, -e);
+    scale[b * NB + myk] = (float)ldexp(1.0, e);
+    S* out = inv + b * (NB * NB);
+#pragma unroll
+    for (int m = 0; m < NB; ++m) {
+      const int j = piv[m];
+      const double a = x[m] * sc;
+      out[((j >> 2) * NB + myk) * 4 + (j & 3)] = H == 1 ? to_bf16(a) : to_fp16(a);
+    }
+  }
+}
+
 // z_b = B_b^-1 r_b with the transposed inverse (M[j][i] = inverse[i][j]): one
 // thread per row, bpb blocks per work-group, r_b staged in LDS.  For each j the
 // threads of a block read one contiguous row of M; four partial sums keep four
@@ -477,6 +576,22 @@ static ldg_status invert_blocks(ldg_precond_s* pc, hipStream_t s) {
   }
   if (nb > 128) { set_error("block size above 128"); return LDG_EUNSUPPORTED; }
   if (zero_int(pc->info, s) != LDG_OK) return LDG_EDEVICE;
+  if (nb == 64) {
+    // one wave per block, the block in registers
+    const dim3 g64((unsigned)pc->nblocks);
+    if (pc->prec == LDG_FP32)
+      hipLaunchKernelGGL((k_gj_invert64<float, 0>), g64, dim3(64), 0, s, pc->scratch, (float*)pc->inv, pc->scale,
+                         pc->info);
+    else if (pc->prec == LDG_BF16)
+      hipLaunchKernelGGL((k_gj_invert64<uint16_t, 1>), g64, dim3(64), 0, s, pc->scratch, (uint16_t*)pc->inv,
+                         pc->scale, pc->info);
+    else if (pc->prec == LDG_FP16)
+      hipLaunchKernelGGL((k_gj_invert64<uint16_t, 2>), g64, dim3(64), 0, s, pc->scratch, (uint16_t*)pc->inv,
+                         pc->scale, pc->info);
+    else
+      hipLaunchKernelGGL((k_gj_invert64<double, 0>), g64, dim3(64), 0, s, pc->scratch, (double*)pc->inv, pc->scale,
+                         pc->info);
+  } else {
   const int threads = 256;
   const size_t lds = use_lds ? bytes : 0;
   const dim3 grid((unsigned)pc->nblocks);
@@ -492,6 +607,7 @@ static ldg_status invert_blocks(ldg_precond_s* pc, hipStream_t s) {
   else
     hipLaunchKernelGGL((k_gj_invert<double, 0>), grid, dim3(threads), lds, s, nb, pc->scratch, (double*)pc->inv,
                        pc->scale, use_lds, pc->info);
+  }
   LDG_TRY(hipGetLastError());
   int h_info = 0;
   LDG_TRY(hipMemcpyAsync(&h_info, pc->info, sizeof(int), hipMemcpyDeviceToHost, s));

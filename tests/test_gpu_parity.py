@@ -148,14 +148,16 @@ def test_jacobian_blocks_per_variable_ns(L):
     assert rel(B[:6], Bref) < 1e-12
 
 
-# Poisson blocks (nb = 64), Euler p=4 (nb = 100) and per-variable NS p=2 (nb = 27); the Euler
-# blocks need row interchanges in the partial-pivoting elimination (76 in the first 6 blocks)
-BJ_APPLY_CASES = [("c2", False, None, False), ("c3", False, 6, True), ("c4p2", True, 6, False)]
+# Poisson blocks (nb = 64), Euler p=4 (nb = 100) and p=3 (nb = 64) and per-variable NS p=2 (nb = 27); the
+# Euler blocks need row interchanges in the partial-pivoting elimination (76 in the first 6 blocks at p=4,
+# 10 at p=3, where the one-wave register-resident inversion of 64 x 64 blocks runs)
+BJ_APPLY_CASES = [("c2", False, None, False), ("c3", False, 6, True), ("c3p3", False, 6, True),
+                  ("c4p2", True, 6, False)]
 
 
 @pytest.mark.parametrize("case,per_variable,ncheck,swaps", BJ_APPLY_CASES)
 def test_block_jacobi_apply_inverts_blocks(L, case, per_variable, ncheck, swaps):
-    c = {"c2": lambda: CS.c2_poisson3d(), "c3": lambda: CS.c3_euler2d(n=4),
+    c = {"c2": lambda: CS.c2_poisson3d(), "c3": lambda: CS.c3_euler2d(n=4), "c3p3": lambda: CS.c3_euler2d(n=4, p=3),
          "c4p2": lambda: CS.c4_ns3d(n=3, p=2)}[case]()
     _say("case", case, "block-Jacobi apply")
     m, md, t, dev = build_gpu(L, c)
@@ -181,8 +183,9 @@ def test_block_jacobi_apply_inverts_blocks(L, case, per_variable, ncheck, swaps)
         assert e < tol
 
 
-# block sizes 64 (16 groups of four columns), 100 (25), 16 (4), per-variable 27 (7, padded)
-BJ16_CASES = [("c2", False, None), ("c3", False, None), ("c5", False, None), ("c4p2", True, 6)]
+# block sizes 64 (16 groups of four columns; Poisson, and Euler p=3 with row interchanges), 100 (25), 16 (4),
+# per-variable 27 (7, padded)
+BJ16_CASES = [("c2", False, None), ("c3", False, None), ("c3p3", False, 6), ("c5", False, None), ("c4p2", True, 6)]
 
 
 @pytest.mark.parametrize("name", ["bf16", "fp16"])
@@ -193,8 +196,8 @@ def test_block_jacobi_16bit_factors_rounding_bound(L, name, case, per_variable, 
     # inverse: |z16 - z32|_i <= (u + 2^-24) sum_j |A_ij r_j| + (fp16 subnormal
     # floor) 2^-24 max_j |A_ij| sum_j |r_j|, with u = 2^-8 (bf16), 2^-11 (fp16)
     prec, u = {"bf16": (L.BF16, 2.0 ** -8), "fp16": (L.FP16, 2.0 ** -11)}[name]
-    c = {"c2": lambda: CS.c2_poisson3d(), "c3": lambda: CS.c3_euler2d(n=4), "c5": lambda: CS.c5_convdiff2d(),
-         "c4p2": lambda: CS.c4_ns3d(n=3, p=2)}[case]()
+    c = {"c2": lambda: CS.c2_poisson3d(), "c3": lambda: CS.c3_euler2d(n=4), "c3p3": lambda: CS.c3_euler2d(n=4, p=3),
+         "c5": lambda: CS.c5_convdiff2d(), "c4p2": lambda: CS.c4_ns3d(n=3, p=2)}[case]()
     _say("case", case, "per-variable" if per_variable else "full", "block-Jacobi", name, "factors")
     m, md, t, dev = build_gpu(L, c)
     u_lin = None if c.kind in (CS.O.MODEL_POISSON, CS.O.MODEL_CONVDIFF) else dev(c.u)
