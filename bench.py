@@ -505,6 +505,9 @@ def main():
     ap.add_argument("--profile-ns-only", action="store_true",
                     help="only --steps FP64 Jacobian-vector products of the 64^3 Navier-Stokes workload with q(u) "
                          "cached (for a kernel trace or counters)")
+    ap.add_argument("--profile-bj-only", action="store_true",
+                    help="only one per-variable block-Jacobi build (FP16 factors) of the 64^3 Navier-Stokes workload "
+                         "at its linearization point (for a kernel trace)")
     ap.add_argument("--profile-wave-only", action="store_true",
                     help="only the wave model + displacement ODE leg (for a kernel trace)")
     args = ap.parse_args()
@@ -530,6 +533,15 @@ def main():
         return
     if args.profile_wave_only:
         print(json.dumps(wave_displacement_steps(ldg, I, log)))
+        return
+    if args.profile_bj_only:
+        _, m, md, u, v, t, _ = ns_workload(ldg, I)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pc = ldg.BlockJacobi(md, u_lin=u, time=t, per_variable=True, prec=ldg.FP16)
+        torch.cuda.synchronize()
+        print(json.dumps({"ns3d_tgv_p3_64cube_bj_build_fp16_s": round(time.perf_counter() - t0, 4)}))
+        del pc
         return
     if args.profile_ns_only:
         _, m, md, u, v, t, _ = ns_workload(ldg, I)
