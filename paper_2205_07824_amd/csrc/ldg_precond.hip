@@ -23,7 +23,8 @@ struct ldg_precond_s {
                           // (zero for 4g+k >= nb)
   float* scale = nullptr; // 16-bit: [nblocks][nb] power-of-two row scales
   int ng = 0;             // 16-bit: column groups of four, ceil(nb / 4)
-  double* scratch = nullptr;  // assembled blocks [nblocks][nb][nb] row-major
+  double* scratch = nullptr;  // assembled blocks [nblocks][nb][nb] row-major (column-major when colmajor)
+  bool colmajor = false;
   int* info = nullptr;        // singular-block counter (device)
   double a0 = 0.0;
 };
@@ -63,8 +64,11 @@ __global__ void k_probe_gather(int n, const int32_t* __restrict__ list, int NB, 
 }
 
 // batched gather: column j0 + y from the y-th result vector
+// (colmajor: each block stored column-major, block[j][i], so that one column is
+// one contiguous write)
 __global__ void k_probe_gather_b(int n, const int32_t* __restrict__ list, int NB, int nn, int j0, int64_t stride,
-                                 int per_variable, const double* __restrict__ Jv, double* __restrict__ blocks) {
+                                 int per_variable, int colmajor, const double* __restrict__ Jv,
+                                 double* __restrict__ blocks) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int j = j0 + blockIdx.y;
   Jv += blockIdx.y * stride;
@@ -74,12 +78,13 @@ __global__ void k_probe_gather_b(int n, const int32_t* __restrict__ list, int NB
     const int i = t % nn;
     const int cv = j / nn, jn = j % nn;
     const int ncu = NB / nn;
-    blocks[(((K * ncu + cv) * nn) + i) * nn + jn] = Jv[K * NB + cv * nn + i];
+    const int64_t o = ((K * ncu + cv) * nn) * nn;
+    blocks[o + (colmajor ? (int64_t)jn * nn + i : (int64_t)i * nn + jn)] = Jv[K * NB + cv * nn + i];
   } else {
     if (t >= (int64_t)n * NB) return;
     const int64_t K = list[t / NB];
     const int i = t % NB;
-    blocks[(K * NB + i) * NB + j] = Jv[K * NB + i];
+    blocks[K * NB * NB + (colmajor ? (int64_t)j * NB + i : (int64_t)i * NB + j)] = Jv[K * NB + i];
   }
 }
 
@@ -235,19 +240,26 @@ __device__ inline double lane_bcast(double v, int lane) {
 // singular-block count as k_gj_invert.
 template <class S, int H>
 __global__ void __launch_bounds__(64) k_gj_invert64(const double* __restrict__ blocks, S* __restrict__ inv,
-                                                    float* __restrict__ scale, int* __restrict__ info) {
+                                                    float* __restrict__ scale, int colmajor,
+                                                    int* __restrict__ info) {
   constexpr int NB = 64;
   __shared__ int piv[NB];
   __shared__ double rowp[NB];   // the pivot row, broadcast through LDS
   const int r = threadIdx.x;
   const int64_t b = blockIdx.x;
-  const double* g = blocks + b * (NB * NB) + (int64_t)r * NB;
   double x[NB];
+  if (colmajor) {   // entry (r, j) at j * NB + r: consecutive lanes read consecutive words
+    const double* g = blocks + b * (NB * NB) + r;
 #pragma unroll
-  for (int j = 0; j < NB; j += 2) {
-    const double2 t = *reinterpret_cast<const double2*>(g + j);
-    x[j] = t.x;
-    x[j + 1] = t.y;
+    for (int j = 0; j < NB; ++j) x[j] = g[j * NB];
+  } else {
+    const double* g = blocks + b * (NB * NB) + (int64_t)r * NB;
+#pragma unroll
+    for (int j = 0; j < NB; j += 2) {
+      const double2 t = *reinterpret_cast<const double2*>(g + j);
+      x[j] = t.x;
+      x[j + 1] = t.y;
+    }
   }
   bool used = false, singular = false;
   int myk = 0;
@@ -434,8 +446,11 @@ static bool is16(ldg_precision p) { return p == LDG_BF16 || p == LDG_FP16; }
 
 // probe = LDG_FP32 for blocks that are stored in FP32 anyway (the probing JVPs
 // then run in FP32 too)
+// colmajor: blocks stored column-major (the block-Jacobi build of 64 x 64 blocks,
+// whose one-wave inversion then reads each row with coalesced loads); only the
+// library's own models take it
 static ldg_status assemble_blocks(Model& md, const ldg_time* t, const double* u_lin, int per_variable,
-                                  double* blocks, ldg_precision probe, hipStream_t s) {
+                                  double* blocks, ldg_precision probe, hipStream_t s, bool colmajor = false) {
   Mesh& m = *md.mesh;
   const int NB = md.ncu * m.nn;
   const int64_t n = (int64_t)md.N();
@@ -520,7 +535,7 @@ static ldg_status assemble_blocks(Model& md, const ldg_time* t, const double* u_
         }
         const int64_t tot = per_variable ? (int64_t)cnt * m.nn : (int64_t)cnt * NB;
         hipLaunchKernelGGL(k_probe_gather_b, dim3((unsigned)((tot + 255) / 256), b), dim3(256), 0, s, cnt, list, NB,
-                           m.nn, j0, n, per_variable, Jvb, blocks);
+                           m.nn, j0, n, per_variable, colmajor ? 1 : 0, Jvb, blocks);
         hipLaunchKernelGGL(k_probe_set_b, dim3((cnt + 255) / 256, b), dim3(256), 0, s, cnt, list, NB, j0, n, 0.0, vb);
       }
     }
@@ -581,16 +596,16 @@ static ldg_status invert_blocks(ldg_precond_s* pc, hipStream_t s) {
     const dim3 g64((unsigned)pc->nblocks);
     if (pc->prec == LDG_FP32)
       hipLaunchKernelGGL((k_gj_invert64<float, 0>), g64, dim3(64), 0, s, pc->scratch, (float*)pc->inv, pc->scale,
-                         pc->info);
+                         (int)pc->colmajor, pc->info);
     else if (pc->prec == LDG_BF16)
       hipLaunchKernelGGL((k_gj_invert64<uint16_t, 1>), g64, dim3(64), 0, s, pc->scratch, (uint16_t*)pc->inv,
-                         pc->scale, pc->info);
+                         pc->scale, (int)pc->colmajor, pc->info);
     else if (pc->prec == LDG_FP16)
       hipLaunchKernelGGL((k_gj_invert64<uint16_t, 2>), g64, dim3(64), 0, s, pc->scratch, (uint16_t*)pc->inv,
-                         pc->scale, pc->info);
+                         pc->scale, (int)pc->colmajor, pc->info);
     else
       hipLaunchKernelGGL((k_gj_invert64<double, 0>), g64, dim3(64), 0, s, pc->scratch, (double*)pc->inv, pc->scale,
-                         pc->info);
+                         (int)pc->colmajor, pc->info);
   } else {
   const int threads = 256;
   const size_t lds = use_lds ? bytes : 0;
@@ -621,8 +636,10 @@ ldg_status precond_rebuild(ldg_precond_s* pc, const ldg_time* t, const double* u
     set_error("the learned preconditioner is rebuilt through its block-Jacobi part");
     return LDG_EINVAL;
   }
+  // 64 x 64 blocks of the library's own models: column-major for k_gj_invert64
+  pc->colmajor = pc->nb == 64 && pc->md->kind != LDG_MODEL_USER;
   ldg_status st = assemble_blocks(*pc->md, t, u_lin, pc->per_variable, pc->scratch,
-                                  pc->prec == LDG_FP64 ? LDG_FP64 : LDG_FP32, s);
+                                  pc->prec == LDG_FP64 ? LDG_FP64 : LDG_FP32, s, pc->colmajor);
   if (st != LDG_OK) return st;
   return invert_blocks(pc, s);
 }
